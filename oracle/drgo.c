@@ -1,0 +1,563 @@
+/*
+ * drgo.c -- CPU oracle for the DRGraph layout hot path (see drgo.h).
+ *
+ * TEST INFRASTRUCTURE ONLY: plain, slow, single-threaded FP64 code written
+ * from the paper's definitions.  Each function names the passage it follows.
+ * Parity pins for every function live in tests/ (marked "not gpu").
+ */
+#include "drgo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 64x64->128 multiplies with    */
+/* the published multipliers and Weyl key increments.                        */
+/* ------------------------------------------------------------------------ */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void drgo_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, x0, &hi0, &lo0);
+        mulhilo64(M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+static void philox_stream(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t c,
+                          uint64_t out[4]) {
+    uint64_t ctr[4] = {a, b, c, 0};
+    uint64_t key[2] = {seed, tag};
+    drgo_philox(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-order nearest neighbours NNG(v_i, k) = {v : SPD(v_i, v) <= k, v != v_i} */
+/* (Sec. 3.2.1), by plain breadth-first search bounded at depth k.           */
+/* ------------------------------------------------------------------------ */
+static int cmp_i32(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* BFS from src; fills q[0..ret) with reached nodes (q[0] = src) and dist[]. */
+static int32_t bfs_bounded(const int32_t* rp, const int32_t* col, int32_t k, int32_t src,
+                           int32_t* dist, int32_t* q) {
+    int32_t head = 0, tail = 0;
+    dist[src] = 0;
+    q[tail++] = src;
+    while (head < tail) {
+        int32_t u = q[head++];
+        if (dist[u] >= k) continue;
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (dist[v] < 0) {
+                dist[v] = dist[u] + 1;
+                q[tail++] = v;
+            }
+        }
+    }
+    return tail;
+}
+
+int64_t drgo_khop_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k,
+                        int64_t* out_rp) {
+    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    out_rp[0] = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        int32_t t = bfs_bounded(rp, col, k, s, dist, q);
+        out_rp[s + 1] = out_rp[s] + (t - 1);
+        for (int32_t x = 0; x < t; ++x) dist[q[x]] = -1;
+    }
+    free(dist);
+    free(q);
+    return out_rp[n];
+}
+
+void drgo_khop_fill(int32_t n, const int32_t* rp, const int32_t* col, int32_t k,
+                    const int64_t* out_rp, int32_t* out_col, uint8_t* out_hop) {
+    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    for (int32_t s = 0; s < n; ++s) {
+        int32_t t = bfs_bounded(rp, col, k, s, dist, q);
+        int64_t o = out_rp[s];
+        /* reached nodes except the source, ascending by id */
+        qsort(q + 1, (size_t)(t - 1), sizeof(int32_t), cmp_i32);
+        for (int32_t x = 1; x < t; ++x) {
+            out_col[o + x - 1] = q[x];
+            out_hop[o + x - 1] = (uint8_t)dist[q[x]];
+        }
+        for (int32_t x = 0; x < t; ++x) dist[q[x]] = -1;
+    }
+    free(dist);
+    free(q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Node similarity (Eq. NS; sparse form in Sec. 3.2.1).                      */
+/*   NS_{j|i} = e_{d_ij} / Z_i,  Z_i = sum_{l in NNG(i,k)} e_{d_il}          */
+/*   NS_ij    = (NS_{i|j} + NS_{j|i}) / (2|V|)                               */
+/* The Gaussian is precomputed for the k hop values; Z_i is the hop         */
+/* histogram weighted by it.  We keep P~ = N_a * NS with N_a the number of  */
+/* non-isolated nodes (the paper's graphs have none isolated, so N_a = |V|).*/
+/* The node weight used for negative sampling is sum_l NS_{j,l} (Sec.       */
+/* 3.2.2), i.e. qt_j / N_a; it is quantised per entry to 2^-32 so that the */
+/* sampling distribution is an exact integer table.                         */
+/* ------------------------------------------------------------------------ */
+void drgo_similarity(int32_t n, int32_t k, double sigma, const int64_t* prp, const int32_t* pcol,
+                     const uint8_t* phop, double* e, double* Z, double* invZ, double* P, double* qt,
+                     uint64_t* W, uint64_t* C) {
+    for (int32_t d = 1; d <= k; ++d) e[d - 1] = exp(-(double)(d * d) / (2.0 * sigma * sigma));
+    int64_t* cnt = (int64_t*)calloc((size_t)(k > 0 ? k : 1), sizeof(int64_t));
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t d = 0; d < k; ++d) cnt[d] = 0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) cnt[phop[x] - 1] += 1;
+        double z = 0.0;
+        for (int32_t d = 0; d < k; ++d) {
+            double term = (double)cnt[d] * e[d];
+            z = z + term;
+        }
+        Z[i] = z;
+        invZ[i] = (prp[i + 1] > prp[i]) ? 1.0 / z : 0.0;
+    }
+    free(cnt);
+    C[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double q = 0.0;
+        uint64_t w = 0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            double s = invZ[i] + invZ[j];
+            double t = e[phop[x] - 1] * s;
+            double p = t * 0.5;
+            P[x] = p;
+            q = q + p;
+            w += (uint64_t)(p * 4294967296.0);
+        }
+        qt[i] = q;
+        W[i] = w;
+        C[i + 1] = C[i] + w;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Negative sampling by node weight (Sec. 3.2.2): inverse of the integer   */
+/* cumulative weight table.                                                  */
+/* ------------------------------------------------------------------------ */
+int32_t drgo_draw(const uint64_t* C, int32_t n, uint64_t w) {
+    uint64_t hi, lo;
+    mulhilo64(w, C[n], &hi, &lo);
+    uint64_t r = hi; /* floor(w * S / 2^64) in [0, S) */
+    int32_t a = 0, b = n - 1;
+    while (a < b) { /* smallest v with C[v+1] > r */
+        int32_t m = a + (b - a) / 2;
+        if (C[m + 1] > r)
+            b = m;
+        else
+            a = m + 1;
+    }
+    return a;
+}
+
+uint64_t drgo_neg_word(uint64_t seed, uint64_t it, int32_t i, int32_t m) {
+    uint64_t out[4];
+    philox_stream(seed, DRGO_TAG_NEG, (uint64_t)(uint32_t)i, it, (uint64_t)(m / 4), out);
+    return out[m % 4];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coarsening (Sec. 3.2.3, Fig. 3): pick a random unassigned node, group it */
+/* with its unassigned first-order neighbours into one coarse node, repeat  */
+/* until every node is assigned.  "Random" is a Philox priority per node,   */
+/* visited in descending (priority, -id) order.                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t pri;
+    int32_t id;
+} prio_t;
+
+static int cmp_prio_desc(const void* a, const void* b) {
+    const prio_t* x = (const prio_t*)a;
+    const prio_t* y = (const prio_t*)b;
+    if (x->pri != y->pri) return (x->pri < y->pri) ? 1 : -1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+int32_t drgo_coarsen_level(int32_t n, const int32_t* rp, const int32_t* col, uint64_t seed,
+                           int32_t level, int32_t* map) {
+    prio_t* order = (prio_t*)malloc(sizeof(prio_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t v = 0; v < n; ++v) {
+        uint64_t out[4];
+        philox_stream(seed, DRGO_TAG_COARSEN, (uint64_t)(uint32_t)v, (uint64_t)(uint32_t)level, 0,
+                      out);
+        order[v].pri = out[0];
+        order[v].id = v;
+        owner[v] = -1;
+    }
+    qsort(order, (size_t)n, sizeof(prio_t), cmp_prio_desc);
+    for (int32_t x = 0; x < n; ++x) {
+        int32_t v = order[x].id;
+        if (owner[v] >= 0) continue;
+        owner[v] = v;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (owner[col[e]] < 0) owner[col[e]] = v;
+    }
+    /* coarse ids: centres ranked by node id */
+    int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t nc = 0;
+    for (int32_t v = 0; v < n; ++v) rank[v] = (owner[v] == v) ? nc++ : -1;
+    for (int32_t v = 0; v < n; ++v) map[v] = rank[owner[v]];
+    free(rank);
+    free(owner);
+    free(order);
+    return nc;
+}
+
+static int cmp_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* An edge of G^l survives into G^{l+1} between the two coarse nodes unless
+ * both ends were grouped into the same coarse node (Sec. 3.2.3). */
+int64_t drgo_contract(int32_t n, const int32_t* rp, const int32_t* col, const int32_t* map,
+                      int32_t nc, int32_t* out_rp, int32_t* out_col) {
+    int64_t m = rp[n];
+    int64_t* key = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int64_t t = 0;
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t a = map[u], b = map[col[e]];
+            if (a != b) key[t++] = (int64_t)a * nc + b;
+        }
+    qsort(key, (size_t)t, sizeof(int64_t), cmp_i64);
+    int64_t u = 0;
+    for (int64_t x = 0; x < t; ++x)
+        if (x == 0 || key[x] != key[x - 1]) key[u++] = key[x];
+    for (int32_t a = 0; a <= nc; ++a) out_rp[a] = 0;
+    for (int64_t x = 0; x < u; ++x) {
+        out_rp[key[x] / nc + 1] += 1;
+        out_col[x] = (int32_t)(key[x] % nc);
+    }
+    for (int32_t a = 0; a < nc; ++a) out_rp[a + 1] += out_rp[a];
+    free(key);
+    return u;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Layout of the coarsest graph: random initialisation (Sec. 3.2.3), each   */
+/* coordinate uniform on [-1, 1) on a 2^-23 grid.                            */
+/* ------------------------------------------------------------------------ */
+void drgo_init(int32_t nl, uint64_t seed, int32_t level, double* y) {
+    for (int32_t v = 0; v < nl; ++v) {
+        uint64_t out[4];
+        philox_stream(seed, DRGO_TAG_INIT, (uint64_t)(uint32_t)v, (uint64_t)(uint32_t)level, 0,
+                      out);
+        double ux = (double)(out[0] >> 40) * (1.0 / 16777216.0);
+        double uy = (double)(out[1] >> 40) * (1.0 / 16777216.0);
+        y[2 * v] = 2.0 * ux - 1.0;
+        y[2 * v + 1] = 2.0 * uy - 1.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forces (Eq. gradient).  With unnormalised proximity w = 1/(1 + d^{2b}),  */
+/* d = ||y_i - y_j||:                                                        */
+/*   d/dy_i log w       = -2b d^{2b-2} (y_i - y_j) / (1 + d^{2b})  (attract) */
+/*   d/dy_i log(1 - w)  =  2b (y_i - y_j) / (d^2 (1 + d^{2b}))     (repel)   */
+/* A pair at distance exactly zero contributes nothing.                      */
+/* ------------------------------------------------------------------------ */
+static double ipow(double x, int32_t b) {
+    double r = 1.0;
+    for (int32_t t = 0; t < b; ++t) r = r * x;
+    return r;
+}
+
+static double clipd(double v, double c) { return v > c ? c : (v < -c ? -c : v); }
+
+/* attraction coefficient: A = coef * delta */
+static double attract_coef(double d2, int32_t b) {
+    double D = ipow(d2, b);
+    return -2.0 * (double)b * ipow(d2, b - 1) / (1.0 + D);
+}
+
+static double repel_coef(double d2, int32_t b) {
+    double D = ipow(d2, b);
+    return 2.0 * (double)b / (d2 * (1.0 + D));
+}
+
+void drgo_step_direction(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
+                         const double* qt, const uint64_t* C, const int32_t* cmap, const double* y,
+                         int32_t M, int32_t b, double gamma, double clip, uint64_t seed,
+                         uint64_t it, double* g) {
+    for (int32_t i = 0; i < n0; ++i) {
+        g[2 * i] = 0.0;
+        g[2 * i + 1] = 0.0;
+        if (prp[i + 1] == prp[i]) continue; /* isolated: never anchors */
+        int32_t a = cmap ? cmap[i] : i;
+        double yx = y[2 * a], yy = y[2 * a + 1];
+        double ax = 0.0, ay = 0.0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t c = cmap ? cmap[pcol[x]] : pcol[x];
+            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = attract_coef(d2, b);
+            ax += P[x] * clipd(k * dx, clip);
+            ay += P[x] * clipd(k * dy, clip);
+        }
+        double rx = 0.0, ry = 0.0;
+        for (int32_t m = 0; m < M; ++m) {
+            int32_t v = drgo_draw(C, n0, drgo_neg_word(seed, it, i, m));
+            int32_t c = cmap ? cmap[v] : v;
+            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = repel_coef(d2, b);
+            rx += clipd(k * dx, clip);
+            ry += clipd(k * dy, clip);
+        }
+        g[2 * i] = ax + gamma * qt[i] * rx;
+        g[2 * i + 1] = ay + gamma * qt[i] * ry;
+    }
+}
+
+/* Gradient sharing across levels (Sec. 3.2.3): the step of fine node i is
+ * forwarded to the level node it was assigned to; forwarded steps add. */
+void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
+                    const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
+                    int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
+                    uint64_t it) {
+    double* g = (double*)malloc(sizeof(double) * 2 * (size_t)(n0 > 0 ? n0 : 1));
+    double* G = (double*)calloc(2 * (size_t)(nl > 0 ? nl : 1), sizeof(double));
+    drgo_step_direction(n0, prp, pcol, P, qt, C, cmap, y, M, b, gamma, clip, seed, it, g);
+    for (int32_t i = 0; i < n0; ++i) {
+        int32_t a = cmap ? cmap[i] : i;
+        G[2 * a] += g[2 * i];
+        G[2 * a + 1] += g[2 * i + 1];
+    }
+    for (int32_t a = 0; a < nl; ++a) {
+        y[2 * a] += eta * G[2 * a];
+        y[2 * a + 1] += eta * G[2 * a + 1];
+    }
+    free(g);
+    free(G);
+}
+
+void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
+                   const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
+                   int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
+                   uint64_t it) {
+    (void)nl;
+    for (int32_t i = 0; i < n0; ++i) {
+        if (prp[i + 1] == prp[i]) continue;
+        int32_t a = cmap ? cmap[i] : i;
+        double yx = y[2 * a], yy = y[2 * a + 1];
+        double ax = 0.0, ay = 0.0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t c = cmap ? cmap[pcol[x]] : pcol[x];
+            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = attract_coef(d2, b);
+            ax += P[x] * clipd(k * dx, clip);
+            ay += P[x] * clipd(k * dy, clip);
+        }
+        double rx = 0.0, ry = 0.0;
+        for (int32_t m = 0; m < M; ++m) {
+            int32_t v = drgo_draw(C, n0, drgo_neg_word(seed, it, i, m));
+            int32_t c = cmap ? cmap[v] : v;
+            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = repel_coef(d2, b);
+            rx += clipd(k * dx, clip);
+            ry += clipd(k * dy, clip);
+        }
+        y[2 * a] += eta * (ax + gamma * qt[i] * rx);
+        y[2 * a + 1] += eta * (ay + gamma * qt[i] * ry);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Objective (Eq. objectfunction).  The expectation over positive pairs    */
+/* (i, j) ~ NS is taken exactly (weights P~); the M negatives per anchor    */
+/* are the drawn ones, each weighted gamma * qt_i.                          */
+/*   L^ = sum_ij P~_ij log w_ij + gamma sum_i qt_i sum_m log(1 - w_{i v_im}) */
+/* log w = -log1p(d^{2b}); log(1 - w) = b log d^2 - log1p(d^{2b}).           */
+/* ------------------------------------------------------------------------ */
+double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
+                      const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                      double gamma, uint64_t seed, uint64_t it) {
+    double L = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (prp[i + 1] == prp[i]) continue;
+        double att = 0.0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
+            double d2 = dx * dx + dy * dy;
+            att += P[x] * (-log1p(ipow(d2, b)));
+        }
+        double rep = 0.0;
+        for (int32_t m = 0; m < M; ++m) {
+            int32_t v = drgo_draw(C, n, drgo_neg_word(seed, it, i, m));
+            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
+            double d2 = dx * dx + dy * dy;
+            if (v == i || d2 == 0.0) continue;
+            rep += (double)b * log(d2) - log1p(ipow(d2, b));
+        }
+        L += att + gamma * qt[i] * rep;
+    }
+    return L;
+}
+
+void drgo_objective_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
+                         const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                         double gamma, uint64_t seed, uint64_t it, double* grad) {
+    for (int32_t i = 0; i < 2 * n; ++i) grad[i] = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (prp[i + 1] == prp[i]) continue;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = attract_coef(d2, b);
+            /* the term P~_ij log w_ij depends on both y_i and y_j */
+            grad[2 * i] += P[x] * k * dx;
+            grad[2 * i + 1] += P[x] * k * dy;
+            grad[2 * j] -= P[x] * k * dx;
+            grad[2 * j + 1] -= P[x] * k * dy;
+        }
+        for (int32_t m = 0; m < M; ++m) {
+            int32_t v = drgo_draw(C, n, drgo_neg_word(seed, it, i, m));
+            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
+            double d2 = dx * dx + dy * dy;
+            if (v == i || d2 == 0.0) continue;
+            double k = gamma * qt[i] * repel_coef(d2, b);
+            grad[2 * i] += k * dx;
+            grad[2 * i + 1] += k * dy;
+            grad[2 * v] -= k * dx;
+            grad[2 * v + 1] -= k * dy;
+        }
+    }
+}
+
+/* probability that a draw returns v */
+static double draw_prob(const uint64_t* C, int32_t n, int32_t v) {
+    return (double)(C[v + 1] - C[v]) / (double)C[n];
+}
+
+double drgo_objective_exact(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
+                            const double* qt, const uint64_t* C, const double* y, int32_t M,
+                            int32_t b, double gamma) {
+    double L = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (prp[i + 1] == prp[i]) continue;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
+            L += P[x] * (-log1p(ipow(dx * dx + dy * dy, b)));
+        }
+        double rep = 0.0;
+        for (int32_t v = 0; v < n; ++v) {
+            double pv = draw_prob(C, n, v);
+            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
+            double d2 = dx * dx + dy * dy;
+            if (v == i || d2 == 0.0 || pv == 0.0) continue;
+            rep += pv * ((double)b * log(d2) - log1p(ipow(d2, b)));
+        }
+        L += gamma * qt[i] * (double)M * rep;
+    }
+    return L;
+}
+
+void drgo_objective_exact_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
+                               const double* qt, const uint64_t* C, const double* y, int32_t M,
+                               int32_t b, double gamma, double* grad) {
+    for (int32_t i = 0; i < 2 * n; ++i) grad[i] = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (prp[i + 1] == prp[i]) continue;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = P[x] * attract_coef(d2, b);
+            grad[2 * i] += k * dx;
+            grad[2 * i + 1] += k * dy;
+            grad[2 * j] -= k * dx;
+            grad[2 * j + 1] -= k * dy;
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            double pv = draw_prob(C, n, v);
+            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
+            double d2 = dx * dx + dy * dy;
+            if (v == i || d2 == 0.0 || pv == 0.0) continue;
+            double k = gamma * qt[i] * (double)M * pv * repel_coef(d2, b);
+            grad[2 * i] += k * dx;
+            grad[2 * i + 1] += k * dy;
+            grad[2 * v] -= k * dx;
+            grad[2 * v + 1] -= k * dy;
+        }
+    }
+}
+
+void drgo_step_expected(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
+                        const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                        double gamma, double* g) {
+    for (int32_t i = 0; i < n; ++i) {
+        g[2 * i] = 0.0;
+        g[2 * i + 1] = 0.0;
+        if (prp[i + 1] == prp[i]) continue;
+        double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            double k = attract_coef(d2, b);
+            ax += P[x] * k * dx;
+            ay += P[x] * k * dy;
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            double pv = draw_prob(C, n, v);
+            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0 || pv == 0.0) continue;
+            double k = repel_coef(d2, b);
+            rx += pv * k * dx;
+            ry += pv * k * dy;
+        }
+        g[2 * i] = ax + gamma * qt[i] * (double)M * rx;
+        g[2 * i + 1] = ay + gamma * qt[i] * (double)M * ry;
+    }
+}

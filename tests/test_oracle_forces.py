@@ -1,0 +1,172 @@
+"""Pins of the oracle's forces, objective and iteration (Sec. 3.2.2,
+Eq. objectfunction and Eq. gradient; Sec. 3.2.3 gradient forwarding).
+Marked "not gpu"."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2008_07799_amd import gen
+
+
+def _setup(oracle_lib, n=30, p=0.15, k=2, sub=0, scale=1.5):
+    g = gen.random_graph(n, p, seed=21, sub=sub)
+    sim = oracle_lib.similarity(g, k)
+    rng = np.random.default_rng(sub)
+    y = rng.uniform(-scale, scale, size=(n, 2))
+    return g, sim, y
+
+
+@pytest.mark.parametrize("b", [1, 2, 3])
+def test_sampled_gradient_matches_central_differences(oracle_lib, b):
+    g, sim, y = _setup(oracle_lib, sub=b)
+    grad = oracle_lib.objective_grad(sim, y, M=5, b=b, gamma=0.1, seed=3, it=7)
+    h = 1e-6
+    rng = np.random.default_rng(b)
+    for i in rng.choice(g.n, 12, replace=False):
+        for c in (0, 1):
+            yp, ym = y.copy(), y.copy()
+            yp[i, c] += h
+            ym[i, c] -= h
+            fd = (oracle_lib.objective(sim, yp, 5, b, 0.1, 3, 7)
+                  - oracle_lib.objective(sim, ym, 5, b, 0.1, 3, 7)) / (2 * h)
+            assert fd == pytest.approx(grad[i, c], rel=1e-5, abs=1e-7)
+
+
+@pytest.mark.parametrize("b", [1, 2])
+def test_exact_gradient_matches_central_differences(oracle_lib, b):
+    g, sim, y = _setup(oracle_lib, n=20, sub=10 + b)
+    grad = oracle_lib.objective_exact_grad(sim, y, M=5, b=b, gamma=0.1)
+    h = 1e-6
+    for i in range(0, g.n, 3):
+        for c in (0, 1):
+            yp, ym = y.copy(), y.copy()
+            yp[i, c] += h
+            ym[i, c] -= h
+            fd = (oracle_lib.objective_exact(sim, yp, 5, b, 0.1)
+                  - oracle_lib.objective_exact(sim, ym, 5, b, 0.1)) / (2 * h)
+            assert fd == pytest.approx(grad[i, c], rel=1e-5, abs=1e-7)
+
+
+def test_two_node_student_t(oracle_lib):
+    """b = 1 is the Student-t kernel: attraction -2D/(1+d^2) and repulsion
+    2D/(d^2 (1+d^2)) for D = y_i - y_j (Eq. gradient with b = 1).  On a single
+    edge P~_01 = 1 and qt = 1, so g_0 = A + gamma * (#draws of node 1) * R."""
+    g = gen.canonical_csr(2, np.array([0]), np.array([1]))
+    sim = oracle_lib.similarity(g, 1)
+    assert sim.P.tolist() == [1.0, 1.0] and sim.qt.tolist() == [1.0, 1.0]
+    y = np.array([[0.3, -0.2], [-0.5, 0.4]])
+    D = y[0] - y[1]
+    d2 = D @ D
+    A = -2 * D / (1 + d2)
+    R = 2 * D / (d2 * (1 + d2))
+    M, gam = 6, 0.25
+    hits = sum(oracle_lib.draw(sim, oracle_lib.neg_word(1, 4, 0, m)) == 1 for m in range(M))
+    gdir = oracle_lib.step_direction(sim, y, None, M, 1, gam, math.inf, 1, 4)
+    assert np.allclose(gdir[0], A + gam * hits * R, rtol=1e-14)
+
+
+@pytest.mark.parametrize("clip", [math.inf, 0.05])
+@pytest.mark.parametrize("b", [1, 3])
+def test_zero_net_attraction(oracle_lib, clip, b):
+    """P~ symmetric and the attraction antisymmetric (clipping is odd), so
+    the attractive forces sum to zero."""
+    g, sim, y = _setup(oracle_lib, n=200, p=0.02, sub=4)
+    gdir = oracle_lib.step_direction(sim, y, None, 5, b, 0.0, clip, 0, 0)
+    assert np.abs(gdir.sum(axis=0)).max() < 1e-12 * max(1.0, np.abs(gdir).sum())
+
+
+def test_gradient_translation_rotation_invariance(oracle_lib):
+    """L^ depends on distances only: zero total force and zero torque."""
+    g, sim, y = _setup(oracle_lib, n=150, p=0.03, sub=5)
+    G = oracle_lib.objective_grad(sim, y, 5, 2, 0.1, 9, 1)
+    scale = np.abs(G).sum()
+    assert np.abs(G.sum(axis=0)).max() < 1e-12 * scale
+    torque = (y[:, 0] * G[:, 1] - y[:, 1] * G[:, 0]).sum()
+    assert abs(torque) < 1e-11 * scale
+
+
+def test_monte_carlo_step_converges_to_expectation(oracle_lib):
+    """Averaged over negative draws, the one-sided step equals its exact
+    expectation; and twice the expectation is the gradient of the expected
+    objective up to the 2^-32 quantisation of the sampling weights."""
+    g, sim, y = _setup(oracle_lib, n=25, p=0.2, k=1, sub=6)
+    S = 3000
+    acc = np.zeros_like(y)
+    acc2 = np.zeros_like(y)
+    for s in range(S):
+        gd = oracle_lib.step_direction(sim, y, None, 5, 2, 0.1, math.inf, s, 0)
+        acc += gd
+        acc2 += gd * gd
+    mean = acc / S
+    se = np.sqrt(np.maximum(acc2 / S - mean ** 2, 0) / S)
+    expd = oracle_lib.step_expected(sim, y, 5, 2, 0.1)
+    z = np.abs(mean - expd) / np.maximum(se, 1e-15)
+    assert z.max() < 5.0
+    grad_exact = oracle_lib.objective_exact_grad(sim, y, 5, 2, 0.1)
+    assert np.allclose(grad_exact, 2 * expd, rtol=1e-6, atol=1e-9)
+
+
+def test_sampled_objective_is_unbiased(oracle_lib):
+    g, sim, y = _setup(oracle_lib, n=25, p=0.2, k=2, sub=7)
+    S = 4000
+    vals = np.array([oracle_lib.objective(sim, y, 5, 2, 0.1, s, 0) for s in range(S)])
+    exact = oracle_lib.objective_exact(sim, y, 5, 2, 0.1)
+    assert abs(vals.mean() - exact) < 5 * vals.std() / math.sqrt(S)
+
+
+def test_forwarding_equals_galerkin_coarse_matrix(oracle_lib):
+    """Summing the fine steps into their level node equals sweeping the
+    coarse matrix C^T P~ C with its diagonal dropped (gamma = 0)."""
+    g = gen.rgg(600, 0.08, seed=8)
+    sim = oracle_lib.similarity(g, 2)
+    h = oracle_lib.hierarchy(g, seed=2, rho=0.8, min_nodes=10, max_levels=3)
+    assert h.levels >= 2
+    l = h.levels - 1
+    cm = h.cmaps[l]
+    nl = h.sizes[l]
+    rng = np.random.default_rng(0)
+    y = rng.uniform(-1, 1, size=(nl, 2))
+    b = 2
+    y_sync = y.copy()
+    oracle_lib.iter_sync(sim, y_sync, cm, M=5, b=b, gamma=0.0, eta=1.0, clip=math.inf)
+    Pm = sp.csr_matrix((sim.P, sim.col, sim.row_ptr), shape=(g.n, g.n))
+    Cm = sp.csr_matrix((np.ones(g.n), (np.arange(g.n), cm)), shape=(g.n, nl))
+    Pc = (Cm.T @ Pm @ Cm).toarray()
+    np.fill_diagonal(Pc, 0.0)
+    D = y[:, None, :] - y[None, :, :]
+    d2 = (D ** 2).sum(-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        coef = np.where(d2 > 0, -2 * b * d2 ** (b - 1) / (1 + d2 ** b), 0.0)
+    Gc = (Pc[:, :, None] * coef[:, :, None] * D).sum(axis=1)
+    assert np.allclose(y_sync, y + Gc, rtol=1e-10, atol=1e-12)
+
+
+def test_sequential_first_node_equals_sync(oracle_lib):
+    g, sim, y = _setup(oracle_lib, n=40, p=0.1, sub=8)
+    a, b = y.copy(), y.copy()
+    oracle_lib.iter_sync(sim, a, None, 5, 2, 0.1, 0.5, 4.0, 0, 3)
+    oracle_lib.iter_sync(sim, b, None, 5, 2, 0.1, 0.5, 4.0, 0, 3, seq=True)
+    first = int(np.nonzero(np.diff(sim.row_ptr))[0][0])
+    assert np.array_equal(a[first], b[first])
+    assert not np.allclose(a, b)
+
+
+def test_isolated_nodes_do_not_move(oracle_lib):
+    g = gen.canonical_csr(30, np.arange(0, 20), np.arange(1, 21))
+    y = oracle_lib.layout(g, k=2, M=5, b=2, T=20, min_nodes=5, seed=0)
+    h = oracle_lib.hierarchy(g, 0, 0.8, 5, 64)
+    y0 = oracle_lib.init(h.sizes[-1], 0, h.levels - 1)[h.cmaps[-1]]
+    assert np.array_equal(y[21:], y0[21:])
+    assert not np.allclose(y[:21], y0[:21])
+
+
+def test_grid17_quality_band(oracle_lib):
+    """Loose band only: the paper reports NP about .85 for DRGraph on the
+    17x17 lattice (Table 5); a single-level k=3, b=3 run lands there."""
+    from oracle import evaluate
+    g = gen.grid(17, 17)
+    y = oracle_lib.layout(g, k=3, M=5, b=3, gamma=0.1, T=400, eta0=1.0, clip=4.0,
+                          min_nodes=1000, seed=0)
+    assert evaluate.neighbourhood_preservation(g, y) > 0.8
