@@ -349,14 +349,28 @@ void drgo_step_direction(int32_t n0, const int64_t* prp, const int32_t* pcol, co
     }
 }
 
-/* Gradient sharing across levels (Sec. 3.2.3): the step of fine node i is
- * forwarded to the level node it was assigned to; forwarded steps add. */
+/* Anchor weight of every level node: w_a = sum_{cmap[i]=a} qt_i, the expected
+ * number of times per iteration that one of its members is selected as the
+ * node whose gradient is computed (qt_i = N_a * sum_j NS_ij, Sec. 3.2.2). */
+static double* level_weights(int32_t n0, const double* qt, const int32_t* cmap, int32_t nl) {
+    double* w = (double*)calloc((size_t)(nl > 0 ? nl : 1), sizeof(double));
+    for (int32_t i = 0; i < n0; ++i) w[cmap ? cmap[i] : i] += qt[i];
+    return w;
+}
+
+/* Synchronous (Jacobi) iteration.  In the paper's SGD (Sec. 3.2.2) a node is
+ * selected about qt_i times per iteration and each selection applies its own
+ * step; with gradient sharing (Sec. 3.2.3) the steps of all fine members are
+ * applied to their level node.  Applied together from one snapshot, those
+ * steps are replaced by one step along their average:
+ *   y_a += eta * (sum_{cmap[i]=a} g_i) / (sum_{cmap[i]=a} qt_i). */
 void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                     const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
                     int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
                     uint64_t it) {
     double* g = (double*)malloc(sizeof(double) * 2 * (size_t)(n0 > 0 ? n0 : 1));
     double* G = (double*)calloc(2 * (size_t)(nl > 0 ? nl : 1), sizeof(double));
+    double* w = level_weights(n0, qt, cmap, nl);
     drgo_step_direction(n0, prp, pcol, P, qt, C, cmap, y, M, b, gamma, clip, seed, it, g);
     for (int32_t i = 0; i < n0; ++i) {
         int32_t a = cmap ? cmap[i] : i;
@@ -364,18 +378,23 @@ void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const d
         G[2 * a + 1] += g[2 * i + 1];
     }
     for (int32_t a = 0; a < nl; ++a) {
-        y[2 * a] += eta * G[2 * a];
-        y[2 * a + 1] += eta * G[2 * a + 1];
+        if (w[a] <= 0.0) continue;
+        y[2 * a] += eta * (G[2 * a] / w[a]);
+        y[2 * a + 1] += eta * (G[2 * a + 1] / w[a]);
     }
+    free(w);
     free(g);
     free(G);
 }
 
+/* Sequential (Gauss-Seidel) iteration in ascending fine-node order: the
+ * step of node i, computed from the current positions, is applied at once
+ * with the same weighting as the synchronous iteration. */
 void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                    const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
                    int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
                    uint64_t it) {
-    (void)nl;
+    double* w = level_weights(n0, qt, cmap, nl);
     for (int32_t i = 0; i < n0; ++i) {
         if (prp[i + 1] == prp[i]) continue;
         int32_t a = cmap ? cmap[i] : i;
@@ -401,9 +420,10 @@ void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const do
             rx += clipd(k * dx, clip);
             ry += clipd(k * dy, clip);
         }
-        y[2 * a] += eta * (ax + gamma * qt[i] * rx);
-        y[2 * a + 1] += eta * (ay + gamma * qt[i] * ry);
+        y[2 * a] += eta * ((ax + gamma * qt[i] * rx) / w[a]);
+        y[2 * a + 1] += eta * ((ay + gamma * qt[i] * ry) / w[a]);
     }
+    free(w);
 }
 
 /* ------------------------------------------------------------------------ */

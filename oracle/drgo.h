@@ -75,7 +75,8 @@ void drgo_step_direction(int32_t n0, const int64_t* prp, const int32_t* pcol, co
                          const double* qt, const uint64_t* C, const int32_t* cmap, const double* y,
                          int32_t M, int32_t b, double gamma, double clip, uint64_t seed,
                          uint64_t it, double* g);
-/* Synchronous (Jacobi) iteration: y[a] += eta * sum_{cmap[i]=a} g_i. */
+/* Synchronous (Jacobi) iteration:
+ * y[a] += eta * (sum_{cmap[i]=a} g_i) / (sum_{cmap[i]=a} qt_i). */
 void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                     const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
                     int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
