@@ -1,0 +1,202 @@
+"""Benchmark of the DRGraph layout hot path on one MI355X.
+
+One step = one complete layout of the workload through the C-ABI library,
+with the input graph already resident in device memory: k-hop sparse
+distance matrix and similarity, negative-sampling table, multilevel
+coarsening, random initial layout, every iteration of the schedule at every
+level, and the refinements between levels.
+
+Metric: pair-updates/s = (T iterations x pairs per iteration) / time to
+layout, pairs per iteration = nnz(P~) + M * N_a (every stored pair is swept
+once and every non-isolated node draws M negatives, at every level).
+
+Prints one JSON line.  Extra objects:
+  roofline     -- the iteration sweep kernel against the HBM peak, with the
+                  algorithmic bytes 16 nnz + 16 M N_a + 28 N per launch and the
+                  launch duration measured with HIP events on the library's
+                  stream over the timed region;
+  cpu_baseline -- the FP64 oracle, single-threaded, timed on a bounded sample
+                  of the same workload family.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # R-MAT power-law graph: 2^20 nodes, 16*2^20 generated edges, k=2, M=5,
+    # 500 iterations, multilevel until < 1000 nodes
+    "rmat20_k2": dict(graph="rmat20", k=2, M=5, b=1, T=500, min_nodes=1000, max_levels=64),
+    # the same family at the paper's own neighbourhood order
+    "rmat20_k1": dict(graph="rmat20", k=1, M=5, b=1, T=500, min_nodes=1000, max_levels=64),
+    # random geometric graph, 100k nodes, radius 0.006, 3 levels
+    "rgg100k_k3": dict(graph="rgg100k", k=3, M=10, b=2, T=500, min_nodes=1, max_levels=3),
+    # 32x32 grid, single level
+    "grid32_k3": dict(graph="grid32", k=3, M=5, b=3, T=300, min_nodes=1 << 30, max_levels=1),
+    # R-MAT 2^18, average degree 16, k=2
+    "rmat18_k2": dict(graph="rmat18", k=2, M=5, b=1, T=500, min_nodes=1000, max_levels=64),
+}
+
+
+def _kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("layout.hip", "drg_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2008_07799_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(workload: str, launches_bytes: float):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != _kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg: dict) -> dict:
+    """The oracle (FP64, one thread) on a bounded sample: an R-MAT of the same
+    generator at scale 14 (edge factor 16) with the workload's k, M and b;
+    similarity built once, then synchronous iterations at level 0 timed."""
+    from oracle import drgo
+    from paper_2008_07799_amd import gen
+
+    if cfg["graph"].startswith("rmat"):
+        g = gen.rmat(14, 16, seed=0)
+        sample = "R-MAT scale 14, edge factor 16"
+    elif cfg["graph"] == "rgg100k":
+        g = gen.rgg(20000, 0.0134, seed=0)
+        sample = "RGG 20k nodes"
+    else:
+        g = gen.grid(32, 32)
+        sample = "32x32 grid"
+    drgo.build()
+    t0 = time.perf_counter()
+    sim = drgo.similarity(g, cfg["k"])
+    t_sim = time.perf_counter() - t0
+    y = drgo.init(g.n, 0, 0)
+    pairs = sim.nnz + cfg["M"] * sim.n_active
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        drgo.iter_sync(sim, y, None, cfg["M"], cfg["b"], 0.1, 1.0, 4.0, 0, iters)
+        iters += 1
+        el = time.perf_counter() - t0
+        if el > 8.0 or iters >= 200:
+            break
+    rate = pairs * iters / el
+    return {"value": rate, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} (n={g.n}, nnz(P)={sim.nnz}), k={cfg['k']}, M={cfg['M']}, "
+                      f"b={cfg['b']}: {iters} synchronous iterations at level 0 in "
+                      f"{el:.2f} s after a {t_sim:.2f} s similarity build"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20_k2", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="sync", choices=["sync", "async"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    from paper_2008_07799_amd import gen
+
+    cfg = WORKLOADS[args.workload]
+    mode = d.DRG_MODE_SYNC if args.mode == "sync" else d.DRG_MODE_ASYNC
+    print(f"[bench] generating {cfg['graph']}", file=sys.stderr, flush=True)
+    g = gen.named(cfg["graph"], seed=0)
+    torch.cuda.set_device(0)
+    rp, col = d.to_device(g)
+    ctx = d.Context(0)
+    params = d.layout_params(k=cfg["k"], M=cfg["M"], b=cfg["b"], T=cfg["T"],
+                             min_nodes=cfg["min_nodes"], max_levels=cfg["max_levels"],
+                             seed=0, mode=mode)
+    y = torch.zeros((g.n, 2), dtype=torch.float32, device="cuda")
+
+    def step():
+        sim = d.drg_build_similarity(ctx, rp, col, cfg["k"])
+        hier = d.drg_coarsen(ctx, rp, col, seed=0, rho=0.8, min_nodes=cfg["min_nodes"],
+                             max_levels=cfg["max_levels"])
+        d.drg_layout_run(ctx, sim, hier, params, y)
+        info = (sim.nnz, sim.n_active, hier.sizes)
+        sim.close()
+        hier.close()
+        return info
+
+    for w in range(args.warmup):
+        print(f"[bench] warmup step {w}", file=sys.stderr, flush=True)
+        step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        print(f"[bench] timed step {s}", file=sys.stderr, flush=True)
+        nnz, n_active, sizes = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, sweep_ms = ctx.kernel_stats()
+    ctx.set_profiling(False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+
+    M, T, n = cfg["M"], cfg["T"], g.n
+    pairs = nnz + M * n_active
+    value = T * pairs / (ms_per_step / 1000.0)
+    avg_ms = sweep_ms / max(1, launches)
+    alg_bytes = 16.0 * nnz + 16.0 * M * n_active + 28.0 * n
+    achieved = alg_bytes / (avg_ms / 1000.0) / 1e9
+    rec = {
+        "metric": "pair-updates/s + time-to-layout, 1M-node R-MAT; batched/autograd vs plain",
+        "value": value,
+        "unit": "pair-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": cfg["graph"], "n": n,
+                   "undirected_edges": g.nnz // 2, "k": cfg["k"], "M": M, "b": cfg["b"],
+                   "T": T, "levels": sizes, "nnz_P": nnz, "n_active": n_active,
+                   "mode": args.mode, "time_to_layout_s": ms_per_step / 1000.0,
+                   "iteration_sweep_pair_updates_per_s": pairs / (avg_ms / 1000.0)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic(args.workload, alg_bytes),
+                     "kernel": "k_sweep", "launches": launches, "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

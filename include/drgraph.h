@@ -1,0 +1,211 @@
+/*
+ * drgraph.h -- C ABI of libdrgraph.so, the MI355X (gfx950) implementation of
+ * DRGraph's layout hot path (Zhu et al., "DRGraph: An Efficient Graph Layout
+ * Algorithm for Large-scale Graphs by Dimensionality Reduction").
+ *
+ * Problem (Sec. 3.1): an undirected, unweighted graph G = (V, E) is mapped to
+ * 2-D positions Y.  The library takes the graph as CSR in device memory and
+ * writes FP32 coordinates [n][2] into caller-owned device memory.
+ *
+ * General conventions
+ *   - Every pointer named *_dev is device memory on the context's device;
+ *     every pointer named *_host (or documented as host) is host memory.
+ *   - Inputs are borrowed for the duration of the call and never retained;
+ *     drg_sim and drg_hier copy what they need.  Opaque objects are owned by
+ *     the library and released by their *_destroy call (NULL-safe).
+ *   - Work is enqueued on the context's HIP stream and is asynchronous unless
+ *     a function says it synchronises.  drg_build_similarity and drg_coarsen
+ *     synchronise internally (they size allocations from device counts).
+ *   - Errors are status codes; no C++ exception crosses this boundary.  On
+ *     error the outputs are unspecified, owned state is unchanged and
+ *     drg_last_error() describes the failure (thread-local string, valid
+ *     until the next call on the same thread).
+ *   - Input CSR contract (Sec. 3.1, undirected unweighted): row_ptr int32
+ *     [n+1] with row_ptr[0] = 0, col int32 [row_ptr[n]]; symmetric, rows
+ *     sorted ascending, no self-loops, no duplicates.  DRG_VALIDATE checks
+ *     this on the device and returns DRG_E_GRAPH if it does not hold.
+ *   - Randomness is a Philox4x64-10 counter generator (Salmon et al., SC'11)
+ *     keyed by {seed, stream tag}; every random choice is a pure function of
+ *     (seed, tag, counter), so results do not depend on launch shapes.
+ */
+#ifndef DRGRAPH_H
+#define DRGRAPH_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+#pragma GCC visibility push(default)
+
+typedef int32_t drg_status;
+#define DRG_OK 0
+#define DRG_E_INVALID -1     /* bad argument (null pointer, out-of-range value) */
+#define DRG_E_GRAPH -2       /* input CSR breaks the contract (DRG_VALIDATE) */
+#define DRG_E_OOM -3         /* device allocation failed; partial allocations freed */
+#define DRG_E_DEVICE -4      /* a HIP runtime call failed */
+#define DRG_E_UNSUPPORTED -5 /* valid request outside the implemented range */
+
+#define DRG_VALIDATE 1u      /* flag: validate the input CSR on the device */
+
+#define DRG_MODE_SYNC 0      /* Jacobi: all steps from one snapshot, deterministic */
+#define DRG_MODE_ASYNC 1     /* Hogwild: steps applied in place while others read */
+
+typedef struct drg_ctx drg_ctx;
+typedef struct drg_sim drg_sim;
+typedef struct drg_hier drg_hier;
+
+/* Undirected graph in CSR form (device pointers, borrowed). */
+typedef struct {
+    int32_t n;
+    int32_t nnz;             /* = row_ptr[n] = 2|E| */
+    const int32_t* row_ptr;  /* device, [n+1] */
+    const int32_t* col;      /* device, [nnz] */
+} drg_csr;
+
+/* Parameters of one optimisation iteration (Sec. 3.2.2, Eq. gradient). */
+typedef struct {
+    int32_t M;               /* negative samples per node, >= 0 */
+    int32_t b;               /* proximity shape parameter, 1..3 (Sec. 4.2) */
+    float gamma;             /* weight of negative samples */
+    float eta;               /* step size of this iteration */
+    float clip;              /* per-pair, per-component force clip, > 0 */
+    int32_t level;           /* hierarchy level being laid out (0 = finest) */
+    int32_t mode;            /* DRG_MODE_SYNC or DRG_MODE_ASYNC */
+    int32_t _pad;
+    uint64_t seed;
+    uint64_t iter;           /* global iteration index; keys the negatives */
+} drg_step_params;
+
+/* Parameters of the whole multilevel layout (Sec. 3.2, Sec. 4 defaults). */
+typedef struct {
+    int32_t k;               /* order of the neighbourhoods NNG(v, k), 1..4 */
+    int32_t M;
+    int32_t b;
+    int32_t T;               /* total iterations, split over levels */
+    double sigma;            /* Gaussian width of the similarity */
+    float gamma;             /* weight of negatives on all but the coarsest level */
+    float gamma_coarsest;    /* on the coarsest level when there are >= 2 levels */
+    float eta0;              /* initial step size, decays linearly per level */
+    float clip;
+    double rho;              /* coarsening stops when |V^{l+1}| > rho |V^l| */
+    int32_t min_nodes;       /* do not coarsen a level with fewer active nodes */
+    int32_t max_levels;      /* at most this many levels (1 = single level) */
+    int32_t mode;            /* DRG_MODE_SYNC or DRG_MODE_ASYNC */
+    int32_t _pad;
+    uint64_t seed;
+} drg_layout_params;
+
+const char* drg_last_error(void);
+const char* drg_version(void);
+
+/* Fills *p with the paper's defaults: k=1, M=5, b=2, T=400, sigma=1,
+ * gamma=0.1, gamma_coarsest=0.01, eta0=1, clip=4, rho=0.8, min_nodes=1000,
+ * max_levels=64, sync mode, seed 0 (Sec. 4 "Parameters", Sec. 3.2.3). */
+drg_status drg_layout_params_default(drg_layout_params* p);
+
+/* Creates a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  The stream is borrowed and must outlive ctx. */
+drg_status drg_ctx_create(int32_t device, void* hip_stream, drg_ctx** out);
+void drg_ctx_destroy(drg_ctx* ctx);
+drg_status drg_ctx_synchronize(drg_ctx* ctx);
+/* Kernel timing: when on, the library brackets every launch of the layout
+ * iteration's sweep kernel with HIP events on the context's stream.
+ * drg_ctx_kernel_stats synchronises and returns the launch count and the
+ * summed duration in milliseconds since the last reset. */
+drg_status drg_ctx_set_profiling(drg_ctx* ctx, int32_t on);
+drg_status drg_ctx_kernel_stats(drg_ctx* ctx, int64_t* launches, double* total_ms);
+
+/* Sparse distance matrix and node similarity (Sec. 3.2.1, Eq. NS):
+ * for every node i the set NNG(i, k) = {j != i : SPD(i, j) <= k} with hop
+ * d_ij = SPD(i, j), by bounded breadth-first search; then
+ *   e_d = exp(-d^2 / (2 sigma^2)),  Z_i = sum_{j in NNG(i,k)} e_{d_ij},
+ *   P~_ij = e_{d_ij} (1/Z_i + 1/Z_j) / 2   (= N_a * NS_ij, symmetric),
+ *   qt_i  = sum_j P~_ij                     (node weight, Sec. 3.2.2),
+ * plus the integer table used to draw negatives with probability
+ * proportional to the node weight.  k in 1..4, n < 2^30.
+ * Synchronises.  The result lives in device memory owned by *out. */
+drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, double sigma,
+                                uint32_t flags, drg_sim** out);
+/* Host-side sizes (no synchronisation needed). */
+drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_active,
+                        int32_t* k);
+/* Copies the similarity to host arrays (each nullable; synchronises):
+ * row_ptr[n+1], col[nnz], hop[nnz] (1..k), P[nnz] (FP64 P~_ij), qt[n] (FP64),
+ * W[n] (uint64 sampling weights), e[k] (FP64), invZ[n] (FP64). */
+drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop,
+                          double* P, double* qt, uint64_t* W, double* e, double* invZ);
+void drg_sim_destroy(drg_sim* s);
+
+/* Multilevel coarsening (Sec. 3.2.3, Fig. 3): repeatedly groups a randomly
+ * chosen node with its unassigned first-order neighbours into one coarse node
+ * until every node is assigned; edges inside a group disappear.  Levels are
+ * added while the level has at least min_nodes non-isolated nodes and fewer
+ * than max_levels levels exist; a new level with more than rho times the
+ * non-isolated nodes of its parent is discarded and coarsening stops.
+ * Random choices come from `seed`.  Synchronises. */
+drg_status drg_coarsen(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho,
+                       int32_t min_nodes, int32_t max_levels, drg_hier** out);
+/* levels (>= 1) and, if sizes_host is non-null, sizes_host[levels] node counts. */
+drg_status drg_hier_info(const drg_hier* h, int32_t* levels, int32_t* sizes_host);
+/* For level >= 1 (host arrays, each nullable; synchronises):
+ * map[n_{level-1}]: node of level-1 -> node of level; cmap[n_0]: finest node
+ * -> node of level; coarse_rp[n_level+1] and coarse_col[nnz_level]: the
+ * contracted graph G^level.  coarse_nnz (nullable) receives nnz_level. */
+drg_status drg_hier_export(const drg_hier* h, int32_t level, int32_t* map, int32_t* cmap,
+                           int32_t* coarse_rp, int32_t* coarse_col, int64_t* coarse_nnz);
+void drg_hier_destroy(drg_hier* h);
+
+/* Random layout of a level (Sec. 3.2.3): y[v] = (2u-1, 2u-1) with 24-bit
+ * uniform fractions u from Philox(seed, node v, level).  y_dev: [n][2]. */
+drg_status drg_init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y_dev);
+/* Refinement (Sec. 3.2.3): y_finer[u] = y_level[map_level(u)] for every node u
+ * of level-1.  level >= 1. */
+drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* y_level_dev,
+                       float* y_finer_dev);
+
+/* One optimisation iteration at level p->level (Sec. 3.2.2 with the
+ * gradient sharing of Sec. 3.2.3).  For every non-isolated finest node i,
+ * with a = c(i) its node on the level:
+ *   g_i = sum_j P~_ij clip(A(y_a - y_c(j))) + gamma qt_i sum_{m<M} clip(R(y_a - y_c(v_im)))
+ *   A(D) = -2b |D|^{2b-2} D / (1 + |D|^{2b}),  R(D) = 2b D / (|D|^2 (1 + |D|^{2b}))
+ * (the attractive and repulsive forces of Eq. gradient) with v_im the
+ * negatives drawn by node weight from (seed, iter, i, m); clip is per pair and
+ * per component; a pair at distance 0 contributes nothing.  Node i is selected
+ * about qt_i times per iteration by the paper's SGD, so a level node moves by
+ * the average of its members' selections:
+ *   sync : y_a += eta * (sum_{c(i)=a} g_i) / (sum_{c(i)=a} qt_i), all g_i from
+ *          one snapshot (deterministic, bit-for-bit repeatable);
+ *   async: eta * g_i / (sum_{c(j)=c(i)} qt_j) is added to y_c(i) as soon as g_i
+ *          is computed, while other nodes read y (Hogwild-style).
+ * h may be NULL for level 0.  y_level_dev: [n_level][2], in/out. */
+drg_status drg_layout_step(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                           const drg_step_params* p, float* y_level_dev);
+
+/* FP64 instances of drg_init_layout, drg_prolong and drg_layout_step (sync
+ * mode only; async returns DRG_E_UNSUPPORTED): the same kernels and the same
+ * order of operations with double coordinates, for trajectory checks against
+ * an FP64 reference. */
+drg_status drg_init_layout_f64(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level,
+                               double* y_dev);
+drg_status drg_prolong_f64(drg_ctx* ctx, const drg_hier* h, int32_t level,
+                           const double* y_level_dev, double* y_finer_dev);
+drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                               const drg_step_params* p, double* y_level_dev);
+
+/* The whole schedule on a built similarity and hierarchy: random layout of the
+ * coarsest level, T iterations split evenly over levels (the finest takes the
+ * remainder) with eta_t = eta0 (1 - t/T_l) restarting per level and
+ * gamma_coarsest on the coarsest level, refinement between levels.
+ * Negatives use the global iteration index.  y_out_dev: [n][2]. */
+drg_status drg_layout_run(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                          const drg_layout_params* p, float* y_out_dev);
+
+/* End to end: drg_build_similarity + drg_coarsen + drg_layout_run. */
+drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p,
+                      float* y_out_dev);
+
+#pragma GCC visibility pop
+#ifdef __cplusplus
+}
+#endif
+#endif

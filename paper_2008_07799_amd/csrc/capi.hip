@@ -1,0 +1,358 @@
+// capi.hip -- the extern "C" boundary of libdrgraph.  Every entry point
+// catches library errors and returns a status code; see include/drgraph.h.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "drg_internal.hpp"
+
+namespace drg {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace drg
+
+using drg::Error;
+
+template <typename F>
+static drg_status guarded(F&& f) {
+    try {
+        drg::g_last_error.clear();
+        f();
+        return DRG_OK;
+    } catch (const Error& e) {
+        drg::set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        drg::set_error("host allocation failed");
+        return DRG_E_OOM;
+    } catch (const std::exception& e) {
+        drg::set_error(e.what());
+        return DRG_E_DEVICE;
+    } catch (...) {
+        drg::set_error("unknown error");
+        return DRG_E_DEVICE;
+    }
+}
+
+static void use_device(int dev) { DRG_HIP(hipSetDevice(dev)); }
+
+static void need(const void* p, const char* what) {
+    if (!p) throw Error(DRG_E_INVALID, std::string(what) + " is NULL");
+}
+
+extern "C" {
+
+const char* drg_last_error(void) { return drg::g_last_error.c_str(); }
+
+const char* drg_version(void) { return "drgraph-mi355x 0.1 (gfx950)"; }
+
+drg_status drg_layout_params_default(drg_layout_params* p) {
+    return guarded([&] {
+        need(p, "params");
+        std::memset(p, 0, sizeof(*p));
+        p->k = 1;
+        p->M = 5;
+        p->b = 2;
+        p->T = 400;
+        p->sigma = 1.0;
+        p->gamma = 0.1f;
+        p->gamma_coarsest = 0.01f;
+        p->eta0 = 1.0f;
+        p->clip = 4.0f;
+        p->rho = 0.8;
+        p->min_nodes = 1000;
+        p->max_levels = 64;
+        p->mode = DRG_MODE_SYNC;
+        p->seed = 0;
+    });
+}
+
+drg_status drg_ctx_create(int32_t device, void* hip_stream, drg_ctx** out) {
+    return guarded([&] {
+        need(out, "out");
+        *out = nullptr;
+        int count = 0;
+        DRG_HIP(hipGetDeviceCount(&count));
+        if (device < 0 || device >= count) throw Error(DRG_E_INVALID, "no such device");
+        use_device(device);
+        auto c = std::make_unique<drg_ctx>();
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        DRG_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+        int lds = 0, lds_optin = 0;
+        DRG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+        if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, device) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            lds_optin = 0;
+        }
+        c->max_lds = std::max(lds, lds_optin);
+        *out = c.release();
+    });
+}
+
+void drg_ctx_destroy(drg_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& e : ctx->events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    delete ctx;
+}
+
+drg_status drg_ctx_synchronize(drg_ctx* ctx) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        DRG_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+drg_status drg_ctx_set_profiling(drg_ctx* ctx, int32_t on) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        ctx->profiling = on != 0;
+        for (auto& e : ctx->events) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ctx->events.clear();
+        ctx->launches = 0;
+        ctx->total_ms = 0.0;
+    });
+}
+
+drg_status drg_ctx_kernel_stats(drg_ctx* ctx, int64_t* launches, double* total_ms) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        DRG_HIP(hipStreamSynchronize(ctx->stream));
+        for (auto& e : ctx->events) {
+            float ms = 0.0f;
+            DRG_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+            ctx->total_ms += ms;
+            ctx->launches += 1;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ctx->events.clear();
+        if (launches) *launches = ctx->launches;
+        if (total_ms) *total_ms = ctx->total_ms;
+    });
+}
+
+drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, double sigma,
+                                uint32_t flags, drg_sim** out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(out, "out");
+        *out = nullptr;
+        use_device(ctx->device);
+        *out = drg::build_similarity(ctx, g, k, sigma, flags);
+    });
+}
+
+drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_active,
+                        int32_t* k) {
+    return guarded([&] {
+        need(s, "sim");
+        if (n) *n = s->n;
+        if (nnz) *nnz = s->nnz;
+        if (n_active) *n_active = s->n_active;
+        if (k) *k = s->k;
+    });
+}
+
+drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop,
+                          double* P, double* qt, uint64_t* W, double* e, double* invZ) {
+    return guarded([&] {
+        need(s, "sim");
+        drg::sim_export(s, row_ptr, col, hop, P, qt, W, e, invZ);
+    });
+}
+
+void drg_sim_destroy(drg_sim* s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
+    delete s;
+}
+
+drg_status drg_coarsen(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho,
+                       int32_t min_nodes, int32_t max_levels, drg_hier** out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(out, "out");
+        *out = nullptr;
+        use_device(ctx->device);
+        *out = drg::build_hierarchy(ctx, g, seed, rho, min_nodes, max_levels);
+    });
+}
+
+drg_status drg_hier_info(const drg_hier* h, int32_t* levels, int32_t* sizes_host) {
+    return guarded([&] {
+        need(h, "hier");
+        if (levels) *levels = (int32_t)h->lv.size();
+        if (sizes_host)
+            for (size_t l = 0; l < h->lv.size(); ++l) sizes_host[l] = h->lv[l].n;
+    });
+}
+
+drg_status drg_hier_export(const drg_hier* h, int32_t level, int32_t* map, int32_t* cmap,
+                           int32_t* coarse_rp, int32_t* coarse_col, int64_t* coarse_nnz) {
+    return guarded([&] {
+        need(h, "hier");
+        if (level < 1 || level >= (int32_t)h->lv.size())
+            throw Error(DRG_E_INVALID, "level out of range");
+        use_device(h->device);
+        DRG_HIP(hipDeviceSynchronize());
+        const drg_level& L = h->lv[level];
+        const int32_t nf = h->lv[level - 1].n;
+        if (map) DRG_HIP(hipMemcpy(map, L.map.get(), sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
+        if (cmap)
+            DRG_HIP(hipMemcpy(cmap, L.cmap.get(), sizeof(int32_t) * h->n0, hipMemcpyDeviceToHost));
+        if (coarse_rp)
+            DRG_HIP(hipMemcpy(coarse_rp, L.rp.get(), sizeof(int32_t) * (L.n + 1),
+                              hipMemcpyDeviceToHost));
+        if (coarse_col && L.nnz > 0)
+            DRG_HIP(hipMemcpy(coarse_col, L.col.get(), sizeof(int32_t) * L.nnz,
+                              hipMemcpyDeviceToHost));
+        if (coarse_nnz) *coarse_nnz = L.nnz;
+    });
+}
+
+void drg_hier_destroy(drg_hier* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+drg_status drg_init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::init_layout(ctx, n, seed, level, y_dev);
+    });
+}
+
+drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* y_level_dev,
+                       float* y_finer_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::prolong(ctx, h, level, y_level_dev, y_finer_dev);
+    });
+}
+
+drg_status drg_layout_step(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                           const drg_step_params* p, float* y_level_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::layout_step(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+    });
+}
+
+drg_status drg_init_layout_f64(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level,
+                               double* y_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::init_layout_t<double>(ctx, n, seed, level, y_dev);
+    });
+}
+
+drg_status drg_prolong_f64(drg_ctx* ctx, const drg_hier* h, int32_t level,
+                           const double* y_level_dev, double* y_finer_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::prolong_t<double>(ctx, h, level, y_level_dev, y_finer_dev);
+    });
+}
+
+drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                               const drg_step_params* p, double* y_level_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::layout_step_t<double>(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+    });
+}
+
+static void check_layout_params(const drg_layout_params* p) {
+    need(p, "params");
+    if (p->T < 0) throw Error(DRG_E_INVALID, "T must be >= 0");
+    if (p->M < 0 || p->b < 1 || p->b > 3) throw Error(DRG_E_INVALID, "M >= 0, b in 1..3");
+    if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "clip must be > 0");
+    if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
+        throw Error(DRG_E_INVALID, "unknown mode");
+}
+
+static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_layout_params* p,
+                         float* y_out) {
+    check_layout_params(p);
+    need(s, "sim");
+    need(h, "hier");
+    need(y_out, "y_out");
+    if (h->n0 != s->n) throw Error(DRG_E_INVALID, "hierarchy is of another graph");
+    const int32_t Lc = (int32_t)h->lv.size();
+    // level buffers: the finest level is y_out, coarser ones are scratch
+    std::vector<drg::DevBuf<float2>> ybuf(Lc);
+    auto ylev = [&](int32_t l) -> float* {
+        return l == 0 ? y_out : reinterpret_cast<float*>(ybuf[l].get());
+    };
+    for (int32_t l = 1; l < Lc; ++l) ybuf[l].alloc(h->lv[l].n);
+    drg::init_layout(ctx, h->lv[Lc - 1].n, p->seed, Lc - 1, ylev(Lc - 1));
+    const int32_t base = p->T / Lc;
+    uint64_t git = 0;
+    for (int32_t l = Lc - 1; l >= 0; --l) {
+        const int32_t Tl = base + (l == 0 ? p->T - base * Lc : 0);
+        const float gam = (l == Lc - 1 && Lc > 1) ? p->gamma_coarsest : p->gamma;
+        drg_step_params sp{};
+        sp.M = p->M;
+        sp.b = p->b;
+        sp.gamma = gam;
+        sp.clip = p->clip;
+        sp.level = l;
+        sp.mode = p->mode;
+        sp.seed = p->seed;
+        for (int32_t t = 0; t < Tl; ++t) {
+            sp.eta = (float)((double)p->eta0 * (1.0 - (double)t / (double)Tl));
+            sp.iter = git++;
+            drg::layout_step(ctx, s, h, &sp, ylev(l));
+        }
+        if (l > 0) drg::prolong(ctx, h, l, ylev(l), ylev(l - 1));
+    }
+    DRG_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+drg_status drg_layout_run(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                          const drg_layout_params* p, float* y_out_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        run_schedule(ctx, const_cast<drg_sim*>(s), h, p, y_out_dev);
+    });
+}
+
+drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p,
+                      float* y_out_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(g, "graph");
+        check_layout_params(p);
+        use_device(ctx->device);
+        std::unique_ptr<drg_sim, void (*)(drg_sim*)> s(
+            drg::build_similarity(ctx, g, p->k, p->sigma, 0), drg_sim_destroy);
+        std::unique_ptr<drg_hier, void (*)(drg_hier*)> h(
+            drg::build_hierarchy(ctx, g, p->seed, p->rho, p->min_nodes, p->max_levels),
+            drg_hier_destroy);
+        run_schedule(ctx, s.get(), h.get(), p, y_out_dev);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// drg_internal.hpp -- library-private state behind the opaque C handles.
+#pragma once
+#include <vector>
+
+#include "../../include/drgraph.h"
+#include "drg_common.hpp"
+#include "drg_prims.hpp"
+
+struct drg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+    int max_lds = 0;   // bytes of LDS one workgroup may use
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+// Sparse similarity P~ over the finest graph plus the sampling table.
+struct drg_sim {
+    int device = 0;
+    int32_t n = 0, k = 0, n_active = 0;
+    int64_t nnz = 0;
+    double sigma = 1.0;
+    double e[4] = {0, 0, 0, 0};
+    drg::DevBuf<int64_t> row_ptr;    // [n+1]
+    drg::DevBuf<uint32_t> colhop;    // [nnz] col | (hop-1) << 30, ascending col per row
+    drg::DevBuf<double> invZ;        // [n]
+    drg::DevBuf<double> qt;          // [n]
+    drg::DevBuf<uint64_t> W;         // [n]
+    drg::DevBuf<uint64_t> C;         // [n+1]
+    drg::DevBuf<int32_t> guide;      // [2^gbits + 1]
+    int gbits = 1;
+    uint64_t S = 0;                  // = C[n]
+    drg::DevBuf<float> invZf;        // [n]
+    drg::DevBuf<float> qtf;          // [n]
+    // per-iteration workspace of the layout step
+    drg::DevBuf<float4> rec;         // [n] staged (y_c(j), invZ_j)
+    drg::DevBuf<float2> g;           // [n] one-sided steps
+    drg::DevBuf<float> wlev;         // [n] anchor weights of level nodes (async)
+    drg::DevBuf<double4> rec64;      // FP64 instance workspace (allocated on use)
+    drg::DevBuf<double2> g64;
+};
+
+struct drg_level {
+    int32_t n = 0, n_active = 0;
+    int64_t nnz = 0;
+    drg::DevBuf<int32_t> rp, col;    // contracted graph G^l (level >= 1)
+    drg::DevBuf<int32_t> map;        // [n_{l-1}] parent node -> node of this level
+    drg::DevBuf<int32_t> cmap;       // [n_0] finest node -> node of this level
+    drg::DevBuf<int32_t> perm;       // [n_0] finest nodes grouped by cmap, ascending within
+    drg::DevBuf<int32_t> seg;        // [n+1] group offsets into perm
+};
+
+struct drg_hier {
+    int device = 0;
+    int32_t n0 = 0;
+    std::vector<drg_level> lv;       // lv[0] describes G^0 (sizes only)
+};
+
+namespace drg {
+void set_error(const std::string& msg);
+
+// similarity.hip
+drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags);
+void validate_csr(drg_ctx* ctx, const drg_csr* g);
+void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,
+                double* qt, uint64_t* W, double* e, double* invZ);
+// coarsen.hip
+drg_hier* build_hierarchy(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho,
+                          int min_nodes, int max_levels);
+// layout.hip
+void init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y);
+void prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* yl, float* yf);
+void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p,
+                 float* y);
+template <typename T>
+void init_layout_t(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, T* y);
+template <typename T>
+void prolong_t(drg_ctx* ctx, const drg_hier* h, int32_t level, const T* yl, T* yf);
+template <typename T>
+void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y);
+}  // namespace drg

@@ -1,0 +1,63 @@
+// drg_prims.hpp -- device-wide building blocks used by the build stages.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace drg {
+
+// RAII device buffer (hipMalloc / hipFree).
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    int64_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(int64_t count) { alloc(count); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            reset();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void alloc(int64_t count);
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T* get() const { return p; }
+};
+
+void* dev_alloc_bytes(int64_t bytes);
+
+template <typename T>
+void DevBuf<T>::alloc(int64_t count) {
+    reset();
+    p = static_cast<T*>(dev_alloc_bytes((count > 0 ? count : 1) * (int64_t)sizeof(T)));
+    n = count;
+}
+
+// out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.  out may
+// alias in only if it is a distinct buffer of n+1 elements (not in place).
+template <typename T>
+void exclusive_scan(const T* in, T* out, int64_t n, hipStream_t s);
+
+// Stable sort of (key, value) pairs by the low key_bits bits of the key.
+void radix_sort_pairs(uint32_t* keys, int32_t* vals, int64_t n, int key_bits, hipStream_t s);
+
+// Number of i in [0, n) with rp[i+1] > rp[i].
+template <typename T>
+int64_t count_nonempty_rows(const T* rp, int64_t n, hipStream_t s);
+
+}  // namespace drg

@@ -1,0 +1,498 @@
+// layout.hip -- one optimisation iteration of the layout (Sec. 3.2.2,
+// Eq. gradient) with the gradient sharing across levels (Sec. 3.2.3), the
+// random initial layout and the refinement step.
+//
+// Sync iteration at level l, three launches on one stream:
+//   stage : rec[j] = (y_l[c_l(j)], 1/Z_j) for every finest node j, so the
+//           sweep gathers one record per neighbour at every level;
+//   sweep : for every non-isolated finest node i, G lanes walk row i of P~
+//           (coalesced 4-byte entries, gathered records), then draw M
+//           negatives from (seed, iter, i, m) and gather theirs; the lane
+//           partials are reduced in a fixed order into g_i;
+//   apply : y_l[a] += eta * (sum g_i) / (sum qt_i) over the members i of a,
+//           in ascending id (no atomics: the iteration is bit-for-bit
+//           repeatable).  Node i is chosen about qt_i times per iteration by
+//           the paper's SGD; applied at once from one snapshot, those steps
+//           become one step along their average.
+// Async iteration: one launch; each g_i is computed from the live y and
+// eta g_i / w_{c(i)} is added to y_l[c_l(i)] at once (Hogwild-style).
+//
+// Every kernel is templated on the coordinate type: float is the product
+// path; the double instance runs the same arithmetic for trajectory checks.
+#include "drg_internal.hpp"
+
+namespace drg {
+
+template <typename T>
+struct VT;
+template <>
+struct VT<float> {
+    using v2 = float2;
+    using v4 = float4;
+};
+template <>
+struct VT<double> {
+    using v2 = double2;
+    using v4 = double4;
+};
+
+template <typename T>
+__device__ __forceinline__ typename VT<T>::v2 mk2(T a, T b) {
+    typename VT<T>::v2 r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ typename VT<T>::v4 mk4(T a, T b, T c, T d) {
+    typename VT<T>::v4 r;
+    r.x = a;
+    r.y = b;
+    r.z = c;
+    r.w = d;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T clampT(T v, T c) {
+    return v > c ? c : (v < -c ? -c : v);
+}
+
+template <int B, typename T>
+__device__ __forceinline__ T powT(T x) {
+    if constexpr (B == 0) return T(1);
+    else if constexpr (B == 1) return x;
+    else if constexpr (B == 2) return x * x;
+    else return x * x * x;
+}
+
+// attraction coefficient -2b d^{2b-2}/(1+d^{2b}); repulsion 2b/(d^2 (1+d^{2b}))
+template <int B, typename T>
+__device__ __forceinline__ T attract_coef(T d2) {
+    return T(-2 * B) * powT<B - 1>(d2) / (T(1) + powT<B>(d2));
+}
+template <int B, typename T>
+__device__ __forceinline__ T repel_coef(T d2) {
+    return T(2 * B) / (d2 * (T(1) + powT<B>(d2)));
+}
+
+template <typename T>
+__global__ void k_init(int32_t n, uint64_t seed, int32_t level, typename VT<T>::v2* __restrict__ y) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const U64x4 r =
+        philox4x64((uint64_t)(uint32_t)v, (uint64_t)(uint32_t)level, 0, 0, seed, TAG_INIT);
+    const T ux = (T)(uint32_t)(r.w[0] >> 40) * (T(1) / T(16777216));
+    const T uy = (T)(uint32_t)(r.w[1] >> 40) * (T(1) / T(16777216));
+    y[v] = mk2<T>(T(2) * ux - T(1), T(2) * uy - T(1));
+}
+
+template <typename T>
+__global__ void k_prolong(int32_t n, const int32_t* __restrict__ map,
+                          const typename VT<T>::v2* __restrict__ yl,
+                          typename VT<T>::v2* __restrict__ yf) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) yf[u] = yl[map[u]];
+}
+
+template <typename T>
+__global__ void k_stage(int32_t n0, const int32_t* __restrict__ cmap,
+                        const typename VT<T>::v2* __restrict__ y, const T* __restrict__ invZ,
+                        typename VT<T>::v4* __restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n0) return;
+    const typename VT<T>::v2 p = y[cmap ? cmap[j] : (int32_t)j];
+    rec[j] = mk4<T>(p.x, p.y, invZ[j], T(0));
+}
+
+template <typename T>
+struct SweepArgs {
+    using v2 = typename VT<T>::v2;
+    using v4 = typename VT<T>::v4;
+    int32_t n0;
+    int32_t M;
+    const int64_t* prp;
+    const uint32_t* colhop;
+    const T* qt;
+    const v4* rec;
+    v2* g;
+    const uint64_t* C;
+    const int32_t* guide;
+    int32_t gbits;
+    uint64_t S;
+    T eh0, eh1, eh2, eh3;  // e_d / 2
+    T gamma, clip;
+    uint64_t seed, iter;
+    // async only
+    v2* y;
+    const int32_t* cmap;
+    const T* invZ;
+    const T* w;            // anchor weight of each level node
+    T eta;
+};
+
+template <typename T>
+__device__ __forceinline__ T half_e(const SweepArgs<T>& a, uint32_t h) {
+    return h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
+}
+
+template <typename T, int B, int G>
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t i = grp; i < a.n0; i += ngrp) {
+        const int64_t rs = a.prp[i], re = a.prp[i + 1];
+        T gx = T(0), gy = T(0);
+        if (rs < re) {
+            const typename VT<T>::v4 ri = a.rec[i];
+            T ax = T(0), ay = T(0);
+            for (int64_t x = rs + lane; x < re; x += G) {
+                const uint32_t e = a.colhop[x];
+                const typename VT<T>::v4 rj = a.rec[e & COL_MASK];
+                const T dx = ri.x - rj.x, dy = ri.y - rj.y;
+                const T d2 = dx * dx + dy * dy;
+                if (d2 > T(0)) {
+                    const T k = attract_coef<B>(d2);
+                    const T w = half_e(a, e >> 30) * (ri.z + rj.z);
+                    ax += w * clampT(k * dx, a.clip);
+                    ay += w * clampT(k * dy, a.clip);
+                }
+            }
+            T rx = T(0), ry = T(0);
+            for (int m = lane; m < a.M; m += G) {
+                const uint64_t w = neg_word(a.seed, a.iter, (int32_t)i, m);
+                const int32_t v = draw_node(w, a.C, a.guide, a.gbits, a.S);
+                const typename VT<T>::v4 rv = a.rec[v];
+                const T dx = ri.x - rv.x, dy = ri.y - rv.y;
+                const T d2 = dx * dx + dy * dy;
+                if (d2 > T(0)) {
+                    const T k = repel_coef<B>(d2);
+                    rx += clampT(k * dx, a.clip);
+                    ry += clampT(k * dy, a.clip);
+                }
+            }
+            ax = group_sum<G>(ax);
+            ay = group_sum<G>(ay);
+            rx = group_sum<G>(rx);
+            ry = group_sum<G>(ry);
+            const T gq = a.gamma * a.qt[i];
+            gx = ax + gq * rx;
+            gy = ay + gq * ry;
+        }
+        if (lane == 0) a.g[i] = mk2<T>(gx, gy);
+    }
+}
+
+template <typename T>
+__global__ void k_apply0(int32_t n, const typename VT<T>::v2* __restrict__ g,
+                         const T* __restrict__ qt, typename VT<T>::v2* __restrict__ y, T eta) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T w = qt[i];
+    if (!(w > T(0))) return;
+    const typename VT<T>::v2 s = g[i];
+    typename VT<T>::v2 p = y[i];
+    p.x += eta * (s.x / w);
+    p.y += eta * (s.y / w);
+    y[i] = p;
+}
+
+// G lanes per level node: strided partial sums over its members (ascending
+// id within each lane), then a fixed-order reduction.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_apply_level(int32_t nl, const int32_t* __restrict__ seg,
+                                                     const int32_t* __restrict__ perm,
+                                                     const typename VT<T>::v2* __restrict__ g,
+                                                     const T* __restrict__ qt,
+                                                     typename VT<T>::v2* __restrict__ y, T eta) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t a = grp; a < nl; a += ngrp) {
+        T sx = T(0), sy = T(0), sw = T(0);
+        for (int32_t x = seg[a] + lane; x < seg[a + 1]; x += G) {
+            const int32_t i = perm[x];
+            const typename VT<T>::v2 s = g[i];
+            sx += s.x;
+            sy += s.y;
+            sw += qt[i];
+        }
+        sx = group_sum<G>(sx);
+        sy = group_sum<G>(sy);
+        sw = group_sum<G>(sw);
+        if (lane == 0 && sw > T(0)) {
+            typename VT<T>::v2 p = y[a];
+            p.x += eta * (sx / sw);
+            p.y += eta * (sy / sw);
+            y[a] = p;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_level_weights(int32_t nl, const int32_t* __restrict__ seg,
+                                const int32_t* __restrict__ perm, const T* __restrict__ qt,
+                                T* __restrict__ w) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nl) return;
+    T s = T(0);
+    for (int32_t x = seg[a]; x < seg[a + 1]; ++x) s += qt[perm[x]];
+    w[a] = s;
+}
+
+// Hogwild: reads the live coordinates, adds eta g_i / w_{c(i)} to y[c(i)] at once.
+template <int B, int G>
+__global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    volatile float* yv = reinterpret_cast<volatile float*>(a.y);
+    for (int64_t i = grp; i < a.n0; i += ngrp) {
+        const int64_t rs = a.prp[i], re = a.prp[i + 1];
+        if (rs >= re) continue;
+        const int32_t ci = a.cmap ? a.cmap[i] : (int32_t)i;
+        const float yix = yv[2 * ci], yiy = yv[2 * ci + 1];
+        const float zi = a.invZ[i];
+        float ax = 0.0f, ay = 0.0f;
+        for (int64_t x = rs + lane; x < re; x += G) {
+            const uint32_t e = a.colhop[x];
+            const int32_t j = (int32_t)(e & COL_MASK);
+            const int32_t cj = a.cmap ? a.cmap[j] : j;
+            const float dx = yix - yv[2 * cj], dy = yiy - yv[2 * cj + 1];
+            const float d2 = dx * dx + dy * dy;
+            if (d2 > 0.0f) {
+                const float k = attract_coef<B>(d2);
+                const float w = half_e(a, e >> 30) * (zi + a.invZ[j]);
+                ax += w * clampT(k * dx, a.clip);
+                ay += w * clampT(k * dy, a.clip);
+            }
+        }
+        float rx = 0.0f, ry = 0.0f;
+        for (int m = lane; m < a.M; m += G) {
+            const uint64_t w = neg_word(a.seed, a.iter, (int32_t)i, m);
+            const int32_t v = draw_node(w, a.C, a.guide, a.gbits, a.S);
+            const int32_t cv = a.cmap ? a.cmap[v] : v;
+            const float dx = yix - yv[2 * cv], dy = yiy - yv[2 * cv + 1];
+            const float d2 = dx * dx + dy * dy;
+            if (d2 > 0.0f) {
+                const float k = repel_coef<B>(d2);
+                rx += clampT(k * dx, a.clip);
+                ry += clampT(k * dy, a.clip);
+            }
+        }
+        ax = group_sum<G>(ax);
+        ay = group_sum<G>(ay);
+        rx = group_sum<G>(rx);
+        ry = group_sum<G>(ry);
+        if (lane == 0) {
+            const float wc = a.w[ci];
+            if (wc > 0.0f) {
+                const float gq = a.gamma * a.qt[i];
+                const float sx = a.eta * ((ax + gq * rx) / wc);
+                const float sy = a.eta * ((ay + gq * ry) / wc);
+                if (a.cmap) {
+                    atomicAdd(&a.y[ci].x, sx);
+                    atomicAdd(&a.y[ci].y, sy);
+                } else {
+                    yv[2 * ci] = yix + sx;
+                    yv[2 * ci + 1] = yiy + sy;
+                }
+            }
+        }
+    }
+}
+
+static int sweep_group(double mean_len) {
+    if (mean_len <= 6) return 4;
+    if (mean_len <= 12) return 8;
+    if (mean_len <= 24) return 16;
+    if (mean_len <= 48) return 32;
+    return 64;
+}
+
+template <typename T, int B, int G>
+static void launch_one(hipStream_t st, const SweepArgs<T>& a, bool async) {
+    const int64_t groups = a.n0;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups * G + 255) / 256,
+                                                                 (int64_t)1 << 22));
+    if constexpr (std::is_same<T, float>::value) {
+        if (async) {
+            hipLaunchKernelGGL((k_sweep_async<B, G>), dim3(grid), dim3(256), 0, st, a);
+            DRG_LAUNCH_CHECK();
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+    DRG_LAUNCH_CHECK();
+}
+
+template <typename T, int B>
+static void launch_sweep(hipStream_t st, const SweepArgs<T>& a, int G, bool async) {
+    switch (G) {
+        case 4: launch_one<T, B, 4>(st, a, async); break;
+        case 8: launch_one<T, B, 8>(st, a, async); break;
+        case 16: launch_one<T, B, 16>(st, a, async); break;
+        case 32: launch_one<T, B, 32>(st, a, async); break;
+        default: launch_one<T, B, 64>(st, a, async); break;
+    }
+}
+
+template <typename T>
+void init_layout_t(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, T* y) {
+    if (n <= 0 || !y) throw Error(DRG_E_INVALID, "init_layout: n must be > 0 and y non-NULL");
+    hipLaunchKernelGGL(k_init<T>, dim3(ceil_div(n, 256)), dim3(256), 0, ctx->stream, n, seed,
+                       level, reinterpret_cast<typename VT<T>::v2*>(y));
+    DRG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void prolong_t(drg_ctx* ctx, const drg_hier* h, int32_t level, const T* yl, T* yf) {
+    if (!h || level < 1 || level >= (int32_t)h->lv.size() || !yl || !yf)
+        throw Error(DRG_E_INVALID, "prolong: bad level or NULL pointer");
+    const int32_t nf = h->lv[level - 1].n;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(ceil_div(nf, 256)), dim3(256), 0, ctx->stream, nf,
+                       h->lv[level].map.get(), reinterpret_cast<const typename VT<T>::v2*>(yl),
+                       reinterpret_cast<typename VT<T>::v2*>(yf));
+    DRG_LAUNCH_CHECK();
+}
+
+template void init_layout_t<float>(drg_ctx*, int32_t, uint64_t, int32_t, float*);
+template void init_layout_t<double>(drg_ctx*, int32_t, uint64_t, int32_t, double*);
+template void prolong_t<float>(drg_ctx*, const drg_hier*, int32_t, const float*, float*);
+template void prolong_t<double>(drg_ctx*, const drg_hier*, int32_t, const double*, double*);
+
+void init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y) {
+    init_layout_t<float>(ctx, n, seed, level, y);
+}
+void prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* yl, float* yf) {
+    prolong_t<float>(ctx, h, level, yl, yf);
+}
+
+template <typename T>
+void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y) {
+    constexpr bool F32 = std::is_same<T, float>::value;
+    if (!s || !p || !y) throw Error(DRG_E_INVALID, "layout_step: NULL argument");
+    if (p->M < 0 || p->b < 1 || p->b > 3)
+        throw Error(DRG_E_INVALID, "layout_step: M >= 0, b in 1..3");
+    if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "layout_step: clip must be > 0");
+    if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
+        throw Error(DRG_E_INVALID, "layout_step: unknown mode");
+    if (!F32 && p->mode == DRG_MODE_ASYNC)
+        throw Error(DRG_E_UNSUPPORTED, "layout_step: the FP64 instance is synchronous only");
+    const int32_t level = p->level;
+    if (level < 0 || (level > 0 && (!h || level >= (int32_t)h->lv.size())))
+        throw Error(DRG_E_INVALID, "layout_step: level out of range");
+    if (h && h->n0 != s->n)
+        throw Error(DRG_E_INVALID, "layout_step: hierarchy is of another graph");
+    hipStream_t st = ctx->stream;
+    const int32_t n0 = s->n;
+    const int32_t nl = level == 0 ? n0 : h->lv[level].n;
+    const int32_t* cmap = level == 0 ? nullptr : h->lv[level].cmap.get();
+    using v2 = typename VT<T>::v2;
+    using v4 = typename VT<T>::v4;
+    const T* invZ;
+    const T* qt;
+    v4* rec;
+    v2* g;
+    if constexpr (F32) {
+        invZ = s->invZf.get();
+        qt = s->qtf.get();
+        rec = s->rec.get();
+        g = s->g.get();
+    } else {
+        if (!s->rec64.get()) s->rec64.alloc(n0);
+        if (!s->g64.get()) s->g64.alloc(n0);
+        invZ = s->invZ.get();
+        qt = s->qt.get();
+        rec = s->rec64.get();
+        g = s->g64.get();
+    }
+    SweepArgs<T> a{};
+    a.n0 = n0;
+    a.M = s->S > 0 ? p->M : 0;
+    a.prp = s->row_ptr.get();
+    a.colhop = s->colhop.get();
+    a.qt = qt;
+    a.rec = rec;
+    a.g = g;
+    a.C = s->C.get();
+    a.guide = s->guide.get();
+    a.gbits = s->gbits;
+    a.S = s->S;
+    a.eh0 = (T)(0.5 * s->e[0]);
+    a.eh1 = (T)(0.5 * s->e[1]);
+    a.eh2 = (T)(0.5 * s->e[2]);
+    a.eh3 = (T)(0.5 * s->e[3]);
+    a.gamma = (T)p->gamma;
+    a.clip = (T)p->clip;
+    a.seed = p->seed;
+    a.iter = p->iter;
+    a.y = reinterpret_cast<v2*>(y);
+    a.cmap = cmap;
+    a.invZ = invZ;
+    a.eta = (T)p->eta;
+    const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
+    const bool async = p->mode == DRG_MODE_ASYNC;
+    if (async) {
+        if (level == 0) {
+            a.w = qt;
+        } else {
+            if (!s->wlev.get()) s->wlev.alloc(n0);
+            const drg_level& L = h->lv[level];
+            hipLaunchKernelGGL(k_level_weights<float>, dim3(ceil_div(nl, 256)), dim3(256), 0, st,
+                               nl, L.seg.get(), L.perm.get(), s->qtf.get(), s->wlev.get());
+            DRG_LAUNCH_CHECK();
+            a.w = reinterpret_cast<const T*>(s->wlev.get());
+        }
+    } else {
+        hipLaunchKernelGGL(k_stage<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, cmap,
+                           reinterpret_cast<const v2*>(y), invZ, rec);
+        DRG_LAUNCH_CHECK();
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+        DRG_HIP(hipEventCreate(&e0));
+        DRG_HIP(hipEventCreate(&e1));
+        DRG_HIP(hipEventRecord(e0, st));
+    }
+    switch (p->b) {
+        case 1: launch_sweep<T, 1>(st, a, G, async); break;
+        case 2: launch_sweep<T, 2>(st, a, G, async); break;
+        default: launch_sweep<T, 3>(st, a, G, async); break;
+    }
+    if (ctx->profiling) {
+        DRG_HIP(hipEventRecord(e1, st));
+        ctx->events.emplace_back(e0, e1);
+    }
+    if (!async) {
+        if (level == 0) {
+            hipLaunchKernelGGL(k_apply0<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, g, qt,
+                               reinterpret_cast<v2*>(y), (T)p->eta);
+        } else {
+            const drg_level& L = h->lv[level];
+            const double mean = (double)n0 / (double)std::max(1, nl);
+            if (mean <= 16)
+                hipLaunchKernelGGL((k_apply_level<T, 8>), dim3(ceil_div((int64_t)nl * 8, 256)),
+                                   dim3(256), 0, st, nl, L.seg.get(), L.perm.get(), g, qt,
+                                   reinterpret_cast<v2*>(y), (T)p->eta);
+            else
+                hipLaunchKernelGGL((k_apply_level<T, 32>), dim3(ceil_div((int64_t)nl * 32, 256)),
+                                   dim3(256), 0, st, nl, L.seg.get(), L.perm.get(), g, qt,
+                                   reinterpret_cast<v2*>(y), (T)p->eta);
+        }
+        DRG_LAUNCH_CHECK();
+    }
+}
+
+template void layout_step_t<float>(drg_ctx*, drg_sim*, const drg_hier*, const drg_step_params*,
+                                   float*);
+template void layout_step_t<double>(drg_ctx*, drg_sim*, const drg_hier*, const drg_step_params*,
+                                    double*);
+
+void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p,
+                 float* y) {
+    layout_step_t<float>(ctx, s, h, p, y);
+}
+
+}  // namespace drg

@@ -1,0 +1,579 @@
+// similarity.hip -- sparse distance matrix and node similarity (Sec. 3.2.1,
+// Eq. NS) plus the node-weight sampling table of the negatives (Sec. 3.2.2).
+//
+// Pattern: for every source s the set NNG(s, k) with hop counts, by a
+// breadth-first search bounded at depth k.  One workgroup owns one source at
+// a time (sources are handed out through an atomic counter).  The visited set
+// is a bitmap over all n nodes held in LDS (global memory when n is too large),
+// so a row comes out sorted by scanning the bitmap: each thread popcounts a
+// few bitmap words and a block prefix sum places the set bits.  Frontier
+// levels 2..k-1 are kept in a per-workgroup queue filled with wave-ballot
+// compaction; hop counts < k are patched into the sorted row afterwards.
+// Two passes: count (hop histogram per row) -> prefix sum -> fill.
+#include <cmath>
+#include <memory>
+
+#include "drg_bitmap.hpp"
+#include "drg_internal.hpp"
+
+namespace drg {
+
+// ------------------------------------------------------------------ checks
+__global__ void k_check_rowptr(int32_t n, int32_t nnz, const int32_t* __restrict__ rp,
+                               int* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int32_t v = rp[i];
+    bool ok = v >= 0 && v <= nnz;
+    if (i == 0) ok = ok && v == 0;
+    if (i == n) ok = ok && v == nnz;
+    if (i < n) ok = ok && rp[i + 1] >= v;
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_check_cols(int32_t nnz, int32_t n, const int32_t* __restrict__ col,
+                             int* __restrict__ bad) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nnz && (col[x] < 0 || col[x] >= n)) atomicOr(bad, 2);
+}
+
+// rows sorted strictly ascending (no duplicates), no self-loops, symmetric
+__global__ void k_check_structure(int32_t n, const int32_t* __restrict__ rp,
+                                  const int32_t* __restrict__ col, int* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s = rp[i], e = rp[i + 1];
+    int flag = 0;
+    for (int32_t x = s; x < e; ++x) {
+        const int32_t v = col[x];
+        if (v == (int32_t)i) flag |= 4;
+        if (x > s && col[x - 1] >= v) flag |= 8;
+        int32_t lo = rp[v], hi = rp[v + 1];
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (col[mid] < (int32_t)i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo >= rp[v + 1] || col[lo] != (int32_t)i) flag |= 16;
+    }
+    if (flag) atomicOr(bad, flag);
+}
+
+static int read_flag(DevBuf<int>& f, hipStream_t s) {
+    int h = 0;
+    DRG_HIP(hipMemcpyAsync(&h, f.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    DRG_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// Cheap bounds checks always run (they keep later kernels inside their
+// buffers); the structural checks run under DRG_VALIDATE.
+void validate_csr_impl(drg_ctx* ctx, const drg_csr* g, bool full) {
+    hipStream_t st = ctx->stream;
+    DevBuf<int> bad(1);
+    DRG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_check_rowptr, dim3(ceil_div((int64_t)g->n + 1, 256)), dim3(256), 0, st,
+                       g->n, g->nnz, g->row_ptr, bad.get());
+    DRG_LAUNCH_CHECK();
+    if (read_flag(bad, st)) throw Error(DRG_E_GRAPH, "row_ptr is not a valid offset array");
+    if (g->nnz > 0) {
+        hipLaunchKernelGGL(k_check_cols, dim3(ceil_div(g->nnz, 256)), dim3(256), 0, st, g->nnz,
+                           g->n, g->col, bad.get());
+        DRG_LAUNCH_CHECK();
+        if (read_flag(bad, st)) throw Error(DRG_E_GRAPH, "column index out of range");
+    }
+    if (full && g->nnz > 0) {
+        hipLaunchKernelGGL(k_check_structure, dim3(ceil_div(g->n, 256)), dim3(256), 0, st, g->n,
+                           g->row_ptr, g->col, bad.get());
+        DRG_LAUNCH_CHECK();
+        const int f = read_flag(bad, st);
+        if (f & 4) throw Error(DRG_E_GRAPH, "self-loop in input graph");
+        if (f & 8) throw Error(DRG_E_GRAPH, "row not sorted or duplicate edge");
+        if (f & 16) throw Error(DRG_E_GRAPH, "input graph is not symmetric");
+    }
+}
+
+void validate_csr(drg_ctx* ctx, const drg_csr* g) { validate_csr_impl(ctx, g, true); }
+
+// ------------------------------------------------------------------ BFS
+constexpr int BFS_BLOCK = 256;
+constexpr int EMIT_WPT = 8;
+
+struct BfsArgs {
+    int32_t n, k, nwords;
+    const int32_t* rp;
+    const int32_t* col;
+    int32_t* cnt;          // count pass: [n][k] nodes per hop
+    const int64_t* prp;    // fill pass: row offsets
+    uint32_t* colhop;      // fill pass: entries
+    int32_t* queue;        // [grid][qcap] frontier levels 2..k-1
+    int64_t qcap;
+    uint32_t* gbm;         // [grid][nwords] bitmaps when not in LDS
+    int32_t* work;         // next source
+};
+
+// Sets the hop of id v inside the sorted row ch[lo..hi); v absent (only
+// possible for a self-loop in an unvalidated graph) writes nothing.
+__device__ __forceinline__ void set_hop(uint32_t* __restrict__ ch, int64_t lo, int64_t hi,
+                                        int32_t v, uint32_t hopbits) {
+    const int64_t end = hi;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int32_t)(ch[mid] & COL_MASK) < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < end && (int32_t)(ch[lo] & COL_MASK) == v) ch[lo] = (uint32_t)v | hopbits;
+}
+
+template <bool FILL, bool LDS_BM, int G>
+__global__ __launch_bounds__(BFS_BLOCK) void k_khop(BfsArgs a) {
+    extern __shared__ uint32_t s_bm[];
+    __shared__ int32_t s_src, s_qtail;
+    __shared__ int32_t s_lvl[8];
+    __shared__ int32_t s_red[BFS_BLOCK / WAVE];
+    uint32_t* bm = LDS_BM ? s_bm : a.gbm + (size_t)blockIdx.x * (size_t)a.nwords;
+    int32_t* q = a.queue ? a.queue + (size_t)blockIdx.x * (size_t)a.qcap : nullptr;
+    const int tid = threadIdx.x;
+    for (int w = tid; w < a.nwords; w += BFS_BLOCK) bm[w] = 0;
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) s_src = atomicAdd(a.work, 1);
+        __syncthreads();
+        const int32_t s = s_src;
+        if (s >= a.n) break;
+        const int32_t rs = a.rp[s], re = a.rp[s + 1];
+        if (rs == re) {
+            if (!FILL && tid < a.k) a.cnt[(int64_t)s * a.k + tid] = 0;
+            __syncthreads();
+            continue;
+        }
+        // hop 1: the source itself (visited) and its neighbours
+        if (tid == 0) {
+            atomicOr(&bm[s >> 5], 1u << (s & 31));
+            s_qtail = 0;
+        }
+        for (int32_t x = rs + tid; x < re; x += BFS_BLOCK) {
+            const int32_t v = a.col[x];
+            atomicOr(&bm[v >> 5], 1u << (v & 31));
+        }
+        __syncthreads();
+        // hops 2..k: expand the previous frontier, G lanes per frontier node
+        int32_t fb = 0, fe = 0;
+        for (int d = 2; d <= a.k; ++d) {
+            const bool from_adj = (d == 2);
+            const int32_t* F = from_adj ? a.col + rs : q + fb;
+            const int32_t flen = from_adj ? (re - rs) : (fe - fb);
+            const bool keep = d < a.k;
+            for (int32_t fi = tid / G; fi < flen; fi += BFS_BLOCK / G) {
+                const int32_t u = F[fi];
+                const int32_t us = a.rp[u], ue = a.rp[u + 1];
+                for (int32_t x = us + (tid % G); x < ue; x += G) {
+                    const int32_t v = a.col[x];
+                    const uint32_t bit = 1u << (v & 31);
+                    if (keep) {
+                        const uint32_t old = atomicOr(&bm[v >> 5], bit);
+                        const bool fresh = !(old & bit);
+                        const uint64_t act = __ballot(1);
+                        const uint64_t fm = __ballot(fresh);
+                        if (fm) {
+                            const int leader = __ffsll((unsigned long long)act) - 1;
+                            int base = 0;
+                            if (__lane_id() == leader) base = atomicAdd(&s_qtail, __popcll(fm));
+                            base = __shfl(base, leader);
+                            if (fresh) q[base + __popcll(fm & lanemask_lt())] = v;
+                        }
+                    } else {
+                        atomicOr(&bm[v >> 5], bit);
+                    }
+                }
+            }
+            __syncthreads();
+            if (keep) {
+                fb = fe;
+                fe = s_qtail;
+                if (tid == 0) s_lvl[d] = fe;
+            }
+        }
+        if constexpr (!FILL) {
+            const int total = bitmap_count_clear<BFS_BLOCK>(bm, a.nwords, s_red);  // with source
+            if (tid == 0) {
+                const int64_t o = (int64_t)s * a.k;
+                int acc = re - rs;
+                a.cnt[o] = re - rs;
+                int prev = 0;
+                for (int d = 2; d < a.k; ++d) {
+                    const int cd = s_lvl[d] - prev;
+                    a.cnt[o + d - 1] = cd;
+                    acc += cd;
+                    prev = s_lvl[d];
+                }
+                if (a.k >= 2) a.cnt[o + a.k - 1] = (total - 1) - acc;
+            }
+            __syncthreads();
+        } else {
+            const int64_t row0 = a.prp[s], row1 = a.prp[s + 1];
+            const uint32_t hopk = (uint32_t)(a.k - 1) << 30;
+            uint32_t* out = a.colhop;
+            bitmap_emit_clear<BFS_BLOCK, EMIT_WPT>(
+                bm, a.nwords, s, row0, s_red, [&](int64_t o, uint32_t v) { out[o] = v | hopk; });
+            __syncthreads();
+            if (a.k >= 2) {
+                for (int32_t x = rs + tid; x < re; x += BFS_BLOCK)
+                    set_hop(a.colhop, row0, row1, a.col[x], 0u);
+                int prev = 0;
+                for (int d = 2; d < a.k; ++d) {
+                    const int end = s_lvl[d];
+                    for (int t = prev + tid; t < end; t += BFS_BLOCK)
+                        set_hop(a.colhop, row0, row1, q[t], (uint32_t)(d - 1) << 30);
+                    prev = end;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <bool FILL, bool LDS_BM>
+static void launch_khop(drg_ctx* ctx, const BfsArgs& a, int G, int grid, size_t lds) {
+    hipStream_t st = ctx->stream;
+#define DRG_KHOP_CASE(GG)                                                                       \
+    case GG: {                                                                                  \
+        auto fn = k_khop<FILL, LDS_BM, GG>;                                                     \
+        if (LDS_BM)                                                                             \
+            DRG_HIP(hipFuncSetAttribute((const void*)fn,                                        \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(BFS_BLOCK), LDS_BM ? lds : 0, st, a);           \
+        break;                                                                                  \
+    }
+    switch (G) {
+        DRG_KHOP_CASE(4)
+        DRG_KHOP_CASE(8)
+        DRG_KHOP_CASE(16)
+        DRG_KHOP_CASE(32)
+        default:
+        DRG_KHOP_CASE(64)
+    }
+#undef DRG_KHOP_CASE
+    DRG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_deg_counts(int32_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ cnt,
+                             int64_t* __restrict__ prp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cnt[i] = rp[i + 1] - rp[i];
+    if (i <= n) prp[i] = rp[i];
+}
+
+__global__ void k_copy_cols(int32_t nnz, const int32_t* __restrict__ col, uint32_t* __restrict__ ch) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nnz) ch[x] = (uint32_t)col[x];  // hop 1 -> high bits 0
+}
+
+__global__ void k_row_len(int32_t n, int32_t k, const int32_t* __restrict__ cnt,
+                          int64_t* __restrict__ len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t s = 0;
+    for (int d = 0; d < k; ++d) s += cnt[i * k + d];
+    len[i] = s;
+}
+
+__global__ void k_sum_deg2(int32_t n, const int32_t* __restrict__ rp,
+                           unsigned long long* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (i < n) {
+        const unsigned long long d = (unsigned long long)(rp[i + 1] - rp[i]);
+        v = d * d;
+    }
+    v = group_sum<WAVE>(v);
+    if (__lane_id() == 0 && v) atomicAdd(out, v);
+}
+
+__device__ __forceinline__ double pick_e(const double* e, uint32_t h) {
+    return h == 0 ? e[0] : (h == 1 ? e[1] : (h == 2 ? e[2] : e[3]));
+}
+
+struct ECoef {
+    double e[4];
+};
+
+// Z_i = sum_d cnt_i(d) e_d accumulated from zero in hop order, every
+// operation rounded on its own; invZ_i = 1 / Z_i (0 for an isolated node).
+__global__ void k_normalise(int32_t n, int32_t k, const int32_t* __restrict__ cnt, ECoef ec,
+                            double* __restrict__ invZ, float* __restrict__ invZf) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double z = 0.0;
+    for (int d = 0; d < k; ++d) {
+        const double c = (double)cnt[i * k + d];
+        const double t = c * pick_e(ec.e, (uint32_t)d);
+        z = z + t;
+    }
+    const double iz = z > 0.0 ? 1.0 / z : 0.0;
+    invZ[i] = iz;
+    invZf[i] = (float)iz;
+}
+
+// P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2.  Per row: W_i = sum_j trunc(P~_ij 2^32)
+// (exact integer), qt_i = sum_j P~_ij (FP64, fixed tree order).
+template <int G>
+__global__ __launch_bounds__(256) void k_row_weights(int32_t n, const int64_t* __restrict__ prp,
+                                                     const uint32_t* __restrict__ ch,
+                                                     const double* __restrict__ invZ, ECoef ec,
+                                                     uint64_t* __restrict__ W,
+                                                     double* __restrict__ qt,
+                                                     float* __restrict__ qtf) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t i = grp; i < n; i += ngrp) {
+        const double izi = invZ[i];
+        unsigned long long ws = 0;
+        double qs = 0.0;
+        for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += G) {
+            const uint32_t e = ch[x];
+            const double s = izi + invZ[e & COL_MASK];
+            const double t = pick_e(ec.e, e >> 30) * s;
+            const double p = t * 0.5;
+            ws += (unsigned long long)(p * 4294967296.0);
+            qs = qs + p;
+        }
+        ws = group_sum<G>(ws);
+        qs = group_sum<G>(qs);
+        if (lane == 0) {
+            W[i] = ws;
+            qt[i] = qs;
+            qtf[i] = (float)qs;
+        }
+    }
+}
+
+// guide[b] = draw result for the smallest word of bucket b (top gbits bits);
+// guide[2^gbits] = draw result for the largest word.
+__global__ void k_guide(int32_t n, const uint64_t* __restrict__ C, int gbits,
+                        int32_t* __restrict__ guide) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = (int64_t)1 << gbits;
+    if (b > nb) return;
+    const uint64_t S = C[n];
+    if (S == 0) {
+        guide[b] = 0;
+        return;
+    }
+    const uint64_t r = b < nb ? __umul64hi((uint64_t)b << (64 - gbits), S) : S - 1;
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (C[mid + 1] > r)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    guide[b] = lo;
+}
+
+__global__ void k_materialise_P(int32_t n, const int64_t* __restrict__ prp,
+                                const uint32_t* __restrict__ ch, const double* __restrict__ invZ,
+                                ECoef ec, double* __restrict__ P) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+        const uint32_t e = ch[x];
+        const double s = invZ[i] + invZ[e & COL_MASK];
+        const double t = pick_e(ec.e, e >> 30) * s;
+        P[x] = t * 0.5;
+    }
+}
+
+static int pick_group(double mean_len) {
+    if (mean_len <= 4) return 4;
+    if (mean_len <= 8) return 8;
+    if (mean_len <= 16) return 16;
+    if (mean_len <= 32) return 32;
+    return 64;
+}
+
+template <int G>
+static void launch_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec) {
+    const int64_t groups = s->n;
+    const int grid = (int)std::min<int64_t>((groups * G + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_row_weights<G>, dim3(std::max(grid, 1)), dim3(256), 0, ctx->stream, s->n,
+                       s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, s->W.get(),
+                       s->qt.get(), s->qtf.get());
+    DRG_LAUNCH_CHECK();
+}
+
+drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags) {
+    if (!g) throw Error(DRG_E_INVALID, "graph is NULL");
+    if (k < 1 || k > 4) throw Error(DRG_E_INVALID, "k must be in 1..4");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) throw Error(DRG_E_INVALID, "sigma must be > 0");
+    if (g->n <= 0 || g->n >= (1 << 30)) throw Error(DRG_E_INVALID, "n must be in 1..2^30-1");
+    if (g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col))
+        throw Error(DRG_E_INVALID, "bad CSR pointers or nnz");
+    validate_csr_impl(ctx, g, (flags & DRG_VALIDATE) != 0);
+    hipStream_t st = ctx->stream;
+    const int32_t n = g->n;
+    auto s = std::make_unique<drg_sim>();
+    s->device = ctx->device;
+    s->n = n;
+    s->k = k;
+    s->sigma = sigma;
+    ECoef ec{};
+    for (int d = 1; d <= 4; ++d) {
+        ec.e[d - 1] = d <= k ? std::exp(-(double)(d * d) / (2.0 * sigma * sigma)) : 0.0;
+        s->e[d - 1] = ec.e[d - 1];
+    }
+    DevBuf<int32_t> cnt((int64_t)n * k);
+    s->row_ptr.alloc((int64_t)n + 1);
+    if (k == 1) {
+        hipLaunchKernelGGL(k_deg_counts, dim3(ceil_div((int64_t)n + 1, 256)), dim3(256), 0, st, n,
+                           g->row_ptr, cnt.get(), s->row_ptr.get());
+        DRG_LAUNCH_CHECK();
+        s->nnz = g->nnz;
+        s->colhop.alloc(s->nnz);
+        if (s->nnz > 0) {
+            hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div(s->nnz, 256)), dim3(256), 0, st, g->nnz,
+                               g->col, s->colhop.get());
+            DRG_LAUNCH_CHECK();
+        }
+    } else {
+        // launch shape: LDS bitmap when it fits, global bitmaps otherwise
+        const int nwords = (n + 31) / 32;
+        const size_t lds = (size_t)nwords * 4;
+        const bool in_lds = lds + 512 <= (size_t)ctx->max_lds;
+        DevBuf<unsigned long long> d2(1);
+        DRG_HIP(hipMemsetAsync(d2.get(), 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_sum_deg2, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, g->row_ptr,
+                           d2.get());
+        DRG_LAUNCH_CHECK();
+        unsigned long long sdeg2 = 0;
+        DRG_HIP(hipMemcpyAsync(&sdeg2, d2.get(), sizeof(sdeg2), hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+        const double visit_deg = g->nnz > 0 ? (double)sdeg2 / (double)g->nnz : 1.0;
+        const int G = pick_group(visit_deg);
+        int per_cu = in_lds ? std::max(1, (int)(ctx->max_lds / (lds + 512))) : 4;
+        per_cu = std::min(per_cu, 8);
+        const int grid = std::max(1, std::min<int>(ctx->num_cu * per_cu, n));
+        DevBuf<int32_t> queue;
+        int64_t qcap = 0;
+        if (k >= 3) {
+            qcap = n;
+            queue.alloc((int64_t)grid * qcap);
+        }
+        DevBuf<uint32_t> gbm;
+        if (!in_lds) gbm.alloc((int64_t)grid * nwords);
+        DevBuf<int32_t> work(1);
+        BfsArgs a{};
+        a.n = n;
+        a.k = k;
+        a.nwords = nwords;
+        a.rp = g->row_ptr;
+        a.col = g->col;
+        a.cnt = cnt.get();
+        a.queue = queue.get();
+        a.qcap = qcap;
+        a.gbm = gbm.get();
+        a.work = work.get();
+        DRG_HIP(hipMemsetAsync(work.get(), 0, sizeof(int32_t), st));
+        if (in_lds)
+            launch_khop<false, true>(ctx, a, G, grid, lds);
+        else
+            launch_khop<false, false>(ctx, a, G, grid, 0);
+        DevBuf<int64_t> len(n);
+        hipLaunchKernelGGL(k_row_len, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k, cnt.get(),
+                           len.get());
+        DRG_LAUNCH_CHECK();
+        exclusive_scan<int64_t>(len.get(), s->row_ptr.get(), n, st);
+        int64_t nnz = 0;
+        DRG_HIP(hipMemcpyAsync(&nnz, s->row_ptr.get() + n, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+        s->nnz = nnz;
+        s->colhop.alloc(nnz);
+        a.prp = s->row_ptr.get();
+        a.colhop = s->colhop.get();
+        DRG_HIP(hipMemsetAsync(work.get(), 0, sizeof(int32_t), st));
+        if (in_lds)
+            launch_khop<true, true>(ctx, a, G, grid, lds);
+        else
+            launch_khop<true, false>(ctx, a, G, grid, 0);
+        DRG_HIP(hipStreamSynchronize(st));
+    }
+    s->invZ.alloc(n);
+    s->invZf.alloc(n);
+    s->qt.alloc(n);
+    s->qtf.alloc(n);
+    s->W.alloc(n);
+    s->C.alloc((int64_t)n + 1);
+    hipLaunchKernelGGL(k_normalise, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k, cnt.get(), ec,
+                       s->invZ.get(), s->invZf.get());
+    DRG_LAUNCH_CHECK();
+    const double mean_len = (double)s->nnz / (double)n;
+    switch (pick_group(mean_len)) {
+        case 4: launch_row_weights<4>(ctx, s.get(), ec); break;
+        case 8: launch_row_weights<8>(ctx, s.get(), ec); break;
+        case 16: launch_row_weights<16>(ctx, s.get(), ec); break;
+        case 32: launch_row_weights<32>(ctx, s.get(), ec); break;
+        default: launch_row_weights<64>(ctx, s.get(), ec); break;
+    }
+    exclusive_scan<uint64_t>(s->W.get(), s->C.get(), n, st);
+    DRG_HIP(hipMemcpyAsync(&s->S, s->C.get() + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    DRG_HIP(hipStreamSynchronize(st));
+    int gbits = 1;
+    while (gbits < 30 && ((int64_t)1 << gbits) < n) ++gbits;
+    s->gbits = gbits;
+    s->guide.alloc(((int64_t)1 << gbits) + 1);
+    hipLaunchKernelGGL(k_guide, dim3(ceil_div(((int64_t)1 << gbits) + 1, 256)), dim3(256), 0, st,
+                       n, s->C.get(), gbits, s->guide.get());
+    DRG_LAUNCH_CHECK();
+    s->n_active = (int32_t)count_nonempty_rows<int64_t>(s->row_ptr.get(), n, st);
+    s->rec.alloc(n);
+    s->g.alloc(n);
+    DRG_HIP(hipStreamSynchronize(st));
+    return s.release();
+}
+
+void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,
+                double* qt, uint64_t* W, double* e, double* invZ) {
+    const int32_t n = s->n;
+    const int64_t nnz = s->nnz;
+    DRG_HIP(hipSetDevice(s->device));
+    DRG_HIP(hipDeviceSynchronize());
+    if (row_ptr)
+        DRG_HIP(hipMemcpy(row_ptr, s->row_ptr.get(), sizeof(int64_t) * (n + 1),
+                          hipMemcpyDeviceToHost));
+    if ((col || hop) && nnz > 0) {
+        std::vector<uint32_t> ch(nnz);
+        DRG_HIP(hipMemcpy(ch.data(), s->colhop.get(), sizeof(uint32_t) * nnz,
+                          hipMemcpyDeviceToHost));
+        for (int64_t x = 0; x < nnz; ++x) {
+            if (col) col[x] = (int32_t)(ch[x] & COL_MASK);
+            if (hop) hop[x] = (uint8_t)((ch[x] >> 30) + 1);
+        }
+    }
+    if (P && nnz > 0) {
+        DevBuf<double> dP(nnz);
+        ECoef ec{};
+        for (int d = 0; d < 4; ++d) ec.e[d] = s->e[d];
+        hipLaunchKernelGGL(k_materialise_P, dim3(ceil_div(n, 256)), dim3(256), 0, nullptr, n,
+                           s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, dP.get());
+        DRG_LAUNCH_CHECK();
+        DRG_HIP(hipMemcpy(P, dP.get(), sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
+    if (qt) DRG_HIP(hipMemcpy(qt, s->qt.get(), sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (W) DRG_HIP(hipMemcpy(W, s->W.get(), sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+    if (invZ) DRG_HIP(hipMemcpy(invZ, s->invZ.get(), sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (e)
+        for (int d = 0; d < s->k; ++d) e[d] = s->e[d];
+}
+
+}  // namespace drg

@@ -1,0 +1,316 @@
+"""Python binding of libdrgraph.so (argument marshalling only).
+
+Functions carry the names of the C entry points in include/drgraph.h.  Device
+arrays are torch tensors on the GPU; every step of the layout runs in the
+library's HIP kernels.  Importing works without a GPU; calling a function
+that needs the library raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdrgraph.so")
+
+DRG_OK = 0
+DRG_E_INVALID = -1
+DRG_E_GRAPH = -2
+DRG_E_OOM = -3
+DRG_E_DEVICE = -4
+DRG_E_UNSUPPORTED = -5
+DRG_VALIDATE = 1
+DRG_MODE_SYNC = 0
+DRG_MODE_ASYNC = 1
+
+
+class DrgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"drgraph status {status}: {msg}")
+        self.status = status
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("M", C.c_int32), ("b", C.c_int32), ("gamma", C.c_float), ("eta", C.c_float),
+                ("clip", C.c_float), ("level", C.c_int32), ("mode", C.c_int32),
+                ("_pad", C.c_int32), ("seed", C.c_uint64), ("iter", C.c_uint64)]
+
+
+class LayoutParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("M", C.c_int32), ("b", C.c_int32), ("T", C.c_int32),
+                ("sigma", C.c_double), ("gamma", C.c_float), ("gamma_coarsest", C.c_float),
+                ("eta0", C.c_float), ("clip", C.c_float), ("rho", C.c_double),
+                ("min_nodes", C.c_int32), ("max_levels", C.c_int32), ("mode", C.c_int32),
+                ("_pad", C.c_int32), ("seed", C.c_uint64)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libdrgraph.so not built ({LIB_PATH}); run "
+                           "python -m paper_2008_07799_amd.build")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int32
+    sig = {
+        "drg_last_error": ([], C.c_char_p),
+        "drg_version": ([], C.c_char_p),
+        "drg_layout_params_default": ([C.POINTER(LayoutParams)], st),
+        "drg_ctx_create": ([C.c_int32, _P, C.POINTER(_P)], st),
+        "drg_ctx_destroy": ([_P], None),
+        "drg_ctx_synchronize": ([_P], st),
+        "drg_ctx_set_profiling": ([_P, C.c_int32], st),
+        "drg_ctx_kernel_stats": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)], st),
+        "drg_build_similarity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double, C.c_uint32,
+                                  C.POINTER(_P)], st),
+        "drg_sim_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                          C.POINTER(C.c_int32)], st),
+        "drg_sim_export": ([_P] + [_P] * 8, st),
+        "drg_sim_destroy": ([_P], None),
+        "drg_coarsen": ([_P, C.POINTER(Csr), C.c_uint64, C.c_double, C.c_int32, C.c_int32,
+                         C.POINTER(_P)], st),
+        "drg_hier_info": ([_P, C.POINTER(C.c_int32), _P], st),
+        "drg_hier_export": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int64)], st),
+        "drg_hier_destroy": ([_P], None),
+        "drg_init_layout": ([_P, C.c_int32, C.c_uint64, C.c_int32, _P], st),
+        "drg_prolong": ([_P, _P, C.c_int32, _P, _P], st),
+        "drg_layout_step": ([_P, _P, _P, C.POINTER(StepParams), _P], st),
+        "drg_init_layout_f64": ([_P, C.c_int32, C.c_uint64, C.c_int32, _P], st),
+        "drg_prolong_f64": ([_P, _P, C.c_int32, _P, _P], st),
+        "drg_layout_step_f64": ([_P, _P, _P, C.POINTER(StepParams), _P], st),
+        "drg_layout_run": ([_P, _P, _P, C.POINTER(LayoutParams), _P], st),
+        "drg_layout": ([_P, C.POINTER(Csr), C.POINTER(LayoutParams), _P], st),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != DRG_OK:
+        raise DrgError(status, lib().drg_last_error().decode(errors="replace"))
+
+
+def _dev(t, dtype, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().drg_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().drg_ctx_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def synchronize(self):
+        _check(lib().drg_ctx_synchronize(self.h))
+
+    def set_profiling(self, on: bool):
+        _check(lib().drg_ctx_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_stats(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(lib().drg_ctx_kernel_stats(self.h, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+
+def _csr(row_ptr, col) -> Csr:
+    import torch
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    return Csr(n, nnz, _dev(row_ptr, torch.int32, "row_ptr").value,
+               _dev(col, torch.int32, "col").value if nnz else None)
+
+
+def to_device(csr, device="cuda"):
+    """gen.CSR -> (row_ptr, col) int32 tensors on the GPU."""
+    import torch
+    rp = torch.from_numpy(np.ascontiguousarray(csr.row_ptr, np.int32)).to(device)
+    col = torch.from_numpy(np.ascontiguousarray(csr.col, np.int32)).to(device)
+    return rp, col
+
+
+# ------------------------------------------------------------------ similarity
+class Similarity:
+    def __init__(self, h):
+        self.h = h
+        n = C.c_int32()
+        nnz = C.c_int64()
+        na = C.c_int32()
+        k = C.c_int32()
+        _check(lib().drg_sim_info(h, C.byref(n), C.byref(nnz), C.byref(na), C.byref(k)))
+        self.n, self.nnz, self.n_active, self.k = n.value, nnz.value, na.value, k.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().drg_sim_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def export(self, values: bool = True) -> dict:
+        n, nnz, k = self.n, self.nnz, self.k
+        out = {"row_ptr": np.zeros(n + 1, np.int64), "col": np.zeros(max(nnz, 1), np.int32),
+               "hop": np.zeros(max(nnz, 1), np.uint8), "qt": np.zeros(n, np.float64),
+               "W": np.zeros(n, np.uint64), "e": np.zeros(max(k, 1), np.float64),
+               "invZ": np.zeros(n, np.float64)}
+        out["P"] = np.zeros(max(nnz, 1), np.float64) if values else None
+        _check(lib().drg_sim_export(self.h, _np_ptr(out["row_ptr"]), _np_ptr(out["col"]),
+                                    _np_ptr(out["hop"]), _np_ptr(out["P"]), _np_ptr(out["qt"]),
+                                    _np_ptr(out["W"]), _np_ptr(out["e"]),
+                                    _np_ptr(out["invZ"])))
+        out["col"] = out["col"][:nnz]
+        out["hop"] = out["hop"][:nnz]
+        if values:
+            out["P"] = out["P"][:nnz]
+        out["e"] = out["e"][:k]
+        return out
+
+
+def drg_build_similarity(ctx: Context, row_ptr, col, k: int, sigma: float = 1.0,
+                         validate: bool = False) -> Similarity:
+    g = _csr(row_ptr, col)
+    h = C.c_void_p()
+    _check(lib().drg_build_similarity(ctx.h, C.byref(g), int(k), float(sigma),
+                                      DRG_VALIDATE if validate else 0, C.byref(h)))
+    return Similarity(h)
+
+
+# ------------------------------------------------------------------ hierarchy
+class Hierarchy:
+    def __init__(self, h):
+        self.h = h
+        lv = C.c_int32()
+        _check(lib().drg_hier_info(h, C.byref(lv), None))
+        self.levels = lv.value
+        sizes = np.zeros(self.levels, np.int32)
+        _check(lib().drg_hier_info(h, C.byref(lv), _np_ptr(sizes)))
+        self.sizes = [int(x) for x in sizes]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().drg_hier_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def export(self, level: int, n0: int) -> dict:
+        nf = self.sizes[level - 1]
+        nl = self.sizes[level]
+        nnz = C.c_int64()
+        _check(lib().drg_hier_export(self.h, level, None, None, None, None, C.byref(nnz)))
+        out = {"map": np.zeros(nf, np.int32), "cmap": np.zeros(n0, np.int32),
+               "row_ptr": np.zeros(nl + 1, np.int32), "col": np.zeros(max(nnz.value, 1), np.int32)}
+        _check(lib().drg_hier_export(self.h, level, _np_ptr(out["map"]), _np_ptr(out["cmap"]),
+                                     _np_ptr(out["row_ptr"]), _np_ptr(out["col"]), C.byref(nnz)))
+        out["col"] = out["col"][: nnz.value]
+        return out
+
+
+def drg_coarsen(ctx: Context, row_ptr, col, seed: int = 0, rho: float = 0.8,
+                min_nodes: int = 1000, max_levels: int = 64) -> Hierarchy:
+    g = _csr(row_ptr, col)
+    h = C.c_void_p()
+    _check(lib().drg_coarsen(ctx.h, C.byref(g), int(seed), float(rho), int(min_nodes),
+                             int(max_levels), C.byref(h)))
+    return Hierarchy(h)
+
+
+# ------------------------------------------------------------------ layout
+def _coords(y, name, shape):
+    """float32 -> the product entry point, float64 -> its FP64 instance."""
+    import torch
+    if isinstance(y, torch.Tensor) and y.dtype == torch.float64:
+        return _dev(y, torch.float64, name, shape), True
+    return _dev(y, torch.float32, name, shape), False
+
+
+def drg_init_layout(ctx: Context, n: int, seed: int, level: int, y):
+    ptr, f64 = _coords(y, "y", (n, 2))
+    fn = lib().drg_init_layout_f64 if f64 else lib().drg_init_layout
+    _check(fn(ctx.h, int(n), int(seed), int(level), ptr))
+
+
+def drg_prolong(ctx: Context, hier: Hierarchy, level: int, y_level, y_finer):
+    a, f64 = _coords(y_level, "y_level", (hier.sizes[level], 2))
+    b, f64b = _coords(y_finer, "y_finer", (hier.sizes[level - 1], 2))
+    if f64 != f64b:
+        raise TypeError("y_level and y_finer must have the same dtype")
+    fn = lib().drg_prolong_f64 if f64 else lib().drg_prolong
+    _check(fn(ctx.h, hier.h, int(level), a, b))
+
+
+def drg_layout_step(ctx: Context, sim: Similarity, hier, y, *, M=5, b=1, gamma=0.1, eta=1.0,
+                    clip=4.0, level=0, mode=DRG_MODE_SYNC, seed=0, iter=0):
+    nl = sim.n if level == 0 else hier.sizes[level]
+    p = StepParams(int(M), int(b), float(gamma), float(eta), float(clip), int(level), int(mode),
+                   0, int(seed), int(iter))
+    ptr, f64 = _coords(y, "y", (nl, 2))
+    fn = lib().drg_layout_step_f64 if f64 else lib().drg_layout_step
+    _check(fn(ctx.h, sim.h, hier.h if hier is not None else None, C.byref(p), ptr))
+
+
+def layout_params(**kw) -> LayoutParams:
+    p = LayoutParams()
+    _check(lib().drg_layout_params_default(C.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def drg_layout_run(ctx: Context, sim: Similarity, hier: Hierarchy, params: LayoutParams, y_out):
+    import torch
+    _check(lib().drg_layout_run(ctx.h, sim.h, hier.h, C.byref(params),
+                                _dev(y_out, torch.float32, "y_out", (sim.n, 2))))
+
+
+def drg_layout(ctx: Context, row_ptr, col, params: LayoutParams, y_out):
+    import torch
+    g = _csr(row_ptr, col)
+    _check(lib().drg_layout(ctx.h, C.byref(g), C.byref(params),
+                            _dev(y_out, torch.float32, "y_out", (g.n, 2))))

@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every entry point its header declares.
+CPU only: no call here reaches the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "drgraph.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(drg_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2008_07799_amd import drgraph
+    if not os.path.exists(drgraph.LIB_PATH):
+        from paper_2008_07799_amd import build
+        build.build()
+    return drgraph.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("drg_build_similarity", "drg_coarsen", "drg_layout_step", "drg_layout"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_defaults_and_argument_errors(lib):
+    from paper_2008_07799_amd import drgraph as d
+    p = d.layout_params()
+    assert (p.k, p.M, p.T, p.max_levels) == (1, 5, 400, 64)
+    assert abs(p.gamma - 0.1) < 1e-7 and abs(p.rho - 0.8) < 1e-12
+    assert lib.drg_layout_params_default(None) == d.DRG_E_INVALID
+    assert b"NULL" in lib.drg_last_error()
+    assert lib.drg_sim_info(None, None, None, None, None) == d.DRG_E_INVALID
+    assert lib.drg_hier_info(None, None, None) == d.DRG_E_INVALID
+    assert lib.drg_layout_step(None, None, None, None, None) == d.DRG_E_INVALID
+    assert lib.drg_ctx_create(0, None, None) == d.DRG_E_INVALID
+    # destroy calls are NULL-safe
+    lib.drg_sim_destroy(None)
+    lib.drg_hier_destroy(None)
+    lib.drg_ctx_destroy(None)
+    assert lib.drg_version().startswith(b"drgraph")
+
+
+def test_struct_layouts_match_header():
+    from paper_2008_07799_amd import drgraph as d
+    assert C.sizeof(d.Csr) == 24
+    assert C.sizeof(d.StepParams) == 48
+    assert C.sizeof(d.LayoutParams) == 72
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2008_07799_amd import drgraph as d
+    monkeypatch.setattr(d, "_lib", None)
+    monkeypatch.setattr(d, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        d.lib()
