@@ -138,10 +138,17 @@ def main():
     y = torch.zeros((g.n, 2), dtype=torch.float32, device="cuda")
 
     def step():
+        t = time.perf_counter()
         sim = d.drg_build_similarity(ctx, rp, col, cfg["k"])
+        print(f"[bench]   similarity nnz={sim.nnz} ({time.perf_counter() - t:.2f} s)",
+              file=sys.stderr, flush=True)
         hier = d.drg_coarsen(ctx, rp, col, seed=0, rho=0.8, min_nodes=cfg["min_nodes"],
                              max_levels=cfg["max_levels"])
+        print(f"[bench]   hierarchy {hier.sizes} ({time.perf_counter() - t:.2f} s)",
+              file=sys.stderr, flush=True)
         d.drg_layout_run(ctx, sim, hier, params, y)
+        print(f"[bench]   layout done ({time.perf_counter() - t:.2f} s)", file=sys.stderr,
+              flush=True)
         info = (sim.nnz, sim.n_active, hier.sizes)
         sim.close()
         hier.close()

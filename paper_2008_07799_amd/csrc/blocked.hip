@@ -1,0 +1,427 @@
+// blocked.hip -- column-blocked copy of P~ and the LDS-staged sweep.
+//
+// The attraction sweep reads one record (y_c(j), 1/Z_j) per stored pair.
+// On a large graph the records do not fit an L2 slice, and a random 16-byte
+// gather drags a whole cache line through the memory hierarchy.  Here the
+// columns are cut into blocks of BW = 2^bits nodes: a workgroup copies one
+// block's records into LDS (BW x 16 bytes, one contiguous read) and sweeps,
+// for a range of rows, the entries whose column falls in that block.  Those
+// entries are stored per block in row order as 16-bit words (block-local
+// column in the low 13 bits, hop-1 above), so the HBM stream is 2 bytes per
+// pair and every neighbour gather is an LDS read.  Each (block, row) pair
+// leaves a partial attraction; a second kernel adds the partials of a row in
+// block order (deterministic), draws the row's negatives and applies the step.
+#include <algorithm>
+#include <cstdlib>
+
+#include "drg_internal.hpp"
+
+namespace drg {
+
+constexpr int BLK_HOP_SHIFT = 13;
+constexpr int SWEEP_BLOCK = 512;
+
+// cnt[b*n + i] = number of entries of row i whose column lies in block b
+__global__ void k_blk_count(int32_t n, int32_t nb, int bits, const int64_t* __restrict__ prp,
+                            const uint32_t* __restrict__ ch, int32_t* __restrict__ cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * nb) return;
+    const int32_t i = (int32_t)(t % n);
+    const int32_t b = (int32_t)(t / n);
+    auto lb = [&](int64_t lo, int64_t hi, uint32_t key) {
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((ch[mid] & COL_MASK) < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return lo;
+    };
+    const int64_t rs = prp[i], re = prp[i + 1];
+    const int64_t s = lb(rs, re, (uint32_t)b << bits);
+    const int64_t e = lb(s, re, (uint32_t)(b + 1) << bits);
+    cnt[t] = (int32_t)(e - s);
+}
+
+__global__ void k_widen(int64_t m, const int32_t* __restrict__ a, int64_t* __restrict__ b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m) b[t] = a[t];
+}
+
+// off[b*(n+1) + i] = flat[b*n + i] - flat[b*n] for i <= n
+__global__ void k_blk_offsets(int32_t n, int32_t nb, const int64_t* __restrict__ flat,
+                              int64_t* __restrict__ base, int32_t* __restrict__ off) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)(n + 1) * nb) return;
+    const int32_t b = (int32_t)(t / (n + 1));
+    const int32_t i = (int32_t)(t % (n + 1));
+    const int64_t b0 = flat[(int64_t)b * n];
+    off[t] = (int32_t)(flat[(int64_t)b * n + i] - b0);
+    if (i == 0) base[b] = b0;
+    if (t == 0) base[nb] = flat[(int64_t)nb * n];
+}
+
+// one wave per row: for each block, copy the row's segment (coalesced)
+__global__ __launch_bounds__(256) void k_blk_fill(int32_t n, int32_t nb, int bits,
+                                                  const int64_t* __restrict__ prp,
+                                                  const uint32_t* __restrict__ ch,
+                                                  const int64_t* __restrict__ base,
+                                                  const int32_t* __restrict__ off,
+                                                  uint16_t* __restrict__ ent) {
+    const int lane = __lane_id();
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (row >= n) return;
+    const int32_t i = (int32_t)row;
+    const int64_t rs = prp[i], re = prp[i + 1];
+    const uint32_t mask = (1u << bits) - 1u;
+    int64_t s = rs;
+    for (int32_t b = 0; b < nb && s < re; ++b) {
+        const int64_t dst = base[b] + off[(int64_t)b * (n + 1) + i];
+        const int32_t len = off[(int64_t)b * (n + 1) + i + 1] - off[(int64_t)b * (n + 1) + i];
+        for (int32_t x = lane; x < len; x += WAVE) {
+            const uint32_t e = ch[s + x];
+            ent[dst + x] = (uint16_t)((e & mask) | ((e >> 30) << BLK_HOP_SHIFT));
+        }
+        s += len;
+    }
+}
+
+// Work items: block b's rows cut where the running cost (entries + rc per
+// row) crosses multiples of `chunk`; rc >= chunk / ROWCAP keeps every item
+// within ROWCAP rows.  item_first[b] = index of b's first item.
+constexpr int ROWCAP = 4096;
+
+__global__ void k_blk_items(int32_t n, int32_t nb, const int32_t* __restrict__ off,
+                            const int32_t* __restrict__ item_first, int64_t chunk, int64_t rc,
+                            int4* __restrict__ items) {
+    const int32_t b = blockIdx.y;
+    const int32_t first = item_first[b], cnt = item_first[b + 1] - first;
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cnt) return;
+    const int32_t* O = off + (int64_t)b * (n + 1);
+    auto row_at = [&](int64_t target) {  // first row i with O[i] + rc i >= target
+        int32_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)O[mid] + rc * (int64_t)mid < target)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return lo;
+    };
+    const int32_t r0 = c == 0 ? 0 : row_at((int64_t)c * chunk);
+    const int32_t r1 = c == cnt - 1 ? n : row_at((int64_t)(c + 1) * chunk);
+    items[first + c] = make_int4(b, r0, r1, 0);
+}
+
+struct BlockedArgs {
+    int32_t n0;
+    int32_t bits;
+    const int4* items;
+    const uint16_t* ent;
+    const int64_t* base;
+    const int32_t* off;
+    const float4* rec;
+    float2* partial;
+    float eh0, eh1, eh2, eh3;
+    float clip;
+};
+
+template <int B>
+__device__ __forceinline__ float blk_attract_coef(float d2) {
+    return -2.0f * (float)B * powi<B - 1>(d2) / (1.0f + powi<B>(d2));
+}
+template <int B>
+__device__ __forceinline__ float blk_repel_coef(float d2) {
+    return 2.0f * (float)B / (d2 * (1.0f + powi<B>(d2)));
+}
+
+template <int B>
+__device__ __forceinline__ void blk_pair(const BlockedArgs& a, const float4& ri, const float4* s_rec,
+                                         uint32_t u, uint32_t lmask, float& ax, float& ay) {
+    const float4 rj = s_rec[u & lmask];
+    const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+    const float d2 = dx * dx + dy * dy;
+    if (d2 > 0.0f) {
+        const uint32_t h = u >> BLK_HOP_SHIFT;
+        const float eh = h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
+        const float k = blk_attract_coef<B>(d2);
+        const float w = eh * (ri.z + rj.z);
+        ax += w * clampf(k * dx, a.clip);
+        ay += w * clampf(k * dy, a.clip);
+    }
+}
+
+// One workgroup per item (block b, rows r0..r1): the block's records and the
+// item's row offsets go to LDS; G lanes per row, U independent entry loads in
+// flight per lane.
+template <int B, int G>
+__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_blocked(BlockedArgs a) {
+    constexpr int U = 4;
+    extern __shared__ float4 s_dyn[];
+    const int32_t bw = 1 << a.bits;
+    float4* s_rec = s_dyn;
+    int32_t* s_off = reinterpret_cast<int32_t*>(s_dyn + bw);
+    const int4 it = a.items[blockIdx.x];
+    const int32_t b = it.x, r0 = it.y, r1 = it.z;
+    const int32_t j0 = b * bw;
+    const int32_t cnt = min(bw, a.n0 - j0);
+    const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
+    for (int32_t t = threadIdx.x; t < cnt; t += SWEEP_BLOCK) s_rec[t] = a.rec[j0 + t];
+    for (int32_t t = threadIdx.x; t <= r1 - r0; t += SWEEP_BLOCK) s_off[t] = O[r0 + t];
+    __syncthreads();
+    const int lane = threadIdx.x % G;
+    const int32_t gid = threadIdx.x / G;
+    constexpr int32_t NG = SWEEP_BLOCK / G;
+    const uint16_t* E = a.ent + a.base[b];
+    float2* P = a.partial + (int64_t)b * a.n0;
+    const uint32_t lmask = (uint32_t)bw - 1u;
+    for (int32_t i = r0 + gid; i < r1; i += NG) {
+        const int32_t s = s_off[i - r0], e = s_off[i - r0 + 1];
+        float ax = 0.0f, ay = 0.0f;
+        if (s < e) {
+            const float4 ri = a.rec[i];
+            int32_t x = s + lane;
+            for (; x + (U - 1) * G < e; x += U * G) {
+                uint32_t u[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) u[q] = E[x + q * G];
+#pragma unroll
+                for (int q = 0; q < U; ++q) blk_pair<B>(a, ri, s_rec, u[q], lmask, ax, ay);
+            }
+            for (; x < e; x += G) blk_pair<B>(a, ri, s_rec, E[x], lmask, ax, ay);
+            ax = group_sum<G>(ax);
+            ay = group_sum<G>(ay);
+        }
+        if (lane == 0) P[i] = make_float2(ax, ay);
+    }
+}
+
+struct FinishArgs {
+    int32_t n0, nb, M;
+    const int64_t* prp;
+    const float2* partial;
+    const float4* rec;
+    const float* qt;
+    const uint64_t* C;
+    const int32_t* guide;
+    int32_t gbits;
+    uint64_t S;
+    float gamma, clip, eta;
+    uint64_t seed, iter;
+    float2* g;   // coarse levels: one-sided steps
+    float2* y;   // level 0: coordinates, updated in place
+};
+
+// One thread per finest node: partials in block order, M negatives, step.
+template <int B>
+__global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n0) return;
+    float gx = 0.0f, gy = 0.0f;
+    const bool active = a.prp[i + 1] > a.prp[i];
+    if (active) {
+        float ax = 0.0f, ay = 0.0f;
+        for (int32_t b = 0; b < a.nb; ++b) {
+            const float2 p = a.partial[(int64_t)b * a.n0 + i];
+            ax += p.x;
+            ay += p.y;
+        }
+        const float4 ri = a.rec[i];
+        float rx = 0.0f, ry = 0.0f;
+        for (int m = 0; m < a.M; ++m) {
+            const uint64_t w = neg_word(a.seed, a.iter, (int32_t)i, m);
+            const int32_t v = draw_node(w, a.C, a.guide, a.gbits, a.S);
+            const float4 rv = a.rec[v];
+            const float dx = ri.x - rv.x, dy = ri.y - rv.y;
+            const float d2 = dx * dx + dy * dy;
+            if (d2 > 0.0f) {
+                const float k = blk_repel_coef<B>(d2);
+                rx += clampf(k * dx, a.clip);
+                ry += clampf(k * dy, a.clip);
+            }
+        }
+        const float gq = a.gamma * a.qt[i];
+        gx = ax + gq * rx;
+        gy = ay + gq * ry;
+    }
+    if (a.g) {
+        a.g[i] = make_float2(gx, gy);
+    } else if (active) {
+        const float w = a.qt[i];
+        float2 p = a.y[i];
+        p.x += a.eta * (gx / w);
+        p.y += a.eta * (gy / w);
+        a.y[i] = p;
+    }
+}
+
+// ------------------------------------------------------------------ host
+static int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+bool blocked_wanted(drg_ctx* ctx, const drg_sim* s) {
+    const int force = env_int("DRG_SWEEP_BLOCKED", -1);  // 1 force on, 0 force off
+    if (force == 0) return false;
+    const int bits = std::min(13, std::max(6, env_int("DRG_BLOCK_BITS", 13)));
+    if ((int64_t)(16u << bits) + 4 * (ROWCAP + 1) + 1024 > (int64_t)ctx->max_lds) return false;
+    if (force == 1) return s->nnz > 0;
+    const int64_t nb = ((int64_t)s->n + (1 << bits) - 1) >> bits;
+    // records of at least half an L2 slice, and rows long enough to amortise
+    // the per-block partials
+    return (int64_t)s->n * 16 >= ((int64_t)2 << 20) && s->nnz > 32 * nb * (int64_t)s->n;
+}
+
+void build_blocked(drg_ctx* ctx, drg_sim* s) {
+    hipStream_t st = ctx->stream;
+    const int bits = std::min(13, std::max(6, env_int("DRG_BLOCK_BITS", 13)));
+    const int32_t n = s->n;
+    const int32_t nb = (int32_t)(((int64_t)n + (1 << bits) - 1) >> bits);
+    if ((int64_t)n * nb >= ((int64_t)1 << 40)) throw Error(DRG_E_UNSUPPORTED, "too many blocks");
+    DevBuf<int32_t> cnt((int64_t)n * nb);
+    hipLaunchKernelGGL(k_blk_count, dim3(ceil_div((int64_t)n * nb, 256)), dim3(256), 0, st, n, nb,
+                       bits, s->row_ptr.get(), s->colhop.get(), cnt.get());
+    DRG_LAUNCH_CHECK();
+    // per-block entry counts must fit 32-bit offsets
+    DevBuf<int64_t> flat((int64_t)n * nb + 1);
+    {
+        DevBuf<int64_t> cnt64((int64_t)n * nb);
+        hipLaunchKernelGGL(k_widen, dim3(ceil_div((int64_t)n * nb, 256)), dim3(256), 0, st,
+                           (int64_t)n * nb, cnt.get(), cnt64.get());
+        DRG_LAUNCH_CHECK();
+        exclusive_scan<int64_t>(cnt64.get(), flat.get(), (int64_t)n * nb, st);
+    }
+    cnt.reset();
+    s->blk_base.alloc(nb + 1);
+    s->blk_off.alloc((int64_t)(n + 1) * nb);
+    hipLaunchKernelGGL(k_blk_offsets, dim3(ceil_div((int64_t)(n + 1) * nb, 256)), dim3(256), 0, st,
+                       n, nb, flat.get(), s->blk_base.get(), s->blk_off.get());
+    DRG_LAUNCH_CHECK();
+    std::vector<int64_t> base(nb + 1);
+    DRG_HIP(hipMemcpyAsync(base.data(), s->blk_base.get(), sizeof(int64_t) * (nb + 1),
+                           hipMemcpyDeviceToHost, st));
+    DRG_HIP(hipStreamSynchronize(st));
+    flat.reset();
+    for (int32_t b = 0; b < nb; ++b)
+        if (base[b + 1] - base[b] >= ((int64_t)1 << 31))
+            throw Error(DRG_E_UNSUPPORTED, "column block too large for 32-bit offsets");
+    s->blk_ent.alloc(std::max<int64_t>(1, s->nnz));
+    hipLaunchKernelGGL(k_blk_fill, dim3(ceil_div((int64_t)n * WAVE, 256)), dim3(256), 0, st, n,
+                       nb, bits, s->row_ptr.get(), s->colhop.get(), s->blk_base.get(),
+                       s->blk_off.get(), s->blk_ent.get());
+    DRG_LAUNCH_CHECK();
+    // work items: about `chunk` units of work each (entries + rc per row),
+    // at most ROWCAP rows each
+    const int64_t want_items = std::max<int64_t>((int64_t)ctx->num_cu * 16, nb);
+    const int64_t chunk =
+        std::max<int64_t>(1 << 16, (s->nnz + 16 * (int64_t)n * nb) / want_items);
+    const int64_t rc = std::max<int64_t>(16, (chunk + ROWCAP - 1) / ROWCAP);
+    std::vector<int32_t> first(nb + 1);
+    first[0] = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int64_t cost = (base[b + 1] - base[b]) + rc * (int64_t)n;
+        first[b + 1] = first[b] + (int32_t)std::max<int64_t>(1, (cost + chunk - 1) / chunk);
+    }
+    DevBuf<int32_t> dfirst(nb + 1);
+    DRG_HIP(hipMemcpyAsync(dfirst.get(), first.data(), sizeof(int32_t) * (nb + 1),
+                           hipMemcpyHostToDevice, st));
+    s->blk_items.alloc(first[nb]);
+    int32_t maxcnt = 0;
+    for (int32_t b = 0; b < nb; ++b) maxcnt = std::max(maxcnt, first[b + 1] - first[b]);
+    hipLaunchKernelGGL(k_blk_items, dim3(ceil_div(maxcnt, 64), nb), dim3(64), 0, st, n, nb,
+                       s->blk_off.get(), dfirst.get(), chunk, rc, s->blk_items.get());
+    DRG_LAUNCH_CHECK();
+    {
+        std::vector<int4> hitems(first[nb]);
+        DRG_HIP(hipMemcpyAsync(hitems.data(), s->blk_items.get(), sizeof(int4) * first[nb],
+                               hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+        for (const int4& it : hitems)
+            if (it.z - it.y > ROWCAP || it.y < 0 || it.z > n || it.z < it.y)
+                throw Error(DRG_E_DEVICE, "blocked sweep: work item outside its row window");
+    }
+    s->blk_partial.alloc((int64_t)n * nb);
+    s->blk_nb = nb;
+    s->blk_bits = bits;
+    s->blk_nitems = first[nb];
+    DRG_HIP(hipStreamSynchronize(st));
+}
+
+template <int B, int G>
+static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
+    const size_t lds = ((size_t)16 << a.bits) + 4 * (ROWCAP + 1);
+    auto fn = k_sweep_blocked<B, G>;
+    DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL(fn, dim3(nitems), dim3(SWEEP_BLOCK), lds, ctx->stream, a);
+    DRG_LAUNCH_CHECK();
+}
+
+// The sweep and finish of one synchronous FP32 iteration on the blocked
+// layout.  `g` non-null: write the steps (coarse level); else update y.
+void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip, float eta,
+                   uint64_t seed, uint64_t iter, float2* g, float2* y, hipEvent_t e0,
+                   hipEvent_t e1) {
+    BlockedArgs a{};
+    a.n0 = s->n;
+    a.bits = s->blk_bits;
+    a.items = s->blk_items.get();
+    a.ent = s->blk_ent.get();
+    a.base = s->blk_base.get();
+    a.off = s->blk_off.get();
+    a.rec = s->rec.get();
+    a.partial = s->blk_partial.get();
+    a.eh0 = (float)(0.5 * s->e[0]);
+    a.eh1 = (float)(0.5 * s->e[1]);
+    a.eh2 = (float)(0.5 * s->e[2]);
+    a.eh3 = (float)(0.5 * s->e[3]);
+    a.clip = clip;
+    const double seg = (double)s->nnz / ((double)std::max(1, s->n_active) * s->blk_nb);
+    const int G = seg <= 24 ? 16 : (seg <= 96 ? 32 : 64);
+    if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));
+#define DRG_BLK(BB)                                                                \
+    case BB:                                                                       \
+        if (G == 16) launch_blocked_b<BB, 16>(ctx, a, s->blk_nitems);              \
+        else if (G == 32) launch_blocked_b<BB, 32>(ctx, a, s->blk_nitems);         \
+        else launch_blocked_b<BB, 64>(ctx, a, s->blk_nitems);                      \
+        break;
+    switch (b) {
+        DRG_BLK(1)
+        DRG_BLK(2)
+        default:
+        DRG_BLK(3)
+    }
+#undef DRG_BLK
+    if (e1) DRG_HIP(hipEventRecord(e1, ctx->stream));
+    FinishArgs f{};
+    f.n0 = s->n;
+    f.nb = s->blk_nb;
+    f.M = s->S > 0 ? M : 0;
+    f.prp = s->row_ptr.get();
+    f.partial = s->blk_partial.get();
+    f.rec = s->rec.get();
+    f.qt = s->qtf.get();
+    f.C = s->C.get();
+    f.guide = s->guide.get();
+    f.gbits = s->gbits;
+    f.S = s->S;
+    f.gamma = gamma;
+    f.clip = clip;
+    f.eta = eta;
+    f.seed = seed;
+    f.iter = iter;
+    f.g = g;
+    f.y = y;
+    switch (b) {
+        case 1: hipLaunchKernelGGL(k_finish<1>, dim3(ceil_div(s->n, 256)), dim3(256), 0, ctx->stream, f); break;
+        case 2: hipLaunchKernelGGL(k_finish<2>, dim3(ceil_div(s->n, 256)), dim3(256), 0, ctx->stream, f); break;
+        default: hipLaunchKernelGGL(k_finish<3>, dim3(ceil_div(s->n, 256)), dim3(256), 0, ctx->stream, f); break;
+    }
+    DRG_LAUNCH_CHECK();
+}
+
+}  // namespace drg

@@ -41,6 +41,13 @@ struct drg_sim {
     drg::DevBuf<float> wlev;         // [n] anchor weights of level nodes (async)
     drg::DevBuf<double4> rec64;      // FP64 instance workspace (allocated on use)
     drg::DevBuf<double2> g64;
+    // column-blocked copy of the pattern for the LDS-staged sweep (blk_nb > 0)
+    int32_t blk_nb = 0, blk_bits = 0, blk_nitems = 0;
+    drg::DevBuf<int64_t> blk_base;   // [nb+1] first entry of each block
+    drg::DevBuf<int32_t> blk_off;    // [nb][n+1] row offsets inside a block
+    drg::DevBuf<uint16_t> blk_ent;   // [nnz] local col | (hop-1) << 13
+    drg::DevBuf<int4> blk_items;     // (block, first row, end row)
+    drg::DevBuf<float2> blk_partial; // [nb][n] partial attraction
 };
 
 struct drg_level {
@@ -67,6 +74,12 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
 void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,
                 double* qt, uint64_t* W, double* e, double* invZ);
+// blocked.hip
+bool blocked_wanted(drg_ctx* ctx, const drg_sim* s);
+void build_blocked(drg_ctx* ctx, drg_sim* s);
+void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip, float eta,
+                   uint64_t seed, uint64_t iter, float2* g, float2* y, hipEvent_t e0,
+                   hipEvent_t e1);
 // coarsen.hip
 drg_hier* build_hierarchy(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho,
                           int min_nodes, int max_levels);

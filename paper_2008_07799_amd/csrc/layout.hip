@@ -147,9 +147,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
         if (rs < re) {
             const typename VT<T>::v4 ri = a.rec[i];
             T ax = T(0), ay = T(0);
-            for (int64_t x = rs + lane; x < re; x += G) {
-                const uint32_t e = a.colhop[x];
-                const typename VT<T>::v4 rj = a.rec[e & COL_MASK];
+            auto pair = [&](uint32_t e, const typename VT<T>::v4& rj) {
                 const T dx = ri.x - rj.x, dy = ri.y - rj.y;
                 const T d2 = dx * dx + dy * dy;
                 if (d2 > T(0)) {
@@ -158,6 +156,22 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
                     ax += w * clampT(k * dx, a.clip);
                     ay += w * clampT(k * dy, a.clip);
                 }
+            };
+            constexpr int U = 4;  // independent entry loads and gathers in flight
+            int64_t x = rs + lane;
+            for (; x + (U - 1) * G < re; x += U * G) {
+                uint32_t e[U];
+                typename VT<T>::v4 rj[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) e[q] = a.colhop[x + q * G];
+#pragma unroll
+                for (int q = 0; q < U; ++q) rj[q] = a.rec[e[q] & COL_MASK];
+#pragma unroll
+                for (int q = 0; q < U; ++q) pair(e[q], rj[q]);
+            }
+            for (; x < re; x += G) {
+                const uint32_t e = a.colhop[x];
+                pair(e, a.rec[e & COL_MASK]);
             }
             T rx = T(0), ry = T(0);
             for (int m = lane; m < a.M; m += G) {
@@ -454,8 +468,33 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     if (ctx->profiling) {
         DRG_HIP(hipEventCreate(&e0));
         DRG_HIP(hipEventCreate(&e1));
-        DRG_HIP(hipEventRecord(e0, st));
     }
+    if constexpr (F32) {
+        if (!async && s->blk_nb > 0) {
+            // LDS-staged sweep over the column-blocked pattern; at level 0 the
+            // finishing kernel applies the step itself
+            sweep_blocked(ctx, s, p->b, a.M, a.gamma, a.clip, a.eta, a.seed, a.iter,
+                          level == 0 ? nullptr : g, level == 0 ? reinterpret_cast<v2*>(y) : nullptr,
+                          e0, e1);
+            if (ctx->profiling) ctx->events.emplace_back(e0, e1);
+            if (level > 0) {
+                const drg_level& L = h->lv[level];
+                const double mean = (double)n0 / (double)std::max(1, nl);
+                if (mean <= 16)
+                    hipLaunchKernelGGL((k_apply_level<T, 8>), dim3(ceil_div((int64_t)nl * 8, 256)),
+                                       dim3(256), 0, st, nl, L.seg.get(), L.perm.get(), g, qt,
+                                       reinterpret_cast<v2*>(y), (T)p->eta);
+                else
+                    hipLaunchKernelGGL((k_apply_level<T, 32>),
+                                       dim3(ceil_div((int64_t)nl * 32, 256)), dim3(256), 0, st,
+                                       nl, L.seg.get(), L.perm.get(), g, qt,
+                                       reinterpret_cast<v2*>(y), (T)p->eta);
+                DRG_LAUNCH_CHECK();
+            }
+            return;
+        }
+    }
+    if (ctx->profiling) DRG_HIP(hipEventRecord(e0, st));
     switch (p->b) {
         case 1: launch_sweep<T, 1>(st, a, G, async); break;
         case 2: launch_sweep<T, 2>(st, a, G, async); break;

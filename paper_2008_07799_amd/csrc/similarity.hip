@@ -539,6 +539,7 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     s->rec.alloc(n);
     s->g.alloc(n);
     DRG_HIP(hipStreamSynchronize(st));
+    if (blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
     return s.release();
 }
 
