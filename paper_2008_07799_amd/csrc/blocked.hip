@@ -19,7 +19,6 @@
 namespace drg {
 
 constexpr int BLK_HOP_SHIFT = 13;
-constexpr int SWEEP_BLOCK = 512;
 
 // cnt[b*n + i] = number of entries of row i whose column lies in block b
 __global__ void k_blk_count(int32_t n, int32_t nb, int bits, const int64_t* __restrict__ prp,
@@ -135,31 +134,41 @@ __device__ __forceinline__ float blk_attract_coef(float d2) {
 }
 template <int B>
 __device__ __forceinline__ float blk_repel_coef(float d2) {
-    return 2.0f * (float)B / (d2 * (1.0f + powi<B>(d2)));
+    return 2.0f * (float)B * rcp_fast(d2 * (1.0f + powi<B>(d2)));
 }
 
+// Attraction of one stored pair.  No zero-distance test is needed: a zero
+// offset gives a zero force through dx = dy = 0.
 template <int B>
 __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const float4& ri, const float4* s_rec,
                                          uint32_t u, uint32_t lmask, float& ax, float& ay) {
     const float4 rj = s_rec[u & lmask];
     const float dx = ri.x - rj.x, dy = ri.y - rj.y;
     const float d2 = dx * dx + dy * dy;
-    if (d2 > 0.0f) {
-        const uint32_t h = u >> BLK_HOP_SHIFT;
-        const float eh = h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
-        const float k = blk_attract_coef<B>(d2);
-        const float w = eh * (ri.z + rj.z);
-        ax += w * clampf(k * dx, a.clip);
-        ay += w * clampf(k * dy, a.clip);
-    }
+    const uint32_t h = u >> BLK_HOP_SHIFT;
+    const float eh = (h & 2u) ? ((h & 1u) ? a.eh3 : a.eh2) : ((h & 1u) ? a.eh1 : a.eh0);
+    const float k = -2.0f * (float)B * powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
+    const float w = eh * (ri.z + rj.z);
+    ax += w * clampf(k * dx, a.clip);
+    ay += w * clampf(k * dy, a.clip);
 }
 
 // One workgroup per item (block b, rows r0..r1): the block's records and the
-// item's row offsets go to LDS; G lanes per row, U independent entry loads in
-// flight per lane.
-template <int B, int G>
-__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_blocked(BlockedArgs a) {
-    constexpr int U = 4;
+// item's row offsets go to LDS.  One wave per row segment; lane l reads the
+// aligned 16-byte chunk (8 entries) c0 + l of the segment, so a wave moves up
+// to 1 KB per load instruction, and the chunk of the wave's next row is
+// requested before the current row is processed.  Lane sums run in a fixed
+// order and the wave reduction is fixed, so the result is repeatable.
+constexpr int STREAM_BLOCK = 1024;
+constexpr int STREAM_WAVES = STREAM_BLOCK / WAVE;
+
+__device__ __forceinline__ uint32_t half16(const uint4& v, int q) {
+    const uint32_t w = q < 2 ? v.x : (q < 4 ? v.y : (q < 6 ? v.z : v.w));
+    return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+template <int B>
+__global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     extern __shared__ float4 s_dyn[];
     const int32_t bw = 1 << a.bits;
     float4* s_rec = s_dyn;
@@ -169,33 +178,57 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     const int32_t j0 = b * bw;
     const int32_t cnt = min(bw, a.n0 - j0);
     const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
-    for (int32_t t = threadIdx.x; t < cnt; t += SWEEP_BLOCK) s_rec[t] = a.rec[j0 + t];
-    for (int32_t t = threadIdx.x; t <= r1 - r0; t += SWEEP_BLOCK) s_off[t] = O[r0 + t];
+    for (int32_t t = threadIdx.x; t < cnt; t += STREAM_BLOCK) s_rec[t] = a.rec[j0 + t];
+    for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
     __syncthreads();
-    const int lane = threadIdx.x % G;
-    const int32_t gid = threadIdx.x / G;
-    constexpr int32_t NG = SWEEP_BLOCK / G;
-    const uint16_t* E = a.ent + a.base[b];
+    const int lane = __lane_id();
+    const int32_t wid = threadIdx.x / WAVE;
+    const int64_t bbase = a.base[b];
+    const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
     float2* P = a.partial + (int64_t)b * a.n0;
     const uint32_t lmask = (uint32_t)bw - 1u;
-    for (int32_t i = r0 + gid; i < r1; i += NG) {
-        const int32_t s = s_off[i - r0], e = s_off[i - r0 + 1];
+    // chunk of row r for this lane (first window), zero when outside
+    auto fetch = [&](int32_t r, int64_t& As, int64_t& Ae, uint4& v) {
+        As = bbase + s_off[r - r0];
+        Ae = bbase + s_off[r - r0 + 1];
+        const int64_t c = (As >> 3) + lane;
+        v = (As < Ae && c * 8 < Ae) ? E4[c] : make_uint4(0, 0, 0, 0);
+    };
+    int32_t r = r0 + wid;
+    int64_t As = 0, Ae = 0;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (r < r1) fetch(r, As, Ae, v);
+    for (; r < r1; r += STREAM_WAVES) {
+        // request the next row's first chunk now
+        const int32_t rn = r + STREAM_WAVES;
+        int64_t Asn = 0, Aen = 0;
+        uint4 vn = make_uint4(0, 0, 0, 0);
+        if (rn < r1) fetch(rn, Asn, Aen, vn);
         float ax = 0.0f, ay = 0.0f;
-        if (s < e) {
-            const float4 ri = a.rec[i];
-            int32_t x = s + lane;
-            for (; x + (U - 1) * G < e; x += U * G) {
-                uint32_t u[U];
+        if (As < Ae) {
+            const float4 ri = a.rec[r];
+            int64_t c = (As >> 3) + lane;
+            uint4 cur = v;
+            while (true) {
+                if (c * 8 < Ae) {
 #pragma unroll
-                for (int q = 0; q < U; ++q) u[q] = E[x + q * G];
-#pragma unroll
-                for (int q = 0; q < U; ++q) blk_pair<B>(a, ri, s_rec, u[q], lmask, ax, ay);
+                    for (int q = 0; q < 8; ++q) {
+                        const int64_t idx = c * 8 + q;
+                        if (idx >= As && idx < Ae)
+                            blk_pair<B>(a, ri, s_rec, half16(cur, q), lmask, ax, ay);
+                    }
+                }
+                c += WAVE;
+                if ((c - lane) * 8 >= Ae) break;  // wave-uniform: window past the end
+                cur = c * 8 < Ae ? E4[c] : make_uint4(0, 0, 0, 0);
             }
-            for (; x < e; x += G) blk_pair<B>(a, ri, s_rec, E[x], lmask, ax, ay);
-            ax = group_sum<G>(ax);
-            ay = group_sum<G>(ay);
+            ax = group_sum<WAVE>(ax);
+            ay = group_sum<WAVE>(ay);
         }
-        if (lane == 0) P[i] = make_float2(ax, ay);
+        if (lane == 0) P[r] = make_float2(ax, ay);
+        As = Asn;
+        Ae = Aen;
+        v = vn;
     }
 }
 
@@ -239,8 +272,8 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
                 const float k = blk_repel_coef<B>(d2);
-                rx += clampf(k * dx, a.clip);
-                ry += clampf(k * dy, a.clip);
+                rx += repel_component(k, dx, a.clip);
+                ry += repel_component(k, dy, a.clip);
             }
         }
         const float gq = a.gamma * a.qt[i];
@@ -309,7 +342,8 @@ void build_blocked(drg_ctx* ctx, drg_sim* s) {
     for (int32_t b = 0; b < nb; ++b)
         if (base[b + 1] - base[b] >= ((int64_t)1 << 31))
             throw Error(DRG_E_UNSUPPORTED, "column block too large for 32-bit offsets");
-    s->blk_ent.alloc(std::max<int64_t>(1, s->nnz));
+    s->blk_ent.alloc(s->nnz + 8);  // 16-byte chunk reads may run 7 entries past the end
+    DRG_HIP(hipMemsetAsync(s->blk_ent.get(), 0, sizeof(uint16_t) * (s->nnz + 8), st));
     hipLaunchKernelGGL(k_blk_fill, dim3(ceil_div((int64_t)n * WAVE, 256)), dim3(256), 0, st, n,
                        nb, bits, s->row_ptr.get(), s->colhop.get(), s->blk_base.get(),
                        s->blk_off.get(), s->blk_ent.get());
@@ -351,13 +385,13 @@ void build_blocked(drg_ctx* ctx, drg_sim* s) {
     DRG_HIP(hipStreamSynchronize(st));
 }
 
-template <int B, int G>
+template <int B>
 static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
     const size_t lds = ((size_t)16 << a.bits) + 4 * (ROWCAP + 1);
-    auto fn = k_sweep_blocked<B, G>;
+    auto fn = k_sweep_blocked<B>;
     DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
-    hipLaunchKernelGGL(fn, dim3(nitems), dim3(SWEEP_BLOCK), lds, ctx->stream, a);
+    hipLaunchKernelGGL(fn, dim3(nitems), dim3(STREAM_BLOCK), lds, ctx->stream, a);
     DRG_LAUNCH_CHECK();
 }
 
@@ -380,22 +414,12 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
     a.eh2 = (float)(0.5 * s->e[2]);
     a.eh3 = (float)(0.5 * s->e[3]);
     a.clip = clip;
-    const double seg = (double)s->nnz / ((double)std::max(1, s->n_active) * s->blk_nb);
-    const int G = seg <= 24 ? 16 : (seg <= 96 ? 32 : 64);
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));
-#define DRG_BLK(BB)                                                                \
-    case BB:                                                                       \
-        if (G == 16) launch_blocked_b<BB, 16>(ctx, a, s->blk_nitems);              \
-        else if (G == 32) launch_blocked_b<BB, 32>(ctx, a, s->blk_nitems);         \
-        else launch_blocked_b<BB, 64>(ctx, a, s->blk_nitems);                      \
-        break;
     switch (b) {
-        DRG_BLK(1)
-        DRG_BLK(2)
-        default:
-        DRG_BLK(3)
+        case 1: launch_blocked_b<1>(ctx, a, s->blk_nitems); break;
+        case 2: launch_blocked_b<2>(ctx, a, s->blk_nitems); break;
+        default: launch_blocked_b<3>(ctx, a, s->blk_nitems); break;
     }
-#undef DRG_BLK
     if (e1) DRG_HIP(hipEventRecord(e1, ctx->stream));
     FinishArgs f{};
     f.n0 = s->n;

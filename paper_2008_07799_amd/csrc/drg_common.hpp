@@ -152,7 +152,18 @@ __device__ __forceinline__ T block_sum(T v, T* sbuf) {
     return tot;
 }
 
-__device__ __forceinline__ float clampf(float v, float c) { return fminf(fmaxf(v, -c), c); }
+__device__ __forceinline__ float clampf(float v, float c) {
+    return __builtin_amdgcn_fmed3f(v, -c, c);  // one v_med3_f32
+}
+
+// 1/x with the hardware reciprocal (v_rcp_f32, 1 ulp).
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Clipped repulsion component k*d.  The coefficient can overflow to inf for
+// a pair at an underflowing distance; a zero component then stays zero.
+__device__ __forceinline__ float repel_component(float k, float d, float c) {
+    return d == 0.0f ? 0.0f : clampf(k * d, c);
+}
 
 template <int B>
 __device__ __forceinline__ float powi(float x) {

@@ -66,14 +66,37 @@ __device__ __forceinline__ T powT(T x) {
     else return x * x * x;
 }
 
-// attraction coefficient -2b d^{2b-2}/(1+d^{2b}); repulsion 2b/(d^2 (1+d^{2b}))
+// attraction coefficient -2b d^{2b-2}/(1+d^{2b}); repulsion 2b/(d^2 (1+d^{2b}));
+// FP32 uses the hardware reciprocal, FP64 the correctly rounded division
+template <typename T>
+__device__ __forceinline__ T recipT(T x) {
+    if constexpr (std::is_same<T, float>::value) return rcp_fast(x);
+    else return T(1) / x;
+}
 template <int B, typename T>
 __device__ __forceinline__ T attract_coef(T d2) {
-    return T(-2 * B) * powT<B - 1>(d2) / (T(1) + powT<B>(d2));
+    if constexpr (std::is_same<T, float>::value)
+        return T(-2 * B) * powT<B - 1>(d2) * recipT(T(1) + powT<B>(d2));
+    else
+        return T(-2 * B) * powT<B - 1>(d2) / (T(1) + powT<B>(d2));
 }
 template <int B, typename T>
 __device__ __forceinline__ T repel_coef(T d2) {
-    return T(2 * B) / (d2 * (T(1) + powT<B>(d2)));
+    if constexpr (std::is_same<T, float>::value)
+        return T(2 * B) * recipT(d2 * (T(1) + powT<B>(d2)));
+    else
+        return T(2 * B) / (d2 * (T(1) + powT<B>(d2)));
+}
+
+template <typename T>
+__device__ __forceinline__ T clampT2(T v, T c) {
+    if constexpr (std::is_same<T, float>::value) return clampf(v, c);
+    else return v > c ? c : (v < -c ? -c : v);
+}
+template <typename T>
+__device__ __forceinline__ T repelT(T k, T d, T c) {
+    if constexpr (std::is_same<T, float>::value) return repel_component(k, d, c);
+    else return clampT2(k * d, c);
 }
 
 template <typename T>
@@ -153,8 +176,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
                 if (d2 > T(0)) {
                     const T k = attract_coef<B>(d2);
                     const T w = half_e(a, e >> 30) * (ri.z + rj.z);
-                    ax += w * clampT(k * dx, a.clip);
-                    ay += w * clampT(k * dy, a.clip);
+                    ax += w * clampT2(k * dx, a.clip);
+                    ay += w * clampT2(k * dy, a.clip);
                 }
             };
             constexpr int U = 4;  // independent entry loads and gathers in flight
@@ -182,8 +205,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
                 const T d2 = dx * dx + dy * dy;
                 if (d2 > T(0)) {
                     const T k = repel_coef<B>(d2);
-                    rx += clampT(k * dx, a.clip);
-                    ry += clampT(k * dy, a.clip);
+                    rx += repelT(k, dx, a.clip);
+                    ry += repelT(k, dy, a.clip);
                 }
             }
             ax = group_sum<G>(ax);
@@ -278,8 +301,8 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             if (d2 > 0.0f) {
                 const float k = attract_coef<B>(d2);
                 const float w = half_e(a, e >> 30) * (zi + a.invZ[j]);
-                ax += w * clampT(k * dx, a.clip);
-                ay += w * clampT(k * dy, a.clip);
+                ax += w * clampT2(k * dx, a.clip);
+                ay += w * clampT2(k * dy, a.clip);
             }
         }
         float rx = 0.0f, ry = 0.0f;
@@ -291,8 +314,8 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
                 const float k = repel_coef<B>(d2);
-                rx += clampT(k * dx, a.clip);
-                ry += clampT(k * dy, a.clip);
+                rx += repelT(k, dx, a.clip);
+                ry += repelT(k, dy, a.clip);
             }
         }
         ax = group_sum<G>(ax);
