@@ -51,16 +51,16 @@ WORKLOADS = {
 
 def _kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("layout.hip", "drg_common.hpp"):
+    for f in ("layout.hip", "blocked.hip", "drg_common.hpp"):
         with open(os.path.join(ROOT, "paper_2008_07799_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(workload: str, launches_bytes: float):
+def _traffic(workload: str, kernel: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if
     they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -115,7 +115,19 @@ def main():
     ap.add_argument("--workload", default="rmat20_k2", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="sync", choices=["sync", "async"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 8 times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_launch": n * 4, "launches": 8}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -149,7 +161,7 @@ def main():
         d.drg_layout_run(ctx, sim, hier, params, y)
         print(f"[bench]   layout done ({time.perf_counter() - t:.2f} s)", file=sys.stderr,
               flush=True)
-        info = (sim.nnz, sim.n_active, hier.sizes)
+        info = (sim.nnz, sim.n_active, hier.sizes, sim.blocked)
         sim.close()
         hier.close()
         return info
@@ -162,7 +174,7 @@ def main():
     t0 = time.perf_counter()
     for s in range(args.steps):
         print(f"[bench] timed step {s}", file=sys.stderr, flush=True)
-        nnz, n_active, sizes = step()
+        nnz, n_active, sizes, blocked = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, sweep_ms = ctx.kernel_stats()
@@ -174,6 +186,7 @@ def main():
     value = T * pairs / (ms_per_step / 1000.0)
     avg_ms = sweep_ms / max(1, launches)
     alg_bytes = 16.0 * nnz + 16.0 * M * n_active + 28.0 * n
+    kernel = "k_sweep_blocked" if blocked else "k_sweep"
     achieved = alg_bytes / (avg_ms / 1000.0) / 1e9
     rec = {
         "metric": "pair-updates/s + time-to-layout, 1M-node R-MAT; batched/autograd vs plain",
@@ -195,8 +208,8 @@ def main():
                    "iteration_sweep_pair_updates_per_s": pairs / (avg_ms / 1000.0)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic(args.workload, alg_bytes),
-                     "kernel": "k_sweep", "launches": launches, "avg_launch_ms": avg_ms,
+                     "traffic": _traffic(args.workload, kernel),
+                     "kernel": kernel, "launches": launches, "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:

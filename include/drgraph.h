@@ -126,9 +126,10 @@ drg_status drg_ctx_kernel_stats(drg_ctx* ctx, int64_t* launches, double* total_m
  * Synchronises.  The result lives in device memory owned by *out. */
 drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, double sigma,
                                 uint32_t flags, drg_sim** out);
-/* Host-side sizes (no synchronisation needed). */
+/* Host-side sizes (no synchronisation needed); *blocked (nullable) is 1 when
+ * the synchronous FP32 sweep runs over the column-blocked copy of P~. */
 drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_active,
-                        int32_t* k);
+                        int32_t* k, int32_t* blocked);
 /* Copies the similarity to host arrays (each nullable; synchronises):
  * row_ptr[n+1], col[nnz], hop[nnz] (1..k), P[nnz] (FP64 P~_ij), qt[n] (FP64),
  * W[n] (uint64 sampling weights), e[k] (FP64), invZ[n] (FP64). */

@@ -124,8 +124,8 @@ struct BlockedArgs {
     const int32_t* off;
     const float4* rec;
     float2* partial;
-    float eh0, eh1, eh2, eh3;
-    float clip;
+    float eh0, eh1, eh2, eh3;   // -2b * e_d / 2 per hop
+    float clip;                 // clip / (2b)
 };
 
 template <int B>
@@ -137,20 +137,30 @@ __device__ __forceinline__ float blk_repel_coef(float d2) {
     return 2.0f * (float)B * rcp_fast(d2 * (1.0f + powi<B>(d2)));
 }
 
-// Attraction of one stored pair.  No zero-distance test is needed: a zero
-// offset gives a zero force through dx = dy = 0.
-template <int B>
+// Attraction of one stored pair, scaled by `valid` (0 or 1) so a lane can
+// run all eight entries of its chunk without branching.  With the -2b factor
+// folded into the weight, -2b clip(p dx, c/(2b)) = clip(-2b p dx, c) because
+// the clip is odd.  A zero offset gives a zero force through dx = dy = 0.
+template <int B, int NH>
 __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const float4& ri, const float4* s_rec,
-                                         uint32_t u, uint32_t lmask, float& ax, float& ay) {
+                                         uint32_t u, uint32_t lmask, bool valid, float& ax,
+                                         float& ay) {
     const float4 rj = s_rec[u & lmask];
     const float dx = ri.x - rj.x, dy = ri.y - rj.y;
     const float d2 = dx * dx + dy * dy;
-    const uint32_t h = u >> BLK_HOP_SHIFT;
-    const float eh = (h & 2u) ? ((h & 1u) ? a.eh3 : a.eh2) : ((h & 1u) ? a.eh1 : a.eh0);
-    const float k = -2.0f * (float)B * powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
-    const float w = eh * (ri.z + rj.z);
-    ax += w * clampf(k * dx, a.clip);
-    ay += w * clampf(k * dy, a.clip);
+    float eh;
+    if constexpr (NH == 1) {
+        eh = a.eh0;
+    } else if constexpr (NH == 2) {
+        eh = (u >> BLK_HOP_SHIFT) ? a.eh1 : a.eh0;
+    } else {
+        const uint32_t h = u >> BLK_HOP_SHIFT;
+        eh = (h & 2u) ? ((h & 1u) ? a.eh3 : a.eh2) : ((h & 1u) ? a.eh1 : a.eh0);
+    }
+    const float p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
+    const float w = valid ? eh * (ri.z + rj.z) : 0.0f;
+    ax += w * clampf(p * dx, a.clip);
+    ay += w * clampf(p * dy, a.clip);
 }
 
 // One workgroup per item (block b, rows r0..r1): the block's records and the
@@ -167,7 +177,7 @@ __device__ __forceinline__ uint32_t half16(const uint4& v, int q) {
     return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
-template <int B>
+template <int B, int NH>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     extern __shared__ float4 s_dyn[];
     const int32_t bw = 1 << a.bits;
@@ -178,7 +188,8 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     const int32_t j0 = b * bw;
     const int32_t cnt = min(bw, a.n0 - j0);
     const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
-    for (int32_t t = threadIdx.x; t < cnt; t += STREAM_BLOCK) s_rec[t] = a.rec[j0 + t];
+    for (int32_t t = threadIdx.x; t < bw; t += STREAM_BLOCK)
+        s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
     __syncthreads();
     const int lane = __lane_id();
@@ -207,20 +218,19 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
         float ax = 0.0f, ay = 0.0f;
         if (As < Ae) {
             const float4 ri = a.rec[r];
-            int64_t c = (As >> 3) + lane;
+            const int32_t len = (int32_t)(Ae - As);
+            // rel: position of this lane's chunk start relative to the segment
+            int32_t rel = (int32_t)(((As >> 3) << 3) - As) + 8 * lane;
             uint4 cur = v;
             while (true) {
-                if (c * 8 < Ae) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int64_t idx = c * 8 + q;
-                        if (idx >= As && idx < Ae)
-                            blk_pair<B>(a, ri, s_rec, half16(cur, q), lmask, ax, ay);
-                    }
+                for (int q = 0; q < 8; ++q) {
+                    const bool valid = (uint32_t)(rel + q) < (uint32_t)len;
+                    blk_pair<B, NH>(a, ri, s_rec, half16(cur, q), lmask, valid, ax, ay);
                 }
-                c += WAVE;
-                if ((c - lane) * 8 >= Ae) break;  // wave-uniform: window past the end
-                cur = c * 8 < Ae ? E4[c] : make_uint4(0, 0, 0, 0);
+                rel += 8 * WAVE;
+                if (rel - 8 * lane >= len) break;  // wave-uniform: window past the end
+                cur = rel < len ? E4[((As + rel) >> 3)] : make_uint4(0, 0, 0, 0);
             }
             ax = group_sum<WAVE>(ax);
             ay = group_sum<WAVE>(ay);
@@ -385,10 +395,10 @@ void build_blocked(drg_ctx* ctx, drg_sim* s) {
     DRG_HIP(hipStreamSynchronize(st));
 }
 
-template <int B>
+template <int B, int NH>
 static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
     const size_t lds = ((size_t)16 << a.bits) + 4 * (ROWCAP + 1);
-    auto fn = k_sweep_blocked<B>;
+    auto fn = k_sweep_blocked<B, NH>;
     DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     hipLaunchKernelGGL(fn, dim3(nitems), dim3(STREAM_BLOCK), lds, ctx->stream, a);
@@ -409,17 +419,25 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
     a.off = s->blk_off.get();
     a.rec = s->rec.get();
     a.partial = s->blk_partial.get();
-    a.eh0 = (float)(0.5 * s->e[0]);
-    a.eh1 = (float)(0.5 * s->e[1]);
-    a.eh2 = (float)(0.5 * s->e[2]);
-    a.eh3 = (float)(0.5 * s->e[3]);
-    a.clip = clip;
+    a.eh0 = (float)(-b * s->e[0]);
+    a.eh1 = (float)(-b * s->e[1]);
+    a.eh2 = (float)(-b * s->e[2]);
+    a.eh3 = (float)(-b * s->e[3]);
+    a.clip = clip / (float)(2 * b);
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));
+#define DRG_BLK(BB)                                                                \
+    case BB:                                                                       \
+        if (s->k == 1) launch_blocked_b<BB, 1>(ctx, a, s->blk_nitems);             \
+        else if (s->k == 2) launch_blocked_b<BB, 2>(ctx, a, s->blk_nitems);        \
+        else launch_blocked_b<BB, 4>(ctx, a, s->blk_nitems);                       \
+        break;
     switch (b) {
-        case 1: launch_blocked_b<1>(ctx, a, s->blk_nitems); break;
-        case 2: launch_blocked_b<2>(ctx, a, s->blk_nitems); break;
-        default: launch_blocked_b<3>(ctx, a, s->blk_nitems); break;
+        DRG_BLK(1)
+        DRG_BLK(2)
+        default:
+        DRG_BLK(3)
     }
+#undef DRG_BLK
     if (e1) DRG_HIP(hipEventRecord(e1, ctx->stream));
     FinishArgs f{};
     f.n0 = s->n;

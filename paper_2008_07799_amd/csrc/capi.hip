@@ -155,9 +155,10 @@ drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, doubl
 }
 
 drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_active,
-                        int32_t* k) {
+                        int32_t* k, int32_t* blocked) {
     return guarded([&] {
         need(s, "sim");
+        if (blocked) *blocked = s->blk_nb > 0 ? 1 : 0;
         if (n) *n = s->n;
         if (nnz) *nnz = s->nnz;
         if (n_active) *n_active = s->n_active;

@@ -78,7 +78,7 @@ def lib():
         "drg_build_similarity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double, C.c_uint32,
                                   C.POINTER(_P)], st),
         "drg_sim_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
-                          C.POINTER(C.c_int32)], st),
+                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
         "drg_sim_export": ([_P] + [_P] * 8, st),
         "drg_sim_destroy": ([_P], None),
         "drg_coarsen": ([_P, C.POINTER(Csr), C.c_uint64, C.c_double, C.c_int32, C.c_int32,
@@ -181,8 +181,11 @@ class Similarity:
         nnz = C.c_int64()
         na = C.c_int32()
         k = C.c_int32()
-        _check(lib().drg_sim_info(h, C.byref(n), C.byref(nnz), C.byref(na), C.byref(k)))
+        blk = C.c_int32()
+        _check(lib().drg_sim_info(h, C.byref(n), C.byref(nnz), C.byref(na), C.byref(k),
+                                  C.byref(blk)))
         self.n, self.nnz, self.n_active, self.k = n.value, nnz.value, na.value, k.value
+        self.blocked = bool(blk.value)
 
     def close(self):
         if getattr(self, "h", None):

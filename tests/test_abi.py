@@ -43,7 +43,7 @@ def test_defaults_and_argument_errors(lib):
     assert abs(p.gamma - 0.1) < 1e-7 and abs(p.rho - 0.8) < 1e-12
     assert lib.drg_layout_params_default(None) == d.DRG_E_INVALID
     assert b"NULL" in lib.drg_last_error()
-    assert lib.drg_sim_info(None, None, None, None, None) == d.DRG_E_INVALID
+    assert lib.drg_sim_info(None, None, None, None, None, None) == d.DRG_E_INVALID
     assert lib.drg_hier_info(None, None, None) == d.DRG_E_INVALID
     assert lib.drg_layout_step(None, None, None, None, None) == d.DRG_E_INVALID
     assert lib.drg_ctx_create(0, None, None) == d.DRG_E_INVALID
