@@ -95,6 +95,15 @@ typedef struct {
     uint64_t seed;
 } drg_layout_params;
 
+/* Parameters of the sampled objective (Eq. objectfunction). */
+typedef struct {
+    int32_t M;               /* negatives per node, >= 0 */
+    int32_t b;               /* 1..3 */
+    double gamma;
+    uint64_t seed;
+    uint64_t iter;           /* keys the negatives like drg_layout_step */
+} drg_obj_params;
+
 const char* drg_last_error(void);
 const char* drg_version(void);
 
@@ -192,6 +201,39 @@ drg_status drg_prolong_f64(drg_ctx* ctx, const drg_hier* h, int32_t level,
                            const double* y_level_dev, double* y_finer_dev);
 drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                                const drg_step_params* p, double* y_level_dev);
+
+/* Sampled objective (Eq. objectfunction), the form used with an autograd
+ * system (Sec. 5: further cost terms can be added to the objective):
+ *   L^(Y) = sum_i sum_j P~_ij log w_ij + gamma sum_i qt_i sum_{m<M} log(1 - w_{i v_im})
+ * with w = 1/(1 + |y_i - y_j|^{2b}) and the negatives v_im of drg_layout_step
+ * for (seed, iter); a negative equal to its node or at distance 0 adds 0.
+ * y_dev: [n][2] finest-level coordinates.  loss_dev: one device scalar
+ * (the row values summed in a fixed order), or NULL; rows_dev: [n] the value
+ * of each row i (its attraction terms plus gamma qt_i times its negatives'
+ * terms), or NULL; not both NULL.  Synchronises.  No clipping (this is the
+ * objective, not the step). */
+drg_status drg_objective_fwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                             const float* y_dev, float* loss_dev, float* rows_dev);
+/* dy_dev[n][2] = dloss * dL^/dY (exact gradient of the sampled objective).
+ * The negatives are drawn again from their counters (nothing is stored by
+ * the forward); contributions to a drawn node are summed in a fixed order,
+ * so the result is deterministic.  dloss_dev: device scalar or NULL (= 1).
+ * Synchronises. */
+drg_status drg_objective_bwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                             const float* y_dev, const float* dloss_dev, float* dy_dev);
+/* FP64 instances (double coordinates, loss and gradient; FP64 P~ and qt). */
+drg_status drg_objective_fwd_f64(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                                 const double* y_dev, double* loss_dev, double* rows_dev);
+drg_status drg_objective_bwd_f64(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                                 const double* y_dev, const double* dloss_dev, double* dy_dev);
+/* The negatives of (seed, iter): out_dev[n][M] node ids, -1 for an isolated
+ * anchor.  For checks and for reference implementations. */
+drg_status drg_sample_negatives(drg_ctx* ctx, const drg_sim* s, int32_t M, uint64_t seed,
+                                uint64_t iter, int32_t* out_dev);
+/* P~ as device COO in CSR order (each pointer nullable): rows_dev[nnz],
+ * cols_dev[nnz], P_dev[nnz] (FP32, from the FP32 1/Z). */
+drg_status drg_sim_coo(drg_ctx* ctx, const drg_sim* s, int32_t* rows_dev, int32_t* cols_dev,
+                       float* P_dev);
 
 /* The whole schedule on a built similarity and hierarchy: random layout of the
  * coarsest level, T iterations split evenly over levels (the finest takes the

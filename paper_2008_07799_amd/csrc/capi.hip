@@ -284,6 +284,60 @@ drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h
     });
 }
 
+drg_status drg_objective_fwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                             const float* y_dev, float* loss_dev, float* rows_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::objective_fwd_t<float>(ctx, const_cast<drg_sim*>(s), p, y_dev, loss_dev, rows_dev);
+    });
+}
+
+drg_status drg_objective_bwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                             const float* y_dev, const float* dloss_dev, float* dy_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::objective_bwd_t<float>(ctx, const_cast<drg_sim*>(s), p, y_dev, dloss_dev, dy_dev);
+    });
+}
+
+drg_status drg_objective_fwd_f64(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                                 const double* y_dev, double* loss_dev, double* rows_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::objective_fwd_t<double>(ctx, const_cast<drg_sim*>(s), p, y_dev, loss_dev, rows_dev);
+    });
+}
+
+drg_status drg_objective_bwd_f64(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                                 const double* y_dev, const double* dloss_dev, double* dy_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::objective_bwd_t<double>(ctx, const_cast<drg_sim*>(s), p, y_dev, dloss_dev, dy_dev);
+    });
+}
+
+drg_status drg_sample_negatives(drg_ctx* ctx, const drg_sim* s, int32_t M, uint64_t seed,
+                                uint64_t iter, int32_t* out_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::sample_negatives(ctx, const_cast<drg_sim*>(s), M, seed, iter, out_dev);
+    });
+}
+
+drg_status drg_sim_coo(drg_ctx* ctx, const drg_sim* s, int32_t* rows_dev, int32_t* cols_dev,
+                       float* P_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::sim_coo(ctx, const_cast<drg_sim*>(s), rows_dev, cols_dev, P_dev);
+    });
+}
+
 static void check_layout_params(const drg_layout_params* p) {
     need(p, "params");
     if (p->T < 0) throw Error(DRG_E_INVALID, "T must be >= 0");

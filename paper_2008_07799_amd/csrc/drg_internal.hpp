@@ -80,6 +80,16 @@ void build_blocked(drg_ctx* ctx, drg_sim* s);
 void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip, float eta,
                    uint64_t seed, uint64_t iter, float2* g, float2* y, hipEvent_t e0,
                    hipEvent_t e1);
+// objective.hip
+template <typename T>
+void objective_fwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T* y, T* loss,
+                     T* rows);
+template <typename T>
+void objective_bwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T* y,
+                     const T* dloss, T* dy);
+void sample_negatives(drg_ctx* ctx, drg_sim* s, int32_t M, uint64_t seed, uint64_t iter,
+                      int32_t* out);
+void sim_coo(drg_ctx* ctx, drg_sim* s, int32_t* rows, int32_t* cols, float* P);
 // coarsen.hip
 drg_hier* build_hierarchy(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho,
                           int min_nodes, int max_levels);

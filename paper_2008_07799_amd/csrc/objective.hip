@@ -1,0 +1,432 @@
+// objective.hip -- the sampled objective L^ (Eq. objectfunction) and its
+// gradient, for use inside an autograd system, plus exports used to check
+// it (the drawn negatives, P~ as device COO).
+//
+//   L^(Y) = sum_i sum_j P~_ij log w_ij + gamma sum_i qt_i sum_{m<M} log(1 - w_{i v_im})
+//   log w = -log1p(d^{2b}),  log(1 - w) = b log d^2 - log1p(d^{2b})
+//
+// A negative equal to its anchor, or at distance 0, contributes nothing.
+// Gradient (unclipped): the attraction of row i appears in rows i and j with
+// the same P~ (symmetric), so it is twice row i's sum; the repulsion term of
+// (u, m) moves both u (own side) and v_um (other side).  The backward draws
+// every negative again from its counter; the other-side terms are grouped by
+// drawn node with a stable sort of (v, pair index) and summed in pair order,
+// so the gradient is deterministic.
+#include "drg_internal.hpp"
+
+namespace drg {
+
+template <typename T>
+struct OV;
+template <>
+struct OV<float> {
+    using v2 = float2;
+};
+template <>
+struct OV<double> {
+    using v2 = double2;
+};
+
+template <typename T>
+__device__ __forceinline__ typename OV<T>::v2 mk2o(T a, T b) {
+    typename OV<T>::v2 r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+
+template <int B, typename T>
+__device__ __forceinline__ T opow(T x) {
+    if constexpr (B == 0) return T(1);
+    else if constexpr (B == 1) return x;
+    else if constexpr (B == 2) return x * x;
+    else return x * x * x;
+}
+
+template <typename T>
+struct ObjArgs {
+    using v2 = typename OV<T>::v2;
+    int32_t n, M;
+    const int64_t* prp;
+    const uint32_t* colhop;
+    const T* invZ;
+    const T* qt;
+    const v2* y;
+    const uint64_t* C;
+    const int32_t* guide;
+    int32_t gbits;
+    uint64_t S;
+    T eh0, eh1, eh2, eh3;  // e_d / 2
+    T gamma;
+    uint64_t seed, iter;
+    const T* dloss;        // backward: scale (NULL = 1)
+    T* row_val;            // forward: per-row value
+    v2* dy;                // backward: gradient
+};
+
+template <typename T>
+__device__ __forceinline__ T oh(const ObjArgs<T>& a, uint32_t h) {
+    return h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
+}
+
+template <typename T>
+__device__ __forceinline__ T log1pT(T x) {
+    if constexpr (std::is_same<T, float>::value) return log1pf(x);
+    else return log1p(x);
+}
+template <typename T>
+__device__ __forceinline__ T logT(T x) {
+    if constexpr (std::is_same<T, float>::value) return logf(x);
+    else return log(x);
+}
+
+template <typename T, int B, int G>
+__global__ __launch_bounds__(256) void k_obj_rows(ObjArgs<T> a) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t i = grp; i < a.n; i += ngrp) {
+        const int64_t rs = a.prp[i], re = a.prp[i + 1];
+        T val = T(0);
+        if (rs < re) {
+            const typename OV<T>::v2 yi = a.y[i];
+            const T zi = a.invZ[i];
+            T att = T(0), rep = T(0);
+            for (int64_t x = rs + lane; x < re; x += G) {
+                const uint32_t e = a.colhop[x];
+                const int32_t j = (int32_t)(e & COL_MASK);
+                const typename OV<T>::v2 yj = a.y[j];
+                const T dx = yi.x - yj.x, dy = yi.y - yj.y;
+                const T d2 = dx * dx + dy * dy;
+                const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
+                att += p * (-log1pT(opow<B>(d2)));
+            }
+            for (int m = lane; m < a.M; m += G) {
+                const int32_t v =
+                    draw_node(neg_word(a.seed, a.iter, (int32_t)i, m), a.C, a.guide, a.gbits, a.S);
+                if (v == (int32_t)i) continue;
+                const typename OV<T>::v2 yv = a.y[v];
+                const T dx = yi.x - yv.x, dy = yi.y - yv.y;
+                const T d2 = dx * dx + dy * dy;
+                if (d2 > T(0)) rep += T(B) * logT(d2) - log1pT(opow<B>(d2));
+            }
+            att = group_sum<G>(att);
+            rep = group_sum<G>(rep);
+            val = att + a.gamma * a.qt[i] * rep;
+        }
+        if (lane == 0) a.row_val[i] = val;
+    }
+}
+
+// Sum of n values in a fixed order: block sums of 1024 then one block.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sum_blocks(int64_t n, const T* __restrict__ v,
+                                                     T* __restrict__ out) {
+    __shared__ T s[1024 / WAVE];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    T x = i < n ? v[i] : T(0);
+    x = block_sum<1024>(x, s);
+    if (threadIdx.x == 0) out[blockIdx.x] = x;
+}
+
+template <typename T, int B, int G>
+__global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    const T dl = a.dloss ? *a.dloss : T(1);
+    for (int64_t i = grp; i < a.n; i += ngrp) {
+        const int64_t rs = a.prp[i], re = a.prp[i + 1];
+        T gx = T(0), gy = T(0);
+        if (rs < re) {
+            const typename OV<T>::v2 yi = a.y[i];
+            const T zi = a.invZ[i];
+            T ax = T(0), ay = T(0), rx = T(0), ry = T(0);
+            for (int64_t x = rs + lane; x < re; x += G) {
+                const uint32_t e = a.colhop[x];
+                const int32_t j = (int32_t)(e & COL_MASK);
+                const typename OV<T>::v2 yj = a.y[j];
+                const T dx = yi.x - yj.x, dy = yi.y - yj.y;
+                const T d2 = dx * dx + dy * dy;
+                const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
+                const T k = p * T(-2 * B) * opow<B - 1>(d2) / (T(1) + opow<B>(d2));
+                ax += k * dx;
+                ay += k * dy;
+            }
+            for (int m = lane; m < a.M; m += G) {
+                const int32_t v =
+                    draw_node(neg_word(a.seed, a.iter, (int32_t)i, m), a.C, a.guide, a.gbits, a.S);
+                if (v == (int32_t)i) continue;
+                const typename OV<T>::v2 yv = a.y[v];
+                const T dx = yi.x - yv.x, dy = yi.y - yv.y;
+                const T d2 = dx * dx + dy * dy;
+                if (d2 > T(0)) {
+                    const T k = T(2 * B) / (d2 * (T(1) + opow<B>(d2)));
+                    rx += k * dx;
+                    ry += k * dy;
+                }
+            }
+            ax = group_sum<G>(ax);
+            ay = group_sum<G>(ay);
+            rx = group_sum<G>(rx);
+            ry = group_sum<G>(ry);
+            const T gq = a.gamma * a.qt[i];
+            gx = T(2) * ax + gq * rx;
+            gy = T(2) * ay + gq * ry;
+        }
+        if (lane == 0) a.dy[i] = mk2o<T>(dl * gx, dl * gy);
+    }
+}
+
+// key = drawn node (n for "none": inactive anchor or self draw), value = u*M+m
+__global__ void k_neg_keys(int32_t n, int32_t M, const int64_t* __restrict__ prp,
+                           const uint64_t* __restrict__ C, const int32_t* __restrict__ guide,
+                           int32_t gbits, uint64_t S, uint64_t seed, uint64_t iter,
+                           uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)n * M) return;
+    const int32_t u = (int32_t)(p / M), m = (int32_t)(p % M);
+    uint32_t key = (uint32_t)n;
+    if (prp[u + 1] > prp[u] && S > 0) {
+        const int32_t v = draw_node(neg_word(seed, iter, u, m), C, guide, gbits, S);
+        if (v != u) key = (uint32_t)v;
+    }
+    keys[p] = key;
+    vals[p] = (int32_t)p;
+}
+
+__global__ void k_key_bounds(int64_t np, int32_t n, const uint32_t* __restrict__ keys,
+                             int32_t* __restrict__ seg) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > n) return;
+    int64_t lo = 0, hi = np;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    seg[c] = (int32_t)lo;
+}
+
+// dy[v] += dl * sum over the pairs (u, m) that drew v, in pair order, of
+// gamma qt_u R(y_v - y_u)
+template <typename T, int B>
+__global__ void k_other_side(ObjArgs<T> a, const int32_t* __restrict__ seg,
+                             const int32_t* __restrict__ pairs) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.n) return;
+    const int32_t s = seg[v], e = seg[v + 1];
+    if (s == e) return;
+    const T dl = a.dloss ? *a.dloss : T(1);
+    const typename OV<T>::v2 yv = a.y[v];
+    T gx = T(0), gy = T(0);
+    for (int32_t x = s; x < e; ++x) {
+        const int32_t u = pairs[x] / a.M;
+        const typename OV<T>::v2 yu = a.y[u];
+        const T dx = yv.x - yu.x, dy = yv.y - yu.y;
+        const T d2 = dx * dx + dy * dy;
+        if (d2 > T(0)) {
+            const T k = a.gamma * a.qt[u] * T(2 * B) / (d2 * (T(1) + opow<B>(d2)));
+            gx += k * dx;
+            gy += k * dy;
+        }
+    }
+    typename OV<T>::v2 o = a.dy[v];
+    o.x += dl * gx;
+    o.y += dl * gy;
+    a.dy[v] = o;
+}
+
+__global__ void k_negatives(int32_t n, int32_t M, const int64_t* __restrict__ prp,
+                            const uint64_t* __restrict__ C, const int32_t* __restrict__ guide,
+                            int32_t gbits, uint64_t S, uint64_t seed, uint64_t iter,
+                            int32_t* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)n * M) return;
+    const int32_t u = (int32_t)(p / M), m = (int32_t)(p % M);
+    out[p] = (prp[u + 1] > prp[u] && S > 0)
+                 ? draw_node(neg_word(seed, iter, u, m), C, guide, gbits, S)
+                 : -1;
+}
+
+__global__ void k_coo(int32_t n, const int64_t* __restrict__ prp, const uint32_t* __restrict__ ch,
+                      const float* __restrict__ invZf, float eh0, float eh1, float eh2, float eh3,
+                      int32_t* __restrict__ rows, int32_t* __restrict__ cols,
+                      float* __restrict__ P) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int lane = __lane_id();
+    if (i >= n) return;
+    for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += WAVE) {
+        const uint32_t e = ch[x];
+        const int32_t j = (int32_t)(e & COL_MASK);
+        const uint32_t h = e >> 30;
+        const float eh = h == 0 ? eh0 : (h == 1 ? eh1 : (h == 2 ? eh2 : eh3));
+        if (rows) rows[x] = (int32_t)i;
+        if (cols) cols[x] = j;
+        if (P) P[x] = eh * (invZf[i] + invZf[j]);
+    }
+}
+
+// ------------------------------------------------------------------ host
+template <typename T>
+static ObjArgs<T> obj_args(drg_sim* s, const drg_obj_params* p, const T* y) {
+    ObjArgs<T> a{};
+    a.n = s->n;
+    a.M = s->S > 0 ? p->M : 0;
+    a.prp = s->row_ptr.get();
+    a.colhop = s->colhop.get();
+    if constexpr (std::is_same<T, float>::value) {
+        a.invZ = s->invZf.get();
+        a.qt = s->qtf.get();
+    } else {
+        a.invZ = s->invZ.get();
+        a.qt = s->qt.get();
+    }
+    a.y = reinterpret_cast<const typename OV<T>::v2*>(y);
+    a.C = s->C.get();
+    a.guide = s->guide.get();
+    a.gbits = s->gbits;
+    a.S = s->S;
+    a.eh0 = (T)(0.5 * s->e[0]);
+    a.eh1 = (T)(0.5 * s->e[1]);
+    a.eh2 = (T)(0.5 * s->e[2]);
+    a.eh3 = (T)(0.5 * s->e[3]);
+    a.gamma = (T)p->gamma;
+    a.seed = p->seed;
+    a.iter = p->iter;
+    return a;
+}
+
+static void check_obj(const drg_sim* s, const drg_obj_params* p, const void* y) {
+    if (!s || !p || !y) throw Error(DRG_E_INVALID, "objective: NULL argument");
+    if (p->M < 0 || p->b < 1 || p->b > 3) throw Error(DRG_E_INVALID, "objective: M >= 0, b in 1..3");
+}
+
+static int obj_group(const drg_sim* s) {
+    const double mean = (double)s->nnz / (double)std::max(1, s->n_active);
+    return mean <= 8 ? 8 : (mean <= 32 ? 32 : 64);
+}
+
+template <typename T, int B, int G>
+static void launch_obj(hipStream_t st, const ObjArgs<T>& a, bool grad) {
+    const int grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(((int64_t)a.n * G + 255) / 256, (int64_t)1 << 22));
+    if (grad)
+        hipLaunchKernelGGL((k_grad_rows<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_obj_rows<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+    DRG_LAUNCH_CHECK();
+}
+
+template <typename T, int B>
+static void launch_obj_g(hipStream_t st, const ObjArgs<T>& a, int G, bool grad) {
+    if (G == 8) launch_obj<T, B, 8>(st, a, grad);
+    else if (G == 32) launch_obj<T, B, 32>(st, a, grad);
+    else launch_obj<T, B, 64>(st, a, grad);
+}
+
+template <typename T>
+void objective_fwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T* y, T* loss,
+                     T* rows) {
+    check_obj(s, p, y);
+    if (!loss && !rows) throw Error(DRG_E_INVALID, "objective: loss and rows are NULL");
+    hipStream_t st = ctx->stream;
+    DevBuf<T> rv;
+    if (!rows) rv.alloc(s->n);
+    ObjArgs<T> a = obj_args<T>(s, p, y);
+    a.row_val = rows ? rows : rv.get();
+    const int G = obj_group(s);
+    switch (p->b) {
+        case 1: launch_obj_g<T, 1>(st, a, G, false); break;
+        case 2: launch_obj_g<T, 2>(st, a, G, false); break;
+        default: launch_obj_g<T, 3>(st, a, G, false); break;
+    }
+    if (!loss) {
+        DRG_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    // fixed-order reduction to one value
+    int64_t m = s->n;
+    DevBuf<T> buf1((m + 1023) / 1024), buf2((m + 1023) / 1024);
+    const T* src = a.row_val;
+    T* dst = buf1.get();
+    while (true) {
+        const int64_t nb = (m + 1023) / 1024;
+        hipLaunchKernelGGL(k_sum_blocks<T>, dim3((unsigned)nb), dim3(1024), 0, st, m, src,
+                           nb == 1 ? loss : dst);
+        DRG_LAUNCH_CHECK();
+        if (nb == 1) break;
+        src = dst;
+        dst = (dst == buf1.get()) ? buf2.get() : buf1.get();
+        m = nb;
+    }
+    DRG_HIP(hipStreamSynchronize(st));
+}
+
+template <typename T>
+void objective_bwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T* y,
+                     const T* dloss, T* dy) {
+    check_obj(s, p, y);
+    if (!dy) throw Error(DRG_E_INVALID, "objective: dy is NULL");
+    hipStream_t st = ctx->stream;
+    ObjArgs<T> a = obj_args<T>(s, p, y);
+    a.dloss = dloss;
+    a.dy = reinterpret_cast<typename OV<T>::v2*>(dy);
+    const int G = obj_group(s);
+    switch (p->b) {
+        case 1: launch_obj_g<T, 1>(st, a, G, true); break;
+        case 2: launch_obj_g<T, 2>(st, a, G, true); break;
+        default: launch_obj_g<T, 3>(st, a, G, true); break;
+    }
+    if (a.M == 0) return;
+    const int64_t np = (int64_t)s->n * a.M;
+    if (np >= ((int64_t)1 << 31)) throw Error(DRG_E_UNSUPPORTED, "objective: n*M >= 2^31");
+    DevBuf<uint32_t> keys(np);
+    DevBuf<int32_t> pairs(np), seg((int64_t)s->n + 2);
+    hipLaunchKernelGGL(k_neg_keys, dim3(ceil_div(np, 256)), dim3(256), 0, st, s->n, a.M,
+                       s->row_ptr.get(), s->C.get(), s->guide.get(), s->gbits, s->S, p->seed,
+                       p->iter, keys.get(), pairs.get());
+    DRG_LAUNCH_CHECK();
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) <= s->n) ++bits;
+    radix_sort_pairs(keys.get(), pairs.get(), np, bits, st);
+    hipLaunchKernelGGL(k_key_bounds, dim3(ceil_div((int64_t)s->n + 1, 256)), dim3(256), 0, st, np,
+                       s->n, keys.get(), seg.get());
+    DRG_LAUNCH_CHECK();
+    switch (p->b) {
+        case 1: hipLaunchKernelGGL((k_other_side<T, 1>), dim3(ceil_div(s->n, 256)), dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+        case 2: hipLaunchKernelGGL((k_other_side<T, 2>), dim3(ceil_div(s->n, 256)), dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+        default: hipLaunchKernelGGL((k_other_side<T, 3>), dim3(ceil_div(s->n, 256)), dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+    }
+    DRG_LAUNCH_CHECK();
+    DRG_HIP(hipStreamSynchronize(st));
+}
+
+template void objective_fwd_t<float>(drg_ctx*, drg_sim*, const drg_obj_params*, const float*, float*, float*);
+template void objective_fwd_t<double>(drg_ctx*, drg_sim*, const drg_obj_params*, const double*, double*, double*);
+template void objective_bwd_t<float>(drg_ctx*, drg_sim*, const drg_obj_params*, const float*, const float*, float*);
+template void objective_bwd_t<double>(drg_ctx*, drg_sim*, const drg_obj_params*, const double*, const double*, double*);
+
+void sample_negatives(drg_ctx* ctx, drg_sim* s, int32_t M, uint64_t seed, uint64_t iter,
+                      int32_t* out) {
+    if (!s || !out || M < 0) throw Error(DRG_E_INVALID, "sample_negatives: bad argument");
+    const int64_t np = (int64_t)s->n * M;
+    if (np == 0) return;
+    hipLaunchKernelGGL(k_negatives, dim3(ceil_div(np, 256)), dim3(256), 0, ctx->stream, s->n, M,
+                       s->row_ptr.get(), s->C.get(), s->guide.get(), s->gbits, s->S, seed, iter,
+                       out);
+    DRG_LAUNCH_CHECK();
+}
+
+void sim_coo(drg_ctx* ctx, drg_sim* s, int32_t* rows, int32_t* cols, float* P) {
+    if (!s) throw Error(DRG_E_INVALID, "sim_coo: sim is NULL");
+    hipLaunchKernelGGL(k_coo, dim3(ceil_div((int64_t)s->n * WAVE, 256)), dim3(256), 0, ctx->stream,
+                       s->n, s->row_ptr.get(), s->colhop.get(), s->invZf.get(),
+                       (float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]), (float)(0.5 * s->e[2]),
+                       (float)(0.5 * s->e[3]), rows, cols, P);
+    DRG_LAUNCH_CHECK();
+}
+
+}  // namespace drg

@@ -44,6 +44,11 @@ class StepParams(C.Structure):
                 ("_pad", C.c_int32), ("seed", C.c_uint64), ("iter", C.c_uint64)]
 
 
+class ObjParams(C.Structure):
+    _fields_ = [("M", C.c_int32), ("b", C.c_int32), ("gamma", C.c_double), ("seed", C.c_uint64),
+                ("iter", C.c_uint64)]
+
+
 class LayoutParams(C.Structure):
     _fields_ = [("k", C.c_int32), ("M", C.c_int32), ("b", C.c_int32), ("T", C.c_int32),
                 ("sigma", C.c_double), ("gamma", C.c_float), ("gamma_coarsest", C.c_float),
@@ -93,6 +98,12 @@ def lib():
         "drg_prolong_f64": ([_P, _P, C.c_int32, _P, _P], st),
         "drg_layout_step_f64": ([_P, _P, _P, C.POINTER(StepParams), _P], st),
         "drg_layout_run": ([_P, _P, _P, C.POINTER(LayoutParams), _P], st),
+        "drg_objective_fwd": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
+        "drg_objective_bwd": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
+        "drg_objective_fwd_f64": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
+        "drg_objective_bwd_f64": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
+        "drg_sample_negatives": ([_P, _P, C.c_int32, C.c_uint64, C.c_uint64, _P], st),
+        "drg_sim_coo": ([_P, _P, _P, _P, _P], st),
         "drg_layout": ([_P, C.POINTER(Csr), C.POINTER(LayoutParams), _P], st),
     }
     for name, (args, res) in sig.items():
@@ -317,3 +328,90 @@ def drg_layout(ctx: Context, row_ptr, col, params: LayoutParams, y_out):
     g = _csr(row_ptr, col)
     _check(lib().drg_layout(ctx.h, C.byref(g), C.byref(params),
                             _dev(y_out, torch.float32, "y_out", (g.n, 2))))
+
+
+# ------------------------------------------------------------------ objective
+def drg_objective_fwd(ctx: Context, sim: Similarity, y, *, M=5, b=1, gamma=0.1, seed=0, iter=0,
+                      rows=False):
+    """The sampled objective L^ at y ([n,2], float32 or float64).  Returns a
+    0-d tensor, or with rows=True the per-row values [n]."""
+    import torch
+    ptr, f64 = _coords(y, "y", (sim.n, 2))
+    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter))
+    out = torch.empty((sim.n,) if rows else (), dtype=y.dtype, device=y.device)
+    fn = lib().drg_objective_fwd_f64 if f64 else lib().drg_objective_fwd
+    optr = C.c_void_p(out.data_ptr())
+    _check(fn(ctx.h, sim.h, C.byref(p), ptr, None if rows else optr, optr if rows else None))
+    return out
+
+
+def drg_objective_bwd(ctx: Context, sim: Similarity, y, dloss=None, *, M=5, b=1, gamma=0.1,
+                      seed=0, iter=0):
+    """dloss * dL^/dy as a tensor like y; dloss is a 0-d device tensor or None."""
+    import torch
+    ptr, f64 = _coords(y, "y", (sim.n, 2))
+    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter))
+    dy = torch.empty_like(y)
+    dl = None
+    if dloss is not None:
+        dloss = dloss.to(dtype=y.dtype).contiguous()
+        dl = C.c_void_p(dloss.data_ptr())
+    fn = lib().drg_objective_bwd_f64 if f64 else lib().drg_objective_bwd
+    _check(fn(ctx.h, sim.h, C.byref(p), ptr, dl, C.c_void_p(dy.data_ptr())))
+    return dy
+
+
+def drg_sample_negatives(ctx: Context, sim: Similarity, M: int, seed: int, iter: int):
+    import torch
+    out = torch.empty((sim.n, M), dtype=torch.int32, device="cuda")
+    _check(lib().drg_sample_negatives(ctx.h, sim.h, int(M), int(seed), int(iter),
+                                      C.c_void_p(out.data_ptr())))
+    return out
+
+
+def drg_sim_coo(ctx: Context, sim: Similarity):
+    """(rows, cols, P) device tensors of P~ in CSR order (FP32 values)."""
+    import torch
+    rows = torch.empty(sim.nnz, dtype=torch.int32, device="cuda")
+    cols = torch.empty(sim.nnz, dtype=torch.int32, device="cuda")
+    P = torch.empty(sim.nnz, dtype=torch.float32, device="cuda")
+    _check(lib().drg_sim_coo(ctx.h, sim.h, C.c_void_p(rows.data_ptr()),
+                             C.c_void_p(cols.data_ptr()), C.c_void_p(P.data_ptr())))
+    return rows, cols, P
+
+
+def _objective_function():
+    import torch
+
+    class DRGObjective(torch.autograd.Function):
+        """L^(y) with the library's forward and hand-written backward.  Only y
+        (and the scalar parameters) are saved; the backward draws the
+        negatives again from their counters."""
+
+        @staticmethod
+        def forward(fctx, y, ctx, sim, M, b, gamma, seed, it):
+            fctx.save_for_backward(y)
+            fctx.args = (ctx, sim, M, b, gamma, seed, it)
+            return drg_objective_fwd(ctx, sim, y.contiguous(), M=M, b=b, gamma=gamma, seed=seed,
+                                     iter=it)
+
+        @staticmethod
+        def backward(fctx, gloss):
+            (y,) = fctx.saved_tensors
+            ctx, sim, M, b, gamma, seed, it = fctx.args
+            dy = drg_objective_bwd(ctx, sim, y.contiguous(), gloss, M=M, b=b, gamma=gamma,
+                                   seed=seed, iter=it)
+            return dy, None, None, None, None, None, None, None
+
+    return DRGObjective
+
+
+_DRGObjective = None
+
+
+def objective(y, ctx: Context, sim: Similarity, *, M=5, b=1, gamma=0.1, seed=0, iter=0):
+    """Differentiable L^(y) (torch.autograd.Function over the library)."""
+    global _DRGObjective
+    if _DRGObjective is None:
+        _DRGObjective = _objective_function()
+    return _DRGObjective.apply(y, ctx, sim, int(M), int(b), float(gamma), int(seed), int(iter))

@@ -59,6 +59,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(d.Csr) == 24
     assert C.sizeof(d.StepParams) == 48
     assert C.sizeof(d.LayoutParams) == 72
+    assert C.sizeof(d.ObjParams) == 32
 
 
 def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
