@@ -107,12 +107,113 @@ def cpu_baseline(cfg: dict) -> dict:
                       f"{el:.2f} s after a {t_sim:.2f} s similarity build"}
 
 
+def bench_autograd(args):
+    """The differentiable form on R-MAT 2^18 (edge factor 8), k=2, M=5, b=1:
+    one step = L^ forward (library) + anchor MSE on 1% of the nodes, backward
+    (hand-written, library), SGD update of Y.  Compared with the same loss
+    written in eager PyTorch on the same P~ (device COO) and negatives."""
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    from paper_2008_07799_amd import gen
+
+    M, b, gamma, lam, lr = 5, 1, 0.1, 1.0, 0.5
+    print("[bench] generating rmat18", file=sys.stderr, flush=True)
+    g = gen.rmat(18, 8, seed=0)
+    torch.cuda.set_device(0)
+    rp, col = d.to_device(g)
+    ctx = d.Context(0)
+    sim = d.drg_build_similarity(ctx, rp, col, 2)
+    n, na = g.n, sim.n_active
+    rng = np.random.default_rng(0)
+    anchors = torch.from_numpy(rng.choice(n, size=n // 100, replace=False)).cuda()
+    targets = torch.from_numpy(rng.uniform(-1, 1, size=(anchors.numel(), 2)).astype(np.float32)).cuda()
+    y0 = torch.from_numpy(rng.uniform(-5, 5, size=(n, 2)).astype(np.float32)).cuda()
+
+    def anchor_term(y):
+        return lam * ((y[anchors] - targets) ** 2).sum(dim=1).mean()
+
+    def ours_loss(y, it):
+        return -d.objective(y, ctx, sim, M=M, b=b, gamma=gamma, seed=0, iter=it) / na + anchor_term(y)
+
+    rows, cols, P = d.drg_sim_coo(ctx, sim)
+    rows, cols = rows.long(), cols.long()
+    qt = torch.from_numpy(sim.export(values=False)["qt"].astype(np.float32)).cuda()
+    ar = torch.arange(n, device="cuda")
+
+    def eager_loss(y, it):
+        neg = d.drg_sample_negatives(ctx, sim, M, 0, it).long()
+        dd = y[rows] - y[cols]
+        d2 = (dd * dd).sum(dim=1)
+        att = (P * -torch.log1p(d2 ** b)).sum()
+        valid = (neg >= 0) & (neg != ar[:, None])
+        vv = neg.clamp(min=0)
+        dn = y[:, None, :] - y[vv]
+        d2n = (dn * dn).sum(dim=-1)
+        ok = valid & (d2n > 0)
+        d2s = torch.where(ok, d2n, torch.ones_like(d2n))
+        term = torch.where(ok, b * torch.log(d2s) - torch.log1p(d2s ** b), torch.zeros_like(d2s))
+        rep = gamma * (qt[:, None] * term).sum()
+        return -(att + rep) / na + anchor_term(y)
+
+    def run(loss_fn, steps, warm):
+        y = y0.clone().requires_grad_(True)
+        for s in range(warm + steps):
+            if s == warm:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            y.grad = None
+            loss = loss_fn(y, s)
+            loss.backward()
+            with torch.no_grad():
+                y -= lr * y.grad
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000.0 / steps, y.detach()
+
+    # accuracy at the same point, both against the FP64 instance of the
+    # library's objective (which matches the FP64 oracle to 1e-10)
+    y64 = y0.double()
+    l64 = float(-d.drg_objective_fwd(ctx, sim, y64, M=M, b=b, gamma=gamma, seed=0, iter=0) / na
+                + lam * ((y64[anchors] - targets.double()) ** 2).sum(dim=1).mean())
+    g64 = -d.drg_objective_bwd(ctx, sim, y64, M=M, b=b, gamma=gamma, seed=0, iter=0) / na
+    g64[anchors] += 2.0 * lam * (y64[anchors] - targets.double()) / anchors.numel()
+    acc = {}
+    for name, fn in (("ours", ours_loss), ("eager", eager_loss)):
+        ya = y0.clone().requires_grad_(True)
+        la = fn(ya, 0)
+        la.backward()
+        acc[name] = {"loss_rel_err_vs_fp64": abs(float(la.detach()) - l64) / abs(l64),
+                     "grad_rel_err_vs_fp64": float((ya.grad.double() - g64).abs().max()
+                                                   / g64.abs().max())}
+        del ya, la
+    torch.cuda.empty_cache()
+    print("[bench] ours", file=sys.stderr, flush=True)
+    ms_ours, _ = run(ours_loss, args.steps, max(1, args.warmup))
+    torch.cuda.empty_cache()
+    print("[bench] eager", file=sys.stderr, flush=True)
+    ms_eager, _ = run(eager_loss, args.steps, max(1, args.warmup))
+    pairs = sim.nnz + M * na
+    rec = {
+        "metric": "pair-updates/s + time-to-layout, 1M-node R-MAT; batched/autograd vs plain",
+        "value": pairs / (ms_ours / 1000.0), "unit": "pair-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": max(1, args.warmup), "ms_per_step": ms_ours,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "autograd_rmat18_k2", "graph": "rmat18", "n": n, "k": 2, "M": M,
+                   "b": b, "nnz_P": sim.nnz, "n_active": na, "anchors": int(anchors.numel()),
+                   "step": "forward + backward + SGD update"},
+        "vs_eager_pytorch": {"eager_ms_per_step": ms_eager, "speedup": ms_eager / ms_ours,
+                             "accuracy": acc},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat20_k2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat20_k2",
+                    choices=sorted(WORKLOADS) + ["autograd_rmat18_k2"])
     ap.add_argument("--mode", default="sync", choices=["sync", "async"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -132,6 +233,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "autograd_rmat18_k2":
+        bench_autograd(args)
+        return
 
     import torch
     from paper_2008_07799_amd import drgraph as d
