@@ -106,6 +106,13 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// Butterfly sum over aligned groups of g lanes (g a power of two <= 64).
+template <typename T>
+__device__ __forceinline__ T group_sum_rt(T v, int g) {
+    for (int off = g >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, g);
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
     const int l = __lane_id();

@@ -1,0 +1,214 @@
+// drg_forces.hpp -- the per-pair forces of Eq. gradient and small vector
+// helpers, shared by the single-graph and the batched iteration kernels so
+// both evaluate every pair with the same operations.
+#pragma once
+#include "drg_common.hpp"
+
+namespace drg {
+
+template <typename T>
+struct VT;
+template <>
+struct VT<float> {
+    using v2 = float2;
+    using v4 = float4;
+};
+template <>
+struct VT<double> {
+    using v2 = double2;
+    using v4 = double4;
+};
+
+template <typename T>
+__device__ __forceinline__ typename VT<T>::v2 mk2(T a, T b) {
+    typename VT<T>::v2 r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ typename VT<T>::v4 mk4(T a, T b, T c, T d) {
+    typename VT<T>::v4 r;
+    r.x = a;
+    r.y = b;
+    r.z = c;
+    r.w = d;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T clampT(T v, T c) {
+    return v > c ? c : (v < -c ? -c : v);
+}
+
+template <int B, typename T>
+__device__ __forceinline__ T powT(T x) {
+    if constexpr (B == 0) return T(1);
+    else if constexpr (B == 1) return x;
+    else if constexpr (B == 2) return x * x;
+    else return x * x * x;
+}
+
+// attraction coefficient -2b d^{2b-2}/(1+d^{2b}); repulsion 2b/(d^2 (1+d^{2b}));
+// FP32 uses the hardware reciprocal, FP64 the correctly rounded division
+template <typename T>
+__device__ __forceinline__ T recipT(T x) {
+    if constexpr (std::is_same<T, float>::value) return rcp_fast(x);
+    else return T(1) / x;
+}
+template <int B, typename T>
+__device__ __forceinline__ T attract_coef(T d2) {
+    if constexpr (std::is_same<T, float>::value)
+        return T(-2 * B) * powT<B - 1>(d2) * recipT(T(1) + powT<B>(d2));
+    else
+        return T(-2 * B) * powT<B - 1>(d2) / (T(1) + powT<B>(d2));
+}
+template <int B, typename T>
+__device__ __forceinline__ T repel_coef(T d2) {
+    if constexpr (std::is_same<T, float>::value)
+        return T(2 * B) * recipT(d2 * (T(1) + powT<B>(d2)));
+    else
+        return T(2 * B) / (d2 * (T(1) + powT<B>(d2)));
+}
+
+template <typename T>
+__device__ __forceinline__ T clampT2(T v, T c) {
+    if constexpr (std::is_same<T, float>::value) return clampf(v, c);
+    else return v > c ? c : (v < -c ? -c : v);
+}
+template <typename T>
+__device__ __forceinline__ T repelT(T k, T d, T c) {
+    if constexpr (std::is_same<T, float>::value) return repel_component(k, d, c);
+    else return clampT2(k * d, c);
+}
+
+// Runtime-b forms with exactly the operations of the compile-time ones.
+template <typename T>
+__device__ __forceinline__ T attract_coef_rt(T d2, int b) {
+    return b == 1 ? attract_coef<1>(d2) : (b == 2 ? attract_coef<2>(d2) : attract_coef<3>(d2));
+}
+template <typename T>
+__device__ __forceinline__ T repel_coef_rt(T d2, int b) {
+    return b == 1 ? repel_coef<1>(d2) : (b == 2 ? repel_coef<2>(d2) : repel_coef<3>(d2));
+}
+
+// ------------------------------------------------------------------ per-node steps
+// These bodies are the whole arithmetic of one node in the iteration; the
+// single-graph and the batched kernels call them with the same arguments, so
+// a graph laid out inside a batch reproduces its single-graph layout bit for
+// bit.
+
+// Random initial point of node v at `level`: uniform in [-1, 1)^2 from the
+// top 24 bits of two Philox words.
+template <typename T>
+__device__ __forceinline__ typename VT<T>::v2 init_point(int32_t v, int32_t level, uint64_t seed) {
+    const U64x4 r =
+        philox4x64((uint64_t)(uint32_t)v, (uint64_t)(uint32_t)level, 0, 0, seed, TAG_INIT);
+    const T ux = (T)(uint32_t)(r.w[0] >> 40) * (T(1) / T(16777216));
+    const T uy = (T)(uint32_t)(r.w[1] >> 40) * (T(1) / T(16777216));
+    return mk2<T>(T(2) * ux - T(1), T(2) * uy - T(1));
+}
+
+// e_d / 2 for hops 1..4
+template <typename T>
+struct HalfE {
+    T h0, h1, h2, h3;
+    __device__ __forceinline__ T operator()(uint32_t h) const {
+        return h == 0 ? h0 : (h == 1 ? h1 : (h == 2 ? h2 : h3));
+    }
+};
+
+// One row of the sweep, computed by the G lanes of a group (lane = 0..G-1):
+// lane l takes pattern entries rs+l, rs+l+G, ... and negative slots l, l+G,
+// ...; the lane partials are then summed by a butterfly over the group.
+// Returns g_i (valid in every lane) = attraction + gq * repulsion, where
+// `key` is the node's own id for the negative words and draw(w) turns a word
+// into the record index of the drawn node.
+template <typename T, int B, typename Draw>
+__device__ __forceinline__ typename VT<T>::v2 sweep_row(
+    const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
+    const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
+    const HalfE<T>& eh, T clip, int M, uint64_t seed, uint64_t iter, int32_t key, Draw draw,
+    T gq) {
+    using v4 = typename VT<T>::v4;
+    T ax = T(0), ay = T(0);
+    auto pair = [&](uint32_t e, const v4& rj) {
+        const T dx = ri.x - rj.x, dy = ri.y - rj.y;
+        const T d2 = dx * dx + dy * dy;
+        if (d2 > T(0)) {
+            const T k = attract_coef<B>(d2);
+            const T w = eh(e >> 30) * (ri.z + rj.z);
+            ax += w * clampT2(k * dx, clip);
+            ay += w * clampT2(k * dy, clip);
+        }
+    };
+    constexpr int U = 4;  // independent entry loads and gathers in flight
+    int64_t x = rs + lane;
+    for (; x + (int64_t)(U - 1) * G < re; x += (int64_t)U * G) {
+        uint32_t e[U];
+        v4 rj[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) e[q] = colhop[x + (int64_t)q * G];
+#pragma unroll
+        for (int q = 0; q < U; ++q) rj[q] = rec[e[q] & COL_MASK];
+#pragma unroll
+        for (int q = 0; q < U; ++q) pair(e[q], rj[q]);
+    }
+    for (; x < re; x += G) {
+        const uint32_t e = colhop[x];
+        pair(e, rec[e & COL_MASK]);
+    }
+    T rx = T(0), ry = T(0);
+    for (int m = lane; m < M; m += G) {
+        const uint64_t w = neg_word(seed, iter, key, m);
+        const v4 rv = rec[draw(w)];
+        const T dx = ri.x - rv.x, dy = ri.y - rv.y;
+        const T d2 = dx * dx + dy * dy;
+        if (d2 > T(0)) {
+            const T k = repel_coef<B>(d2);
+            rx += repelT(k, dx, clip);
+            ry += repelT(k, dy, clip);
+        }
+    }
+    ax = group_sum_rt(ax, G);
+    ay = group_sum_rt(ay, G);
+    rx = group_sum_rt(rx, G);
+    ry = group_sum_rt(ry, G);
+    return mk2<T>(ax + gq * rx, ay + gq * ry);
+}
+
+// Finest-level step of node i: y_i += eta g_i / qt_i (nodes with qt_i = 0 stay).
+template <typename T>
+__device__ __forceinline__ void apply_node(const typename VT<T>::v2& s, T w,
+                                           typename VT<T>::v2* __restrict__ yp, T eta) {
+    if (!(w > T(0))) return;
+    typename VT<T>::v2 p = *yp;
+    p.x += eta * (s.x / w);
+    p.y += eta * (s.y / w);
+    *yp = p;
+}
+
+// Coarse-level step of level node a: the members' steps and anchor weights
+// summed in ascending member id (perm[x] + pbase indexes g and qt).
+template <typename T>
+__device__ __forceinline__ void apply_group(int32_t xb, int32_t xe, const int32_t* __restrict__ perm,
+                                            int64_t pbase, const typename VT<T>::v2* __restrict__ g,
+                                            const T* __restrict__ qt,
+                                            typename VT<T>::v2* __restrict__ yp, T eta) {
+    T sx = T(0), sy = T(0), sw = T(0);
+    for (int32_t x = xb; x < xe; ++x) {
+        const int64_t i = pbase + perm[x];
+        const typename VT<T>::v2 s = g[i];
+        sx += s.x;
+        sy += s.y;
+        sw += qt[i];
+    }
+    if (sw > T(0)) {
+        typename VT<T>::v2 p = *yp;
+        p.x += eta * (sx / sw);
+        p.y += eta * (sy / sw);
+        *yp = p;
+    }
+}
+
+}  // namespace drg

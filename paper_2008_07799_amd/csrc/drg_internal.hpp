@@ -69,8 +69,22 @@ struct drg_hier {
 namespace drg {
 void set_error(const std::string& msg);
 
+// A union of disjoint graphs: graph c owns the node ids base[c] .. base[c+1]-1
+// and its edges stay inside that range.
+struct UnionInfo {
+    int32_t count = 0;
+    std::vector<int32_t> base;            // [count+1], host
+    const int32_t* node_base = nullptr;   // [n], device: base of the node's graph
+    int32_t max_comp = 0;                 // largest graph
+    std::vector<int64_t> nnz;             // out: pattern entries of each graph
+};
+
 // similarity.hip
-drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags);
+// With u, the pattern is built for every graph of the union at once, each
+// graph's row weights with the launch shape of its own single-graph build;
+// the sampling guide and the column-blocked copy are then left out.
+drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
+                          UnionInfo* u = nullptr);
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
 void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,
                 double* qt, uint64_t* W, double* e, double* invZ);

@@ -19,95 +19,15 @@
 //
 // Every kernel is templated on the coordinate type: float is the product
 // path; the double instance runs the same arithmetic for trajectory checks.
+#include "drg_forces.hpp"
 #include "drg_internal.hpp"
 
 namespace drg {
 
 template <typename T>
-struct VT;
-template <>
-struct VT<float> {
-    using v2 = float2;
-    using v4 = float4;
-};
-template <>
-struct VT<double> {
-    using v2 = double2;
-    using v4 = double4;
-};
-
-template <typename T>
-__device__ __forceinline__ typename VT<T>::v2 mk2(T a, T b) {
-    typename VT<T>::v2 r;
-    r.x = a;
-    r.y = b;
-    return r;
-}
-template <typename T>
-__device__ __forceinline__ typename VT<T>::v4 mk4(T a, T b, T c, T d) {
-    typename VT<T>::v4 r;
-    r.x = a;
-    r.y = b;
-    r.z = c;
-    r.w = d;
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T clampT(T v, T c) {
-    return v > c ? c : (v < -c ? -c : v);
-}
-
-template <int B, typename T>
-__device__ __forceinline__ T powT(T x) {
-    if constexpr (B == 0) return T(1);
-    else if constexpr (B == 1) return x;
-    else if constexpr (B == 2) return x * x;
-    else return x * x * x;
-}
-
-// attraction coefficient -2b d^{2b-2}/(1+d^{2b}); repulsion 2b/(d^2 (1+d^{2b}));
-// FP32 uses the hardware reciprocal, FP64 the correctly rounded division
-template <typename T>
-__device__ __forceinline__ T recipT(T x) {
-    if constexpr (std::is_same<T, float>::value) return rcp_fast(x);
-    else return T(1) / x;
-}
-template <int B, typename T>
-__device__ __forceinline__ T attract_coef(T d2) {
-    if constexpr (std::is_same<T, float>::value)
-        return T(-2 * B) * powT<B - 1>(d2) * recipT(T(1) + powT<B>(d2));
-    else
-        return T(-2 * B) * powT<B - 1>(d2) / (T(1) + powT<B>(d2));
-}
-template <int B, typename T>
-__device__ __forceinline__ T repel_coef(T d2) {
-    if constexpr (std::is_same<T, float>::value)
-        return T(2 * B) * recipT(d2 * (T(1) + powT<B>(d2)));
-    else
-        return T(2 * B) / (d2 * (T(1) + powT<B>(d2)));
-}
-
-template <typename T>
-__device__ __forceinline__ T clampT2(T v, T c) {
-    if constexpr (std::is_same<T, float>::value) return clampf(v, c);
-    else return v > c ? c : (v < -c ? -c : v);
-}
-template <typename T>
-__device__ __forceinline__ T repelT(T k, T d, T c) {
-    if constexpr (std::is_same<T, float>::value) return repel_component(k, d, c);
-    else return clampT2(k * d, c);
-}
-
-template <typename T>
 __global__ void k_init(int32_t n, uint64_t seed, int32_t level, typename VT<T>::v2* __restrict__ y) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const U64x4 r =
-        philox4x64((uint64_t)(uint32_t)v, (uint64_t)(uint32_t)level, 0, 0, seed, TAG_INIT);
-    const T ux = (T)(uint32_t)(r.w[0] >> 40) * (T(1) / T(16777216));
-    const T uy = (T)(uint32_t)(r.w[1] >> 40) * (T(1) / T(16777216));
-    y[v] = mk2<T>(T(2) * ux - T(1), T(2) * uy - T(1));
+    if (v < n) y[v] = init_point<T>((int32_t)v, level, seed);
 }
 
 template <typename T>
@@ -164,60 +84,18 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
     const int lane = threadIdx.x % G;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    const HalfE<T> eh{a.eh0, a.eh1, a.eh2, a.eh3};
     for (int64_t i = grp; i < a.n0; i += ngrp) {
         const int64_t rs = a.prp[i], re = a.prp[i + 1];
-        T gx = T(0), gy = T(0);
-        if (rs < re) {
-            const typename VT<T>::v4 ri = a.rec[i];
-            T ax = T(0), ay = T(0);
-            auto pair = [&](uint32_t e, const typename VT<T>::v4& rj) {
-                const T dx = ri.x - rj.x, dy = ri.y - rj.y;
-                const T d2 = dx * dx + dy * dy;
-                if (d2 > T(0)) {
-                    const T k = attract_coef<B>(d2);
-                    const T w = half_e(a, e >> 30) * (ri.z + rj.z);
-                    ax += w * clampT2(k * dx, a.clip);
-                    ay += w * clampT2(k * dy, a.clip);
-                }
-            };
-            constexpr int U = 4;  // independent entry loads and gathers in flight
-            int64_t x = rs + lane;
-            for (; x + (U - 1) * G < re; x += U * G) {
-                uint32_t e[U];
-                typename VT<T>::v4 rj[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) e[q] = a.colhop[x + q * G];
-#pragma unroll
-                for (int q = 0; q < U; ++q) rj[q] = a.rec[e[q] & COL_MASK];
-#pragma unroll
-                for (int q = 0; q < U; ++q) pair(e[q], rj[q]);
-            }
-            for (; x < re; x += G) {
-                const uint32_t e = a.colhop[x];
-                pair(e, a.rec[e & COL_MASK]);
-            }
-            T rx = T(0), ry = T(0);
-            for (int m = lane; m < a.M; m += G) {
-                const uint64_t w = neg_word(a.seed, a.iter, (int32_t)i, m);
-                const int32_t v = draw_node(w, a.C, a.guide, a.gbits, a.S);
-                const typename VT<T>::v4 rv = a.rec[v];
-                const T dx = ri.x - rv.x, dy = ri.y - rv.y;
-                const T d2 = dx * dx + dy * dy;
-                if (d2 > T(0)) {
-                    const T k = repel_coef<B>(d2);
-                    rx += repelT(k, dx, a.clip);
-                    ry += repelT(k, dy, a.clip);
-                }
-            }
-            ax = group_sum<G>(ax);
-            ay = group_sum<G>(ay);
-            rx = group_sum<G>(rx);
-            ry = group_sum<G>(ry);
-            const T gq = a.gamma * a.qt[i];
-            gx = ax + gq * rx;
-            gy = ay + gq * ry;
-        }
-        if (lane == 0) a.g[i] = mk2<T>(gx, gy);
+        typename VT<T>::v2 gi = mk2<T>(T(0), T(0));
+        if (rs < re)
+            gi = sweep_row<T, B>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh, a.clip, a.M,
+                                 a.seed, a.iter, (int32_t)i,
+                                 [&](uint64_t w) {
+                                     return draw_node(w, a.C, a.guide, a.gbits, a.S);
+                                 },
+                                 a.gamma * a.qt[i]);
+        if (lane == 0) a.g[i] = gi;
     }
 }
 
@@ -225,46 +103,19 @@ template <typename T>
 __global__ void k_apply0(int32_t n, const typename VT<T>::v2* __restrict__ g,
                          const T* __restrict__ qt, typename VT<T>::v2* __restrict__ y, T eta) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const T w = qt[i];
-    if (!(w > T(0))) return;
-    const typename VT<T>::v2 s = g[i];
-    typename VT<T>::v2 p = y[i];
-    p.x += eta * (s.x / w);
-    p.y += eta * (s.y / w);
-    y[i] = p;
+    if (i < n) apply_node<T>(g[i], qt[i], y + i, eta);
 }
 
-// G lanes per level node: strided partial sums over its members (ascending
-// id within each lane), then a fixed-order reduction.
-template <typename T, int G>
+// One thread per level node: the members' steps and anchor weights summed in
+// ascending member id.
+template <typename T>
 __global__ __launch_bounds__(256) void k_apply_level(int32_t nl, const int32_t* __restrict__ seg,
                                                      const int32_t* __restrict__ perm,
                                                      const typename VT<T>::v2* __restrict__ g,
                                                      const T* __restrict__ qt,
                                                      typename VT<T>::v2* __restrict__ y, T eta) {
-    const int lane = threadIdx.x % G;
-    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
-    for (int64_t a = grp; a < nl; a += ngrp) {
-        T sx = T(0), sy = T(0), sw = T(0);
-        for (int32_t x = seg[a] + lane; x < seg[a + 1]; x += G) {
-            const int32_t i = perm[x];
-            const typename VT<T>::v2 s = g[i];
-            sx += s.x;
-            sy += s.y;
-            sw += qt[i];
-        }
-        sx = group_sum<G>(sx);
-        sy = group_sum<G>(sy);
-        sw = group_sum<G>(sw);
-        if (lane == 0 && sw > T(0)) {
-            typename VT<T>::v2 p = y[a];
-            p.x += eta * (sx / sw);
-            p.y += eta * (sy / sw);
-            y[a] = p;
-        }
-    }
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < nl) apply_group<T>(seg[a], seg[a + 1], perm, 0, g, qt, y + a, eta);
 }
 
 template <typename T>
@@ -502,16 +353,9 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
             if (ctx->profiling) ctx->events.emplace_back(e0, e1);
             if (level > 0) {
                 const drg_level& L = h->lv[level];
-                const double mean = (double)n0 / (double)std::max(1, nl);
-                if (mean <= 16)
-                    hipLaunchKernelGGL((k_apply_level<T, 8>), dim3(ceil_div((int64_t)nl * 8, 256)),
-                                       dim3(256), 0, st, nl, L.seg.get(), L.perm.get(), g, qt,
-                                       reinterpret_cast<v2*>(y), (T)p->eta);
-                else
-                    hipLaunchKernelGGL((k_apply_level<T, 32>),
-                                       dim3(ceil_div((int64_t)nl * 32, 256)), dim3(256), 0, st,
-                                       nl, L.seg.get(), L.perm.get(), g, qt,
-                                       reinterpret_cast<v2*>(y), (T)p->eta);
+                hipLaunchKernelGGL(k_apply_level<T>, dim3(ceil_div(nl, 256)), dim3(256), 0, st, nl,
+                                   L.seg.get(), L.perm.get(), g, qt, reinterpret_cast<v2*>(y),
+                                   (T)p->eta);
                 DRG_LAUNCH_CHECK();
             }
             return;
@@ -533,15 +377,9 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
                                reinterpret_cast<v2*>(y), (T)p->eta);
         } else {
             const drg_level& L = h->lv[level];
-            const double mean = (double)n0 / (double)std::max(1, nl);
-            if (mean <= 16)
-                hipLaunchKernelGGL((k_apply_level<T, 8>), dim3(ceil_div((int64_t)nl * 8, 256)),
-                                   dim3(256), 0, st, nl, L.seg.get(), L.perm.get(), g, qt,
-                                   reinterpret_cast<v2*>(y), (T)p->eta);
-            else
-                hipLaunchKernelGGL((k_apply_level<T, 32>), dim3(ceil_div((int64_t)nl * 32, 256)),
-                                   dim3(256), 0, st, nl, L.seg.get(), L.perm.get(), g, qt,
-                                   reinterpret_cast<v2*>(y), (T)p->eta);
+            hipLaunchKernelGGL(k_apply_level<T>, dim3(ceil_div(nl, 256)), dim3(256), 0, st, nl,
+                               L.seg.get(), L.perm.get(), g, qt, reinterpret_cast<v2*>(y),
+                               (T)p->eta);
         }
         DRG_LAUNCH_CHECK();
     }

@@ -112,6 +112,7 @@ struct BfsArgs {
     int64_t qcap;
     uint32_t* gbm;         // [grid][nwords] bitmaps when not in LDS
     int32_t* work;         // next source
+    const int32_t* node_base;  // per node: first id of its graph in a batch (NULL: 0)
 };
 
 // Sets the hop of id v inside the sorted row ch[lo..hi); v absent (only
@@ -145,6 +146,8 @@ __global__ __launch_bounds__(BFS_BLOCK) void k_khop(BfsArgs a) {
         __syncthreads();
         const int32_t s = s_src;
         if (s >= a.n) break;
+        // bitmap bit of node v is v - base: a source only reaches its own graph
+        const int32_t base = a.node_base ? a.node_base[s] : 0;
         const int32_t rs = a.rp[s], re = a.rp[s + 1];
         if (rs == re) {
             if (!FILL && tid < a.k) a.cnt[(int64_t)s * a.k + tid] = 0;
@@ -153,12 +156,13 @@ __global__ __launch_bounds__(BFS_BLOCK) void k_khop(BfsArgs a) {
         }
         // hop 1: the source itself (visited) and its neighbours
         if (tid == 0) {
-            atomicOr(&bm[s >> 5], 1u << (s & 31));
+            const int32_t sb = s - base;
+            atomicOr(&bm[sb >> 5], 1u << (sb & 31));
             s_qtail = 0;
         }
         for (int32_t x = rs + tid; x < re; x += BFS_BLOCK) {
-            const int32_t v = a.col[x];
-            atomicOr(&bm[v >> 5], 1u << (v & 31));
+            const int32_t vb = a.col[x] - base;
+            atomicOr(&bm[vb >> 5], 1u << (vb & 31));
         }
         __syncthreads();
         // hops 2..k: expand the previous frontier, G lanes per frontier node
@@ -173,21 +177,22 @@ __global__ __launch_bounds__(BFS_BLOCK) void k_khop(BfsArgs a) {
                 const int32_t us = a.rp[u], ue = a.rp[u + 1];
                 for (int32_t x = us + (tid % G); x < ue; x += G) {
                     const int32_t v = a.col[x];
-                    const uint32_t bit = 1u << (v & 31);
+                    const int32_t vb = v - base;
+                    const uint32_t bit = 1u << (vb & 31);
                     if (keep) {
-                        const uint32_t old = atomicOr(&bm[v >> 5], bit);
+                        const uint32_t old = atomicOr(&bm[vb >> 5], bit);
                         const bool fresh = !(old & bit);
                         const uint64_t act = __ballot(1);
                         const uint64_t fm = __ballot(fresh);
                         if (fm) {
                             const int leader = __ffsll((unsigned long long)act) - 1;
-                            int base = 0;
-                            if (__lane_id() == leader) base = atomicAdd(&s_qtail, __popcll(fm));
-                            base = __shfl(base, leader);
-                            if (fresh) q[base + __popcll(fm & lanemask_lt())] = v;
+                            int qpos = 0;
+                            if (__lane_id() == leader) qpos = atomicAdd(&s_qtail, __popcll(fm));
+                            qpos = __shfl(qpos, leader);
+                            if (fresh) q[qpos + __popcll(fm & lanemask_lt())] = v;
                         }
                     } else {
-                        atomicOr(&bm[v >> 5], bit);
+                        atomicOr(&bm[vb >> 5], bit);
                     }
                 }
             }
@@ -219,7 +224,8 @@ __global__ __launch_bounds__(BFS_BLOCK) void k_khop(BfsArgs a) {
             const uint32_t hopk = (uint32_t)(a.k - 1) << 30;
             uint32_t* out = a.colhop;
             bitmap_emit_clear<BFS_BLOCK, EMIT_WPT>(
-                bm, a.nwords, s, row0, s_red, [&](int64_t o, uint32_t v) { out[o] = v | hopk; });
+                bm, a.nwords, s - base, row0, s_red,
+                [&](int64_t o, uint32_t v) { out[o] = ((uint32_t)base + v) | hopk; });
             __syncthreads();
             if (a.k >= 2) {
                 for (int32_t x = rs + tid; x < re; x += BFS_BLOCK)
@@ -322,7 +328,35 @@ __global__ void k_normalise(int32_t n, int32_t k, const int32_t* __restrict__ cn
 }
 
 // P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2.  Per row: W_i = sum_j trunc(P~_ij 2^32)
-// (exact integer), qt_i = sum_j P~_ij (FP64, fixed tree order).
+// (exact integer), qt_i = sum_j P~_ij (FP64: lane l of the G lanes sums
+// entries l, l+G, ... in order, then a butterfly over the group).
+__device__ __forceinline__ void row_weights_row(int64_t i, int lane, int G,
+                                                const int64_t* __restrict__ prp,
+                                                const uint32_t* __restrict__ ch,
+                                                const double* __restrict__ invZ, const ECoef& ec,
+                                                uint64_t* __restrict__ W, double* __restrict__ qt,
+                                                float* __restrict__ qtf) {
+#pragma clang fp contract(off)
+    const double izi = invZ[i];
+    unsigned long long ws = 0;
+    double qs = 0.0;
+    for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += G) {
+        const uint32_t e = ch[x];
+        const double s = izi + invZ[e & COL_MASK];
+        const double t = pick_e(ec.e, e >> 30) * s;
+        const double p = t * 0.5;
+        ws += (unsigned long long)(p * 4294967296.0);
+        qs = qs + p;
+    }
+    ws = group_sum_rt(ws, G);
+    qs = group_sum_rt(qs, G);
+    if (lane == 0) {
+        W[i] = ws;
+        qt[i] = qs;
+        qtf[i] = (float)qs;
+    }
+}
+
 template <int G>
 __global__ __launch_bounds__(256) void k_row_weights(int32_t n, const int64_t* __restrict__ prp,
                                                      const uint32_t* __restrict__ ch,
@@ -330,29 +364,41 @@ __global__ __launch_bounds__(256) void k_row_weights(int32_t n, const int64_t* _
                                                      uint64_t* __restrict__ W,
                                                      double* __restrict__ qt,
                                                      float* __restrict__ qtf) {
-#pragma clang fp contract(off)
     const int lane = threadIdx.x % G;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
-    for (int64_t i = grp; i < n; i += ngrp) {
-        const double izi = invZ[i];
-        unsigned long long ws = 0;
-        double qs = 0.0;
-        for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += G) {
-            const uint32_t e = ch[x];
-            const double s = izi + invZ[e & COL_MASK];
-            const double t = pick_e(ec.e, e >> 30) * s;
-            const double p = t * 0.5;
-            ws += (unsigned long long)(p * 4294967296.0);
-            qs = qs + p;
+    for (int64_t i = grp; i < n; i += ngrp) row_weights_row(i, lane, G, prp, ch, invZ, ec, W, qt, qtf);
+}
+
+// Union of graphs: every graph keeps the group size its own single-graph
+// build picks, so its weights come out bit for bit the same.  Graph c owns
+// waves woff[c] .. woff[c+1]-1, each wave 64/G consecutive rows of it.
+__global__ __launch_bounds__(256) void k_row_weights_union(int32_t count,
+                                                           const int32_t* __restrict__ woff,
+                                                           const int4* __restrict__ gtab,
+                                                           const int64_t* __restrict__ prp,
+                                                           const uint32_t* __restrict__ ch,
+                                                           const double* __restrict__ invZ,
+                                                           ECoef ec, uint64_t* __restrict__ W,
+                                                           double* __restrict__ qt,
+                                                           float* __restrict__ qtf) {
+    const int32_t total = woff[count];
+    const int32_t nwaves = (int32_t)(gridDim.x * (blockDim.x / WAVE));
+    for (int32_t gw = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * (blockDim.x / WAVE) +
+                                                               threadIdx.x / WAVE));
+         gw < total; gw += nwaves) {
+        int32_t lo = 0, hi = count - 1;  // last c with woff[c] <= gw
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (woff[mid] <= gw)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
-        ws = group_sum<G>(ws);
-        qs = group_sum<G>(qs);
-        if (lane == 0) {
-            W[i] = ws;
-            qt[i] = qs;
-            qtf[i] = (float)qs;
-        }
+        const int4 t = gtab[lo];  // (base, n, G, -)
+        const int G = t.z;
+        const int32_t r = (gw - woff[lo]) * (WAVE / G) + (int32_t)(__lane_id() / G);
+        if (r < t.y) row_weights_row((int64_t)t.x + r, __lane_id() % G, G, prp, ch, invZ, ec, W, qt, qtf);
     }
 }
 
@@ -412,7 +458,56 @@ static void launch_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec) {
     DRG_LAUNCH_CHECK();
 }
 
-drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags) {
+__global__ void k_gather_rowptr(int32_t m, const int32_t* __restrict__ at,
+                                const int64_t* __restrict__ prp, int64_t* __restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < m) out[c] = prp[at[c]];
+}
+
+// Row weights of a union, graph by graph (see k_row_weights_union).
+static void union_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec, UnionInfo* u) {
+    hipStream_t st = ctx->stream;
+    const int32_t m = u->count + 1;
+    DevBuf<int32_t> at(m);
+    DevBuf<int64_t> rpv(m);
+    DRG_HIP(hipMemcpyAsync(at.get(), u->base.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice,
+                           st));
+    hipLaunchKernelGGL(k_gather_rowptr, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, at.get(),
+                       s->row_ptr.get(), rpv.get());
+    DRG_LAUNCH_CHECK();
+    std::vector<int64_t> h(m);
+    DRG_HIP(hipMemcpyAsync(h.data(), rpv.get(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st));
+    DRG_HIP(hipStreamSynchronize(st));
+    u->nnz.assign(u->count, 0);
+    std::vector<int4> tab(u->count);
+    std::vector<int32_t> woff(u->count + 1, 0);
+    for (int32_t c = 0; c < u->count; ++c) {
+        const int32_t nc = u->base[c + 1] - u->base[c];
+        u->nnz[c] = h[c + 1] - h[c];
+        const int G = pick_group((double)u->nnz[c] / (double)nc);
+        tab[c] = make_int4(u->base[c], nc, G, 0);
+        const int64_t w = ((int64_t)nc + WAVE / G - 1) / (WAVE / G);
+        if ((int64_t)woff[c] + w >= ((int64_t)1 << 31))
+            throw Error(DRG_E_INVALID, "union too large");
+        woff[c + 1] = woff[c] + (int32_t)w;
+    }
+    DevBuf<int4> dtab(u->count);
+    DevBuf<int32_t> dwoff(m);
+    DRG_HIP(hipMemcpyAsync(dtab.get(), tab.data(), sizeof(int4) * u->count, hipMemcpyHostToDevice,
+                           st));
+    DRG_HIP(hipMemcpyAsync(dwoff.get(), woff.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice,
+                           st));
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((woff[u->count] + 3) / 4,
+                                                                  (int64_t)ctx->num_cu * 64));
+    hipLaunchKernelGGL(k_row_weights_union, dim3((unsigned)blocks), dim3(256), 0, st, u->count,
+                       dwoff.get(), dtab.get(), s->row_ptr.get(), s->colhop.get(), s->invZ.get(),
+                       ec, s->W.get(), s->qt.get(), s->qtf.get());
+    DRG_LAUNCH_CHECK();
+    DRG_HIP(hipStreamSynchronize(st));
+}
+
+drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
+                          UnionInfo* u) {
     if (!g) throw Error(DRG_E_INVALID, "graph is NULL");
     if (k < 1 || k > 4) throw Error(DRG_E_INVALID, "k must be in 1..4");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) throw Error(DRG_E_INVALID, "sigma must be > 0");
@@ -446,8 +541,10 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
             DRG_LAUNCH_CHECK();
         }
     } else {
-        // launch shape: LDS bitmap when it fits, global bitmaps otherwise
-        const int nwords = (n + 31) / 32;
+        // launch shape: LDS bitmap when it fits, global bitmaps otherwise; in a
+        // batch the bitmap spans the largest graph only
+        const int32_t span = u ? u->max_comp : n;
+        const int nwords = (span + 31) / 32;
         const size_t lds = (size_t)nwords * 4;
         const bool in_lds = lds + 512 <= (size_t)ctx->max_lds;
         DevBuf<unsigned long long> d2(1);
@@ -466,7 +563,7 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
         DevBuf<int32_t> queue;
         int64_t qcap = 0;
         if (k >= 3) {
-            qcap = n;
+            qcap = span;
             queue.alloc((int64_t)grid * qcap);
         }
         DevBuf<uint32_t> gbm;
@@ -483,6 +580,7 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
         a.qcap = qcap;
         a.gbm = gbm.get();
         a.work = work.get();
+        a.node_base = u ? u->node_base : nullptr;
         DRG_HIP(hipMemsetAsync(work.get(), 0, sizeof(int32_t), st));
         if (in_lds)
             launch_khop<false, true>(ctx, a, G, grid, lds);
@@ -518,16 +616,28 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
                        s->invZ.get(), s->invZf.get());
     DRG_LAUNCH_CHECK();
     const double mean_len = (double)s->nnz / (double)n;
-    switch (pick_group(mean_len)) {
-        case 4: launch_row_weights<4>(ctx, s.get(), ec); break;
-        case 8: launch_row_weights<8>(ctx, s.get(), ec); break;
-        case 16: launch_row_weights<16>(ctx, s.get(), ec); break;
-        case 32: launch_row_weights<32>(ctx, s.get(), ec); break;
-        default: launch_row_weights<64>(ctx, s.get(), ec); break;
+    if (u) {
+        union_row_weights(ctx, s.get(), ec, u);
+    } else {
+        switch (pick_group(mean_len)) {
+            case 4: launch_row_weights<4>(ctx, s.get(), ec); break;
+            case 8: launch_row_weights<8>(ctx, s.get(), ec); break;
+            case 16: launch_row_weights<16>(ctx, s.get(), ec); break;
+            case 32: launch_row_weights<32>(ctx, s.get(), ec); break;
+            default: launch_row_weights<64>(ctx, s.get(), ec); break;
+        }
     }
     exclusive_scan<uint64_t>(s->W.get(), s->C.get(), n, st);
     DRG_HIP(hipMemcpyAsync(&s->S, s->C.get() + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     DRG_HIP(hipStreamSynchronize(st));
+    s->n_active = (int32_t)count_nonempty_rows<int64_t>(s->row_ptr.get(), n, st);
+    s->rec.alloc(n);
+    s->g.alloc(n);
+    if (u) {  // per-graph guides belong to the batch
+        s->gbits = 0;
+        DRG_HIP(hipStreamSynchronize(st));
+        return s.release();
+    }
     int gbits = 1;
     while (gbits < 30 && ((int64_t)1 << gbits) < n) ++gbits;
     s->gbits = gbits;
@@ -535,9 +645,6 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     hipLaunchKernelGGL(k_guide, dim3(ceil_div(((int64_t)1 << gbits) + 1, 256)), dim3(256), 0, st,
                        n, s->C.get(), gbits, s->guide.get());
     DRG_LAUNCH_CHECK();
-    s->n_active = (int32_t)count_nonempty_rows<int64_t>(s->row_ptr.get(), n, st);
-    s->rec.alloc(n);
-    s->g.alloc(n);
     DRG_HIP(hipStreamSynchronize(st));
     if (blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
     return s.release();
