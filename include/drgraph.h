@@ -53,6 +53,7 @@ typedef int32_t drg_status;
 typedef struct drg_ctx drg_ctx;
 typedef struct drg_sim drg_sim;
 typedef struct drg_hier drg_hier;
+typedef struct drg_batch drg_batch;
 
 /* Undirected graph in CSR form (device pointers, borrowed). */
 typedef struct {
@@ -246,6 +247,39 @@ drg_status drg_layout_run(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
 /* End to end: drg_build_similarity + drg_coarsen + drg_layout_run. */
 drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p,
                       float* y_out_dev);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent graphs laid out together (Sec. 3.2.2 iteration, Sec. 3.2.3
+ * multilevel scheme, synchronous mode).  graphs[count] and params[count] are
+ * host arrays; each drg_csr holds DEVICE pointers of one graph (the same
+ * contract as drg_layout: symmetric, sorted rows, no self-loops).  Every
+ * graph keeps its own parameters (M, b, T, gamma, gamma_coarsest, eta0, clip,
+ * rho, min_nodes, max_levels, seed); k and sigma must be equal over the batch
+ * and mode must be DRG_MODE_SYNC (else DRG_E_INVALID / DRG_E_UNSUPPORTED).
+ * The coordinates of graph c come out as the rows base_c .. base_c + n_c - 1
+ * of y_out_dev (float [sum n_c][2], device), base_c = n_0 + ... + n_{c-1},
+ * and equal, bit for bit, what drg_layout gives for that graph alone when its
+ * single-graph sweep is the row-per-group one (graphs below the column-blocked
+ * threshold).  The union must stay below 2^30 nodes and 2^31 input edges.
+ *
+ * drg_batch_create builds the similarity of all graphs at once, one hierarchy
+ * per graph and the per-graph schedules, then records the whole run (initial
+ * layout, T iterations, prolongations) into one hipGraph; the batch owns its
+ * device memory and the input graphs are not read afterwards.
+ * drg_batch_run replays that graph on the context's stream and copies the
+ * finest coordinates to y_out_dev; it returns when they are there.  Runs of
+ * one batch must not overlap. */
+drg_status drg_batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
+                            const drg_layout_params* params, drg_batch** out);
+/* Sizes: total nodes, total pattern entries, iterations of the longest
+ * schedule; nodes_host[count] and levels_host[count] (host, optional). */
+drg_status drg_batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,
+                          int32_t* nodes_host, int32_t* levels_host);
+drg_status drg_batch_run(drg_ctx* ctx, drg_batch* b, float* y_out_dev);
+void drg_batch_destroy(drg_batch* b);
+/* One shot: create, run once, destroy. */
+drg_status drg_layout_batched(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
+                              const drg_layout_params* params, float* y_out_dev);
 
 #pragma GCC visibility pop
 #ifdef __cplusplus

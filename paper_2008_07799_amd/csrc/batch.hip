@@ -1,0 +1,698 @@
+// batch.hip -- many independent graphs laid out together, every graph on
+// its own multilevel schedule (Sec. 3.2.3), synchronous iteration (Sec. 3.2.2).
+//
+// The graphs are joined into one union graph: graph c owns the node ids
+// base[c] .. base[c+1]-1.  The sparse similarity of the union is built in one
+// pass (a source's search stays inside its own graph, so its row is the row of
+// the single-graph build shifted by base[c]); the negatives of a node are drawn
+// from its own graph's sampling table.  Each graph keeps its own hierarchy,
+// iteration count, learning-rate schedule and parameters.
+//
+// Iteration t is three launches that each cover every graph, whatever level
+// the graph is at: stage (records of every finest node from its graph's
+// current level), sweep (waves own row ranges of one graph; a graph keeps the
+// lanes per row its single-graph sweep uses) and apply (one thread per node of
+// each graph's current level).  Prolongations run between iterations where a
+// graph moves to a finer level.  The whole run -- initial layout, T
+// iterations, prolongations -- is recorded once into a hipGraph and replayed
+// by every run.  Every node goes through the same per-node arithmetic as in
+// the single-graph path, so graph c of a batch reproduces its single-graph
+// layout bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <memory>
+
+#include "drg_forces.hpp"
+#include "drg_internal.hpp"
+
+namespace drg {
+
+struct BGraph {              // constants of graph c
+    int32_t base, n;         // finest nodes are union ids base .. base+n-1
+    int32_t G, b, M, L;      // lanes per row, exponent, negatives (0 if S = 0), levels
+    int32_t gbits, guide_off, lv_off, pad;
+    uint64_t S, Cbase;       // sampling total and C[base]
+    uint64_t seed;
+    float clip, pad2;
+};
+
+struct BLevel {              // graph c at level l
+    int32_t n;               // nodes of the level
+    int32_t pbase;           // union id of the graph's finest node 0
+    int64_t yoff;            // first coordinate of the level in the batch buffer
+    const int32_t* cmap;     // [n0] finest node -> level node (level >= 1)
+    const int32_t* seg;      // [n+1] member offsets into perm (level >= 1)
+    const int32_t* perm;     // [n0] finest members, ascending inside a node
+    const int32_t* map;      // [n_{l-1}] finer node -> node of this level (level >= 1)
+};
+
+struct BSched {              // graph c at iteration t
+    int32_t level;           // -1: the graph has finished
+    float eta, gamma;
+    int32_t pad;
+};
+
+// largest c in [0, count) with off[c] <= x (off ascending, off[0] = 0)
+__device__ __forceinline__ int32_t find_owner(const int32_t* __restrict__ off, int32_t count,
+                                              int64_t x) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)off[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ union graph
+struct UGraph {
+    const int32_t* rp;
+    const int32_t* col;
+    int32_t base, n;
+    int32_t ebase, nnz;
+};
+
+__global__ void k_union_nodes(int32_t N, int32_t count, const int32_t* __restrict__ nbase,
+                              const UGraph* __restrict__ ug, int32_t* __restrict__ urp,
+                              int32_t* __restrict__ node_base, int32_t* __restrict__ gid) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int32_t c = find_owner(nbase, count, j);
+    const UGraph u = ug[c];
+    const int32_t v = (int32_t)j - u.base;
+    urp[j] = u.ebase + u.rp[v];
+    node_base[j] = u.base;
+    gid[j] = c;
+    if (v == u.n - 1 && c == count - 1) urp[N] = u.ebase + u.rp[u.n];
+}
+
+__global__ void k_union_edges(int32_t E, int32_t count, const int32_t* __restrict__ ebase,
+                              const UGraph* __restrict__ ug, int32_t* __restrict__ ucol) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= E) return;
+    const int32_t c = find_owner(ebase, count, x);
+    const UGraph u = ug[c];
+    ucol[x] = u.col[x - u.ebase] + u.base;
+}
+
+// Row offsets of every graph lie inside its own edge range, ascending, and
+// start and end where its nnz says.
+__global__ void k_check_union_rows(int32_t N, const int32_t* __restrict__ gid,
+                                   const UGraph* __restrict__ ug, const int32_t* __restrict__ urp,
+                                   int* __restrict__ bad) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const UGraph u = ug[gid[j]];
+    const int32_t a = urp[j], e = urp[j + 1];
+    bool ok = a >= u.ebase && e <= u.ebase + u.nnz && e >= a;
+    if (j == u.base) ok = ok && a == u.ebase;
+    if (j == (int64_t)u.base + u.n - 1) ok = ok && e == u.ebase + u.nnz;
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_check_union_cols(int32_t N, const int32_t* __restrict__ gid,
+                                   const UGraph* __restrict__ ug, const int32_t* __restrict__ urp,
+                                   const int32_t* __restrict__ ucol, int* __restrict__ bad) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const UGraph u = ug[gid[j]];
+    for (int32_t x = urp[j]; x < urp[j + 1]; ++x) {
+        const int32_t v = ucol[x];
+        if (v < u.base || v >= u.base + u.n) {
+            atomicOr(bad, 2);
+            return;
+        }
+    }
+}
+
+__global__ void k_count_active(int32_t N, const int32_t* __restrict__ gid,
+                               const int64_t* __restrict__ prp, int32_t* __restrict__ cnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N && prp[j + 1] > prp[j]) atomicAdd(&cnt[gid[j]], 1);
+}
+
+// ------------------------------------------------------------------ sampling guides
+// Per graph: guide[b] = draw result of the smallest word of bucket b, and
+// guide[2^gbits] that of the largest word (as the single-graph table).
+__global__ void k_b_guide(int32_t total, int32_t count, const int32_t* __restrict__ goff,
+                          const BGraph* __restrict__ gt, const uint64_t* __restrict__ C,
+                          int32_t* __restrict__ guide) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const int32_t c = find_owner(goff, count, x);
+    const BGraph g = gt[c];
+    const int64_t b = x - goff[c];
+    const int64_t nb = (int64_t)1 << g.gbits;
+    if (g.S == 0) {
+        guide[x] = 0;
+        return;
+    }
+    const uint64_t r = b < nb ? __umul64hi((uint64_t)b << (64 - g.gbits), g.S) : g.S - 1;
+    const uint64_t* Cg = C + g.base;
+    int32_t lo = 0, hi = g.n - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (Cg[mid + 1] - g.Cbase > r)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    guide[x] = lo;
+}
+
+// Negative draw inside graph g: the local v with C_g[v+1] > floor(w S_g / 2^64).
+__device__ __forceinline__ int32_t draw_in_graph(uint64_t w, const uint64_t* __restrict__ C,
+                                                 const int32_t* __restrict__ guide,
+                                                 const BGraph& g) {
+    const uint64_t r = __umul64hi(w, g.S);
+    const uint32_t bkt = (uint32_t)(w >> (64 - g.gbits));
+    const int32_t* gd = guide + g.guide_off;
+    const uint64_t* Cg = C + g.base;
+    int32_t lo = gd[bkt], hi = gd[bkt + 1];
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (Cg[mid + 1] - g.Cbase > r)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ iteration kernels
+__global__ void k_b_init(int32_t total, int32_t count, const int32_t* __restrict__ off,
+                         const BGraph* __restrict__ gt, const BLevel* __restrict__ lt,
+                         float2* __restrict__ y) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const int32_t c = find_owner(off, count, x);
+    const BGraph g = gt[c];
+    const int32_t v = (int32_t)(x - off[c]);
+    y[lt[g.lv_off + g.L - 1].yoff + v] = init_point<float>(v, g.L - 1, g.seed);
+}
+
+__global__ void k_b_stage(int32_t N, int32_t count, int32_t t, const int32_t* __restrict__ gid,
+                          const BGraph* __restrict__ gt, const BLevel* __restrict__ lt,
+                          const BSched* __restrict__ sched, const float* __restrict__ invZ,
+                          const float2* __restrict__ y, float4* __restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int32_t c = gid[j];
+    const int32_t l = sched[(int64_t)t * count + c].level;
+    if (l < 0) return;
+    const BGraph g = gt[c];
+    const BLevel d = lt[g.lv_off + l];
+    const int32_t v = (int32_t)j - g.base;
+    const float2 p = y[d.yoff + (l == 0 ? v : d.cmap[v])];
+    rec[j] = mk4<float>(p.x, p.y, invZ[j], 0.0f);
+}
+
+struct BSweepArgs {
+    int32_t count, t;
+    const int32_t* woff;      // [count+1] waves of each graph
+    const BGraph* gt;
+    const BSched* sched;
+    const int64_t* prp;
+    const uint32_t* colhop;
+    const float4* rec;
+    const float* qt;
+    const uint64_t* C;
+    const int32_t* guide;
+    float2* g;
+    HalfE<float> eh;
+};
+
+template <int B>
+__device__ __forceinline__ float2 b_row(const BSweepArgs& a, const BGraph& g, int64_t i,
+                                        int32_t v, int lane, float gamma) {
+    return sweep_row<float, B>(a.rec[i], a.prp[i], a.prp[i + 1], lane, g.G, a.colhop, a.rec, a.eh,
+                               g.clip, g.M, g.seed, (uint64_t)a.t, v,
+                               [&](uint64_t w) {
+                                   return g.base + draw_in_graph(w, a.C, a.guide, g);
+                               },
+                               gamma * a.qt[i]);
+}
+
+// Graph c owns waves woff[c] .. woff[c+1]-1; each handles 64/G consecutive rows.
+__global__ __launch_bounds__(256) void k_b_sweep(BSweepArgs a) {
+    const int32_t total = a.woff[a.count];
+    const int32_t nwaves = (int32_t)(gridDim.x * (blockDim.x / WAVE));
+    for (int32_t gw = __builtin_amdgcn_readfirstlane(
+             (int32_t)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE));
+         gw < total; gw += nwaves) {
+        const int32_t c = find_owner(a.woff, a.count, gw);
+        const BSched sc = a.sched[(int64_t)a.t * a.count + c];
+        if (sc.level < 0) continue;
+        const BGraph g = a.gt[c];
+        const int lane = __lane_id() % g.G;
+        const int32_t v = (gw - a.woff[c]) * (WAVE / g.G) + (int32_t)(__lane_id() / g.G);
+        if (v >= g.n) continue;
+        const int64_t i = (int64_t)g.base + v;
+        float2 gi = make_float2(0.0f, 0.0f);
+        if (a.prp[i] < a.prp[i + 1]) {
+            if (g.b == 1)
+                gi = b_row<1>(a, g, i, v, lane, sc.gamma);
+            else if (g.b == 2)
+                gi = b_row<2>(a, g, i, v, lane, sc.gamma);
+            else
+                gi = b_row<3>(a, g, i, v, lane, sc.gamma);
+        }
+        if (lane == 0) a.g[i] = gi;
+    }
+}
+
+// One thread per node of each graph's current level (off: this phase's prefix).
+__global__ void k_b_apply(int32_t total, int32_t count, int32_t t, const int32_t* __restrict__ off,
+                          const BGraph* __restrict__ gt, const BLevel* __restrict__ lt,
+                          const BSched* __restrict__ sched, const float2* __restrict__ g,
+                          const float* __restrict__ qt, float2* __restrict__ y) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const int32_t c = find_owner(off, count, x);
+    const BSched sc = sched[(int64_t)t * count + c];
+    const BGraph gg = gt[c];
+    const BLevel d = lt[gg.lv_off + sc.level];
+    const int32_t v = (int32_t)(x - off[c]);
+    if (sc.level == 0) {
+        const int64_t i = (int64_t)gg.base + v;
+        apply_node<float>(g[i], qt[i], y + d.yoff + v, sc.eta);
+    } else {
+        apply_group<float>(d.seg[v], d.seg[v + 1], d.perm, d.pbase, g, qt, y + d.yoff + v,
+                           sc.eta);
+    }
+}
+
+// y_{l-1}[u] = y_l[map_l[u]] for the graphs of one prolongation round.
+__global__ void k_b_prolong(int32_t total, int32_t m, const int32_t* __restrict__ off,
+                            const int2* __restrict__ ops, const BGraph* __restrict__ gt,
+                            const BLevel* __restrict__ lt, float2* __restrict__ y) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const int32_t k = find_owner(off, m, x);
+    const int2 op = ops[k];  // (graph, level left)
+    const BGraph g = gt[op.x];
+    const BLevel d = lt[g.lv_off + op.y];
+    const BLevel f = lt[g.lv_off + op.y - 1];
+    const int32_t u = (int32_t)(x - off[k]);
+    y[f.yoff + u] = y[d.yoff + d.map[u]];
+}
+
+}  // namespace drg
+
+// ------------------------------------------------------------------ the batch
+struct drg_batch {
+    int device = 0;
+    int32_t count = 0, T = 0;
+    int64_t n_total = 0, nnz_total = 0, y_total = 0;
+    std::vector<int32_t> base, levels;
+    std::unique_ptr<drg_sim, void (*)(drg_sim*)> sim{nullptr, drg_sim_destroy};
+    drg::UnionHier hier;
+    drg::DevBuf<drg::BGraph> gt;
+    drg::DevBuf<drg::BLevel> lt;
+    drg::DevBuf<drg::BSched> sched;
+    drg::DevBuf<int32_t> gid, guide, woff, init_off, phase_off, pro_off;
+    drg::DevBuf<int2> pro_ops;
+    drg::DevBuf<float2> y;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~drg_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace drg {
+
+void check_layout_params(const drg_layout_params* p) {
+    if (!p) throw Error(DRG_E_INVALID, "params is NULL");
+    if (p->T < 0) throw Error(DRG_E_INVALID, "T must be >= 0");
+    if (p->M < 0 || p->b < 1 || p->b > 3) throw Error(DRG_E_INVALID, "M >= 0, b in 1..3");
+    if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "clip must be > 0");
+    if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
+        throw Error(DRG_E_INVALID, "unknown mode");
+}
+
+template <typename T>
+static void upload(DevBuf<T>& d, const std::vector<T>& h, hipStream_t st) {
+    d.alloc((int64_t)h.size());
+    if (!h.empty())
+        DRG_HIP(hipMemcpyAsync(d.get(), h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, st));
+}
+
+static int read_flag(DevBuf<int>& f, hipStream_t s) {
+    int h = 0;
+    DRG_HIP(hipMemcpyAsync(&h, f.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    DRG_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
+                        const drg_layout_params* params) {
+    if (!graphs || !params) throw Error(DRG_E_INVALID, "graphs or params is NULL");
+    if (count < 1) throw Error(DRG_E_INVALID, "count must be >= 1");
+    for (int32_t c = 0; c < count; ++c) {
+        const drg_layout_params& p = params[c];
+        check_layout_params(&p);
+        if (p.mode != DRG_MODE_SYNC)
+            throw Error(DRG_E_UNSUPPORTED, "batched layout: synchronous mode only");
+        if (p.k != params[0].k || p.sigma != params[0].sigma)
+            throw Error(DRG_E_INVALID, "batched layout: k and sigma must agree over the batch");
+        if (!(p.rho > 0.0 && p.rho <= 1.0) || p.max_levels < 1 || p.min_nodes < 0)
+            throw Error(DRG_E_INVALID, "batched layout: bad coarsening parameters");
+        const drg_csr& g = graphs[c];
+        if (g.n <= 0 || g.nnz < 0 || !g.row_ptr || (g.nnz > 0 && !g.col))
+            throw Error(DRG_E_INVALID, "batched layout: bad CSR of graph " + std::to_string(c));
+    }
+    hipStream_t st = ctx->stream;
+    auto b = std::make_unique<drg_batch>();
+    b->device = ctx->device;
+    b->count = count;
+    // ---- union graph
+    std::vector<int32_t> nbase(count + 1, 0), ebase(count + 1, 0);
+    std::vector<UGraph> ug(count);
+    int32_t max_comp = 0;
+    for (int32_t c = 0; c < count; ++c) {
+        const int64_t nb = (int64_t)nbase[c] + graphs[c].n;
+        const int64_t eb = (int64_t)ebase[c] + graphs[c].nnz;
+        if (nb >= ((int64_t)1 << 30) || eb >= ((int64_t)1 << 31))
+            throw Error(DRG_E_INVALID, "batched layout: union exceeds 2^30 nodes or 2^31 edges");
+        nbase[c + 1] = (int32_t)nb;
+        ebase[c + 1] = (int32_t)eb;
+        ug[c] = UGraph{graphs[c].row_ptr, graphs[c].col, nbase[c], graphs[c].n, ebase[c],
+                       (int32_t)graphs[c].nnz};
+        max_comp = std::max(max_comp, graphs[c].n);
+    }
+    const int32_t N = nbase[count], E = ebase[count];
+    b->n_total = N;
+    b->base = nbase;
+    DevBuf<UGraph> dug;
+    DevBuf<int32_t> dnb, deb, urp((int64_t)N + 1), ucol(E), node_base(N);
+    upload(dug, ug, st);
+    upload(dnb, nbase, st);
+    upload(deb, ebase, st);
+    b->gid.alloc(N);
+    hipLaunchKernelGGL(k_union_nodes, dim3(ceil_div(N, 256)), dim3(256), 0, st, N, count,
+                       dnb.get(), dug.get(), urp.get(), node_base.get(), b->gid.get());
+    DRG_LAUNCH_CHECK();
+    if (E > 0) {
+        hipLaunchKernelGGL(k_union_edges, dim3(ceil_div(E, 256)), dim3(256), 0, st, E, count,
+                           deb.get(), dug.get(), ucol.get());
+        DRG_LAUNCH_CHECK();
+    }
+    {
+        DevBuf<int> bad(1);
+        DRG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
+        hipLaunchKernelGGL(k_check_union_rows, dim3(ceil_div(N, 256)), dim3(256), 0, st, N,
+                           b->gid.get(), dug.get(), urp.get(), bad.get());
+        DRG_LAUNCH_CHECK();
+        if (read_flag(bad, st)) throw Error(DRG_E_GRAPH, "row_ptr is not a valid offset array");
+        hipLaunchKernelGGL(k_check_union_cols, dim3(ceil_div(N, 256)), dim3(256), 0, st, N,
+                           b->gid.get(), dug.get(), urp.get(), ucol.get(), bad.get());
+        DRG_LAUNCH_CHECK();
+        if (read_flag(bad, st)) throw Error(DRG_E_GRAPH, "column index out of range");
+    }
+    // ---- similarity of the union
+    drg_csr uc{N, E, urp.get(), ucol.get()};
+    UnionInfo ui;
+    ui.count = count;
+    ui.base = nbase;
+    ui.node_base = node_base.get();
+    ui.max_comp = max_comp;
+    b->sim.reset(build_similarity(ctx, &uc, params[0].k, params[0].sigma, 0, &ui));
+    drg_sim* s = b->sim.get();
+    b->nnz_total = s->nnz;
+    // per-graph active rows and sampling totals
+    std::vector<int32_t> nact(count, 0);
+    std::vector<uint64_t> Cb(count + 1, 0);
+    {
+        DevBuf<int32_t> cnt(count);
+        DRG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * count, st));
+        hipLaunchKernelGGL(k_count_active, dim3(ceil_div(N, 256)), dim3(256), 0, st, N,
+                           b->gid.get(), s->row_ptr.get(), cnt.get());
+        DRG_LAUNCH_CHECK();
+        DRG_HIP(hipMemcpyAsync(nact.data(), cnt.get(), sizeof(int32_t) * count,
+                               hipMemcpyDeviceToHost, st));
+        for (int32_t c = 0; c <= count; ++c)
+            DRG_HIP(hipMemcpyAsync(&Cb[c], s->C.get() + nbase[c], sizeof(uint64_t),
+                                   hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+    }
+    // ---- hierarchies of all graphs, level by level over the union
+    build_hierarchy_union(ctx, &uc, b->gid.get(), nbase, params, b->hier);
+    // ---- per-graph tables
+    std::vector<BGraph> gt(count);
+    std::vector<BLevel> lt;
+    std::vector<int32_t> goff(count + 1, 0), woff(count + 1, 0);
+    b->levels.resize(count);
+    int64_t yoff = N;  // finest coordinates first, in union order
+    for (int32_t c = 0; c < count; ++c) {
+        const drg_layout_params& p = params[c];
+        const int32_t L = (int32_t)b->hier.n[c].size();
+        const int32_t n = graphs[c].n;
+        BGraph& g = gt[c];
+        g.base = nbase[c];
+        g.n = n;
+        g.G = sweep_group((double)ui.nnz[c] / (double)std::max(1, nact[c]));
+        g.b = p.b;
+        g.S = Cb[c + 1] - Cb[c];
+        g.Cbase = Cb[c];
+        g.M = g.S > 0 ? p.M : 0;
+        g.L = L;
+        int gbits = 1;
+        while (gbits < 30 && ((int64_t)1 << gbits) < n) ++gbits;
+        g.gbits = gbits;
+        g.guide_off = goff[c];
+        goff[c + 1] = goff[c] + (1 << gbits) + 1;
+        g.lv_off = (int32_t)lt.size();
+        g.seed = p.seed;
+        g.clip = p.clip;
+        const int64_t w = ((int64_t)n + WAVE / g.G - 1) / (WAVE / g.G);
+        if ((int64_t)woff[c] + w >= ((int64_t)1 << 31))
+            throw Error(DRG_E_INVALID, "batched layout: too many rows");
+        woff[c + 1] = woff[c] + (int32_t)w;
+        b->levels[c] = L;
+        for (int32_t l = 0; l < L; ++l) {
+            BLevel d{};
+            d.n = b->hier.n[c][l];
+            d.pbase = nbase[c];
+            if (l == 0) {
+                d.yoff = nbase[c];
+            } else {
+                const UnionHier::Pool& P = b->hier.lv[l];
+                d.yoff = yoff;
+                yoff += d.n;
+                d.cmap = P.cmap.get() + P.co[c];
+                d.seg = P.seg.get() + P.so[c];
+                d.perm = P.perm.get() + P.co[c];
+                d.map = P.map.get() + P.mo[c];
+            }
+            lt.push_back(d);
+        }
+    }
+    b->y_total = yoff;
+    upload(b->gt, gt, st);
+    upload(b->lt, lt, st);
+    upload(b->woff, woff, st);
+    {
+        DevBuf<int32_t> dgoff;
+        upload(dgoff, goff, st);
+        b->guide.alloc(goff[count]);
+        hipLaunchKernelGGL(k_b_guide, dim3(ceil_div(goff[count], 256)), dim3(256), 0, st,
+                           goff[count], count, dgoff.get(), b->gt.get(), s->C.get(),
+                           b->guide.get());
+        DRG_LAUNCH_CHECK();
+        DRG_HIP(hipStreamSynchronize(st));
+    }
+    // ---- schedules: graph c spends T_c / L_c iterations per level, coarsest
+    // first, the remainder at the finest; prolongation after each coarse level
+    int32_t T = 0;
+    for (int32_t c = 0; c < count; ++c) T = std::max(T, params[c].T);
+    b->T = T;
+    std::vector<BSched> sch((size_t)T * count);
+    // prolongation rounds before iteration t (t = 0..T): (t, round) -> ops
+    std::map<std::pair<int32_t, int32_t>, std::vector<int2>> pro;
+    for (int32_t c = 0; c < count; ++c) {
+        const drg_layout_params& p = params[c];
+        const int32_t L = gt[c].L;
+        const int32_t per = p.T / L;
+        int32_t t = 0;
+        for (int32_t l = L - 1; l >= 0; --l) {
+            const int32_t Tl = per + (l == 0 ? p.T - per * L : 0);
+            const float gam = (l == L - 1 && L > 1) ? p.gamma_coarsest : p.gamma;
+            for (int32_t s2 = 0; s2 < Tl; ++s2, ++t) {
+                BSched& e = sch[(size_t)t * count + c];
+                e.level = l;
+                e.eta = (float)((double)p.eta0 * (1.0 - (double)s2 / (double)Tl));
+                e.gamma = gam;
+            }
+            if (l > 0) {
+                int32_t round = 0;
+                while (pro.count({t, round}) && !pro[{t, round}].empty() &&
+                       pro[{t, round}].back().x == c)
+                    ++round;
+                pro[{t, round}].push_back(make_int2(c, l));
+            }
+        }
+        for (; t < T; ++t) sch[(size_t)t * count + c].level = -1;
+    }
+    upload(b->sched, sch, st);
+    // apply phases: runs of iterations with the same level in every graph
+    std::vector<int32_t> phase_of(T, 0), ph;
+    std::vector<int32_t> phase_total;
+    for (int32_t t = 0; t < T; ++t) {
+        bool same = t > 0;
+        for (int32_t c = 0; same && c < count; ++c)
+            same = sch[(size_t)t * count + c].level == sch[(size_t)(t - 1) * count + c].level;
+        if (!same) {
+            const size_t o = ph.size();
+            ph.resize(o + count + 1);
+            ph[o] = 0;
+            for (int32_t c = 0; c < count; ++c) {
+                const int32_t l = sch[(size_t)t * count + c].level;
+                ph[o + c + 1] = ph[o + c] + (l < 0 ? 0 : lt[gt[c].lv_off + l].n);
+            }
+            phase_total.push_back(ph[o + count]);
+        }
+        phase_of[t] = (int32_t)phase_total.size() - 1;
+    }
+    upload(b->phase_off, ph, st);
+    // prolongation rounds: ops and per-op node prefix, concatenated
+    struct Round {
+        int32_t t, ofirst, pfirst, m, total;
+    };
+    std::vector<Round> rounds;
+    std::vector<int2> ops;
+    std::vector<int32_t> poff;
+    for (auto& kv : pro) {  // ascending (t, round)
+        Round r{kv.first.first, (int32_t)ops.size(), (int32_t)poff.size(),
+                (int32_t)kv.second.size(), 0};
+        poff.push_back(0);
+        for (const int2& op : kv.second) {
+            ops.push_back(op);
+            poff.push_back(poff.back() + lt[gt[op.x].lv_off + op.y - 1].n);
+        }
+        r.total = poff.back();
+        rounds.push_back(r);
+    }
+    upload(b->pro_ops, ops, st);
+    upload(b->pro_off, poff, st);
+    std::vector<int32_t> ioff(count + 1, 0);
+    for (int32_t c = 0; c < count; ++c)
+        ioff[c + 1] = ioff[c] + lt[gt[c].lv_off + gt[c].L - 1].n;
+    upload(b->init_off, ioff, st);
+    b->y.alloc(b->y_total);
+    DRG_HIP(hipStreamSynchronize(st));
+    // ---- record the whole run into a graph
+    hipStream_t cap = nullptr;
+    DRG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{cap};
+    DRG_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    try {
+        hipLaunchKernelGGL(k_b_init, dim3(ceil_div(ioff[count], 256)), dim3(256), 0, cap,
+                           ioff[count], count, b->init_off.get(), b->gt.get(), b->lt.get(),
+                           b->y.get());
+        DRG_LAUNCH_CHECK();
+        size_t ri = 0;
+        auto prolong_rounds = [&](int32_t t) {
+            for (; ri < rounds.size() && rounds[ri].t == t; ++ri) {
+                const Round& r = rounds[ri];
+                if (r.total > 0) {
+                    hipLaunchKernelGGL(k_b_prolong, dim3(ceil_div(r.total, 256)), dim3(256), 0,
+                                       cap, r.total, r.m, b->pro_off.get() + r.pfirst,
+                                       b->pro_ops.get() + r.ofirst, b->gt.get(), b->lt.get(),
+                                       b->y.get());
+                    DRG_LAUNCH_CHECK();
+                }
+            }
+        };
+        BSweepArgs sa{};
+        sa.count = count;
+        sa.woff = b->woff.get();
+        sa.gt = b->gt.get();
+        sa.sched = b->sched.get();
+        sa.prp = s->row_ptr.get();
+        sa.colhop = s->colhop.get();
+        sa.rec = s->rec.get();
+        sa.qt = s->qtf.get();
+        sa.C = s->C.get();
+        sa.guide = b->guide.get();
+        sa.g = s->g.get();
+        sa.eh = HalfE<float>{(float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]),
+                             (float)(0.5 * s->e[2]), (float)(0.5 * s->e[3])};
+        const int64_t sweep_blocks = std::max<int64_t>(
+            1, std::min<int64_t>(((int64_t)woff[count] + 3) / 4, (int64_t)ctx->num_cu * 64));
+        for (int32_t t = 0; t < T; ++t) {
+            prolong_rounds(t);
+            hipLaunchKernelGGL(k_b_stage, dim3(ceil_div(N, 256)), dim3(256), 0, cap, N, count, t,
+                               b->gid.get(), b->gt.get(), b->lt.get(), b->sched.get(),
+                               s->invZf.get(), b->y.get(), s->rec.get());
+            DRG_LAUNCH_CHECK();
+            sa.t = t;
+            hipLaunchKernelGGL(k_b_sweep, dim3((unsigned)sweep_blocks), dim3(256), 0, cap, sa);
+            DRG_LAUNCH_CHECK();
+            const int32_t p = phase_of[t];
+            const int32_t tot = phase_total[p];
+            if (tot > 0) {
+                hipLaunchKernelGGL(k_b_apply, dim3(ceil_div(tot, 256)), dim3(256), 0, cap, tot,
+                                   count, t, b->phase_off.get() + (int64_t)p * (count + 1),
+                                   b->gt.get(), b->lt.get(), b->sched.get(), s->g.get(),
+                                   s->qtf.get(), b->y.get());
+                DRG_LAUNCH_CHECK();
+            }
+        }
+        prolong_rounds(T);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    DRG_HIP(hipStreamEndCapture(cap, &b->graph));
+    DRG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return b.release();
+}
+
+void batch_run(drg_ctx* ctx, drg_batch* b, float* y_out) {
+    if (!b || !y_out) throw Error(DRG_E_INVALID, "batch or y_out is NULL");
+    if (b->device != ctx->device) throw Error(DRG_E_INVALID, "batch is of another device");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+        DRG_HIP(hipEventCreate(&e0));
+        DRG_HIP(hipEventCreate(&e1));
+        DRG_HIP(hipEventRecord(e0, ctx->stream));
+    }
+    DRG_HIP(hipGraphLaunch(b->exec, ctx->stream));
+    if (ctx->profiling) {
+        DRG_HIP(hipEventRecord(e1, ctx->stream));
+        ctx->events.emplace_back(e0, e1);
+    }
+    DRG_HIP(hipMemcpyAsync(y_out, b->y.get(), sizeof(float2) * b->n_total,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+    DRG_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+void batch_destroy(drg_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    delete b;
+}
+
+void batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,
+                int32_t* nodes, int32_t* levels) {
+    if (!b) throw Error(DRG_E_INVALID, "batch is NULL");
+    if (n_total) *n_total = b->n_total;
+    if (nnz_total) *nnz_total = b->nnz_total;
+    if (T) *T = b->T;
+    for (int32_t c = 0; c < b->count; ++c) {
+        if (nodes) nodes[c] = b->base[c + 1] - b->base[c];
+        if (levels) levels[c] = b->levels[c];
+    }
+}
+
+}  // namespace drg

@@ -338,14 +338,7 @@ drg_status drg_sim_coo(drg_ctx* ctx, const drg_sim* s, int32_t* rows_dev, int32_
     });
 }
 
-static void check_layout_params(const drg_layout_params* p) {
-    need(p, "params");
-    if (p->T < 0) throw Error(DRG_E_INVALID, "T must be >= 0");
-    if (p->M < 0 || p->b < 1 || p->b > 3) throw Error(DRG_E_INVALID, "M >= 0, b in 1..3");
-    if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "clip must be > 0");
-    if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
-        throw Error(DRG_E_INVALID, "unknown mode");
-}
+using drg::check_layout_params;
 
 static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_layout_params* p,
                          float* y_out) {
@@ -407,6 +400,44 @@ drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p
             drg::build_hierarchy(ctx, g, p->seed, p->rho, p->min_nodes, p->max_levels),
             drg_hier_destroy);
         run_schedule(ctx, s.get(), h.get(), p, y_out_dev);
+    });
+}
+
+drg_status drg_batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
+                            const drg_layout_params* params, drg_batch** out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(out, "out");
+        *out = nullptr;
+        use_device(ctx->device);
+        *out = drg::batch_create(ctx, graphs, count, params);
+    });
+}
+
+drg_status drg_batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,
+                          int32_t* nodes_host, int32_t* levels_host) {
+    return guarded([&] { drg::batch_info(b, n_total, nnz_total, T, nodes_host, levels_host); });
+}
+
+drg_status drg_batch_run(drg_ctx* ctx, drg_batch* b, float* y_out_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::batch_run(ctx, b, y_out_dev);
+    });
+}
+
+void drg_batch_destroy(drg_batch* b) { drg::batch_destroy(b); }
+
+drg_status drg_layout_batched(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
+                              const drg_layout_params* params, float* y_out_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(y_out_dev, "y_out");
+        use_device(ctx->device);
+        std::unique_ptr<drg_batch, void (*)(drg_batch*)> b(
+            drg::batch_create(ctx, graphs, count, params), drg_batch_destroy);
+        drg::batch_run(ctx, b.get(), y_out_dev);
     });
 }
 

@@ -133,6 +133,7 @@ struct ContractArgs {
     int32_t* ccol;         // fill pass
     uint32_t* gbm;
     int32_t* work;
+    const int32_t* node_base;  // per coarse node: first coarse id of its graph (NULL: 0)
 };
 
 template <bool FILL, bool LDS_BM, int G>
@@ -149,12 +150,14 @@ __global__ __launch_bounds__(CT_BLOCK) void k_contract(ContractArgs a) {
         __syncthreads();
         const int32_t c = s_c;
         if (c >= a.nc) break;
+        // bitmap bit of coarse node t is t - cb: a group only reaches its own graph
+        const int32_t cb = a.node_base ? a.node_base[c] : 0;
         const int32_t mb = a.seg[c], me = a.seg[c + 1];
         for (int32_t fi = tid / G; fi < me - mb; fi += CT_BLOCK / G) {
             const int32_t u = a.perm[mb + fi];
             for (int32_t x = a.rp[u] + (tid % G); x < a.rp[u + 1]; x += G) {
                 const int32_t t = a.map[a.col[x]];
-                if (t != c) atomicOr(&bm[t >> 5], 1u << (t & 31));
+                if (t != c) atomicOr(&bm[(t - cb) >> 5], 1u << ((t - cb) & 31));
             }
         }
         __syncthreads();
@@ -163,8 +166,9 @@ __global__ __launch_bounds__(CT_BLOCK) void k_contract(ContractArgs a) {
             if (tid == 0) a.cnt[c] = total;
         } else {
             int32_t* out = a.ccol;
-            bitmap_emit_clear<CT_BLOCK, CT_WPT>(bm, a.nwords, -1, (int64_t)a.crp[c], s_red,
-                                               [&](int64_t o, uint32_t v) { out[o] = (int32_t)v; });
+            bitmap_emit_clear<CT_BLOCK, CT_WPT>(
+                bm, a.nwords, -1, (int64_t)a.crp[c], s_red,
+                [&](int64_t o, uint32_t v) { out[o] = cb + (int32_t)v; });
         }
         __syncthreads();
     }
@@ -212,14 +216,72 @@ static void group_by(drg_ctx* ctx, int32_t n, int32_t nc, const int32_t* map, in
     DRG_HIP(hipStreamSynchronize(st));
 }
 
-// One level: map (n -> nc) and the contracted graph.
+// A union of graphs being coarsened together: node v belongs to graph
+// gid[v], whose nodes start at gbase[gid[v]] (device arrays indexed by graph).
+struct UnionLevel {
+    const int32_t* gid = nullptr;
+    const int32_t* gbase = nullptr;
+    const uint64_t* gseed = nullptr;
+    std::vector<int32_t> members;   // graphs of the union, ascending
+    std::vector<int32_t> hbase;     // [count] node base of each member (host)
+    std::vector<int32_t> hn;        // [count] node count of each member (host)
+    // out
+    std::vector<int32_t> cbase, cn; // [count] coarse base and size of each member
+    DevBuf<int32_t> cgid;           // [nc] graph of each coarse node
+};
+
+__global__ void k_prio_union(int32_t n, const int32_t* __restrict__ gid,
+                             const int32_t* __restrict__ gbase, const uint64_t* __restrict__ gseed,
+                             int32_t level, uint64_t* __restrict__ pri) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = gid[v];
+    pri[v] = philox4x64((uint64_t)(uint32_t)((int32_t)v - gbase[c]), (uint64_t)(uint32_t)level, 0,
+                        0, gseed[c], TAG_COARSEN)
+                 .w[0];
+}
+
+// Graph and coarse base of every coarse node, from its first member.
+__global__ void k_coarse_owner(int32_t nc, const int32_t* __restrict__ seg,
+                               const int32_t* __restrict__ perm, const int32_t* __restrict__ gid,
+                               const int32_t* __restrict__ cbase, int32_t* __restrict__ cgid,
+                               int32_t* __restrict__ cnb) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nc) return;
+    const int32_t c = gid[perm[seg[u]]];
+    cgid[u] = c;
+    cnb[u] = cbase[c];
+}
+
+__global__ void k_gather_i32(int32_t m, const int32_t* __restrict__ at,
+                             const int32_t* __restrict__ src, int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) out[i] = src[at[i]];
+}
+
+template <typename T>
+static void to_dev(DevBuf<T>& d, const std::vector<T>& h, hipStream_t st) {
+    d.alloc((int64_t)h.size());
+    if (!h.empty())
+        DRG_HIP(hipMemcpyAsync(d.get(), h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, st));
+}
+
+// One level: map (n -> nc) and the contracted graph.  With u, the graphs of
+// a union are coarsened at once: priorities are keyed by each graph's own
+// node ids and seed, coarse ids of a graph are contiguous (its centres in id
+// order), and map values and coarse columns are union coarse ids.
 static void coarsen_one(drg_ctx* ctx, int32_t n, const int32_t* rp, const int32_t* col,
-                        int64_t nnz, uint64_t seed, int32_t level, drg_level& out) {
+                        int64_t nnz, uint64_t seed, int32_t level, drg_level& out,
+                        UnionLevel* u = nullptr) {
     hipStream_t st = ctx->stream;
     DevBuf<uint64_t> pri(n);
     DevBuf<int32_t> state(n), owner(n), is_centre(n), rank((int64_t)n + 1), flag(1);
-    hipLaunchKernelGGL(k_prio, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, seed, level,
-                       pri.get());
+    if (u)
+        hipLaunchKernelGGL(k_prio_union, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, u->gid,
+                           u->gbase, u->gseed, level, pri.get());
+    else
+        hipLaunchKernelGGL(k_prio, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, seed, level,
+                           pri.get());
     DRG_LAUNCH_CHECK();
     DRG_HIP(hipMemsetAsync(state.get(), 0, sizeof(int32_t) * n, st));
     for (int round = 0;; ++round) {
@@ -248,7 +310,49 @@ static void coarsen_one(drg_ctx* ctx, int32_t n, const int32_t* rp, const int32_
     // members of each coarse node, then the contracted adjacency
     DevBuf<int32_t> perm(n), seg((int64_t)nc + 1), cnt(nc);
     group_by(ctx, n, nc, out.map.get(), perm.get(), seg.get());
-    const int nwords = (nc + 31) / 32;
+    int32_t span = nc;
+    DevBuf<int32_t> cnb;
+    if (u) {
+        // coarse base of every member graph = rank of its first node
+        const int32_t m = (int32_t)u->members.size();
+        std::vector<int32_t> at(2 * m);
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t c = u->members[i];
+            at[2 * i] = u->hbase[c];
+            at[2 * i + 1] = u->hbase[c] + u->hn[c];
+        }
+        DevBuf<int32_t> dat, dv(2 * m);
+        to_dev(dat, at, st);
+        hipLaunchKernelGGL(k_gather_i32, dim3(ceil_div(2 * m, 256)), dim3(256), 0, st, 2 * m,
+                           dat.get(), rank.get(), dv.get());
+        DRG_LAUNCH_CHECK();
+        std::vector<int32_t> hv(2 * m);
+        DRG_HIP(hipMemcpyAsync(hv.data(), dv.get(), sizeof(int32_t) * 2 * m,
+                               hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+        const int32_t count = (int32_t)u->hbase.size();
+        u->cbase.assign(count, -1);
+        u->cn.assign(count, 0);
+        span = 1;
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t c = u->members[i];
+            u->cbase[c] = hv[2 * i];
+            u->cn[c] = hv[2 * i + 1] - hv[2 * i];
+            span = std::max(span, u->cn[c]);
+        }
+        DevBuf<int32_t> dcb;
+        to_dev(dcb, u->cbase, st);
+        u->cgid.alloc(nc);
+        cnb.alloc(nc);
+        if (nc > 0) {
+            hipLaunchKernelGGL(k_coarse_owner, dim3(ceil_div(nc, 256)), dim3(256), 0, st, nc,
+                               seg.get(), perm.get(), u->gid, dcb.get(), u->cgid.get(),
+                               cnb.get());
+            DRG_LAUNCH_CHECK();
+        }
+        DRG_HIP(hipStreamSynchronize(st));
+    }
+    const int nwords = (span + 31) / 32;
     const size_t lds = (size_t)nwords * 4;
     const bool in_lds = lds + 256 <= (size_t)ctx->max_lds;
     int per_cu = in_lds ? std::max(1, (int)(ctx->max_lds / (lds + 256))) : 4;
@@ -270,6 +374,7 @@ static void coarsen_one(drg_ctx* ctx, int32_t n, const int32_t* rp, const int32_
     a.cnt = cnt.get();
     a.gbm = gbm.get();
     a.work = work.get();
+    a.node_base = u ? cnb.get() : nullptr;
     DRG_HIP(hipMemsetAsync(work.get(), 0, sizeof(int32_t), st));
     if (in_lds)
         launch_contract<false, true>(ctx, a, G, grid, lds);
@@ -339,6 +444,345 @@ drg_hier* build_hierarchy(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double 
     }
     DRG_HIP(hipStreamSynchronize(st));
     return h.release();
+}
+
+// ------------------------------------------------------------------ unions
+__global__ void k_count_active_i32(int32_t n, const int32_t* __restrict__ gid,
+                                   const int32_t* __restrict__ rp, int32_t* __restrict__ cnt) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && rp[v + 1] > rp[v]) atomicAdd(&cnt[gid[v]], 1);
+}
+
+// Keeps the graphs with nb[c] >= 0: node v of graph c becomes nb[c] + (v -
+// ob[c]), its row moves by ne[c] - oe[c] and its columns by nb[c] - ob[c].
+__global__ void k_compact(int32_t n, const int32_t* __restrict__ gid,
+                          const int32_t* __restrict__ ob, const int32_t* __restrict__ nb,
+                          const int32_t* __restrict__ oe, const int32_t* __restrict__ ne,
+                          const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          int32_t* __restrict__ nrp, int32_t* __restrict__ ncol,
+                          int32_t* __restrict__ ngid) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = gid[v];
+    if (nb[c] < 0) return;
+    const int32_t nv = nb[c] + ((int32_t)v - ob[c]);
+    const int32_t eoff = ne[c] - oe[c], voff = nb[c] - ob[c];
+    nrp[nv] = rp[v] + eoff;
+    ngid[nv] = c;
+    for (int32_t x = rp[v]; x < rp[v + 1]; ++x) ncol[x + eoff] = col[x] + voff;
+}
+
+// map pool entry of every node of a kept graph: its coarse id, graph-local.
+__global__ void k_store_map(int32_t n, const int32_t* __restrict__ gid,
+                            const int32_t* __restrict__ vb, const int32_t* __restrict__ cb,
+                            const int64_t* __restrict__ mo, const int32_t* __restrict__ map,
+                            int32_t* __restrict__ pool) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = gid[v];
+    if (mo[c] < 0) return;
+    pool[mo[c] + ((int32_t)v - vb[c])] = map[v] - cb[c];
+}
+
+// cmap_l(j) = map_l(cmap_{l-1}(j)) for the finest nodes of kept graphs, and
+// the sort key (graph's first level-l union id + cmap) of every finest node.
+__global__ void k_compose_union(int32_t n0, const int32_t* __restrict__ gid0,
+                                const int32_t* __restrict__ base0,
+                                const int64_t* __restrict__ prev_co,
+                                const int32_t* __restrict__ prev_cmap,
+                                const int64_t* __restrict__ mo, const int32_t* __restrict__ mpool,
+                                const int64_t* __restrict__ co, const int32_t* __restrict__ kb,
+                                int32_t* __restrict__ cpool, uint32_t* __restrict__ keys,
+                                int32_t* __restrict__ vals) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n0) return;
+    const int32_t c = gid0[j];
+    vals[j] = (int32_t)j;
+    if (co[c] < 0) {
+        keys[j] = 0xFFFFFFFFu;
+        return;
+    }
+    const int32_t loc = (int32_t)j - base0[c];
+    const int32_t prev = prev_cmap ? prev_cmap[prev_co[c] + loc] : loc;
+    const int32_t cm = mpool[mo[c] + prev];
+    cpool[co[c] + loc] = cm;
+    keys[j] = (uint32_t)(kb[c] + cm);
+}
+
+// perm pool: the sorted finest members, graph-local.
+__global__ void k_store_perm(int32_t m, const int32_t* __restrict__ vals,
+                             const int32_t* __restrict__ gid0, const int32_t* __restrict__ base0,
+                             int32_t* __restrict__ ppool) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= m) return;
+    const int32_t j = vals[x];
+    ppool[x] = j - base0[gid0[j]];
+}
+
+// seg pool: member offsets of every level node of a kept graph, relative to
+// the graph's first member; the entry after a graph's last node is n_0.
+__global__ void k_store_seg(int32_t nl, int32_t m, const int32_t* __restrict__ kgraph,
+                            const int32_t* __restrict__ kbk, int32_t nk,
+                            const uint32_t* __restrict__ keys, const int64_t* __restrict__ co,
+                            const int64_t* __restrict__ so, const int32_t* __restrict__ n0,
+                            int32_t* __restrict__ spool) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nl) return;
+    // kept graph owning level-node u: last i with kbk[i] <= u
+    int32_t lo = 0, hi = nk - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)kbk[mid] <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int32_t c = kgraph[lo];
+    const int32_t a = (int32_t)u - kbk[lo];
+    int32_t l = 0, h = m;  // first sorted key >= u
+    while (l < h) {
+        const int32_t mid = l + ((h - l) >> 1);
+        if ((int64_t)keys[mid] < u)
+            l = mid + 1;
+        else
+            h = mid;
+    }
+    spool[so[c] + a] = l - (int32_t)co[c];
+    const bool last = (lo + 1 < nk) ? (u + 1 == kbk[lo + 1]) : (u + 1 == nl);
+    if (last) spool[so[c] + a + 1] = n0[c];
+}
+
+// Level-synchronous: level l of every graph that still coarsens is built in
+// one pass over the union of their level l-1 graphs.  A graph stops exactly
+// where build_hierarchy stops it (max_levels, min_nodes, no active node, or
+// too little reduction); graphs leave the union as they stop.
+void build_hierarchy_union(drg_ctx* ctx, const drg_csr* g, const int32_t* gid,
+                           const std::vector<int32_t>& base, const drg_layout_params* params,
+                           UnionHier& out) {
+    hipStream_t st = ctx->stream;
+    const int32_t count = (int32_t)base.size() - 1;
+    const int32_t N0 = g->n;
+    out.lv.clear();
+    out.lv.emplace_back();
+    out.n.assign(count, {});
+    for (int32_t c = 0; c < count; ++c) out.n[c].push_back(base[c + 1] - base[c]);
+    std::vector<uint64_t> seeds(count);
+    for (int32_t c = 0; c < count; ++c) seeds[c] = params[c].seed;
+    DevBuf<uint64_t> dseed;
+    DevBuf<int32_t> dbase0, dn0;
+    to_dev(dseed, seeds, st);
+    to_dev(dbase0, base, st);
+    {
+        std::vector<int32_t> n0(count);
+        for (int32_t c = 0; c < count; ++c) n0[c] = out.n[c][0];
+        to_dev(dn0, n0, st);
+    }
+    // current union (level l-1)
+    int32_t cn = N0;
+    int64_t cnnz = g->nnz;
+    const int32_t* crp = g->row_ptr;
+    const int32_t* ccol = g->col;
+    const int32_t* cgid = gid;
+    DevBuf<int32_t> own_rp, own_col, own_gid;
+    std::vector<int32_t> vb(base.begin(), base.end() - 1), vn(count), ve(count), vm(count);
+    std::vector<int32_t> na(count, 0);
+    {
+        std::vector<int32_t> rpb(count + 1);
+        for (int32_t c = 0; c <= count; ++c)
+            DRG_HIP(hipMemcpyAsync(&rpb[c], g->row_ptr + base[c], sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, st));
+        DevBuf<int32_t> cnt(count);
+        DRG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * count, st));
+        hipLaunchKernelGGL(k_count_active_i32, dim3(ceil_div(N0, 256)), dim3(256), 0, st, N0, gid,
+                           g->row_ptr, cnt.get());
+        DRG_LAUNCH_CHECK();
+        DRG_HIP(hipMemcpyAsync(na.data(), cnt.get(), sizeof(int32_t) * count,
+                               hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+        for (int32_t c = 0; c < count; ++c) {
+            vn[c] = out.n[c][0];
+            ve[c] = rpb[c];
+            vm[c] = rpb[c + 1] - rpb[c];
+        }
+    }
+    std::vector<char> member(count, 1);
+    for (int32_t l = 1;; ++l) {
+        // graphs that try one more level
+        std::vector<int32_t> E;
+        for (int32_t c = 0; c < count; ++c)
+            if (member[c] && l < params[c].max_levels && na[c] > 0 && na[c] >= params[c].min_nodes)
+                E.push_back(c);
+        if (E.empty()) break;
+        // drop the others from the union
+        auto compact = [&](const std::vector<char>& keep) {
+            std::vector<int32_t> nb(count, -1), ne(count, -1), ob(count, 0), oe(count, 0);
+            int32_t tn = 0, te = 0;
+            for (int32_t c = 0; c < count; ++c) {
+                ob[c] = member[c] ? vb[c] : 0;
+                oe[c] = member[c] ? ve[c] : 0;
+                if (member[c] && keep[c]) {
+                    nb[c] = tn;
+                    ne[c] = te;
+                    tn += vn[c];
+                    te += vm[c];
+                }
+            }
+            DevBuf<int32_t> dob, dnb, doe, dne, nrp((int64_t)tn + 1), ncol(te), ngid(tn);
+            to_dev(dob, ob, st);
+            to_dev(dnb, nb, st);
+            to_dev(doe, oe, st);
+            to_dev(dne, ne, st);
+            hipLaunchKernelGGL(k_compact, dim3(ceil_div(cn, 256)), dim3(256), 0, st, cn, cgid,
+                               dob.get(), dnb.get(), doe.get(), dne.get(), crp, ccol, nrp.get(),
+                               ncol.get(), ngid.get());
+            DRG_LAUNCH_CHECK();
+            DRG_HIP(hipMemcpyAsync(nrp.get() + tn, &te, sizeof(int32_t), hipMemcpyHostToDevice,
+                                   st));
+            DRG_HIP(hipStreamSynchronize(st));
+            own_rp = std::move(nrp);
+            own_col = std::move(ncol);
+            own_gid = std::move(ngid);
+            crp = own_rp.get();
+            ccol = own_col.get();
+            cgid = own_gid.get();
+            cn = tn;
+            cnnz = te;
+            for (int32_t c = 0; c < count; ++c) {
+                if (!(member[c] && keep[c])) member[c] = 0;
+                if (member[c]) {
+                    vb[c] = nb[c];
+                    ve[c] = ne[c];
+                }
+            }
+        };
+        if ((int32_t)E.size() != (int32_t)std::count(member.begin(), member.end(), 1)) {
+            std::vector<char> keep(count, 0);
+            for (int32_t c : E) keep[c] = 1;
+            compact(keep);
+        }
+        // coarsen the union of E
+        UnionLevel u;
+        DevBuf<int32_t> dvb;
+        to_dev(dvb, vb, st);
+        u.gid = cgid;
+        u.gbase = dvb.get();
+        u.gseed = dseed.get();
+        u.members = E;
+        u.hbase = vb;
+        u.hn = vn;
+        drg_level nxt;
+        coarsen_one(ctx, cn, crp, ccol, cnnz, 0, l - 1, nxt, &u);
+        // active nodes of every coarse graph; keep the ones that shrank enough
+        std::vector<int32_t> nna(count, 0);
+        {
+            DevBuf<int32_t> cnt(count);
+            DRG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * count, st));
+            if (nxt.n > 0) {
+                hipLaunchKernelGGL(k_count_active_i32, dim3(ceil_div(nxt.n, 256)), dim3(256), 0,
+                                   st, nxt.n, u.cgid.get(), nxt.rp.get(), cnt.get());
+                DRG_LAUNCH_CHECK();
+            }
+            DRG_HIP(hipMemcpyAsync(nna.data(), cnt.get(), sizeof(int32_t) * count,
+                                   hipMemcpyDeviceToHost, st));
+        }
+        std::vector<int32_t> cedge(count, 0), cerow(count, 0);
+        {
+            // coarse edge range of every graph: rows cbase .. cbase + cn
+            for (int32_t c : E) {
+                DRG_HIP(hipMemcpyAsync(&cerow[c], nxt.rp.get() + u.cbase[c], sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, st));
+                DRG_HIP(hipMemcpyAsync(&cedge[c], nxt.rp.get() + u.cbase[c] + u.cn[c],
+                                       sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            }
+            DRG_HIP(hipStreamSynchronize(st));
+        }
+        std::vector<int32_t> K;
+        std::vector<char> keep(count, 0);
+        for (int32_t c : E)
+            if (!((double)nna[c] > params[c].rho * (double)na[c])) {
+                K.push_back(c);
+                keep[c] = 1;
+            }
+        if (K.empty()) break;
+        // level l pools of the kept graphs
+        UnionHier::Pool P;
+        P.mo.assign(count, -1);
+        P.co.assign(count, -1);
+        P.so.assign(count, -1);
+        std::vector<int32_t> kb(count, 0), kgraph, kbk;
+        int64_t tm = 0, tc = 0, ts = 0;
+        int32_t tl = 0;
+        for (int32_t c : K) {
+            P.mo[c] = tm;
+            P.co[c] = tc;
+            P.so[c] = ts;
+            kb[c] = tl;
+            kgraph.push_back(c);
+            kbk.push_back(tl);
+            tm += vn[c];
+            tc += out.n[c][0];
+            ts += u.cn[c] + 1;
+            tl += u.cn[c];
+        }
+        P.map.alloc(tm);
+        P.cmap.alloc(tc);
+        P.perm.alloc(tc);
+        P.seg.alloc(ts);
+        DevBuf<int64_t> dmo, dco, dso, dpco;
+        DevBuf<int32_t> dcb, dkb, dkg, dkbk;
+        to_dev(dmo, P.mo, st);
+        to_dev(dco, P.co, st);
+        to_dev(dso, P.so, st);
+        to_dev(dcb, u.cbase, st);
+        to_dev(dkb, kb, st);
+        to_dev(dkg, kgraph, st);
+        to_dev(dkbk, kbk, st);
+        hipLaunchKernelGGL(k_store_map, dim3(ceil_div(cn, 256)), dim3(256), 0, st, cn, cgid,
+                           dvb.get(), dcb.get(), dmo.get(), nxt.map.get(), P.map.get());
+        DRG_LAUNCH_CHECK();
+        const UnionHier::Pool* prev = l >= 2 ? &out.lv[l - 1] : nullptr;
+        if (prev) to_dev(dpco, prev->co, st);
+        DevBuf<uint32_t> keys(N0);
+        DevBuf<int32_t> vals(N0);
+        hipLaunchKernelGGL(k_compose_union, dim3(ceil_div(N0, 256)), dim3(256), 0, st, N0, gid,
+                           dbase0.get(), prev ? dpco.get() : nullptr,
+                           prev ? prev->cmap.get() : nullptr, dmo.get(), P.map.get(), dco.get(),
+                           dkb.get(), P.cmap.get(), keys.get(), vals.get());
+        DRG_LAUNCH_CHECK();
+        const bool all = (int64_t)tc == (int64_t)N0;
+        radix_sort_pairs(keys.get(), vals.get(), N0, all ? key_bits_for(tl) : 32, st);
+        hipLaunchKernelGGL(k_store_perm, dim3(ceil_div(tc, 256)), dim3(256), 0, st, (int32_t)tc,
+                           vals.get(), gid, dbase0.get(), P.perm.get());
+        DRG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_store_seg, dim3(ceil_div(tl, 256)), dim3(256), 0, st, tl,
+                           (int32_t)tc, dkg.get(), dkbk.get(), (int32_t)K.size(), keys.get(),
+                           dco.get(), dso.get(), dn0.get(), P.seg.get());
+        DRG_LAUNCH_CHECK();
+        DRG_HIP(hipStreamSynchronize(st));
+        for (int32_t c : K) out.n[c].push_back(u.cn[c]);
+        out.lv.push_back(std::move(P));
+        // the kept coarse graphs become the next union
+        own_rp = std::move(nxt.rp);
+        own_col = std::move(nxt.col);
+        own_gid = std::move(u.cgid);
+        crp = own_rp.get();
+        ccol = own_col.get();
+        cgid = own_gid.get();
+        cn = nxt.n;
+        cnnz = nxt.nnz;
+        for (int32_t c = 0; c < count; ++c) {
+            member[c] = 0;
+        }
+        for (int32_t c : E) {
+            member[c] = 1;
+            vb[c] = u.cbase[c];
+            vn[c] = u.cn[c];
+            ve[c] = cerow[c];
+            vm[c] = cedge[c] - cerow[c];
+            na[c] = nna[c];
+        }
+        if (K.size() != E.size()) compact(keep);
+    }
 }
 
 }  // namespace drg

@@ -79,6 +79,15 @@ struct UnionInfo {
     std::vector<int64_t> nnz;             // out: pattern entries of each graph
 };
 
+// Lanes per row of the row-per-group sweep, from the mean pattern row length.
+inline int sweep_group(double mean_len) {
+    if (mean_len <= 6) return 4;
+    if (mean_len <= 12) return 8;
+    if (mean_len <= 24) return 16;
+    if (mean_len <= 48) return 32;
+    return 64;
+}
+
 // similarity.hip
 // With u, the pattern is built for every graph of the union at once, each
 // graph's row weights with the launch shape of its own single-graph build;
@@ -107,6 +116,23 @@ void sim_coo(drg_ctx* ctx, drg_sim* s, int32_t* rows, int32_t* cols, float* P);
 // coarsen.hip
 drg_hier* build_hierarchy(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho,
                           int min_nodes, int max_levels);
+
+// Hierarchies of all graphs of a union.  Level l >= 1 of graph c lives in
+// pools shared by the graphs that have that level; its arrays hold the same
+// (graph-local) values as the single-graph hierarchy:
+//   map  at pool.map  + mo[c]  [n_{l-1}]   cmap at pool.cmap + co[c]  [n_0]
+//   perm at pool.perm + co[c]  [n_0]       seg  at pool.seg  + so[c]  [n_l+1]
+struct UnionHier {
+    struct Pool {
+        DevBuf<int32_t> map, cmap, perm, seg;
+        std::vector<int64_t> mo, co, so;  // [count], -1: graph has no such level
+    };
+    std::vector<Pool> lv;                 // lv[0] unused
+    std::vector<std::vector<int32_t>> n;  // [c][l] nodes per level
+};
+void build_hierarchy_union(drg_ctx* ctx, const drg_csr* g, const int32_t* gid,
+                           const std::vector<int32_t>& base, const drg_layout_params* params,
+                           UnionHier& out);
 // layout.hip
 void init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y);
 void prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* yl, float* yf);
@@ -118,4 +144,12 @@ template <typename T>
 void prolong_t(drg_ctx* ctx, const drg_hier* h, int32_t level, const T* yl, T* yf);
 template <typename T>
 void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y);
+// batch.hip
+void check_layout_params(const drg_layout_params* p);
+drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
+                        const drg_layout_params* params);
+void batch_run(drg_ctx* ctx, drg_batch* b, float* y_out);
+void batch_destroy(drg_batch* b);
+void batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,
+                int32_t* nodes, int32_t* levels);
 }  // namespace drg

@@ -191,14 +191,6 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
     }
 }
 
-static int sweep_group(double mean_len) {
-    if (mean_len <= 6) return 4;
-    if (mean_len <= 12) return 8;
-    if (mean_len <= 24) return 16;
-    if (mean_len <= 48) return 32;
-    return 64;
-}
-
 template <typename T, int B, int G>
 static void launch_one(hipStream_t st, const SweepArgs<T>& a, bool async) {
     const int64_t groups = a.n0;

@@ -69,6 +69,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libdrgraph.so not built ({LIB_PATH}); run "
                            "python -m paper_2008_07799_amd.build")
+    # torch ships its own HIP runtime; loading it first makes the library bind
+    # to that same runtime (one runtime per process, shared streams and
+    # pointers) instead of bringing in a second one, which then finds no device
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     st = C.c_int32
     sig = {
@@ -105,6 +109,13 @@ def lib():
         "drg_sample_negatives": ([_P, _P, C.c_int32, C.c_uint64, C.c_uint64, _P], st),
         "drg_sim_coo": ([_P, _P, _P, _P, _P], st),
         "drg_layout": ([_P, C.POINTER(Csr), C.POINTER(LayoutParams), _P], st),
+        "drg_batch_create": ([_P, C.POINTER(Csr), C.c_int32, C.POINTER(LayoutParams),
+                              C.POINTER(_P)], st),
+        "drg_batch_info": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                            C.POINTER(C.c_int32), _P, _P], st),
+        "drg_batch_run": ([_P, _P, _P], st),
+        "drg_batch_destroy": ([_P], None),
+        "drg_layout_batched": ([_P, C.POINTER(Csr), C.c_int32, C.POINTER(LayoutParams), _P], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -146,11 +157,12 @@ class Context:
         self.stream = stream
         h = C.c_void_p()
         _check(lib().drg_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._free = lib().drg_ctx_destroy  # kept: module globals are gone at exit
         self.h = h
 
     def close(self):
         if getattr(self, "h", None):
-            lib().drg_ctx_destroy(self.h)
+            self._free(self.h)
             self.h = None
 
     __del__ = close
@@ -187,6 +199,7 @@ def to_device(csr, device="cuda"):
 # ------------------------------------------------------------------ similarity
 class Similarity:
     def __init__(self, h):
+        self._free = lib().drg_sim_destroy
         self.h = h
         n = C.c_int32()
         nnz = C.c_int64()
@@ -200,7 +213,7 @@ class Similarity:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().drg_sim_destroy(self.h)
+            self._free(self.h)
             self.h = None
 
     __del__ = close
@@ -236,6 +249,7 @@ def drg_build_similarity(ctx: Context, row_ptr, col, k: int, sigma: float = 1.0,
 # ------------------------------------------------------------------ hierarchy
 class Hierarchy:
     def __init__(self, h):
+        self._free = lib().drg_hier_destroy
         self.h = h
         lv = C.c_int32()
         _check(lib().drg_hier_info(h, C.byref(lv), None))
@@ -246,7 +260,7 @@ class Hierarchy:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().drg_hier_destroy(self.h)
+            self._free(self.h)
             self.h = None
 
     __del__ = close
@@ -328,6 +342,66 @@ def drg_layout(ctx: Context, row_ptr, col, params: LayoutParams, y_out):
     g = _csr(row_ptr, col)
     _check(lib().drg_layout(ctx.h, C.byref(g), C.byref(params),
                             _dev(y_out, torch.float32, "y_out", (g.n, 2))))
+
+
+# ------------------------------------------------------------------ batches
+def _batch_args(graphs, params):
+    """graphs: list of (row_ptr, col) device int32 tensors; params: one
+    LayoutParams for all or a list of them."""
+    if isinstance(params, LayoutParams):
+        params = [params] * len(graphs)
+    if len(params) != len(graphs) or not graphs:
+        raise ValueError("need one LayoutParams per graph and at least one graph")
+    ga = (Csr * len(graphs))(*[_csr(rp, col) for rp, col in graphs])
+    pa = (LayoutParams * len(graphs))(*params)
+    return ga, pa
+
+
+class Batch:
+    """A recorded batched run (drg_batch_create); run() replays it."""
+
+    def __init__(self, ctx: Context, graphs, params):
+        ga, pa = _batch_args(graphs, params)
+        self.count = len(graphs)
+        h = C.c_void_p()
+        _check(lib().drg_batch_create(ctx.h, ga, self.count, pa, C.byref(h)))
+        self._free = lib().drg_batch_destroy
+        self.h = h
+        n = C.c_int64()
+        nnz = C.c_int64()
+        T = C.c_int32()
+        nodes = np.zeros(self.count, np.int32)
+        levels = np.zeros(self.count, np.int32)
+        _check(lib().drg_batch_info(h, C.byref(n), C.byref(nnz), C.byref(T), _np_ptr(nodes),
+                                    _np_ptr(levels)))
+        self.n_total, self.nnz, self.T = n.value, nnz.value, T.value
+        self.nodes = [int(x) for x in nodes]
+        self.levels = [int(x) for x in levels]
+        self.base = np.concatenate([[0], np.cumsum(nodes, dtype=np.int64)])
+
+    def run(self, ctx: Context, y_out):
+        import torch
+        _check(lib().drg_batch_run(ctx.h, self.h,
+                                   _dev(y_out, torch.float32, "y_out", (self.n_total, 2))))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._free(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+def drg_batch_create(ctx: Context, graphs, params) -> Batch:
+    return Batch(ctx, graphs, params)
+
+
+def drg_layout_batched(ctx: Context, graphs, params, y_out):
+    import torch
+    ga, pa = _batch_args(graphs, params)
+    n = sum(int(rp.numel()) - 1 for rp, _ in graphs)
+    _check(lib().drg_layout_batched(ctx.h, ga, len(graphs), pa,
+                                    _dev(y_out, torch.float32, "y_out", (n, 2))))
 
 
 # ------------------------------------------------------------------ objective
