@@ -237,8 +237,8 @@ def bench_batch(args):
               f"levels {min(b.levels)}..{max(b.levels)} ({t_create:.2f} s)",
               file=sys.stderr, flush=True)
         b.run(ctx, y)
-        print(f"[bench]   batch run done ({time.perf_counter() - t:.2f} s)", file=sys.stderr,
-              flush=True)
+        print(f"[bench]   batch run done ({time.perf_counter() - t:.2f} s), sweep tuning "
+              f"{b.tuning()}", file=sys.stderr, flush=True)
         return b, t_create
 
     for w in range(args.warmup):
@@ -260,6 +260,7 @@ def bench_batch(args):
     launches, run_ms = ctx.kernel_stats()
     ctx.set_profiling(False)
     run_ms /= max(1, launches)
+    tuning = b.tuning()
     yb = y.cpu().numpy()
     # per-graph active rows, for the pair count
     nnz_total = b.nnz
@@ -292,6 +293,7 @@ def bench_batch(args):
                    "nnz_P": nnz_total, "n_active": n_active, "k": k, "M": M, "T": T,
                    "b": "3 (grids), 1 (BA)", "time_to_layout_s": ms_per_step / 1000.0,
                    "create_s": t_create, "replay_ms": run_ms,
+                   "sweep_tuning": tuning,
                    "replay_pair_updates_per_s": T * pairs / (run_ms / 1000.0)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -275,6 +275,15 @@ drg_status drg_batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
  * schedule; nodes_host[count] and levels_host[count] (host, optional). */
 drg_status drg_batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,
                           int32_t* nodes_host, int32_t* levels_host);
+/* The sweep forms drg_batch_create timed on the batch (it picks the fastest;
+ * all give the same bits): *n candidates; for i < cap, rpl[i] = 0 for the row
+ * form (a group of lanes per row, records gathered from global memory) or the
+ * rows per group of the LDS-windowed form, ch[i] its LDS chunk in records,
+ * ms[i] the time of one sweep; *chosen = index of the form in use (-1 when the
+ * form was forced by the environment and nothing was timed).  Host arrays,
+ * each optional. */
+drg_status drg_batch_tuning(const drg_batch* b, int32_t cap, int32_t* n, int32_t* chosen,
+                            int32_t* rpl, int32_t* ch, float* ms);
 drg_status drg_batch_run(drg_ctx* ctx, drg_batch* b, float* y_out_dev);
 void drg_batch_destroy(drg_batch* b);
 /* One shot: create, run once, destroy. */

@@ -20,8 +20,10 @@
 // layout bit for bit.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <memory>
+#include <string>
 
 #include "drg_forces.hpp"
 #include "drg_internal.hpp"
@@ -45,6 +47,10 @@ struct BLevel {              // graph c at level l
     const int32_t* seg;      // [n+1] member offsets into perm (level >= 1)
     const int32_t* perm;     // [n0] finest members, ascending inside a node
     const int32_t* map;      // [n_{l-1}] finer node -> node of this level (level >= 1)
+};
+
+struct SweepForm {           // rpl = 0: row form; else windowed with rpl rows per group
+    int rpl = 0, ch = 0;
 };
 
 struct BSched {              // graph c at iteration t
@@ -236,32 +242,71 @@ __device__ __forceinline__ float2 b_row(const BSweepArgs& a, const BGraph& g, in
                                gamma * a.qt[i]);
 }
 
-// Graph c owns waves woff[c] .. woff[c+1]-1; each handles 64/G consecutive rows.
+// Graph c owns waves woff[c] .. woff[c+1]-1; each handles 64/G consecutive
+// rows.  A block runs 4 consecutive waves; the blocks of one XCD take a
+// contiguous range of waves, so each XCD works through few graphs at a time.
 __global__ __launch_bounds__(256) void k_b_sweep(BSweepArgs a) {
     const int32_t total = a.woff[a.count];
-    const int32_t nwaves = (int32_t)(gridDim.x * (blockDim.x / WAVE));
-    for (int32_t gw = __builtin_amdgcn_readfirstlane(
-             (int32_t)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE));
-         gw < total; gw += nwaves) {
-        const int32_t c = find_owner(a.woff, a.count, gw);
-        const BSched sc = a.sched[(int64_t)a.t * a.count + c];
-        if (sc.level < 0) continue;
-        const BGraph g = a.gt[c];
-        const int lane = __lane_id() % g.G;
-        const int32_t v = (gw - a.woff[c]) * (WAVE / g.G) + (int32_t)(__lane_id() / g.G);
-        if (v >= g.n) continue;
-        const int64_t i = (int64_t)g.base + v;
-        float2 gi = make_float2(0.0f, 0.0f);
-        if (a.prp[i] < a.prp[i + 1]) {
-            if (g.b == 1)
-                gi = b_row<1>(a, g, i, v, lane, sc.gamma);
-            else if (g.b == 2)
-                gi = b_row<2>(a, g, i, v, lane, sc.gamma);
-            else
-                gi = b_row<3>(a, g, i, v, lane, sc.gamma);
-        }
-        if (lane == 0) a.g[i] = gi;
+    const int32_t gw = __builtin_amdgcn_readfirstlane(
+        xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * 4 + (int32_t)(threadIdx.x / WAVE));
+    if (gw >= total) return;
+    const int32_t c = find_owner(a.woff, a.count, gw);
+    const BSched sc = a.sched[(int64_t)a.t * a.count + c];
+    if (sc.level < 0) return;
+    const BGraph g = a.gt[c];
+    const int lane = __lane_id() % g.G;
+    const int32_t v = (gw - a.woff[c]) * (WAVE / g.G) + (int32_t)(__lane_id() / g.G);
+    if (v >= g.n) return;
+    const int64_t i = (int64_t)g.base + v;
+    float2 gi = make_float2(0.0f, 0.0f);
+    if (a.prp[i] < a.prp[i + 1]) {
+        if (g.b == 1)
+            gi = b_row<1>(a, g, i, v, lane, sc.gamma);
+        else if (g.b == 2)
+            gi = b_row<2>(a, g, i, v, lane, sc.gamma);
+        else
+            gi = b_row<3>(a, g, i, v, lane, sc.gamma);
     }
+    if (lane == 0) a.g[i] = gi;
+}
+
+// Windowed form (bit-identical to k_b_sweep): one workgroup per item.
+struct BWinArgs {
+    int32_t count, t, CH;
+    const WinItem* items;
+    const BGraph* gt;
+    const BSched* sched;
+    const int64_t* prp;
+    const uint32_t* colhop;
+    const float4* rec;
+    const float* qt;
+    const uint64_t* C;
+    const int32_t* guide;
+    float2* g;
+    HalfE<float> eh;
+};
+
+template <int RPL>
+__global__ __launch_bounds__(WIN_BLOCK) void k_b_sweep_win(BWinArgs a) {
+    extern __shared__ float4 s_rec[];
+    const WinItem it = a.items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
+    const BSched sc = a.sched[(int64_t)a.t * a.count + it.graph];
+    if (sc.level < 0) return;  // the whole workgroup leaves
+    const BGraph g = a.gt[it.graph];
+    auto draw = [&](uint64_t w) { return g.base + draw_in_graph(w, a.C, a.guide, g); };
+    auto key = [&](int64_t i) { return (int32_t)(i - g.base); };
+    if (g.b == 1)
+        window_item<1, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
+                                       g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
+                                       a.g);
+    else if (g.b == 2)
+        window_item<2, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
+                                       g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
+                                       a.g);
+    else
+        window_item<3, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
+                                       g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
+                                       a.g);
 }
 
 // One thread per node of each graph's current level (off: this phase's prefix).
@@ -314,6 +359,9 @@ struct drg_batch {
     drg::DevBuf<drg::BLevel> lt;
     drg::DevBuf<drg::BSched> sched;
     drg::DevBuf<int32_t> gid, guide, woff, init_off, phase_off, pro_off;
+    drg::DevBuf<drg::WinItem> win_items;        // items of the chosen windowed form
+    drg::SweepForm form;                        // chosen sweep form
+    std::vector<std::pair<drg::SweepForm, float>> tune;  // candidates and their times
     drg::DevBuf<int2> pro_ops;
     drg::DevBuf<float2> y;
     hipGraph_t graph = nullptr;
@@ -585,6 +633,119 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
     upload(b->init_off, ioff, st);
     b->y.alloc(b->y_total);
     DRG_HIP(hipStreamSynchronize(st));
+    // ---- the sweep: row form (k_b_sweep) or windowed form (k_b_sweep_win,
+    // RPL rows per group, CH records per LDS chunk).  Both give the same bits;
+    // the faster one on this batch is picked by timing each candidate once on
+    // the first iteration's records (env DRG_BATCH_SWEEP=row|win forces one).
+    BSweepArgs sa{};
+    sa.count = count;
+    sa.woff = b->woff.get();
+    sa.gt = b->gt.get();
+    sa.sched = b->sched.get();
+    sa.prp = s->row_ptr.get();
+    sa.colhop = s->colhop.get();
+    sa.rec = s->rec.get();
+    sa.qt = s->qtf.get();
+    sa.C = s->C.get();
+    sa.guide = b->guide.get();
+    sa.g = s->g.get();
+    sa.eh = HalfE<float>{(float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]), (float)(0.5 * s->e[2]),
+                         (float)(0.5 * s->e[3])};
+    const int64_t sweep_blocks = std::max<int64_t>(1, ((int64_t)woff[count] + 3) / 4);
+    BWinArgs wa{};
+    wa.count = count;
+    wa.gt = sa.gt;
+    wa.sched = sa.sched;
+    wa.prp = sa.prp;
+    wa.colhop = sa.colhop;
+    wa.rec = sa.rec;
+    wa.qt = sa.qt;
+    wa.C = sa.C;
+    wa.guide = sa.guide;
+    wa.g = sa.g;
+    wa.eh = sa.eh;
+    std::map<int, std::pair<std::unique_ptr<DevBuf<WinItem>>, int32_t>> items;  // rpl -> items
+    auto items_for = [&](int rpl) -> std::pair<const WinItem*, int32_t> {
+        auto it = items.find(rpl);
+        if (it == items.end()) {
+            std::vector<int32_t> R(count);
+            for (int32_t c = 0; c < count; ++c) R[c] = (WIN_BLOCK / gt[c].G) * rpl;
+            auto buf = std::make_unique<DevBuf<WinItem>>();
+            const int32_t ni = build_window_items(ctx, s, nbase, R, *buf);
+            it = items.emplace(rpl, std::make_pair(std::move(buf), ni)).first;
+        }
+        return {it->second.first->get(), it->second.second};
+    };
+    auto win_kernel = [](int rpl) -> void (*)(BWinArgs) {
+        return rpl == 1 ? k_b_sweep_win<1>
+                        : (rpl == 2 ? k_b_sweep_win<2> : (rpl == 4 ? k_b_sweep_win<4> : k_b_sweep_win<8>));
+    };
+    const int max_ch = (ctx->max_lds - 1024) / (int)sizeof(float4);
+    auto launch_form = [&](const SweepForm& f, int32_t t, hipStream_t stream) {
+        if (f.rpl == 0) {
+            sa.t = t;
+            hipLaunchKernelGGL(k_b_sweep, dim3((unsigned)sweep_blocks), dim3(256), 0, stream, sa);
+        } else {
+            const auto its = items_for(f.rpl);
+            if (its.second == 0) return;
+            wa.t = t;
+            wa.CH = f.ch;
+            wa.items = its.first;
+            auto fn = win_kernel(f.rpl);
+            const size_t lds = (size_t)f.ch * sizeof(float4);
+            DRG_HIP(hipFuncSetAttribute((const void*)fn,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(fn, dim3(its.second), dim3(WIN_BLOCK), lds, stream, wa);
+        }
+        DRG_LAUNCH_CHECK();
+    };
+    std::vector<SweepForm> cands;
+    const char* force = std::getenv("DRG_BATCH_SWEEP");
+    if (force && std::string(force) == "row") {
+        cands.push_back({0, 0});
+    } else if (force && std::string(force) == "win") {
+        cands.push_back({win_rpl(), win_chunk(ctx)});
+    } else {
+        cands.push_back({0, 0});
+        for (int rpl : {2, 4, 8})
+            if (8192 <= max_ch) cands.push_back({rpl, 8192});
+        if (4096 <= max_ch) cands.push_back({4, 4096});
+    }
+    b->form = cands[0];
+    b->tune.clear();
+    if (cands.size() > 1) {
+        // records of iteration 0, then one warm and one timed launch per candidate
+        hipLaunchKernelGGL(k_b_init, dim3(ceil_div(std::max(ioff[count], 1), 256)), dim3(256), 0,
+                           st, ioff[count], count, b->init_off.get(), b->gt.get(), b->lt.get(),
+                           b->y.get());
+        DRG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_b_stage, dim3(ceil_div(N, 256)), dim3(256), 0, st, N, count, 0,
+                           b->gid.get(), b->gt.get(), b->lt.get(), b->sched.get(), s->invZf.get(),
+                           b->y.get(), s->rec.get());
+        DRG_LAUNCH_CHECK();
+        hipEvent_t e0, e1;
+        DRG_HIP(hipEventCreate(&e0));
+        DRG_HIP(hipEventCreate(&e1));
+        float best = 0.0f;
+        for (const SweepForm& f : cands) {
+            launch_form(f, 0, st);
+            DRG_HIP(hipEventRecord(e0, st));
+            launch_form(f, 0, st);
+            DRG_HIP(hipEventRecord(e1, st));
+            DRG_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            DRG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            b->tune.push_back({f, ms});
+            if (b->tune.size() == 1 || ms < best) {
+                best = ms;
+                b->form = f;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } else if (b->form.rpl > 0) {
+        items_for(b->form.rpl);
+    }
     // ---- record the whole run into a graph
     hipStream_t cap = nullptr;
     DRG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -611,31 +772,13 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
                 }
             }
         };
-        BSweepArgs sa{};
-        sa.count = count;
-        sa.woff = b->woff.get();
-        sa.gt = b->gt.get();
-        sa.sched = b->sched.get();
-        sa.prp = s->row_ptr.get();
-        sa.colhop = s->colhop.get();
-        sa.rec = s->rec.get();
-        sa.qt = s->qtf.get();
-        sa.C = s->C.get();
-        sa.guide = b->guide.get();
-        sa.g = s->g.get();
-        sa.eh = HalfE<float>{(float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]),
-                             (float)(0.5 * s->e[2]), (float)(0.5 * s->e[3])};
-        const int64_t sweep_blocks = std::max<int64_t>(
-            1, std::min<int64_t>(((int64_t)woff[count] + 3) / 4, (int64_t)ctx->num_cu * 64));
         for (int32_t t = 0; t < T; ++t) {
             prolong_rounds(t);
             hipLaunchKernelGGL(k_b_stage, dim3(ceil_div(N, 256)), dim3(256), 0, cap, N, count, t,
                                b->gid.get(), b->gt.get(), b->lt.get(), b->sched.get(),
                                s->invZf.get(), b->y.get(), s->rec.get());
             DRG_LAUNCH_CHECK();
-            sa.t = t;
-            hipLaunchKernelGGL(k_b_sweep, dim3((unsigned)sweep_blocks), dim3(256), 0, cap, sa);
-            DRG_LAUNCH_CHECK();
+            launch_form(b->form, t, cap);
             const int32_t p = phase_of[t];
             const int32_t tot = phase_total[p];
             if (tot > 0) {
@@ -654,6 +797,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         throw;
     }
     DRG_HIP(hipStreamEndCapture(cap, &b->graph));
+    if (b->form.rpl > 0) b->win_items = std::move(*items[b->form.rpl].first);
     DRG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     return b.release();
 }
@@ -681,6 +825,21 @@ void batch_destroy(drg_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
     delete b;
+}
+
+void batch_tuning(const drg_batch* b, int32_t cap, int32_t* n, int32_t* chosen, int32_t* rpl,
+                  int32_t* ch, float* ms) {
+    if (!b || !n) throw Error(DRG_E_INVALID, "batch or n is NULL");
+    *n = (int32_t)b->tune.size();
+    if (chosen) *chosen = -1;
+    for (int32_t i = 0; i < (int32_t)b->tune.size(); ++i) {
+        const auto& e = b->tune[i];
+        if (chosen && e.first.rpl == b->form.rpl && e.first.ch == b->form.ch) *chosen = i;
+        if (i >= cap) continue;
+        if (rpl) rpl[i] = e.first.rpl;
+        if (ch) ch[i] = e.first.ch;
+        if (ms) ms[i] = e.second;
+    }
 }
 
 void batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,

@@ -419,6 +419,11 @@ drg_status drg_batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_tot
     return guarded([&] { drg::batch_info(b, n_total, nnz_total, T, nodes_host, levels_host); });
 }
 
+drg_status drg_batch_tuning(const drg_batch* b, int32_t cap, int32_t* n, int32_t* chosen,
+                            int32_t* rpl, int32_t* ch, float* ms) {
+    return guarded([&] { drg::batch_tuning(b, cap, n, chosen, rpl, ch, ms); });
+}
+
 drg_status drg_batch_run(drg_ctx* ctx, drg_batch* b, float* y_out_dev) {
     return guarded([&] {
         need(ctx, "ctx");

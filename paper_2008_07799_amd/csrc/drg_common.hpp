@@ -180,6 +180,15 @@ __device__ __forceinline__ float powi(float x) {
     else return x * x * x;
 }
 
+// Work index of block b of an nblocks-block launch.  Blocks go to the 8 XCDs
+// round-robin (b % 8); this gives the blocks of one XCD a contiguous range of
+// work, so each XCD's L2 serves a narrow slice of the data at a time.
+__device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nblocks) {
+    const int32_t x = b & 7, lb = b >> 3;
+    const int32_t per = nblocks >> 3, rem = nblocks & 7;
+    return x * per + min(x, rem) + lb;
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace drg

@@ -118,12 +118,59 @@ struct HalfE {
     }
 };
 
+// Attraction of one pattern entry e (record rj) on the node with record ri,
+// added to the lane's partial (ax, ay).
+template <typename T, int B>
+__device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
+                                             const typename VT<T>::v4& rj, const HalfE<T>& eh,
+                                             T clip, T& ax, T& ay) {
+    const T dx = ri.x - rj.x, dy = ri.y - rj.y;
+    const T d2 = dx * dx + dy * dy;
+    if (d2 > T(0)) {
+        const T k = attract_coef<B>(d2);
+        const T w = eh(e >> 30) * (ri.z + rj.z);
+        ax += w * clampT2(k * dx, clip);
+        ay += w * clampT2(k * dy, clip);
+    }
+}
+
+// Repulsion partial of lane `lane` of G: negative slots lane, lane+G, ...
+template <typename T, int B, typename Draw>
+__device__ __forceinline__ void repel_lane(const typename VT<T>::v4& ri,
+                                           const typename VT<T>::v4* __restrict__ rec, int lane,
+                                           int G, int M, uint64_t seed, uint64_t iter, int32_t key,
+                                           Draw draw, T clip, T& rx, T& ry) {
+    rx = T(0);
+    ry = T(0);
+    for (int m = lane; m < M; m += G) {
+        const uint64_t w = neg_word(seed, iter, key, m);
+        const typename VT<T>::v4 rv = rec[draw(w)];
+        const T dx = ri.x - rv.x, dy = ri.y - rv.y;
+        const T d2 = dx * dx + dy * dy;
+        if (d2 > T(0)) {
+            const T k = repel_coef<B>(d2);
+            rx += repelT(k, dx, clip);
+            ry += repelT(k, dy, clip);
+        }
+    }
+}
+
+// Butterfly sums over the group, then g_i = attraction + gq * repulsion.
+template <typename T>
+__device__ __forceinline__ typename VT<T>::v2 row_total(T ax, T ay, T rx, T ry, int G, T gq) {
+    ax = group_sum_rt(ax, G);
+    ay = group_sum_rt(ay, G);
+    rx = group_sum_rt(rx, G);
+    ry = group_sum_rt(ry, G);
+    return mk2<T>(ax + gq * rx, ay + gq * ry);
+}
+
 // One row of the sweep, computed by the G lanes of a group (lane = 0..G-1):
-// lane l takes pattern entries rs+l, rs+l+G, ... and negative slots l, l+G,
-// ...; the lane partials are then summed by a butterfly over the group.
-// Returns g_i (valid in every lane) = attraction + gq * repulsion, where
-// `key` is the node's own id for the negative words and draw(w) turns a word
-// into the record index of the drawn node.
+// lane l takes pattern entries rs+l, rs+l+G, ... in that order and negative
+// slots l, l+G, ...; the lane partials are then summed by a butterfly over
+// the group.  Returns g_i (valid in every lane) = attraction + gq *
+// repulsion, where `key` is the node's own id for the negative words and
+// draw(w) turns a word into the record index of the drawn node.
 template <typename T, int B, typename Draw>
 __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
@@ -132,16 +179,6 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     T gq) {
     using v4 = typename VT<T>::v4;
     T ax = T(0), ay = T(0);
-    auto pair = [&](uint32_t e, const v4& rj) {
-        const T dx = ri.x - rj.x, dy = ri.y - rj.y;
-        const T d2 = dx * dx + dy * dy;
-        if (d2 > T(0)) {
-            const T k = attract_coef<B>(d2);
-            const T w = eh(e >> 30) * (ri.z + rj.z);
-            ax += w * clampT2(k * dx, clip);
-            ay += w * clampT2(k * dy, clip);
-        }
-    };
     constexpr int U = 4;  // independent entry loads and gathers in flight
     int64_t x = rs + lane;
     for (; x + (int64_t)(U - 1) * G < re; x += (int64_t)U * G) {
@@ -152,29 +189,106 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
 #pragma unroll
         for (int q = 0; q < U; ++q) rj[q] = rec[e[q] & COL_MASK];
 #pragma unroll
-        for (int q = 0; q < U; ++q) pair(e[q], rj[q]);
+        for (int q = 0; q < U; ++q) attract_pair<T, B>(ri, e[q], rj[q], eh, clip, ax, ay);
     }
     for (; x < re; x += G) {
         const uint32_t e = colhop[x];
-        pair(e, rec[e & COL_MASK]);
+        attract_pair<T, B>(ri, e, rec[e & COL_MASK], eh, clip, ax, ay);
     }
-    T rx = T(0), ry = T(0);
-    for (int m = lane; m < M; m += G) {
-        const uint64_t w = neg_word(seed, iter, key, m);
-        const v4 rv = rec[draw(w)];
-        const T dx = ri.x - rv.x, dy = ri.y - rv.y;
-        const T d2 = dx * dx + dy * dy;
-        if (d2 > T(0)) {
-            const T k = repel_coef<B>(d2);
-            rx += repelT(k, dx, clip);
-            ry += repelT(k, dy, clip);
+    T rx, ry;
+    repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, rx, ry);
+    return row_total<T>(ax, ay, rx, ry, G, gq);
+}
+
+// ------------------------------------------------------------------ windowed sweep
+// The same per-lane order with the gathered records taken from LDS: a
+// workgroup owns the rows of one item (rows r0 .. r0+nrows-1 of one graph,
+// all columns inside [c0, c1)).  Its groups of G lanes each hold RPL rows;
+// the column window is staged chunk by chunk (CH records) and every lane
+// continues its rows' entries, in ascending position, up to the chunk's end.
+// Each lane thus adds exactly the terms it adds in sweep_row, in the same
+// order, so the result is bit-identical to sweep_row; only the source of the
+// neighbour records (LDS instead of global memory) differs.
+struct WinItem {
+    int32_t graph;     // batch graph index (0 for a single graph)
+    int32_t r0, nrows; // rows
+    int32_t c0, c1;    // column window
+    int32_t pad[3];
+};
+
+template <int B, int RPL, int BLOCK, typename Draw, typename Key>
+__device__ __forceinline__ void window_item(
+    const WinItem& it, int G, float4* __restrict__ lds, int CH,
+    const int64_t* __restrict__ prp, const uint32_t* __restrict__ colhop,
+    const float4* __restrict__ rec, const float* __restrict__ qt, const HalfE<float>& eh,
+    float clip, int M, uint64_t seed, uint64_t iter, float gamma, Draw draw, Key key,
+    float2* __restrict__ g) {
+    const int tid = threadIdx.x;
+    const int NG = BLOCK / G;
+    const int lane = tid % G, grp = tid / G;
+    float ax[RPL], ay[RPL];
+    int64_t xs[RPL], xe[RPL];
+    float4 ri[RPL];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int32_t r = grp + k * NG;
+        ax[k] = 0.0f;
+        ay[k] = 0.0f;
+        xs[k] = 0;
+        xe[k] = 0;
+        if (r < it.nrows) {
+            const int64_t i = (int64_t)it.r0 + r;
+            xs[k] = prp[i] + lane;
+            xe[k] = prp[i + 1];
+            ri[k] = rec[i];
         }
     }
-    ax = group_sum_rt(ax, G);
-    ay = group_sum_rt(ay, G);
-    rx = group_sum_rt(rx, G);
-    ry = group_sum_rt(ry, G);
-    return mk2<T>(ax + gq * rx, ay + gq * ry);
+    for (int32_t b0 = it.c0; b0 < it.c1; b0 += CH) {
+        const int32_t b1 = min(b0 + CH, it.c1);
+        __syncthreads();
+        for (int32_t j = tid; j < b1 - b0; j += BLOCK) lds[j] = rec[b0 + j];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            int64_t x = xs[k];
+            const int64_t e_end = xe[k];
+            float sx = ax[k], sy = ay[k];
+            constexpr int U = 4;  // entry loads in flight; past-the-end slots read a sentinel
+            while (x < e_end) {
+                uint32_t e[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int64_t xq = x + (int64_t)q * G;
+                    e[q] = xq < e_end ? colhop[xq] : 0xFFFFFFFFu;
+                }
+                int q = 0;
+#pragma unroll
+                for (; q < U; ++q) {
+                    const int32_t c = (int32_t)(e[q] & COL_MASK);
+                    if (c >= b1) break;
+                    attract_pair<float, B>(ri[k], e[q], lds[c - b0], eh, clip, sx, sy);
+                }
+                x += (int64_t)q * G;
+                if (q < U) break;
+            }
+            xs[k] = x;
+            ax[k] = sx;
+            ay[k] = sy;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int32_t r = grp + k * NG;
+        if (r >= it.nrows) continue;
+        const int64_t i = (int64_t)it.r0 + r;
+        float2 gi = make_float2(0.0f, 0.0f);
+        if (prp[i] < prp[i + 1]) {
+            float rx, ry;
+            repel_lane<float, B>(ri[k], rec, lane, G, M, seed, iter, key(i), draw, clip, rx, ry);
+            gi = row_total<float>(ax[k], ay[k], rx, ry, G, gamma * qt[i]);
+        }
+        if (lane == 0) g[i] = gi;
+    }
 }
 
 // Finest-level step of node i: y_i += eta g_i / qt_i (nodes with qt_i = 0 stay).

@@ -4,6 +4,7 @@
 
 #include "../../include/drgraph.h"
 #include "drg_common.hpp"
+#include "drg_forces.hpp"
 #include "drg_prims.hpp"
 
 struct drg_ctx {
@@ -48,6 +49,9 @@ struct drg_sim {
     drg::DevBuf<uint16_t> blk_ent;   // [nnz] local col | (hop-1) << 13
     drg::DevBuf<int4> blk_items;     // (block, first row, end row)
     drg::DevBuf<float2> blk_partial; // [nb][n] partial attraction
+    // work items of the windowed sweep (built on first use)
+    drg::DevBuf<drg::WinItem> win_items;
+    int32_t win_n = 0, win_rpl = 0;
 };
 
 struct drg_level {
@@ -144,12 +148,26 @@ template <typename T>
 void prolong_t(drg_ctx* ctx, const drg_hier* h, int32_t level, const T* yl, T* yf);
 template <typename T>
 void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y);
+// window.hip
+// Items of rows_per_item[c] consecutive rows of graph c (rows base[c] ..
+// base[c+1]-1 of s) with the column window of their entries; returns the
+// number of items.
+int32_t build_window_items(drg_ctx* ctx, const drg_sim* s, const std::vector<int32_t>& base,
+                           const std::vector<int32_t>& rows_per_item, DevBuf<WinItem>& out);
+// Windowed sweep shape: lanes per workgroup and LDS records per chunk.
+constexpr int WIN_BLOCK = 1024;
+int win_rpl();        // rows per group (env DRG_WIN_RPL: 1, 2, 4, 8; default 4)
+int win_chunk(drg_ctx* ctx);  // records per chunk (env DRG_WIN_CH; default fills 128 KB)
+bool window_wanted(const drg_sim* s);  // env DRG_SWEEP_WINDOW=1 (default 0)
+
 // batch.hip
 void check_layout_params(const drg_layout_params* p);
 drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
                         const drg_layout_params* params);
 void batch_run(drg_ctx* ctx, drg_batch* b, float* y_out);
 void batch_destroy(drg_batch* b);
+void batch_tuning(const drg_batch* b, int32_t cap, int32_t* n, int32_t* chosen, int32_t* rpl,
+                  int32_t* ch, float* ms);
 void batch_info(const drg_batch* b, int64_t* n_total, int64_t* nnz_total, int32_t* T,
                 int32_t* nodes, int32_t* levels);
 }  // namespace drg

@@ -99,6 +99,41 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
     }
 }
 
+// Windowed form of k_sweep (same result bit for bit): one workgroup per item.
+template <int B, int RPL>
+__global__ __launch_bounds__(WIN_BLOCK) void k_sweep_win(const WinItem* __restrict__ items, int G,
+                                                         int CH, SweepArgs<float> a) {
+    extern __shared__ float4 s_rec[];
+    const HalfE<float> eh{a.eh0, a.eh1, a.eh2, a.eh3};
+    const WinItem it = items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
+    window_item<B, RPL, WIN_BLOCK>(
+        it, G, s_rec, CH, a.prp, a.colhop, a.rec, a.qt, eh, a.clip, a.M, a.seed, a.iter, a.gamma,
+        [&](uint64_t w) { return draw_node(w, a.C, a.guide, a.gbits, a.S); },
+        [&](int64_t i) { return (int32_t)i; }, a.g);
+}
+
+template <int B, int RPL>
+static void launch_win_rpl(drg_ctx* ctx, drg_sim* s, const SweepArgs<float>& a, int G) {
+    const int CH = win_chunk(ctx);
+    const size_t lds = (size_t)CH * sizeof(float4);
+    auto fn = k_sweep_win<B, RPL>;
+    DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL(fn, dim3(s->win_n), dim3(WIN_BLOCK), lds, ctx->stream, s->win_items.get(),
+                       G, CH, a);
+    DRG_LAUNCH_CHECK();
+}
+
+template <int B>
+static void launch_win(drg_ctx* ctx, drg_sim* s, const SweepArgs<float>& a, int G) {
+    switch (s->win_rpl) {
+        case 1: launch_win_rpl<B, 1>(ctx, s, a, G); break;
+        case 2: launch_win_rpl<B, 2>(ctx, s, a, G); break;
+        case 4: launch_win_rpl<B, 4>(ctx, s, a, G); break;
+        default: launch_win_rpl<B, 8>(ctx, s, a, G); break;
+    }
+}
+
 template <typename T>
 __global__ void k_apply0(int32_t n, const typename VT<T>::v2* __restrict__ g,
                          const T* __restrict__ qt, typename VT<T>::v2* __restrict__ y, T eta) {
@@ -353,11 +388,33 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
             return;
         }
     }
+    bool win = false;
+    if constexpr (F32) {
+        if (!async && window_wanted(s)) {
+            const int rpl = win_rpl();
+            if (s->win_rpl != rpl) {
+                s->win_n = build_window_items(ctx, s, {0, n0}, {(WIN_BLOCK / G) * rpl},
+                                              s->win_items);
+                s->win_rpl = rpl;
+            }
+            win = s->win_n > 0;
+        }
+    }
     if (ctx->profiling) DRG_HIP(hipEventRecord(e0, st));
-    switch (p->b) {
-        case 1: launch_sweep<T, 1>(st, a, G, async); break;
-        case 2: launch_sweep<T, 2>(st, a, G, async); break;
-        default: launch_sweep<T, 3>(st, a, G, async); break;
+    if (win) {
+        if constexpr (F32) {
+            switch (p->b) {
+                case 1: launch_win<1>(ctx, s, a, G); break;
+                case 2: launch_win<2>(ctx, s, a, G); break;
+                default: launch_win<3>(ctx, s, a, G); break;
+            }
+        }
+    } else {
+        switch (p->b) {
+            case 1: launch_sweep<T, 1>(st, a, G, async); break;
+            case 2: launch_sweep<T, 2>(st, a, G, async); break;
+            default: launch_sweep<T, 3>(st, a, G, async); break;
+        }
     }
     if (ctx->profiling) {
         DRG_HIP(hipEventRecord(e1, st));

@@ -114,6 +114,8 @@ def lib():
         "drg_batch_info": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int32), _P, _P], st),
         "drg_batch_run": ([_P, _P, _P], st),
+        "drg_batch_tuning": ([_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
+                              _P], st),
         "drg_batch_destroy": ([_P], None),
         "drg_layout_batched": ([_P, C.POINTER(Csr), C.c_int32, C.POINTER(LayoutParams), _P], st),
     }
@@ -378,6 +380,20 @@ class Batch:
         self.nodes = [int(x) for x in nodes]
         self.levels = [int(x) for x in levels]
         self.base = np.concatenate([[0], np.cumsum(nodes, dtype=np.int64)])
+
+    def tuning(self) -> dict:
+        """Sweep forms timed at creation: list of (rows per group or 0 for the
+        row form, LDS chunk, ms) and the index in use."""
+        n = C.c_int32()
+        ch = C.c_int32()
+        _check(lib().drg_batch_tuning(self.h, 0, C.byref(n), C.byref(ch), None, None, None))
+        rpl = np.zeros(max(n.value, 1), np.int32)
+        chunk = np.zeros(max(n.value, 1), np.int32)
+        ms = np.zeros(max(n.value, 1), np.float32)
+        _check(lib().drg_batch_tuning(self.h, n.value, C.byref(n), C.byref(ch), _np_ptr(rpl),
+                                      _np_ptr(chunk), _np_ptr(ms)))
+        return {"candidates": [(int(rpl[i]), int(chunk[i]), float(ms[i])) for i in range(n.value)],
+                "chosen": ch.value}
 
     def run(self, ctx: Context, y_out):
         import torch

@@ -76,6 +76,40 @@ def test_mixed_batch_equals_single_graph_layouts(k):
     assert torch.equal(y, y2)
 
 
+def test_sweep_forms_agree(monkeypatch):
+    """Row form, windowed form (small LDS chunks) and the tuned choice give
+    the same bits; the tuner reports every candidate it timed."""
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    say("batch sweep forms")
+    graphs = [gen.ba(3000, 3, 0, sub=2), gen.grid_deleted(2000, 0.05, 0, sub=3),
+              gen.random_graph(400, 0.01, seed=5), gen.ba(900, 3, 0, sub=4)]
+    params = [_params(i, g, 30, 3) for i, g in enumerate(graphs)]
+    devs = [dev_graph(g) for g in graphs]
+    outs = []
+    for env in ({"DRG_BATCH_SWEEP": "row"},
+                {"DRG_BATCH_SWEEP": "win", "DRG_WIN_RPL": "2", "DRG_WIN_CH": "300"},
+                {"DRG_BATCH_SWEEP": "win", "DRG_WIN_RPL": "8", "DRG_WIN_CH": "8192"},
+                {}):
+        for k in ("DRG_BATCH_SWEEP", "DRG_WIN_RPL", "DRG_WIN_CH"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        b = d.drg_batch_create(ctx(), devs, params)
+        y = torch.empty((b.n_total, 2), dtype=torch.float32, device="cuda")
+        b.run(ctx(), y)
+        outs.append(y.cpu().numpy())
+        tune = b.tuning()
+        say("  ", env, tune)
+        if env:
+            assert tune["chosen"] == -1
+        else:
+            assert len(tune["candidates"]) >= 2 and 0 <= tune["chosen"] < len(tune["candidates"])
+            assert tune["candidates"][0][0] == 0  # the row form is always a candidate
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_single_graph_batch_and_one_shot():
     import torch
     from paper_2008_07799_amd import drgraph as d

@@ -325,3 +325,41 @@ def test_blocked_sweep_every_level(oracle_lib, monkeypatch, bits):
         err = normwise_rel(outs[0], yr)
         say("  level", l, "err", err)
         assert err < 2e-6
+
+
+@pytest.mark.parametrize("name,k,b", [("grid32", 3, 3), ("er300", 2, 2), ("rmat12", 2, 1),
+                                      ("ba2000", 3, 1), ("rgg20k", 3, 2)])
+def test_windowed_sweep_is_bit_identical_to_row_sweep(monkeypatch, name, k, b):
+    """The LDS-windowed sweep keeps every lane's order of terms: five sync
+    steps per level (from the same start) equal the global-gather row sweep
+    bit for bit, for every rows-per-group setting and a small LDS chunk."""
+    from paper_2008_07799_amd import drgraph as d
+    say("windowed vs row sweep", name, k)
+    g = _graphs_small()[name]
+    c = ctx()
+    rp, col = dev_graph(g)
+    sim = d.drg_build_similarity(c, rp, col, k)
+    h = d.drg_coarsen(c, rp, col, seed=1, rho=0.8, min_nodes=50, max_levels=3)
+    rng = np.random.default_rng(11)
+    starts = [rng.uniform(-3, 3, size=(h.sizes[l], 2)).astype(np.float32) for l in range(h.levels)]
+
+    def run():
+        outs = []
+        for l in range(h.levels):
+            y = to_y(starts[l])
+            for it in range(5):
+                d.drg_layout_step(c, sim, h, y, M=5, b=b, gamma=0.1, eta=0.5, clip=4.0, level=l,
+                                  seed=3, iter=it)
+            outs.append(y.cpu().numpy())
+        return outs
+
+    monkeypatch.setenv("DRG_SWEEP_BLOCKED", "0")
+    monkeypatch.setenv("DRG_SWEEP_WINDOW", "0")
+    want = run()
+    monkeypatch.setenv("DRG_SWEEP_WINDOW", "1")
+    for rpl, ch in ((1, 8192), (2, 300), (4, 8192), (8, 1000)):
+        monkeypatch.setenv("DRG_WIN_RPL", str(rpl))
+        monkeypatch.setenv("DRG_WIN_CH", str(ch))
+        got = run()
+        for l in range(h.levels):
+            assert np.array_equal(got[l], want[l]), (rpl, ch, l)
