@@ -113,25 +113,29 @@ __device__ __forceinline__ typename VT<T>::v2 init_point(int32_t v, int32_t leve
 template <typename T>
 struct HalfE {
     T h0, h1, h2, h3;
+    // two selects on the bits of h (no branches)
     __device__ __forceinline__ T operator()(uint32_t h) const {
-        return h == 0 ? h0 : (h == 1 ? h1 : (h == 2 ? h2 : h3));
+        const T lo = (h & 1u) ? h1 : h0;
+        const T hi = (h & 1u) ? h3 : h2;
+        return (h & 2u) ? hi : lo;
     }
 };
 
 // Attraction of one pattern entry e (record rj) on the node with record ri,
-// added to the lane's partial (ax, ay).
+// added to the lane's partial (ax, ay).  Coincident nodes contribute nothing;
+// no test is needed for that: at d2 = 0 the coefficient is finite (-2b for
+// b = 1, -0 otherwise) and dx = dy = +0, so both terms are zeros, which leave
+// the partial's value unchanged.
 template <typename T, int B>
 __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
                                              const typename VT<T>::v4& rj, const HalfE<T>& eh,
                                              T clip, T& ax, T& ay) {
     const T dx = ri.x - rj.x, dy = ri.y - rj.y;
     const T d2 = dx * dx + dy * dy;
-    if (d2 > T(0)) {
-        const T k = attract_coef<B>(d2);
-        const T w = eh(e >> 30) * (ri.z + rj.z);
-        ax += w * clampT2(k * dx, clip);
-        ay += w * clampT2(k * dy, clip);
-    }
+    const T k = attract_coef<B>(d2);
+    const T w = eh(e >> 30) * (ri.z + rj.z);
+    ax += w * clampT2(k * dx, clip);
+    ay += w * clampT2(k * dy, clip);
 }
 
 // Repulsion partial of lane `lane` of G: negative slots lane, lane+G, ...
@@ -179,17 +183,34 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     T gq) {
     using v4 = typename VT<T>::v4;
     T ax = T(0), ay = T(0);
-    constexpr int U = 4;  // independent entry loads and gathers in flight
+    // U entries per step; the next step's entries are loaded while this
+    // step's records are gathered and used (the terms still go in order)
+    constexpr int U = 4;
+    const int64_t step = (int64_t)U * G;
     int64_t x = rs + lane;
-    for (; x + (int64_t)(U - 1) * G < re; x += (int64_t)U * G) {
-        uint32_t e[U];
-        v4 rj[U];
+    uint32_t e[U];
+    bool full = x + (int64_t)(U - 1) * G < re;
+    if (full) {
 #pragma unroll
         for (int q = 0; q < U; ++q) e[q] = colhop[x + (int64_t)q * G];
+    }
+    while (full) {
+        v4 rj[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) rj[q] = rec[e[q] & COL_MASK];
+        const int64_t xn = x + step;
+        const bool next = xn + (int64_t)(U - 1) * G < re;
+        // past the row the loads are clamped to its last entry (and unused)
+        const int64_t xl = next ? xn : re - 1 - (int64_t)(U - 1) * G;
+        uint32_t en[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) en[q] = colhop[max(xl + (int64_t)q * G, x)];
 #pragma unroll
         for (int q = 0; q < U; ++q) attract_pair<T, B>(ri, e[q], rj[q], eh, clip, ax, ay);
+#pragma unroll
+        for (int q = 0; q < U; ++q) e[q] = en[q];
+        x = xn;
+        full = next;
     }
     for (; x < re; x += G) {
         const uint32_t e = colhop[x];
