@@ -126,6 +126,7 @@ struct BlockedArgs {
     float2* partial;
     float eh0, eh1, eh2, eh3;   // -2b * e_d / 2 per hop
     float clip;                 // clip / (2b)
+    int32_t lanes;              // lanes per row segment (16, 32, 64; 0: per item)
 };
 
 template <int B>
@@ -177,6 +178,77 @@ __device__ __forceinline__ uint32_t half16(const uint4& v, int q) {
     return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// The rows of an item, S lanes per row segment (64/S rows per wave at a
+// time): lane l of a group reads the aligned 16-byte chunk c0 + l of its
+// segment, so a group covers 8 S entries per step; short segments use small
+// groups so fewer lanes idle.  The first chunk of a group's next row is
+// requested before the current row is processed.
+template <int B, int NH, int S>
+__device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_rec,
+                                         const int32_t* s_off, int32_t b, int32_t r0, int32_t r1) {
+    constexpr int R = WAVE / S;
+    const int lane = __lane_id();
+    const int sl = lane % S, sub = lane / S;
+    const int32_t wid = threadIdx.x / WAVE;
+    const int64_t bbase = a.base[b];
+    const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
+    float2* P = a.partial + (int64_t)b * a.n0;
+    const uint32_t lmask = (1u << a.bits) - 1u;
+    // chunk of row r for this lane (first window), zero when outside
+    auto fetch = [&](int32_t r, int64_t& As, int64_t& Ae, uint4& v) {
+        As = bbase + s_off[r - r0];
+        Ae = bbase + s_off[r - r0 + 1];
+        const int64_t c = (As >> 3) + sl;
+        v = (As < Ae && c * 8 < Ae) ? E4[c] : make_uint4(0, 0, 0, 0);
+    };
+    const int32_t rstep = STREAM_WAVES * R;
+    int32_t r = r0 + wid * R + sub;
+    int64_t As = 0, Ae = 0;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (r < r1) fetch(r, As, Ae, v);
+    for (; r < r1; r += rstep) {
+        // request the next row's first chunk now
+        const int32_t rn = r + rstep;
+        int64_t Asn = 0, Aen = 0;
+        uint4 vn = make_uint4(0, 0, 0, 0);
+        if (rn < r1) fetch(rn, Asn, Aen, vn);
+        float ax = 0.0f, ay = 0.0f;
+        if (As < Ae) {
+            const float4 ri = a.rec[r];
+            const int32_t len = (int32_t)(Ae - As);
+            // rel: position of this lane's chunk start relative to the segment
+            int32_t rel = (int32_t)(((As >> 3) << 3) - As) + 8 * sl;
+            uint4 cur = v;
+            while (true) {
+                // the next window's chunk is requested before this one is used
+                const int32_t reln = rel + 8 * S;
+                const bool more = reln - 8 * sl < len;  // group-uniform
+                const uint4 nxt = (more && reln < len) ? E4[((As + reln) >> 3)]
+                                                       : make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool valid = (uint32_t)(rel + q) < (uint32_t)len;
+                    blk_pair<B, NH>(a, ri, s_rec, half16(cur, q), lmask, valid, ax, ay);
+                }
+                if (!more) break;
+                rel = reln;
+                cur = nxt;
+            }
+            ax = group_sum<S>(ax);
+            ay = group_sum<S>(ay);
+        }
+        if (sl == 0) P[r] = make_float2(ax, ay);
+        As = Asn;
+        Ae = Aen;
+        v = vn;
+    }
+}
+
+// One workgroup per item (block b, rows r0..r1): the block's records and the
+// item's row offsets go to LDS, then the rows are swept with the lanes per
+// segment that suit the item's mean segment length.  Lane sums run in a
+// fixed order and the group reductions are fixed, so the result is
+// repeatable.
 template <int B, int NH>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     extern __shared__ float4 s_dyn[];
@@ -192,54 +264,18 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
         s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
     __syncthreads();
-    const int lane = __lane_id();
-    const int32_t wid = threadIdx.x / WAVE;
-    const int64_t bbase = a.base[b];
-    const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
-    float2* P = a.partial + (int64_t)b * a.n0;
-    const uint32_t lmask = (uint32_t)bw - 1u;
-    // chunk of row r for this lane (first window), zero when outside
-    auto fetch = [&](int32_t r, int64_t& As, int64_t& Ae, uint4& v) {
-        As = bbase + s_off[r - r0];
-        Ae = bbase + s_off[r - r0 + 1];
-        const int64_t c = (As >> 3) + lane;
-        v = (As < Ae && c * 8 < Ae) ? E4[c] : make_uint4(0, 0, 0, 0);
-    };
-    int32_t r = r0 + wid;
-    int64_t As = 0, Ae = 0;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (r < r1) fetch(r, As, Ae, v);
-    for (; r < r1; r += STREAM_WAVES) {
-        // request the next row's first chunk now
-        const int32_t rn = r + STREAM_WAVES;
-        int64_t Asn = 0, Aen = 0;
-        uint4 vn = make_uint4(0, 0, 0, 0);
-        if (rn < r1) fetch(rn, Asn, Aen, vn);
-        float ax = 0.0f, ay = 0.0f;
-        if (As < Ae) {
-            const float4 ri = a.rec[r];
-            const int32_t len = (int32_t)(Ae - As);
-            // rel: position of this lane's chunk start relative to the segment
-            int32_t rel = (int32_t)(((As >> 3) << 3) - As) + 8 * lane;
-            uint4 cur = v;
-            while (true) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const bool valid = (uint32_t)(rel + q) < (uint32_t)len;
-                    blk_pair<B, NH>(a, ri, s_rec, half16(cur, q), lmask, valid, ax, ay);
-                }
-                rel += 8 * WAVE;
-                if (rel - 8 * lane >= len) break;  // wave-uniform: window past the end
-                cur = rel < len ? E4[((As + rel) >> 3)] : make_uint4(0, 0, 0, 0);
-            }
-            ax = group_sum<WAVE>(ax);
-            ay = group_sum<WAVE>(ay);
-        }
-        if (lane == 0) P[r] = make_float2(ax, ay);
-        As = Asn;
-        Ae = Aen;
-        v = vn;
+    int S = a.lanes;
+    if (S == 0) {
+        const int32_t rows = max(1, r1 - r0);
+        const int32_t mean = (s_off[r1 - r0] - s_off[0]) / rows;
+        S = mean >= 320 ? 64 : (mean >= 96 ? 32 : 16);
     }
+    if (S == 16)
+        blk_rows<B, NH, 16>(a, s_rec, s_off, b, r0, r1);
+    else if (S == 32)
+        blk_rows<B, NH, 32>(a, s_rec, s_off, b, r0, r1);
+    else
+        blk_rows<B, NH, 64>(a, s_rec, s_off, b, r0, r1);
 }
 
 struct FinishArgs {
@@ -424,6 +460,10 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
     a.eh2 = (float)(-b * s->e[2]);
     a.eh3 = (float)(-b * s->e[3]);
     a.clip = clip / (float)(2 * b);
+    {
+        const int l = env_int("DRG_BLK_LANES", 0);  // force 16, 32 or 64 lanes per segment
+        a.lanes = (l == 16 || l == 32 || l == 64) ? l : 0;
+    }
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));
 #define DRG_BLK(BB)                                                                \
     case BB:                                                                       \

@@ -294,15 +294,17 @@ def test_full_layout_statistics(oracle_lib, mode):
     assert abs(np_g - np_r) <= 0.01
 
 
-@pytest.mark.parametrize("bits", [8, 10])
-def test_blocked_sweep_every_level(oracle_lib, monkeypatch, bits):
+@pytest.mark.parametrize("bits,lanes", [(8, 0), (10, 0), (8, 16), (10, 32), (10, 64)])
+def test_blocked_sweep_every_level(oracle_lib, monkeypatch, bits, lanes):
     """The LDS-staged sweep over the column-blocked pattern (forced on, with
-    small blocks so a small graph spans many): one FP32 step per level from
-    the same state vs the oracle, and bit-identical reruns."""
+    small blocks so a small graph spans many; lanes per row segment chosen per
+    item or forced to 16, 32, 64): one FP32 step per level from the same state
+    vs the oracle, and bit-identical reruns."""
     from paper_2008_07799_amd import drgraph as d
     monkeypatch.setenv("DRG_SWEEP_BLOCKED", "1")
     monkeypatch.setenv("DRG_BLOCK_BITS", str(bits))
-    say("blocked sweep, bits", bits)
+    monkeypatch.setenv("DRG_BLK_LANES", str(lanes))
+    say("blocked sweep, bits", bits, "lanes", lanes or "per item")
     g = _graphs_small()["rmat12"]
     c = ctx()
     rp, col = dev_graph(g)
