@@ -198,9 +198,11 @@ def bench_autograd(args):
     torch.cuda.empty_cache()
     print("[bench] ours", file=sys.stderr, flush=True)
     ms_ours, _ = run(ours_loss, args.steps, max(1, args.warmup))
-    torch.cuda.empty_cache()
-    print("[bench] eager", file=sys.stderr, flush=True)
-    ms_eager, _ = run(eager_loss, args.steps, max(1, args.warmup))
+    ms_eager = None
+    if not args.no_compare:
+        torch.cuda.empty_cache()
+        print("[bench] eager", file=sys.stderr, flush=True)
+        ms_eager, _ = run(eager_loss, args.steps, max(1, args.warmup))
     pairs = sim.nnz + M * na
     rec = {
         "metric": "pair-updates/s + time-to-layout, 1M-node R-MAT; batched/autograd vs plain",
@@ -211,7 +213,8 @@ def bench_autograd(args):
         "config": {"workload": "autograd_rmat18_k2", "graph": "rmat18", "n": n, "k": 2, "M": M,
                    "b": b, "nnz_P": sim.nnz, "n_active": na, "anchors": int(anchors.numel()),
                    "step": "forward + backward + SGD update"},
-        "vs_eager_pytorch": {"eager_ms_per_step": ms_eager, "speedup": ms_eager / ms_ours,
+        "vs_eager_pytorch": {"eager_ms_per_step": ms_eager,
+                             "speedup": ms_eager / ms_ours if ms_eager else None,
                              "accuracy": acc},
     }
     print(json.dumps(rec), flush=True)
