@@ -127,6 +127,7 @@ struct BlockedArgs {
     float eh0, eh1, eh2, eh3;   // -2b * e_d / 2 per hop
     float clip;                 // clip / (2b)
     int32_t lanes;              // lanes per row segment (16, 32, 64; 0: per item)
+    int32_t flat;               // chunks per lane of the flat (merge-path) form; 0: row form
 };
 
 template <int B>
@@ -164,12 +165,7 @@ __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const float4& ri,
     ay += w * clampf(p * dy, a.clip);
 }
 
-// One workgroup per item (block b, rows r0..r1): the block's records and the
-// item's row offsets go to LDS.  One wave per row segment; lane l reads the
-// aligned 16-byte chunk (8 entries) c0 + l of the segment, so a wave moves up
-// to 1 KB per load instruction, and the chunk of the wave's next row is
-// requested before the current row is processed.  Lane sums run in a fixed
-// order and the wave reduction is fixed, so the result is repeatable.
+// Workgroups of 1024 threads; an entry chunk is 16 bytes (eight 16-bit words).
 constexpr int STREAM_BLOCK = 1024;
 constexpr int STREAM_WAVES = STREAM_BLOCK / WAVE;
 
@@ -244,6 +240,215 @@ __device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_r
     }
 }
 
+// ------------------------------------------------------------------ flat form
+// The entries of an item (rows r0..r1 of block b) are contiguous, so the
+// item is swept as one stream regardless of row boundaries: wave w takes a
+// contiguous range of its 16-byte chunks, lane l the chunk w0 + l of each
+// 64-chunk window; every lane walks its 8 entries, tracking the row through
+// the LDS row offsets.  A row that starts and ends inside one lane is
+// complete there.  A row that crosses lanes is summed by a keyed segmented
+// scan over the lanes' last-row partials (in lane order), a row that crosses
+// windows is carried by the wave, and a row that crosses waves is closed by
+// one thread after the workgroup barrier, in wave order.  All of it depends
+// only on the layout of the data, so the result is repeatable.
+struct WaveFrag {
+    int32_t hrow, trow, same, pad;  // open head row, open tail row (-1: none)
+    float hx, hy, tx, ty;
+};
+
+// largest i in [lo, hi] with off[i] <= p
+__device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t lo, int32_t hi, int32_t p) {
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// largest i in [lo, hi] with off[i] <= p, given off[lo] <= p: doubling steps
+// from lo, then bisection (cheap when the answer is near lo)
+__device__ __forceinline__ int32_t row_from(const int32_t* off, int32_t lo, int32_t hi, int32_t p) {
+    int32_t step = 1;
+    while (lo + step <= hi && off[lo + step] <= p) {
+        lo += step;
+        step <<= 1;
+    }
+    return row_of(off, lo, min(lo + step - 1, hi), p);
+}
+
+template <int B, int NH, int CPL>
+__device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_rec,
+                                         const int32_t* s_off, WaveFrag* s_frag, int32_t b,
+                                         int32_t r0, int32_t r1) {
+    constexpr int EPL = 8 * CPL;          // entries per lane per window
+    constexpr int WCH = WAVE * CPL;       // chunks per window
+    const int lane = __lane_id();
+    const int wid = threadIdx.x / WAVE;
+    const int32_t nr = r1 - r0;
+    const int64_t bbase = a.base[b];
+    const int32_t e0 = s_off[0], e1 = s_off[nr];
+    float2* P = a.partial + (int64_t)b * a.n0 + r0;
+    const float4* R = a.rec + r0;
+    const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
+    const uint32_t lmask = (1u << a.bits) - 1u;
+    const int64_t cA = (bbase + e0) >> 3;
+    const int64_t nch = e1 > e0 ? ((bbase + e1 + 7) >> 3) - cA : 0;
+    const int64_t per = (nch + STREAM_WAVES - 1) / STREAM_WAVES;
+    const int64_t wc0 = cA + min(nch, per * wid), wc1 = cA + min(nch, per * (wid + 1));
+    // the wave's first row and whether it started before the wave's range
+    int32_t w_first = -1;
+    bool w_open = false;
+    if (wc0 < wc1) {
+        const int32_t fp = max((int32_t)(8 * wc0 - bbase), e0);
+        w_first = row_of(s_off, 0, nr - 1, fp);
+        w_open = s_off[w_first] < fp;
+    }
+    if (lane == 0) {
+        s_frag[wid].hrow = -1;
+        s_frag[wid].trow = -1;
+        s_frag[wid].same = 0;
+    }
+    // a complete row: written, unless it is the wave's open first row
+    auto close_row = [&](int32_t row, float x, float y) {
+        if (row == w_first && w_open) {
+            s_frag[wid].hrow = row;
+            s_frag[wid].hx = x;
+            s_frag[wid].hy = y;
+        } else {
+            P[row] = make_float2(x, y);
+        }
+    };
+    int32_t c_row = -1;  // row carried from the previous window (wave-uniform)
+    float c_x = 0.0f, c_y = 0.0f;
+    int32_t ilo = max(w_first, 0);
+    uint4 vn[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int64_t c = wc0 + (int64_t)lane * CPL + k;
+        vn[k] = c < wc1 ? E4[c] : make_uint4(0, 0, 0, 0);
+    }
+    for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
+        const int64_t c = w0 + (int64_t)lane * CPL;  // the lane's first chunk
+        const int32_t nl = (int32_t)min((int64_t)WAVE, (wc1 - w0 + CPL - 1) / CPL);
+        const bool has = lane < nl;
+        uint4 v[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            v[k] = vn[k];
+            const int64_t cn = c + WCH + k;
+            vn[k] = cn < wc1 ? E4[cn] : make_uint4(0, 0, 0, 0);
+        }
+        const int32_t pbase = (int32_t)(8 * c - bbase);
+        const int32_t pf = max(pbase, e0);                                  // first valid slot
+        const int32_t pl = min(min(pbase + EPL, (int32_t)(8 * wc1 - bbase)), e1);  // end of valid slots
+        // rows spanned by the window, then the lane's first row
+        const int32_t wp0 = max((int32_t)(8 * w0 - bbase), e0);
+        const int32_t wp1 = min((int32_t)(8 * min(w0 + WCH, wc1) - bbase), e1) - 1;
+        const int32_t i0 = row_from(s_off, ilo, nr - 1, wp0);
+        const int32_t i1 = row_from(s_off, i0, nr - 1, wp1);
+        int32_t i = has ? row_of(s_off, i0, i1, pf) : i1;
+        int32_t nxt = s_off[i + 1];
+        float4 ri = R[i];
+        float ax = 0.0f, ay = 0.0f, hx = 0.0f, hy = 0.0f;
+        const int32_t hrow = i;
+        bool hopen = true;  // still on the lane's first row
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int32_t p = pbase + 8 * k + q;
+                const bool valid = has && p >= pf && p < pl;
+                if (valid && p >= nxt) {  // the row ends before this slot
+                    if (hopen) {
+                        hx = ax;
+                        hy = ay;
+                        hopen = false;
+                    } else {
+                        close_row(i, ax, ay);  // started and ended inside this lane
+                    }
+                    do {
+                        ++i;
+                        nxt = s_off[i + 1];
+                    } while (p >= nxt);
+                    ri = R[i];
+                    ax = 0.0f;
+                    ay = 0.0f;
+                }
+                blk_pair<B, NH>(a, ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
+            }
+        }
+        // the window's carried row continues into lane 0
+        if (lane == 0 && hrow == c_row) {
+            if (hopen) {
+                ax = c_x + ax;
+                ay = c_y + ay;
+            } else {
+                hx = c_x + hx;
+                hy = c_y + hy;
+            }
+        }
+        // keyed inclusive scan of the lanes' last-row partials
+        const int32_t tk = has ? i : -2 - lane;
+        float sx = ax, sy = ay;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const float ox = __shfl_up(sx, d), oy = __shfl_up(sy, d);
+            const int32_t ok = __shfl_up(tk, d);
+            if (lane >= d && ok == tk) {
+                sx = ox + sx;
+                sy = oy + sy;
+            }
+        }
+        // a first row that ended inside the lane: add what earlier lanes hold
+        const float px = __shfl_up(sx, 1), py = __shfl_up(sy, 1);
+        const int32_t pk = __shfl_up(tk, 1);
+        if (has && !hopen) {
+            const bool cin = lane > 0 && pk == hrow;
+            close_row(hrow, cin ? px + hx : hx, cin ? py + hy : hy);
+        }
+        // the last row: complete unless it goes on past this lane (into the
+        // next lane, the next window or the next wave)
+        const bool cont = has && nxt > pl;
+        if (has && !cont) close_row(i, sx, sy);
+        // carry of the window's last lane
+        const int32_t L = nl - 1;
+        const bool lcont = __shfl(cont ? 1 : 0, L) != 0;
+        const int32_t lrow = __shfl(i, L);
+        const float lx = __shfl(sx, L), ly = __shfl(sy, L);
+        c_row = lcont ? lrow : -1;
+        c_x = lcont ? lx : 0.0f;
+        c_y = lcont ? ly : 0.0f;
+        ilo = i1;
+    }
+    // the wave's open tail (its last row goes on into the next wave)
+    if (c_row >= 0 && lane == 0) {
+        s_frag[wid].trow = c_row;
+        s_frag[wid].tx = c_x;
+        s_frag[wid].ty = c_y;
+        s_frag[wid].same = (c_row == w_first && w_open) ? 1 : 0;
+    }
+    __syncthreads();
+    // rows across waves, in wave order: an open tail runs on through waves
+    // that lie inside it and is closed by the next wave's open head
+    if (threadIdx.x == 0) {
+        float x = 0.0f, y = 0.0f;
+        for (int w = 0; w < STREAM_WAVES; ++w) {
+            const WaveFrag f = s_frag[w];
+            if (f.same) {
+                x = x + f.tx;
+                y = y + f.ty;
+                continue;
+            }
+            if (f.hrow >= 0) P[f.hrow] = make_float2(x + f.hx, y + f.hy);
+            x = f.trow >= 0 ? f.tx : 0.0f;
+            y = f.trow >= 0 ? f.ty : 0.0f;
+        }
+    }
+}
+
 // One workgroup per item (block b, rows r0..r1): the block's records and the
 // item's row offsets go to LDS, then the rows are swept with the lanes per
 // segment that suit the item's mean segment length.  Lane sums run in a
@@ -255,6 +460,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     const int32_t bw = 1 << a.bits;
     float4* s_rec = s_dyn;
     int32_t* s_off = reinterpret_cast<int32_t*>(s_dyn + bw);
+    WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
     const int4 it = a.items[blockIdx.x];
     const int32_t b = it.x, r0 = it.y, r1 = it.z;
     const int32_t j0 = b * bw;
@@ -264,6 +470,22 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
         s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
     __syncthreads();
+    if (a.flat == 1) {
+        blk_flat<B, NH, 1>(a, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    if (a.flat == 2) {
+        blk_flat<B, NH, 2>(a, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    if (a.flat == 4) {
+        blk_flat<B, NH, 4>(a, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    if (a.flat == 8) {
+        blk_flat<B, NH, 8>(a, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
     int S = a.lanes;
     if (S == 0) {
         const int32_t rows = max(1, r1 - r0);
@@ -425,6 +647,8 @@ void build_blocked(drg_ctx* ctx, drg_sim* s) {
                 throw Error(DRG_E_DEVICE, "blocked sweep: work item outside its row window");
     }
     s->blk_partial.alloc((int64_t)n * nb);
+    // the flat sweep writes only rows with entries in a block; the others stay 0
+    DRG_HIP(hipMemsetAsync(s->blk_partial.get(), 0, sizeof(float2) * (int64_t)n * nb, st));
     s->blk_nb = nb;
     s->blk_bits = bits;
     s->blk_nitems = first[nb];
@@ -433,7 +657,8 @@ void build_blocked(drg_ctx* ctx, drg_sim* s) {
 
 template <int B, int NH>
 static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
-    const size_t lds = ((size_t)16 << a.bits) + 4 * (ROWCAP + 1);
+    const size_t lds = ((size_t)16 << a.bits) + 16 * ((ROWCAP + 4) / 4) +
+                       sizeof(WaveFrag) * STREAM_WAVES;
     auto fn = k_sweep_blocked<B, NH>;
     DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
@@ -463,6 +688,8 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
     {
         const int l = env_int("DRG_BLK_LANES", 0);  // force 16, 32 or 64 lanes per segment
         a.lanes = (l == 16 || l == 32 || l == 64) ? l : 0;
+        const int f = env_int("DRG_BLK_FLAT", 4);
+        a.flat = (f == 1 || f == 2 || f == 4 || f == 8) ? f : 0;
     }
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));
 #define DRG_BLK(BB)                                                                \

@@ -294,17 +294,24 @@ def test_full_layout_statistics(oracle_lib, mode):
     assert abs(np_g - np_r) <= 0.01
 
 
-@pytest.mark.parametrize("bits,lanes", [(8, 0), (10, 0), (8, 16), (10, 32), (10, 64)])
-def test_blocked_sweep_every_level(oracle_lib, monkeypatch, bits, lanes):
+@pytest.mark.parametrize("bits,form", [(8, "flat2"), (10, "flat1"), (10, "flat4"), (12, "flat8"),
+                                       (8, "rows0"), (8, "rows16"), (10, "rows32"),
+                                       (10, "rows64")])
+def test_blocked_sweep_every_level(oracle_lib, monkeypatch, bits, form):
     """The LDS-staged sweep over the column-blocked pattern (forced on, with
-    small blocks so a small graph spans many; lanes per row segment chosen per
-    item or forced to 16, 32, 64): one FP32 step per level from the same state
-    vs the oracle, and bit-identical reruns."""
+    small blocks so a small graph spans many): the flat form with 1, 2 or 4
+    chunks per lane and the row form with lanes per segment chosen per item or
+    forced; one FP32 step per level from the same state vs the oracle, and
+    bit-identical reruns."""
     from paper_2008_07799_amd import drgraph as d
     monkeypatch.setenv("DRG_SWEEP_BLOCKED", "1")
     monkeypatch.setenv("DRG_BLOCK_BITS", str(bits))
-    monkeypatch.setenv("DRG_BLK_LANES", str(lanes))
-    say("blocked sweep, bits", bits, "lanes", lanes or "per item")
+    if form.startswith("flat"):
+        monkeypatch.setenv("DRG_BLK_FLAT", form[4:])
+    else:
+        monkeypatch.setenv("DRG_BLK_FLAT", "0")
+        monkeypatch.setenv("DRG_BLK_LANES", form[4:])
+    say("blocked sweep, bits", bits, form)
     g = _graphs_small()["rmat12"]
     c = ctx()
     rp, col = dev_graph(g)
