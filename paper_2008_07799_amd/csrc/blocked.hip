@@ -143,21 +143,33 @@ __device__ __forceinline__ float blk_repel_coef(float d2) {
 // run all eight entries of its chunk without branching.  With the -2b factor
 // folded into the weight, -2b clip(p dx, c/(2b)) = clip(-2b p dx, c) because
 // the clip is odd.  A zero offset gives a zero force through dx = dy = 0.
+struct HopW {  // -2b e_d / 2 per hop, held in vector registers inside the loops
+    float e0, e1, e2, e3;
+};
+
+__device__ __forceinline__ HopW hop_weights(const BlockedArgs& a) {
+    HopW h{a.eh0, a.eh1, a.eh2, a.eh3};
+    // vector copies made once: selecting between two scalar operands would
+    // otherwise copy both into vector registers at every pair
+    asm volatile("" : "+v"(h.e0), "+v"(h.e1), "+v"(h.e2), "+v"(h.e3));
+    return h;
+}
+
 template <int B, int NH>
-__device__ __forceinline__ void blk_pair(const BlockedArgs& a, const float4& ri, const float4* s_rec,
-                                         uint32_t u, uint32_t lmask, bool valid, float& ax,
-                                         float& ay) {
+__device__ __forceinline__ void blk_pair(const BlockedArgs& a, const HopW& hw, const float4& ri,
+                                         const float4* s_rec, uint32_t u, uint32_t lmask,
+                                         bool valid, float& ax, float& ay) {
     const float4 rj = s_rec[u & lmask];
     const float dx = ri.x - rj.x, dy = ri.y - rj.y;
     const float d2 = dx * dx + dy * dy;
     float eh;
     if constexpr (NH == 1) {
-        eh = a.eh0;
+        eh = hw.e0;
     } else if constexpr (NH == 2) {
-        eh = (u >> BLK_HOP_SHIFT) ? a.eh1 : a.eh0;
+        eh = (u >> BLK_HOP_SHIFT) ? hw.e1 : hw.e0;
     } else {
         const uint32_t h = u >> BLK_HOP_SHIFT;
-        eh = (h & 2u) ? ((h & 1u) ? a.eh3 : a.eh2) : ((h & 1u) ? a.eh1 : a.eh0);
+        eh = (h & 2u) ? ((h & 1u) ? hw.e3 : hw.e2) : ((h & 1u) ? hw.e1 : hw.e0);
     }
     const float p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
     const float w = valid ? eh * (ri.z + rj.z) : 0.0f;
@@ -190,6 +202,7 @@ __device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_r
     const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
     float2* P = a.partial + (int64_t)b * a.n0;
     const uint32_t lmask = (1u << a.bits) - 1u;
+    const HopW hw = hop_weights(a);
     // chunk of row r for this lane (first window), zero when outside
     auto fetch = [&](int32_t r, int64_t& As, int64_t& Ae, uint4& v) {
         As = bbase + s_off[r - r0];
@@ -224,7 +237,7 @@ __device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_r
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const bool valid = (uint32_t)(rel + q) < (uint32_t)len;
-                    blk_pair<B, NH>(a, ri, s_rec, half16(cur, q), lmask, valid, ax, ay);
+                    blk_pair<B, NH>(a, hw, ri, s_rec, half16(cur, q), lmask, valid, ax, ay);
                 }
                 if (!more) break;
                 rel = reln;
@@ -294,6 +307,7 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
     const float4* R = a.rec + r0;
     const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
     const uint32_t lmask = (1u << a.bits) - 1u;
+    const HopW hw = hop_weights(a);
     const int64_t cA = (bbase + e0) >> 3;
     const int64_t nch = e1 > e0 ? ((bbase + e1 + 7) >> 3) - cA : 0;
     const int64_t per = (nch + STREAM_WAVES - 1) / STREAM_WAVES;
@@ -324,26 +338,22 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
     int32_t c_row = -1;  // row carried from the previous window (wave-uniform)
     float c_x = 0.0f, c_y = 0.0f;
     int32_t ilo = max(w_first, 0);
+    // chunk loads are unconditional, clamped to the wave's last chunk (slots
+    // past the range are masked), so the counters of outstanding loads stay
+    // exact and a wait for one load does not drain the prefetches
+    const int64_t clast = max(wc1 - 1, wc0);
     uint4 vn[CPL];
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-        const int64_t c = wc0 + (int64_t)lane * CPL + k;
-        vn[k] = c < wc1 ? E4[c] : make_uint4(0, 0, 0, 0);
-    }
+    for (int k = 0; k < CPL; ++k) vn[k] = E4[min(wc0 + (int64_t)lane * CPL + k, clast)];
     for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
         const int64_t c = w0 + (int64_t)lane * CPL;  // the lane's first chunk
         const int32_t nl = (int32_t)min((int64_t)WAVE, (wc1 - w0 + CPL - 1) / CPL);
         const bool has = lane < nl;
-        uint4 v[CPL];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            v[k] = vn[k];
-            const int64_t cn = c + WCH + k;
-            vn[k] = cn < wc1 ? E4[cn] : make_uint4(0, 0, 0, 0);
-        }
         const int32_t pbase = (int32_t)(8 * c - bbase);
         const int32_t pf = max(pbase, e0);                                  // first valid slot
         const int32_t pl = min(min(pbase + EPL, (int32_t)(8 * wc1 - bbase)), e1);  // end of valid slots
+        // the same bounds relative to the lane's first slot (none valid without a chunk)
+        const int32_t qlo = pf - pbase, qhi = has ? pl - pbase : 0;
         // rows spanned by the window, then the lane's first row
         const int32_t wp0 = max((int32_t)(8 * w0 - bbase), e0);
         const int32_t wp1 = min((int32_t)(8 * min(w0 + WCH, wc1) - bbase), e1) - 1;
@@ -351,17 +361,28 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
         const int32_t i1 = row_from(s_off, i0, nr - 1, wp1);
         int32_t i = has ? row_of(s_off, i0, i1, pf) : i1;
         int32_t nxt = s_off[i + 1];
+        // the row record is requested before the next window's chunks, so
+        // waiting for it does not wait for them
         float4 ri = R[i];
+        uint4 v[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            v[k] = vn[k];
+            vn[k] = E4[min(c + WCH + k, clast)];
+        }
         float ax = 0.0f, ay = 0.0f, hx = 0.0f, hy = 0.0f;
         const int32_t hrow = i;
         bool hopen = true;  // still on the lane's first row
+        int32_t qn = nxt - pbase;  // slot where the current row ends
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int32_t p = pbase + 8 * k + q;
-                const bool valid = has && p >= pf && p < pl;
-                if (valid && p >= nxt) {  // the row ends before this slot
+                constexpr int32_t Q0 = 0;
+                const int32_t Q = Q0 + 8 * k + q;
+                const bool valid = Q >= qlo && Q < qhi;
+                if (valid && Q >= qn) {  // the row ends before this slot
+                    const int32_t p = pbase + Q;
                     if (hopen) {
                         hx = ax;
                         hy = ay;
@@ -373,11 +394,16 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
                         ++i;
                         nxt = s_off[i + 1];
                     } while (p >= nxt);
-                    ri = R[i];
+                    qn = nxt - pbase;
+                    float4 rt = R[i];
+                    // keeps the reload on this (rare) path: otherwise the load is
+                    // moved past the branch and every entry waits for it
+                    asm volatile("" : "+v"(rt.x), "+v"(rt.y), "+v"(rt.z));
+                    ri = rt;
                     ax = 0.0f;
                     ay = 0.0f;
                 }
-                blk_pair<B, NH>(a, ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
+                blk_pair<B, NH>(a, hw, ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
             }
         }
         // the window's carried row continues into lane 0
