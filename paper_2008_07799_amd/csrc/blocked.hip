@@ -177,6 +177,65 @@ __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const HopW& hw, c
     ay += w * clampf(p * dy, a.clip);
 }
 
+// Pair operators of the flat sweep: what one stored pair (record rj, entry u)
+// adds to the lane's partial of its row.  `valid` = 0 masks a slot.
+template <int NH>
+__device__ __forceinline__ float hop_weight(const HopW& hw, uint32_t u) {
+    if constexpr (NH == 1) {
+        return hw.e0;
+    } else if constexpr (NH == 2) {
+        return (u >> BLK_HOP_SHIFT) ? hw.e1 : hw.e0;
+    } else {
+        const uint32_t h = u >> BLK_HOP_SHIFT;
+        return (h & 2u) ? ((h & 1u) ? hw.e3 : hw.e2) : ((h & 1u) ? hw.e1 : hw.e0);
+    }
+}
+
+// the layout step: clipped attraction (weights carry -2b)
+template <int B, int NH>
+struct LayoutOp {
+    const BlockedArgs* a;
+    HopW hw;
+    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
+                                               uint32_t lmask, bool valid, float& ax,
+                                               float& ay) const {
+        blk_pair<B, NH>(*a, hw, ri, s_rec, u, lmask, valid, ax, ay);
+    }
+};
+
+// the objective: P~_ij log w_ij = -P~_ij log1p(d^{2b}) (weights are e_d / 2)
+template <int B, int NH>
+struct ObjValOp {
+    HopW hw;
+    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
+                                               uint32_t lmask, bool valid, float& ax,
+                                               float& ay) const {
+        const float4 rj = s_rec[u & lmask];
+        const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+        const float d2 = dx * dx + dy * dy;
+        const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
+        ax += pw * (-log1pf(powi<B>(d2)));
+        (void)ay;
+    }
+};
+
+// its gradient's attraction (unclipped): P~_ij (-2b d^{2b-2} / (1 + d^{2b})) (y_i - y_j)
+template <int B, int NH>
+struct ObjGradOp {
+    HopW hw;
+    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
+                                               uint32_t lmask, bool valid, float& ax,
+                                               float& ay) const {
+        const float4 rj = s_rec[u & lmask];
+        const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+        const float d2 = dx * dx + dy * dy;
+        const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
+        const float k = pw * (float)(-2 * B) * powi<B - 1>(d2) / (1.0f + powi<B>(d2));
+        ax += k * dx;
+        ay += k * dy;
+    }
+};
+
 // Workgroups of 1024 threads; an entry chunk is 16 bytes (eight 16-bit words).
 constexpr int STREAM_BLOCK = 1024;
 constexpr int STREAM_WAVES = STREAM_BLOCK / WAVE;
@@ -292,8 +351,8 @@ __device__ __forceinline__ int32_t row_from(const int32_t* off, int32_t lo, int3
     return row_of(off, lo, min(lo + step - 1, hi), p);
 }
 
-template <int B, int NH, int CPL>
-__device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_rec,
+template <int CPL, typename Op>
+__device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, const float4* s_rec,
                                          const int32_t* s_off, WaveFrag* s_frag, int32_t b,
                                          int32_t r0, int32_t r1) {
     constexpr int EPL = 8 * CPL;          // entries per lane per window
@@ -307,7 +366,6 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
     const float4* R = a.rec + r0;
     const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
     const uint32_t lmask = (1u << a.bits) - 1u;
-    const HopW hw = hop_weights(a);
     const int64_t cA = (bbase + e0) >> 3;
     const int64_t nch = e1 > e0 ? ((bbase + e1 + 7) >> 3) - cA : 0;
     const int64_t per = (nch + STREAM_WAVES - 1) / STREAM_WAVES;
@@ -403,7 +461,7 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
                     ax = 0.0f;
                     ay = 0.0f;
                 }
-                blk_pair<B, NH>(a, hw, ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
+                op(ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
             }
         }
         // the window's carried row continues into lane 0
@@ -480,6 +538,19 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const float4* s_r
 // segment that suit the item's mean segment length.  Lane sums run in a
 // fixed order and the group reductions are fixed, so the result is
 // repeatable.
+// Stages block b's records and the item's row offsets into LDS.
+__device__ __forceinline__ void blk_stage(const BlockedArgs& a, float4* s_rec, int32_t* s_off,
+                                          int32_t b, int32_t r0, int32_t r1) {
+    const int32_t bw = 1 << a.bits;
+    const int32_t j0 = b * bw;
+    const int32_t cnt = min(bw, a.n0 - j0);
+    const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
+    for (int32_t t = threadIdx.x; t < bw; t += STREAM_BLOCK)
+        s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
+    __syncthreads();
+}
+
 template <int B, int NH>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     extern __shared__ float4 s_dyn[];
@@ -489,27 +560,22 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
     const int4 it = a.items[blockIdx.x];
     const int32_t b = it.x, r0 = it.y, r1 = it.z;
-    const int32_t j0 = b * bw;
-    const int32_t cnt = min(bw, a.n0 - j0);
-    const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
-    for (int32_t t = threadIdx.x; t < bw; t += STREAM_BLOCK)
-        s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
-    __syncthreads();
+    blk_stage(a, s_rec, s_off, b, r0, r1);
+    const LayoutOp<B, NH> op{&a, hop_weights(a)};
     if (a.flat == 1) {
-        blk_flat<B, NH, 1>(a, s_rec, s_off, s_frag, b, r0, r1);
+        blk_flat<1>(a, op, s_rec, s_off, s_frag, b, r0, r1);
         return;
     }
     if (a.flat == 2) {
-        blk_flat<B, NH, 2>(a, s_rec, s_off, s_frag, b, r0, r1);
+        blk_flat<2>(a, op, s_rec, s_off, s_frag, b, r0, r1);
         return;
     }
     if (a.flat == 4) {
-        blk_flat<B, NH, 4>(a, s_rec, s_off, s_frag, b, r0, r1);
+        blk_flat<4>(a, op, s_rec, s_off, s_frag, b, r0, r1);
         return;
     }
     if (a.flat == 8) {
-        blk_flat<B, NH, 8>(a, s_rec, s_off, s_frag, b, r0, r1);
+        blk_flat<8>(a, op, s_rec, s_off, s_frag, b, r0, r1);
         return;
     }
     int S = a.lanes;
@@ -524,6 +590,30 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
         blk_rows<B, NH, 32>(a, s_rec, s_off, b, r0, r1);
     else
         blk_rows<B, NH, 64>(a, s_rec, s_off, b, r0, r1);
+}
+
+// The objective's attraction terms over the blocked layout (flat form): the
+// row value (KIND 0) or the row's attraction gradient (KIND 1) per block.
+template <int B, int NH, int KIND>
+__global__ __launch_bounds__(STREAM_BLOCK) void k_obj_blocked(BlockedArgs a) {
+    extern __shared__ float4 s_dyn[];
+    const int32_t bw = 1 << a.bits;
+    float4* s_rec = s_dyn;
+    int32_t* s_off = reinterpret_cast<int32_t*>(s_dyn + bw);
+    WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
+    const int4 it = a.items[blockIdx.x];
+    const int32_t b = it.x, r0 = it.y, r1 = it.z;
+    blk_stage(a, s_rec, s_off, b, r0, r1);
+    if constexpr (KIND == 0)
+        blk_flat<4>(a, ObjValOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
+    else
+        blk_flat<4>(a, ObjGradOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
+}
+
+__global__ void k_stage_y(int32_t n, const float2* __restrict__ y, const float* __restrict__ invZ,
+                          float4* __restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) rec[j] = make_float4(y[j].x, y[j].y, invZ[j], 0.0f);
 }
 
 struct FinishArgs {
@@ -690,6 +780,48 @@ static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
                                 (int)lds));
     hipLaunchKernelGGL(fn, dim3(nitems), dim3(STREAM_BLOCK), lds, ctx->stream, a);
     DRG_LAUNCH_CHECK();
+}
+
+template <int B, int NH, int KIND>
+static void launch_obj_blocked(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
+    const size_t lds = ((size_t)16 << a.bits) + 16 * ((ROWCAP + 4) / 4) +
+                       sizeof(WaveFrag) * STREAM_WAVES;
+    auto fn = k_obj_blocked<B, NH, KIND>;
+    DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL(fn, dim3(nitems), dim3(STREAM_BLOCK), lds, ctx->stream, a);
+    DRG_LAUNCH_CHECK();
+}
+
+void sweep_blocked_objective(drg_ctx* ctx, drg_sim* s, int b, const float* y, int kind) {
+    hipLaunchKernelGGL(k_stage_y, dim3(ceil_div(s->n, 256)), dim3(256), 0, ctx->stream, s->n,
+                       reinterpret_cast<const float2*>(y), s->invZf.get(), s->rec.get());
+    DRG_LAUNCH_CHECK();
+    BlockedArgs a{};
+    a.n0 = s->n;
+    a.bits = s->blk_bits;
+    a.items = s->blk_items.get();
+    a.ent = s->blk_ent.get();
+    a.base = s->blk_base.get();
+    a.off = s->blk_off.get();
+    a.rec = s->rec.get();
+    a.partial = s->blk_partial.get();
+    a.eh0 = (float)(0.5 * s->e[0]);
+    a.eh1 = (float)(0.5 * s->e[1]);
+    a.eh2 = (float)(0.5 * s->e[2]);
+    a.eh3 = (float)(0.5 * s->e[3]);
+    const int nh = s->k == 1 ? 1 : (s->k == 2 ? 2 : 4);
+#define DRG_OBJ(BB, NN)                                                                  \
+    if (b == BB && nh == NN) {                                                           \
+        if (kind == 0) launch_obj_blocked<BB, NN, 0>(ctx, a, s->blk_nitems);             \
+        else launch_obj_blocked<BB, NN, 1>(ctx, a, s->blk_nitems);                       \
+        return;                                                                          \
+    }
+    DRG_OBJ(1, 1) DRG_OBJ(1, 2) DRG_OBJ(1, 4)
+    DRG_OBJ(2, 1) DRG_OBJ(2, 2) DRG_OBJ(2, 4)
+    DRG_OBJ(3, 1) DRG_OBJ(3, 2) DRG_OBJ(3, 4)
+#undef DRG_OBJ
+    throw Error(DRG_E_INVALID, "objective: b in 1..3");
 }
 
 // The sweep and finish of one synchronous FP32 iteration on the blocked

@@ -107,6 +107,9 @@ void build_blocked(drg_ctx* ctx, drg_sim* s);
 void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip, float eta,
                    uint64_t seed, uint64_t iter, float2* g, float2* y, hipEvent_t e0,
                    hipEvent_t e1);
+// The objective's attraction terms per (block, row) into s->blk_partial from
+// coordinates y: kind 0 = row values, 1 = attraction gradients.
+void sweep_blocked_objective(drg_ctx* ctx, drg_sim* s, int b, const float* y, int kind);
 // objective.hip
 template <typename T>
 void objective_fwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T* y, T* loss,

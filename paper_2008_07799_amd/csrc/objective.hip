@@ -12,6 +12,8 @@
 // every negative again from its counter; the other-side terms are grouped by
 // drawn node with a stable sort of (v, pair index) and summed in pair order,
 // so the gradient is deterministic.
+#include <cstdlib>
+
 #include "drg_internal.hpp"
 
 namespace drg {
@@ -178,6 +180,52 @@ __global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
     }
 }
 
+// FP32 with the column-blocked layout: the attraction terms come per (block,
+// row) from the flat blocked sweep; one thread per row adds them in block
+// order, adds its own negatives and writes the row value (KIND 0) or the
+// row's own gradient (KIND 1).
+template <int B, int KIND>
+__global__ void k_obj_finish(ObjArgs<float> a, int32_t nb, const float2* __restrict__ partial) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const float dl = (KIND == 1 && a.dloss) ? *a.dloss : 1.0f;
+    if (a.prp[i] >= a.prp[i + 1]) {
+        if constexpr (KIND == 0) a.row_val[i] = 0.0f;
+        else a.dy[i] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    float ax = 0.0f, ay = 0.0f;
+    for (int32_t b = 0; b < nb; ++b) {
+        const float2 p = partial[(int64_t)b * a.n + i];
+        ax += p.x;
+        ay += p.y;
+    }
+    const float2 yi = a.y[i];
+    float rx = 0.0f, ry = 0.0f;
+    for (int m = 0; m < a.M; ++m) {
+        const int32_t v =
+            draw_node(neg_word(a.seed, a.iter, (int32_t)i, m), a.C, a.guide, a.gbits, a.S);
+        if (v == (int32_t)i) continue;
+        const float2 yv = a.y[v];
+        const float dx = yi.x - yv.x, dy = yi.y - yv.y;
+        const float d2 = dx * dx + dy * dy;
+        if (!(d2 > 0.0f)) continue;
+        if constexpr (KIND == 0) {
+            rx += (float)B * logf(d2) - log1pf(opow<B>(d2));
+        } else {
+            const float k = (float)(2 * B) / (d2 * (1.0f + opow<B>(d2)));
+            rx += k * dx;
+            ry += k * dy;
+        }
+    }
+    const float gq = a.gamma * a.qt[i];
+    if constexpr (KIND == 0) {
+        a.row_val[i] = ax + gq * rx;
+    } else {
+        a.dy[i] = make_float2(dl * (2.0f * ax + gq * rx), dl * (2.0f * ay + gq * ry));
+    }
+}
+
 // key = drawn node (n for "none": inactive anchor or self draw), value = u*M+m
 __global__ void k_neg_keys(int32_t n, int32_t M, const int64_t* __restrict__ prp,
                            const uint64_t* __restrict__ C, const int32_t* __restrict__ guide,
@@ -327,6 +375,49 @@ static void launch_obj_g(hipStream_t st, const ObjArgs<T>& a, int G, bool grad) 
     else launch_obj<T, B, 64>(st, a, grad);
 }
 
+static bool obj_blocked_wanted() {
+    const char* v = std::getenv("DRG_OBJ_BLOCKED");
+    return !(v && *v == '0');
+}
+
+// Attraction and own-side terms of every row: the blocked flat sweep when the
+// similarity has the column-blocked copy (FP32), else the row kernels.
+template <typename T>
+static void obj_rows(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const ObjArgs<T>& a,
+                     bool grad) {
+    hipStream_t st = ctx->stream;
+    if constexpr (std::is_same<T, float>::value) {
+        if (s->blk_nb > 0 && obj_blocked_wanted()) {
+            sweep_blocked_objective(ctx, s, p->b, reinterpret_cast<const float*>(a.y), grad ? 1 : 0);
+            const float2* part = s->blk_partial.get();
+#define DRG_FIN(BB)                                                                          \
+    case BB:                                                                                 \
+        if (grad)                                                                            \
+            hipLaunchKernelGGL((k_obj_finish<BB, 1>), dim3(ceil_div(s->n, 256)), dim3(256), 0, \
+                               st, a, s->blk_nb, part);                                      \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_obj_finish<BB, 0>), dim3(ceil_div(s->n, 256)), dim3(256), 0, \
+                               st, a, s->blk_nb, part);                                      \
+        break;
+            switch (p->b) {
+                DRG_FIN(1)
+                DRG_FIN(2)
+                default:
+                DRG_FIN(3)
+            }
+#undef DRG_FIN
+            DRG_LAUNCH_CHECK();
+            return;
+        }
+    }
+    const int G = obj_group(s);
+    switch (p->b) {
+        case 1: launch_obj_g<T, 1>(st, a, G, grad); break;
+        case 2: launch_obj_g<T, 2>(st, a, G, grad); break;
+        default: launch_obj_g<T, 3>(st, a, G, grad); break;
+    }
+}
+
 template <typename T>
 void objective_fwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T* y, T* loss,
                      T* rows) {
@@ -337,12 +428,7 @@ void objective_fwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T*
     if (!rows) rv.alloc(s->n);
     ObjArgs<T> a = obj_args<T>(s, p, y);
     a.row_val = rows ? rows : rv.get();
-    const int G = obj_group(s);
-    switch (p->b) {
-        case 1: launch_obj_g<T, 1>(st, a, G, false); break;
-        case 2: launch_obj_g<T, 2>(st, a, G, false); break;
-        default: launch_obj_g<T, 3>(st, a, G, false); break;
-    }
+    obj_rows<T>(ctx, s, p, a, false);
     if (!loss) {
         DRG_HIP(hipStreamSynchronize(st));
         return;
@@ -374,12 +460,7 @@ void objective_bwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T*
     ObjArgs<T> a = obj_args<T>(s, p, y);
     a.dloss = dloss;
     a.dy = reinterpret_cast<typename OV<T>::v2*>(dy);
-    const int G = obj_group(s);
-    switch (p->b) {
-        case 1: launch_obj_g<T, 1>(st, a, G, true); break;
-        case 2: launch_obj_g<T, 2>(st, a, G, true); break;
-        default: launch_obj_g<T, 3>(st, a, G, true); break;
-    }
+    obj_rows<T>(ctx, s, p, a, true);
     if (a.M == 0) return;
     const int64_t np = (int64_t)s->n * a.M;
     if (np >= ((int64_t)1 << 31)) throw Error(DRG_E_UNSUPPORTED, "objective: n*M >= 2^31");
