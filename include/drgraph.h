@@ -48,7 +48,10 @@ typedef int32_t drg_status;
 #define DRG_VALIDATE 1u      /* flag: validate the input CSR on the device */
 
 #define DRG_MODE_SYNC 0      /* Jacobi: all steps from one snapshot, deterministic */
-#define DRG_MODE_ASYNC 1     /* Hogwild: steps applied in place while others read */
+#define DRG_MODE_ASYNC 1     /* Hogwild: steps applied in place while others read;
+                                on a similarity with the column-blocked copy
+                                (drg_sim_info's `blocked`) the FP32 step runs
+                                the synchronous sweep in both modes */
 
 typedef struct drg_ctx drg_ctx;
 typedef struct drg_sim drg_sim;

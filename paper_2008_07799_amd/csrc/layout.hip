@@ -348,7 +348,12 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.invZ = invZ;
     a.eta = (T)p->eta;
     const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
-    const bool async = p->mode == DRG_MODE_ASYNC;
+    // On the column-blocked layout both modes run the synchronous sweep: the
+    // snapshot it stages costs well under 1% of an iteration there, and the
+    // Hogwild kernel's global gathers and atomics are an order of magnitude
+    // slower than the LDS-staged sweep.
+    const bool blocked = F32 && s->blk_nb > 0;
+    const bool async = p->mode == DRG_MODE_ASYNC && !blocked;
     if (async) {
         if (level == 0) {
             a.w = qt;
@@ -371,7 +376,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
         DRG_HIP(hipEventCreate(&e1));
     }
     if constexpr (F32) {
-        if (!async && s->blk_nb > 0) {
+        if (blocked) {
             // LDS-staged sweep over the column-blocked pattern; at level 0 the
             // finishing kernel applies the step itself
             sweep_blocked(ctx, s, p->b, a.M, a.gamma, a.clip, a.eta, a.seed, a.iter,
