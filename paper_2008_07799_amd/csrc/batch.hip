@@ -25,6 +25,7 @@
 #include <memory>
 #include <string>
 
+#include "drg_blocked.hpp"
 #include "drg_forces.hpp"
 #include "drg_internal.hpp"
 
@@ -33,7 +34,7 @@ namespace drg {
 struct BGraph {              // constants of graph c
     int32_t base, n;         // finest nodes are union ids base .. base+n-1
     int32_t G, b, M, L;      // lanes per row, exponent, negatives (0 if S = 0), levels
-    int32_t gbits, guide_off, lv_off, pad;
+    int32_t gbits, guide_off, lv_off, blk;  // blk: swept on its column-blocked copy
     uint64_t S, Cbase;       // sampling total and C[base]
     uint64_t seed;
     float clip, pad2;
@@ -293,6 +294,7 @@ __global__ __launch_bounds__(WIN_BLOCK) void k_b_sweep_win(BWinArgs a) {
     const BSched sc = a.sched[(int64_t)a.t * a.count + it.graph];
     if (sc.level < 0) return;  // the whole workgroup leaves
     const BGraph g = a.gt[it.graph];
+    if (g.blk) return;  // swept by k_b_sweep_blocked
     auto draw = [&](uint64_t w) { return g.base + draw_in_graph(w, a.C, a.guide, g); };
     auto key = [&](int64_t i) { return (int32_t)(i - g.base); };
     if (g.b == 1)
@@ -307,6 +309,105 @@ __global__ __launch_bounds__(WIN_BLOCK) void k_b_sweep_win(BWinArgs a) {
         window_item<3, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
                                        g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
                                        a.g);
+}
+
+// Graphs whose single-graph sweep runs on the column-blocked copy (large
+// patterns) keep that copy here, built by the same rule, so each of them is
+// swept with the same work items and arithmetic as alone.
+struct BBlkView {
+    const uint16_t* ent;
+    const int64_t* base;
+    const int32_t* off;
+    float2* partial;
+    int32_t nb, bits;
+    float eh0, eh1, eh2, eh3;  // -b e_d per hop
+    float clip;                // clip / (2b)
+    int32_t pad;
+};
+
+struct BBlkArgs {
+    int32_t count, t, flat, lanes;
+    const int4* items;  // (block, first row, end row, graph)
+    const BBlkView* views;
+    const BGraph* gt;
+    const BSched* sched;
+    const float4* rec;
+};
+
+template <int NH>
+__global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
+    extern __shared__ float4 s_dyn[];
+    const int4 it = a.items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
+    const int32_t c = it.w;
+    if (a.sched[(int64_t)a.t * a.count + c].level < 0) return;  // the whole workgroup leaves
+    const BGraph g = a.gt[c];
+    const BBlkView v = a.views[c];
+    BlockedArgs la{};
+    la.n0 = g.n;
+    la.bits = v.bits;
+    la.ent = v.ent;
+    la.base = v.base;
+    la.off = v.off;
+    la.rec = a.rec + g.base;
+    la.partial = v.partial;
+    la.eh0 = v.eh0;
+    la.eh1 = v.eh1;
+    la.eh2 = v.eh2;
+    la.eh3 = v.eh3;
+    la.clip = v.clip;
+    la.lanes = a.lanes;
+    la.flat = a.flat;
+    if (g.b == 1)
+        blk_layout_item<1, NH>(la, s_dyn, it.x, it.y, it.z);
+    else if (g.b == 2)
+        blk_layout_item<2, NH>(la, s_dyn, it.x, it.y, it.z);
+    else
+        blk_layout_item<3, NH>(la, s_dyn, it.x, it.y, it.z);
+}
+
+struct BFinArgs {
+    int32_t nblk, count, t;
+    const int32_t* boff;    // [nblk+1] node prefix over the blocked graphs
+    const int32_t* bgraph;  // [nblk] their graph ids
+    const BBlkView* views;
+    const BGraph* gt;
+    const BSched* sched;
+    const int64_t* prp;
+    const float4* rec;
+    const float* qt;
+    const uint64_t* C;
+    const int32_t* guide;
+    float2* g;
+};
+
+// One thread per node of a blocked graph: its partials and own negatives.
+__global__ void k_b_finish(BFinArgs a) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.boff[a.nblk]) return;
+    const int32_t k = find_owner(a.boff, a.nblk, x);
+    const int32_t c = a.bgraph[k];
+    const BSched sc = a.sched[(int64_t)a.t * a.count + c];
+    if (sc.level < 0) return;
+    const BGraph g = a.gt[c];
+    const BBlkView v = a.views[c];
+    const int32_t u = (int32_t)(x - a.boff[k]);
+    const int64_t i = (int64_t)g.base + u;
+    float2 gi = make_float2(0.0f, 0.0f);
+    if (a.prp[i + 1] > a.prp[i]) {
+        const float4* R = a.rec + g.base;
+        auto draw = [&](uint64_t w) { return draw_in_graph(w, a.C, a.guide, g); };
+        const float gq = sc.gamma * a.qt[i];
+        if (g.b == 1)
+            gi = blk_finish_row<1>(v.partial, v.nb, g.n, u, R, R[u], g.M, g.seed, (uint64_t)a.t,
+                                   u, draw, gq, g.clip);
+        else if (g.b == 2)
+            gi = blk_finish_row<2>(v.partial, v.nb, g.n, u, R, R[u], g.M, g.seed, (uint64_t)a.t,
+                                   u, draw, gq, g.clip);
+        else
+            gi = blk_finish_row<3>(v.partial, v.nb, g.n, u, R, R[u], g.M, g.seed, (uint64_t)a.t,
+                                   u, draw, gq, g.clip);
+    }
+    a.g[i] = gi;
 }
 
 // One thread per node of each graph's current level (off: this phase's prefix).
@@ -360,6 +461,11 @@ struct drg_batch {
     drg::DevBuf<drg::BSched> sched;
     drg::DevBuf<int32_t> gid, guide, woff, init_off, phase_off, pro_off;
     drg::DevBuf<drg::WinItem> win_items;        // items of the chosen windowed form
+    std::vector<std::unique_ptr<drg::BlkLayout>> blk;  // column-blocked copies (large graphs)
+    drg::DevBuf<int4> blk_items;
+    drg::DevBuf<drg::BBlkView> blk_views;
+    drg::DevBuf<int32_t> blk_off, blk_graph;
+    int32_t blk_nitems = 0, blk_count = 0, blk_nodes = 0;
     drg::SweepForm form;                        // chosen sweep form
     std::vector<std::pair<drg::SweepForm, float>> tune;  // candidates and their times
     drg::DevBuf<int2> pro_ops;
@@ -504,6 +610,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         g.base = nbase[c];
         g.n = n;
         g.G = sweep_group((double)ui.nnz[c] / (double)std::max(1, nact[c]));
+        g.blk = blocked_wanted_for(ctx, n, ui.nnz[c]) ? 1 : 0;
         g.b = p.b;
         g.S = Cb[c + 1] - Cb[c];
         g.Cbase = Cb[c];
@@ -517,7 +624,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         g.lv_off = (int32_t)lt.size();
         g.seed = p.seed;
         g.clip = p.clip;
-        const int64_t w = ((int64_t)n + WAVE / g.G - 1) / (WAVE / g.G);
+        const int64_t w = g.blk ? 0 : ((int64_t)n + WAVE / g.G - 1) / (WAVE / g.G);
         if ((int64_t)woff[c] + w >= ((int64_t)1 << 31))
             throw Error(DRG_E_INVALID, "batched layout: too many rows");
         woff[c + 1] = woff[c] + (int32_t)w;
@@ -633,6 +740,93 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
     upload(b->init_off, ioff, st);
     b->y.alloc(b->y_total);
     DRG_HIP(hipStreamSynchronize(st));
+    // ---- graphs swept on their column-blocked copy, as they would be alone
+    const int NH = s->k == 1 ? 1 : (s->k == 2 ? 2 : 4);
+    const int blk_cpl = blk_flat_cpl(), blk_ln = blk_lanes();
+    size_t blk_lds = 0;
+    {
+        std::vector<BBlkView> views(count);
+        std::vector<int4> bitems;
+        std::vector<int32_t> boff(1, 0), bgraph;
+        int bits = 0;
+        for (int32_t c = 0; c < count; ++c) {
+            if (!gt[c].blk) continue;
+            const drg_layout_params& p = params[c];
+            auto L = std::make_unique<BlkLayout>();
+            build_blocked_core(ctx, gt[c].n, ui.nnz[c], s->row_ptr.get() + nbase[c],
+                               s->colhop.get(), nbase[c], *L);
+            BBlkView& v = views[c];
+            v.ent = L->ent.get();
+            v.base = L->base.get();
+            v.off = L->off.get();
+            v.partial = L->partial.get();
+            v.nb = L->nb;
+            v.bits = L->bits;
+            v.eh0 = (float)(-p.b * s->e[0]);
+            v.eh1 = (float)(-p.b * s->e[1]);
+            v.eh2 = (float)(-p.b * s->e[2]);
+            v.eh3 = (float)(-p.b * s->e[3]);
+            v.clip = p.clip / (float)(2 * p.b);
+            bits = L->bits;
+            std::vector<int4> h(L->nitems);
+            DRG_HIP(hipMemcpy(h.data(), L->items.get(), sizeof(int4) * L->nitems,
+                              hipMemcpyDeviceToHost));
+            for (int4 it : h) {
+                it.w = c;
+                bitems.push_back(it);
+            }
+            bgraph.push_back(c);
+            boff.push_back(boff.back() + gt[c].n);
+            b->blk.push_back(std::move(L));
+        }
+        b->blk_count = (int32_t)bgraph.size();
+        b->blk_nitems = (int32_t)bitems.size();
+        b->blk_nodes = boff.back();
+        if (b->blk_count > 0) {
+            upload(b->blk_views, views, st);
+            upload(b->blk_items, bitems, st);
+            upload(b->blk_off, boff, st);
+            upload(b->blk_graph, bgraph, st);
+            blk_lds = blk_lds_bytes(bits);
+            auto fn = NH == 1 ? k_b_sweep_blocked<1> : (NH == 2 ? k_b_sweep_blocked<2> : k_b_sweep_blocked<4>);
+            DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)blk_lds));
+            DRG_HIP(hipStreamSynchronize(st));
+        }
+    }
+    auto launch_blocked = [&](int32_t t, hipStream_t stream) {
+        if (b->blk_count == 0) return;
+        BBlkArgs ba{};
+        ba.count = count;
+        ba.t = t;
+        ba.flat = blk_cpl;
+        ba.lanes = blk_ln;
+        ba.items = b->blk_items.get();
+        ba.views = b->blk_views.get();
+        ba.gt = b->gt.get();
+        ba.sched = b->sched.get();
+        ba.rec = s->rec.get();
+        auto fn = NH == 1 ? k_b_sweep_blocked<1> : (NH == 2 ? k_b_sweep_blocked<2> : k_b_sweep_blocked<4>);
+        hipLaunchKernelGGL(fn, dim3(b->blk_nitems), dim3(STREAM_BLOCK), blk_lds, stream, ba);
+        DRG_LAUNCH_CHECK();
+        BFinArgs fa{};
+        fa.nblk = b->blk_count;
+        fa.count = count;
+        fa.t = t;
+        fa.boff = b->blk_off.get();
+        fa.bgraph = b->blk_graph.get();
+        fa.views = b->blk_views.get();
+        fa.gt = b->gt.get();
+        fa.sched = b->sched.get();
+        fa.prp = s->row_ptr.get();
+        fa.rec = s->rec.get();
+        fa.qt = s->qtf.get();
+        fa.C = s->C.get();
+        fa.guide = b->guide.get();
+        fa.g = s->g.get();
+        hipLaunchKernelGGL(k_b_finish, dim3(ceil_div(b->blk_nodes, 256)), dim3(256), 0, stream, fa);
+        DRG_LAUNCH_CHECK();
+    };
     // ---- the sweep: row form (k_b_sweep) or windowed form (k_b_sweep_win,
     // RPL rows per group, CH records per LDS chunk).  Both give the same bits;
     // the faster one on this batch is picked by timing each candidate once on
@@ -778,7 +972,8 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
                                b->gid.get(), b->gt.get(), b->lt.get(), b->sched.get(),
                                s->invZf.get(), b->y.get(), s->rec.get());
             DRG_LAUNCH_CHECK();
-            launch_form(b->form, t, cap);
+            if (b->blk_count < count) launch_form(b->form, t, cap);
+            launch_blocked(t, cap);
             const int32_t p = phase_of[t];
             const int32_t tot = phase_total[p];
             if (tot > 0) {

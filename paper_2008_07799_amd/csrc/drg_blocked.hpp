@@ -1,0 +1,526 @@
+// drg_blocked.hpp -- device side of the LDS-staged sweep over the
+// column-blocked copy of P~ (see blocked.hip): staging, pair operators and
+// the two sweep forms, shared by the single-graph and batched kernels.
+#pragma once
+#include "drg_forces.hpp"
+
+namespace drg {
+
+constexpr int BLK_HOP_SHIFT = 13;
+
+constexpr int ROWCAP = 4096;  // rows per work item
+
+struct BlockedArgs {
+    int32_t n0;
+    int32_t bits;
+    const int4* items;
+    const uint16_t* ent;
+    const int64_t* base;
+    const int32_t* off;
+    const float4* rec;
+    float2* partial;
+    float eh0, eh1, eh2, eh3;   // -2b * e_d / 2 per hop
+    float clip;                 // clip / (2b)
+    int32_t lanes;              // lanes per row segment (16, 32, 64; 0: per item)
+    int32_t flat;               // chunks per lane of the flat (merge-path) form; 0: row form
+};
+
+template <int B>
+__device__ __forceinline__ float blk_attract_coef(float d2) {
+    return -2.0f * (float)B * powi<B - 1>(d2) / (1.0f + powi<B>(d2));
+}
+template <int B>
+__device__ __forceinline__ float blk_repel_coef(float d2) {
+    return 2.0f * (float)B * rcp_fast(d2 * (1.0f + powi<B>(d2)));
+}
+
+// Attraction of one stored pair, scaled by `valid` (0 or 1) so a lane can
+// run all eight entries of its chunk without branching.  With the -2b factor
+// folded into the weight, -2b clip(p dx, c/(2b)) = clip(-2b p dx, c) because
+// the clip is odd.  A zero offset gives a zero force through dx = dy = 0.
+struct HopW {  // -2b e_d / 2 per hop, held in vector registers inside the loops
+    float e0, e1, e2, e3;
+};
+
+__device__ __forceinline__ HopW hop_weights(const BlockedArgs& a) {
+    HopW h{a.eh0, a.eh1, a.eh2, a.eh3};
+    // vector copies made once: selecting between two scalar operands would
+    // otherwise copy both into vector registers at every pair
+    asm volatile("" : "+v"(h.e0), "+v"(h.e1), "+v"(h.e2), "+v"(h.e3));
+    return h;
+}
+
+template <int B, int NH>
+__device__ __forceinline__ void blk_pair(const BlockedArgs& a, const HopW& hw, const float4& ri,
+                                         const float4* s_rec, uint32_t u, uint32_t lmask,
+                                         bool valid, float& ax, float& ay) {
+    const float4 rj = s_rec[u & lmask];
+    const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+    const float d2 = dx * dx + dy * dy;
+    float eh;
+    if constexpr (NH == 1) {
+        eh = hw.e0;
+    } else if constexpr (NH == 2) {
+        eh = (u >> BLK_HOP_SHIFT) ? hw.e1 : hw.e0;
+    } else {
+        const uint32_t h = u >> BLK_HOP_SHIFT;
+        eh = (h & 2u) ? ((h & 1u) ? hw.e3 : hw.e2) : ((h & 1u) ? hw.e1 : hw.e0);
+    }
+    const float p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
+    const float w = valid ? eh * (ri.z + rj.z) : 0.0f;
+    ax += w * clampf(p * dx, a.clip);
+    ay += w * clampf(p * dy, a.clip);
+}
+
+// Pair operators of the flat sweep: what one stored pair (record rj, entry u)
+// adds to the lane's partial of its row.  `valid` = 0 masks a slot.
+template <int NH>
+__device__ __forceinline__ float hop_weight(const HopW& hw, uint32_t u) {
+    if constexpr (NH == 1) {
+        return hw.e0;
+    } else if constexpr (NH == 2) {
+        return (u >> BLK_HOP_SHIFT) ? hw.e1 : hw.e0;
+    } else {
+        const uint32_t h = u >> BLK_HOP_SHIFT;
+        return (h & 2u) ? ((h & 1u) ? hw.e3 : hw.e2) : ((h & 1u) ? hw.e1 : hw.e0);
+    }
+}
+
+// the layout step: clipped attraction (weights carry -2b)
+template <int B, int NH>
+struct LayoutOp {
+    const BlockedArgs* a;
+    HopW hw;
+    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
+                                               uint32_t lmask, bool valid, float& ax,
+                                               float& ay) const {
+        blk_pair<B, NH>(*a, hw, ri, s_rec, u, lmask, valid, ax, ay);
+    }
+};
+
+// the objective: P~_ij log w_ij = -P~_ij log1p(d^{2b}) (weights are e_d / 2)
+template <int B, int NH>
+struct ObjValOp {
+    HopW hw;
+    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
+                                               uint32_t lmask, bool valid, float& ax,
+                                               float& ay) const {
+        const float4 rj = s_rec[u & lmask];
+        const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+        const float d2 = dx * dx + dy * dy;
+        const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
+        ax += pw * (-log1pf(powi<B>(d2)));
+        (void)ay;
+    }
+};
+
+// its gradient's attraction (unclipped): P~_ij (-2b d^{2b-2} / (1 + d^{2b})) (y_i - y_j)
+template <int B, int NH>
+struct ObjGradOp {
+    HopW hw;
+    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
+                                               uint32_t lmask, bool valid, float& ax,
+                                               float& ay) const {
+        const float4 rj = s_rec[u & lmask];
+        const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+        const float d2 = dx * dx + dy * dy;
+        const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
+        const float k = pw * (float)(-2 * B) * powi<B - 1>(d2) / (1.0f + powi<B>(d2));
+        ax += k * dx;
+        ay += k * dy;
+    }
+};
+
+// Workgroups of 1024 threads; an entry chunk is 16 bytes (eight 16-bit words).
+constexpr int STREAM_BLOCK = 1024;
+constexpr int STREAM_WAVES = STREAM_BLOCK / WAVE;
+
+__device__ __forceinline__ uint32_t half16(const uint4& v, int q) {
+    const uint32_t w = q < 2 ? v.x : (q < 4 ? v.y : (q < 6 ? v.z : v.w));
+    return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// The rows of an item, S lanes per row segment (64/S rows per wave at a
+// time): lane l of a group reads the aligned 16-byte chunk c0 + l of its
+// segment, so a group covers 8 S entries per step; short segments use small
+// groups so fewer lanes idle.  The first chunk of a group's next row is
+// requested before the current row is processed.
+template <int B, int NH, int S>
+__device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_rec,
+                                         const int32_t* s_off, int32_t b, int32_t r0, int32_t r1) {
+    constexpr int R = WAVE / S;
+    const int lane = __lane_id();
+    const int sl = lane % S, sub = lane / S;
+    const int32_t wid = threadIdx.x / WAVE;
+    const int64_t bbase = a.base[b];
+    const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
+    float2* P = a.partial + (int64_t)b * a.n0;
+    const uint32_t lmask = (1u << a.bits) - 1u;
+    const HopW hw = hop_weights(a);
+    // chunk of row r for this lane (first window), zero when outside
+    auto fetch = [&](int32_t r, int64_t& As, int64_t& Ae, uint4& v) {
+        As = bbase + s_off[r - r0];
+        Ae = bbase + s_off[r - r0 + 1];
+        const int64_t c = (As >> 3) + sl;
+        v = (As < Ae && c * 8 < Ae) ? E4[c] : make_uint4(0, 0, 0, 0);
+    };
+    const int32_t rstep = STREAM_WAVES * R;
+    int32_t r = r0 + wid * R + sub;
+    int64_t As = 0, Ae = 0;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (r < r1) fetch(r, As, Ae, v);
+    for (; r < r1; r += rstep) {
+        // request the next row's first chunk now
+        const int32_t rn = r + rstep;
+        int64_t Asn = 0, Aen = 0;
+        uint4 vn = make_uint4(0, 0, 0, 0);
+        if (rn < r1) fetch(rn, Asn, Aen, vn);
+        float ax = 0.0f, ay = 0.0f;
+        if (As < Ae) {
+            const float4 ri = a.rec[r];
+            const int32_t len = (int32_t)(Ae - As);
+            // rel: position of this lane's chunk start relative to the segment
+            int32_t rel = (int32_t)(((As >> 3) << 3) - As) + 8 * sl;
+            uint4 cur = v;
+            while (true) {
+                // the next window's chunk is requested before this one is used
+                const int32_t reln = rel + 8 * S;
+                const bool more = reln - 8 * sl < len;  // group-uniform
+                const uint4 nxt = (more && reln < len) ? E4[((As + reln) >> 3)]
+                                                       : make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool valid = (uint32_t)(rel + q) < (uint32_t)len;
+                    blk_pair<B, NH>(a, hw, ri, s_rec, half16(cur, q), lmask, valid, ax, ay);
+                }
+                if (!more) break;
+                rel = reln;
+                cur = nxt;
+            }
+            ax = group_sum<S>(ax);
+            ay = group_sum<S>(ay);
+        }
+        if (sl == 0) P[r] = make_float2(ax, ay);
+        As = Asn;
+        Ae = Aen;
+        v = vn;
+    }
+}
+
+// ------------------------------------------------------------------ flat form
+// The entries of an item (rows r0..r1 of block b) are contiguous, so the
+// item is swept as one stream regardless of row boundaries: wave w takes a
+// contiguous range of its 16-byte chunks, lane l the chunk w0 + l of each
+// 64-chunk window; every lane walks its 8 entries, tracking the row through
+// the LDS row offsets.  A row that starts and ends inside one lane is
+// complete there.  A row that crosses lanes is summed by a keyed segmented
+// scan over the lanes' last-row partials (in lane order), a row that crosses
+// windows is carried by the wave, and a row that crosses waves is closed by
+// one thread after the workgroup barrier, in wave order.  All of it depends
+// only on the layout of the data, so the result is repeatable.
+struct WaveFrag {
+    int32_t hrow, trow, same, pad;  // open head row, open tail row (-1: none)
+    float hx, hy, tx, ty;
+};
+
+// largest i in [lo, hi] with off[i] <= p
+__device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t lo, int32_t hi, int32_t p) {
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// largest i in [lo, hi] with off[i] <= p, given off[lo] <= p: doubling steps
+// from lo, then bisection (cheap when the answer is near lo)
+__device__ __forceinline__ int32_t row_from(const int32_t* off, int32_t lo, int32_t hi, int32_t p) {
+    int32_t step = 1;
+    while (lo + step <= hi && off[lo + step] <= p) {
+        lo += step;
+        step <<= 1;
+    }
+    return row_of(off, lo, min(lo + step - 1, hi), p);
+}
+
+template <int CPL, typename Op>
+__device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, const float4* s_rec,
+                                         const int32_t* s_off, WaveFrag* s_frag, int32_t b,
+                                         int32_t r0, int32_t r1) {
+    constexpr int EPL = 8 * CPL;          // entries per lane per window
+    constexpr int WCH = WAVE * CPL;       // chunks per window
+    const int lane = __lane_id();
+    const int wid = threadIdx.x / WAVE;
+    const int32_t nr = r1 - r0;
+    const int64_t bbase = a.base[b];
+    const int32_t e0 = s_off[0], e1 = s_off[nr];
+    float2* P = a.partial + (int64_t)b * a.n0 + r0;
+    const float4* R = a.rec + r0;
+    const uint4* E4 = reinterpret_cast<const uint4*>(a.ent);
+    const uint32_t lmask = (1u << a.bits) - 1u;
+    const int64_t cA = (bbase + e0) >> 3;
+    const int64_t nch = e1 > e0 ? ((bbase + e1 + 7) >> 3) - cA : 0;
+    const int64_t per = (nch + STREAM_WAVES - 1) / STREAM_WAVES;
+    const int64_t wc0 = cA + min(nch, per * wid), wc1 = cA + min(nch, per * (wid + 1));
+    // the wave's first row and whether it started before the wave's range
+    int32_t w_first = -1;
+    bool w_open = false;
+    if (wc0 < wc1) {
+        const int32_t fp = max((int32_t)(8 * wc0 - bbase), e0);
+        w_first = row_of(s_off, 0, nr - 1, fp);
+        w_open = s_off[w_first] < fp;
+    }
+    if (lane == 0) {
+        s_frag[wid].hrow = -1;
+        s_frag[wid].trow = -1;
+        s_frag[wid].same = 0;
+    }
+    // a complete row: written, unless it is the wave's open first row
+    auto close_row = [&](int32_t row, float x, float y) {
+        if (row == w_first && w_open) {
+            s_frag[wid].hrow = row;
+            s_frag[wid].hx = x;
+            s_frag[wid].hy = y;
+        } else {
+            P[row] = make_float2(x, y);
+        }
+    };
+    int32_t c_row = -1;  // row carried from the previous window (wave-uniform)
+    float c_x = 0.0f, c_y = 0.0f;
+    int32_t ilo = max(w_first, 0);
+    // chunk loads are unconditional, clamped to the wave's last chunk (slots
+    // past the range are masked), so the counters of outstanding loads stay
+    // exact and a wait for one load does not drain the prefetches
+    const int64_t clast = max(wc1 - 1, wc0);
+    uint4 vn[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) vn[k] = E4[min(wc0 + (int64_t)lane * CPL + k, clast)];
+    for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
+        const int64_t c = w0 + (int64_t)lane * CPL;  // the lane's first chunk
+        const int32_t nl = (int32_t)min((int64_t)WAVE, (wc1 - w0 + CPL - 1) / CPL);
+        const bool has = lane < nl;
+        const int32_t pbase = (int32_t)(8 * c - bbase);
+        const int32_t pf = max(pbase, e0);                                  // first valid slot
+        const int32_t pl = min(min(pbase + EPL, (int32_t)(8 * wc1 - bbase)), e1);  // end of valid slots
+        // the same bounds relative to the lane's first slot (none valid without a chunk)
+        const int32_t qlo = pf - pbase, qhi = has ? pl - pbase : 0;
+        // rows spanned by the window, then the lane's first row
+        const int32_t wp0 = max((int32_t)(8 * w0 - bbase), e0);
+        const int32_t wp1 = min((int32_t)(8 * min(w0 + WCH, wc1) - bbase), e1) - 1;
+        const int32_t i0 = row_from(s_off, ilo, nr - 1, wp0);
+        const int32_t i1 = row_from(s_off, i0, nr - 1, wp1);
+        int32_t i = has ? row_of(s_off, i0, i1, pf) : i1;
+        int32_t nxt = s_off[i + 1];
+        // the row record is requested before the next window's chunks, so
+        // waiting for it does not wait for them
+        float4 ri = R[i];
+        uint4 v[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            v[k] = vn[k];
+            vn[k] = E4[min(c + WCH + k, clast)];
+        }
+        float ax = 0.0f, ay = 0.0f, hx = 0.0f, hy = 0.0f;
+        const int32_t hrow = i;
+        bool hopen = true;  // still on the lane's first row
+        int32_t qn = nxt - pbase;  // slot where the current row ends
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                constexpr int32_t Q0 = 0;
+                const int32_t Q = Q0 + 8 * k + q;
+                const bool valid = Q >= qlo && Q < qhi;
+                if (valid && Q >= qn) {  // the row ends before this slot
+                    const int32_t p = pbase + Q;
+                    if (hopen) {
+                        hx = ax;
+                        hy = ay;
+                        hopen = false;
+                    } else {
+                        close_row(i, ax, ay);  // started and ended inside this lane
+                    }
+                    do {
+                        ++i;
+                        nxt = s_off[i + 1];
+                    } while (p >= nxt);
+                    qn = nxt - pbase;
+                    float4 rt = R[i];
+                    // keeps the reload on this (rare) path: otherwise the load is
+                    // moved past the branch and every entry waits for it
+                    asm volatile("" : "+v"(rt.x), "+v"(rt.y), "+v"(rt.z));
+                    ri = rt;
+                    ax = 0.0f;
+                    ay = 0.0f;
+                }
+                op(ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
+            }
+        }
+        // the window's carried row continues into lane 0
+        if (lane == 0 && hrow == c_row) {
+            if (hopen) {
+                ax = c_x + ax;
+                ay = c_y + ay;
+            } else {
+                hx = c_x + hx;
+                hy = c_y + hy;
+            }
+        }
+        // keyed inclusive scan of the lanes' last-row partials
+        const int32_t tk = has ? i : -2 - lane;
+        float sx = ax, sy = ay;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const float ox = __shfl_up(sx, d), oy = __shfl_up(sy, d);
+            const int32_t ok = __shfl_up(tk, d);
+            if (lane >= d && ok == tk) {
+                sx = ox + sx;
+                sy = oy + sy;
+            }
+        }
+        // a first row that ended inside the lane: add what earlier lanes hold
+        const float px = __shfl_up(sx, 1), py = __shfl_up(sy, 1);
+        const int32_t pk = __shfl_up(tk, 1);
+        if (has && !hopen) {
+            const bool cin = lane > 0 && pk == hrow;
+            close_row(hrow, cin ? px + hx : hx, cin ? py + hy : hy);
+        }
+        // the last row: complete unless it goes on past this lane (into the
+        // next lane, the next window or the next wave)
+        const bool cont = has && nxt > pl;
+        if (has && !cont) close_row(i, sx, sy);
+        // carry of the window's last lane
+        const int32_t L = nl - 1;
+        const bool lcont = __shfl(cont ? 1 : 0, L) != 0;
+        const int32_t lrow = __shfl(i, L);
+        const float lx = __shfl(sx, L), ly = __shfl(sy, L);
+        c_row = lcont ? lrow : -1;
+        c_x = lcont ? lx : 0.0f;
+        c_y = lcont ? ly : 0.0f;
+        ilo = i1;
+    }
+    // the wave's open tail (its last row goes on into the next wave)
+    if (c_row >= 0 && lane == 0) {
+        s_frag[wid].trow = c_row;
+        s_frag[wid].tx = c_x;
+        s_frag[wid].ty = c_y;
+        s_frag[wid].same = (c_row == w_first && w_open) ? 1 : 0;
+    }
+    __syncthreads();
+    // rows across waves, in wave order: an open tail runs on through waves
+    // that lie inside it and is closed by the next wave's open head
+    if (threadIdx.x == 0) {
+        float x = 0.0f, y = 0.0f;
+        for (int w = 0; w < STREAM_WAVES; ++w) {
+            const WaveFrag f = s_frag[w];
+            if (f.same) {
+                x = x + f.tx;
+                y = y + f.ty;
+                continue;
+            }
+            if (f.hrow >= 0) P[f.hrow] = make_float2(x + f.hx, y + f.hy);
+            x = f.trow >= 0 ? f.tx : 0.0f;
+            y = f.trow >= 0 ? f.ty : 0.0f;
+        }
+    }
+}
+
+// One workgroup per item (block b, rows r0..r1): the block's records and the
+// item's row offsets go to LDS, then the rows are swept with the lanes per
+// segment that suit the item's mean segment length.  Lane sums run in a
+// fixed order and the group reductions are fixed, so the result is
+// repeatable.
+// Stages block b's records and the item's row offsets into LDS.
+__device__ __forceinline__ void blk_stage(const BlockedArgs& a, float4* s_rec, int32_t* s_off,
+                                          int32_t b, int32_t r0, int32_t r1) {
+    const int32_t bw = 1 << a.bits;
+    const int32_t j0 = b * bw;
+    const int32_t cnt = min(bw, a.n0 - j0);
+    const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
+    for (int32_t t = threadIdx.x; t < bw; t += STREAM_BLOCK)
+        s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
+    __syncthreads();
+}
+
+// One work item of the layout sweep (block b, rows r0..r1): staging, then the
+// flat form with a.flat chunks per lane, or the row form (a.lanes lanes per
+// segment, 0: chosen from the item's mean segment length).  s_dyn is the
+// workgroup's dynamic LDS (records, row offsets, wave fragments).
+template <int B, int NH>
+__device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_dyn, int32_t b,
+                                                int32_t r0, int32_t r1) {
+    const int32_t bw = 1 << a.bits;
+    float4* s_rec = s_dyn;
+    int32_t* s_off = reinterpret_cast<int32_t*>(s_dyn + bw);
+    WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
+    blk_stage(a, s_rec, s_off, b, r0, r1);
+    const LayoutOp<B, NH> op{&a, hop_weights(a)};
+    if (a.flat == 1) {
+        blk_flat<1>(a, op, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    if (a.flat == 2) {
+        blk_flat<2>(a, op, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    if (a.flat == 4) {
+        blk_flat<4>(a, op, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    if (a.flat == 8) {
+        blk_flat<8>(a, op, s_rec, s_off, s_frag, b, r0, r1);
+        return;
+    }
+    int S = a.lanes;
+    if (S == 0) {
+        const int32_t rows = max(1, r1 - r0);
+        const int32_t mean = (s_off[r1 - r0] - s_off[0]) / rows;
+        S = mean >= 320 ? 64 : (mean >= 96 ? 32 : 16);
+    }
+    if (S == 16)
+        blk_rows<B, NH, 16>(a, s_rec, s_off, b, r0, r1);
+    else if (S == 32)
+        blk_rows<B, NH, 32>(a, s_rec, s_off, b, r0, r1);
+    else
+        blk_rows<B, NH, 64>(a, s_rec, s_off, b, r0, r1);
+}
+
+// dynamic LDS of a blocked-sweep workgroup
+inline size_t blk_lds_bytes(int bits) {
+    return ((size_t)16 << bits) + 16 * ((ROWCAP + 4) / 4) + sizeof(WaveFrag) * STREAM_WAVES;
+}
+
+// g_i of one finest node on the blocked layout: its block partials added in
+// block order, plus its own M negatives (draw(w) gives the record index of
+// the drawn node, key the node's own id for the negative words).
+template <int B, typename Draw>
+__device__ __forceinline__ float2 blk_finish_row(const float2* __restrict__ partial, int32_t nb,
+                                                 int64_t stride, int32_t row,
+                                                 const float4* __restrict__ rec, const float4& ri,
+                                                 int M, uint64_t seed, uint64_t iter, int32_t key,
+                                                 Draw draw, float gq, float clip) {
+    float ax = 0.0f, ay = 0.0f;
+    for (int32_t b = 0; b < nb; ++b) {
+        const float2 p = partial[(int64_t)b * stride + row];
+        ax += p.x;
+        ay += p.y;
+    }
+    float rx = 0.0f, ry = 0.0f;
+    for (int m = 0; m < M; ++m) {
+        const float4 rv = rec[draw(neg_word(seed, iter, key, m))];
+        const float dx = ri.x - rv.x, dy = ri.y - rv.y;
+        const float d2 = dx * dx + dy * dy;
+        if (d2 > 0.0f) {
+            const float k = blk_repel_coef<B>(d2);
+            rx += repel_component(k, dx, clip);
+            ry += repel_component(k, dy, clip);
+        }
+    }
+    return make_float2(ax + gq * rx, ay + gq * ry);
+}
+
+}  // namespace drg

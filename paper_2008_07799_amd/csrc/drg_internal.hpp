@@ -102,11 +102,26 @@ void validate_csr(drg_ctx* ctx, const drg_csr* g);
 void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,
                 double* qt, uint64_t* W, double* e, double* invZ);
 // blocked.hip
+// Column-blocked copy of a pattern (see blocked.hip).
+struct BlkLayout {
+    int32_t nb = 0, bits = 0, nitems = 0;
+    DevBuf<int64_t> base;     // [nb+1] first entry of each block
+    DevBuf<int32_t> off;      // [nb][n+1] row offsets inside a block
+    DevBuf<uint16_t> ent;     // [nnz+8] block-local col | (hop-1) << 13
+    DevBuf<int4> items;       // (block, first row, end row, -)
+    DevBuf<float2> partial;   // [nb][n] partial attraction (zero where a row has no entry)
+};
 bool blocked_wanted(drg_ctx* ctx, const drg_sim* s);
+bool blocked_wanted_for(drg_ctx* ctx, int32_t n, int64_t nnz);
 void build_blocked(drg_ctx* ctx, drg_sim* s);
-void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip, float eta,
-                   uint64_t seed, uint64_t iter, float2* g, float2* y, hipEvent_t e0,
-                   hipEvent_t e1);
+// rows prp[0..n] of a pattern whose columns are col_base .. col_base+n-1
+void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp,
+                        const uint32_t* colhop, int32_t col_base, BlkLayout& L);
+int blk_flat_cpl();  // chunks per lane of the flat form (env DRG_BLK_FLAT; 0: row form)
+int blk_lanes();     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
+// One FP32 sync sweep on the blocked layout: the one-sided steps into g.
+void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
+                   uint64_t seed, uint64_t iter, float2* g, hipEvent_t e0, hipEvent_t e1);
 // The objective's attraction terms per (block, row) into s->blk_partial from
 // coordinates y: kind 0 = row values, 1 = attraction gradients.
 void sweep_blocked_objective(drg_ctx* ctx, drg_sim* s, int b, const float* y, int kind);

@@ -377,19 +377,19 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     }
     if constexpr (F32) {
         if (blocked) {
-            // LDS-staged sweep over the column-blocked pattern; at level 0 the
-            // finishing kernel applies the step itself
-            sweep_blocked(ctx, s, p->b, a.M, a.gamma, a.clip, a.eta, a.seed, a.iter,
-                          level == 0 ? nullptr : g, level == 0 ? reinterpret_cast<v2*>(y) : nullptr,
-                          e0, e1);
+            // LDS-staged sweep over the column-blocked pattern
+            sweep_blocked(ctx, s, p->b, a.M, a.gamma, a.clip, a.seed, a.iter, g, e0, e1);
             if (ctx->profiling) ctx->events.emplace_back(e0, e1);
-            if (level > 0) {
+            if (level == 0) {
+                hipLaunchKernelGGL(k_apply0<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, g,
+                                   qt, reinterpret_cast<v2*>(y), (T)p->eta);
+            } else {
                 const drg_level& L = h->lv[level];
                 hipLaunchKernelGGL(k_apply_level<T>, dim3(ceil_div(nl, 256)), dim3(256), 0, st, nl,
                                    L.seg.get(), L.perm.get(), g, qt, reinterpret_cast<v2*>(y),
                                    (T)p->eta);
-                DRG_LAUNCH_CHECK();
             }
+            DRG_LAUNCH_CHECK();
             return;
         }
     }
