@@ -322,7 +322,7 @@ struct BBlkView {
     int32_t nb, bits;
     float eh0, eh1, eh2, eh3;  // -b e_d per hop
     float clip;                // clip / (2b)
-    int32_t pad;
+    int32_t noclip;            // the clip cannot bind (blk_clip_free)
 };
 
 struct BBlkArgs {
@@ -334,7 +334,7 @@ struct BBlkArgs {
     const float4* rec;
 };
 
-template <int NH>
+template <int NH, int F>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
     extern __shared__ float4 s_dyn[];
     const int4 it = a.items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
@@ -355,14 +355,30 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
     la.eh2 = v.eh2;
     la.eh3 = v.eh3;
     la.clip = v.clip;
+    la.noclip = v.noclip;
     la.lanes = a.lanes;
     la.flat = a.flat;
     if (g.b == 1)
-        blk_layout_item<1, NH>(la, s_dyn, it.x, it.y, it.z);
+        blk_layout_item<1, NH, F>(la, s_dyn, it.x, it.y, it.z);
     else if (g.b == 2)
-        blk_layout_item<2, NH>(la, s_dyn, it.x, it.y, it.z);
+        blk_layout_item<2, NH, F>(la, s_dyn, it.x, it.y, it.z);
     else
-        blk_layout_item<3, NH>(la, s_dyn, it.x, it.y, it.z);
+        blk_layout_item<3, NH, F>(la, s_dyn, it.x, it.y, it.z);
+}
+
+template <int NH>
+static auto b_blk_kernel_nh(int form) {
+    return form == 4   ? k_b_sweep_blocked<NH, 4>
+           : form == 8 ? k_b_sweep_blocked<NH, 8>
+           : form == 2 ? k_b_sweep_blocked<NH, 2>
+           : form == 1 ? k_b_sweep_blocked<NH, 1>
+                       : k_b_sweep_blocked<NH, 0>;
+}
+
+// the batch's blocked-sweep kernel for NH hop weights and sweep form F
+static auto b_blk_kernel(int NH, int form) {
+    return NH == 1 ? b_blk_kernel_nh<1>(form)
+                   : (NH == 2 ? b_blk_kernel_nh<2>(form) : b_blk_kernel_nh<4>(form));
 }
 
 struct BFinArgs {
@@ -767,6 +783,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             v.eh2 = (float)(-p.b * s->e[2]);
             v.eh3 = (float)(-p.b * s->e[3]);
             v.clip = p.clip / (float)(2 * p.b);
+            v.noclip = blk_clip_free(p.b, v.clip) ? 1 : 0;
             bits = L->bits;
             std::vector<int4> h(L->nitems);
             DRG_HIP(hipMemcpy(h.data(), L->items.get(), sizeof(int4) * L->nitems,
@@ -788,7 +805,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             upload(b->blk_off, boff, st);
             upload(b->blk_graph, bgraph, st);
             blk_lds = blk_lds_bytes(bits);
-            auto fn = NH == 1 ? k_b_sweep_blocked<1> : (NH == 2 ? k_b_sweep_blocked<2> : k_b_sweep_blocked<4>);
+            auto fn = b_blk_kernel(NH, blk_form(blk_cpl));
             DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)blk_lds));
             DRG_HIP(hipStreamSynchronize(st));
@@ -806,7 +823,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         ba.gt = b->gt.get();
         ba.sched = b->sched.get();
         ba.rec = s->rec.get();
-        auto fn = NH == 1 ? k_b_sweep_blocked<1> : (NH == 2 ? k_b_sweep_blocked<2> : k_b_sweep_blocked<4>);
+        auto fn = b_blk_kernel(NH, blk_form(blk_cpl));
         hipLaunchKernelGGL(fn, dim3(b->blk_nitems), dim3(STREAM_BLOCK), blk_lds, stream, ba);
         DRG_LAUNCH_CHECK();
         BFinArgs fa{};

@@ -12,6 +12,7 @@
 // leaves a partial attraction; a second kernel adds the partials of a row in
 // block order (deterministic), draws the row's negatives and applies the step.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 #include "drg_blocked.hpp"
@@ -117,11 +118,11 @@ __global__ void k_blk_items(int32_t n, int32_t nb, const int32_t* __restrict__ o
     items[first + c] = make_int4(b, r0, r1, 0);
 }
 
-template <int B, int NH>
+template <int B, int NH, int F>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked(BlockedArgs a) {
     extern __shared__ float4 s_dyn[];
     const int4 it = a.items[blockIdx.x];
-    blk_layout_item<B, NH>(a, s_dyn, it.x, it.y, it.z);
+    blk_layout_item<B, NH, F>(a, s_dyn, it.x, it.y, it.z);
 }
 
 // The objective's attraction terms over the blocked layout (flat form): the
@@ -301,11 +302,25 @@ int blk_flat_cpl() {
     return (f == 1 || f == 2 || f == 4 || f == 8) ? f : 0;
 }
 
+// True when clip(p dx, c) with c = clip / (2b) can never bind: for an
+// offset of length d, |p dx| <= d^{2b-1} / (1 + d^{2b}), whose maximum over d
+// (at d^{2b} = 2b - 1) is (2b-1)^{(2b-1)/(2b)} / (2b).  A 1% margin covers
+// the FP32 rounding of p and d^2.
+bool blk_clip_free(int b, float clip_over_2b) {
+    const double m = std::pow(2.0 * b - 1.0, (2.0 * b - 1.0) / (2.0 * b)) / (2.0 * b);
+    return (double)clip_over_2b >= 1.01 * m;
+}
+
 template <int B, int NH>
 static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
     const size_t lds = ((size_t)16 << a.bits) + 16 * ((ROWCAP + 4) / 4) +
                        sizeof(WaveFrag) * STREAM_WAVES;
-    auto fn = k_sweep_blocked<B, NH>;
+    const int form = blk_form(a.flat);
+    auto fn = form == 4   ? k_sweep_blocked<B, NH, 4>
+              : form == 8 ? k_sweep_blocked<B, NH, 8>
+              : form == 2 ? k_sweep_blocked<B, NH, 2>
+              : form == 1 ? k_sweep_blocked<B, NH, 1>
+                          : k_sweep_blocked<B, NH, 0>;
     DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     hipLaunchKernelGGL(fn, dim3(nitems), dim3(STREAM_BLOCK), lds, ctx->stream, a);
@@ -372,6 +387,7 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
     a.eh2 = (float)(-b * s->e[2]);
     a.eh3 = (float)(-b * s->e[3]);
     a.clip = clip / (float)(2 * b);
+    a.noclip = blk_clip_free(b, a.clip) ? 1 : 0;
     a.lanes = blk_lanes();
     a.flat = blk_flat_cpl();
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));

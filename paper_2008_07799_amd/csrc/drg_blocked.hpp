@@ -2,6 +2,8 @@
 // column-blocked copy of P~ (see blocked.hip): staging, pair operators and
 // the two sweep forms, shared by the single-graph and batched kernels.
 #pragma once
+#include <type_traits>
+
 #include "drg_forces.hpp"
 
 namespace drg {
@@ -23,6 +25,7 @@ struct BlockedArgs {
     float clip;                 // clip / (2b)
     int32_t lanes;              // lanes per row segment (16, 32, 64; 0: per item)
     int32_t flat;               // chunks per lane of the flat (merge-path) form; 0: row form
+    int32_t noclip;             // 1: the clip cannot bind (blk_clip_free), flat form skips it
 };
 
 template <int B>
@@ -50,6 +53,32 @@ __device__ __forceinline__ HopW hop_weights(const BlockedArgs& a) {
     return h;
 }
 
+// The hop weight of entry u by bit masks: m = the hop bit sign-extended
+// (v_bfe_i32), then one bit-field insert (v_bfi_b32) per select.  Written
+// as plain selects, a chain over four values is turned into an indexed load
+// from a private copy of the table, and a single select into a compare and
+// a conditional move.
+__device__ __forceinline__ float mask_pick(int32_t m, float if_set, float if_clear) {
+    float r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(if_set), "v"(if_clear));
+    return r;
+}
+
+template <int NH>
+__device__ __forceinline__ float hop_weight(const HopW& hw, uint32_t u) {
+    if constexpr (NH == 1) {
+        return hw.e0;
+    } else {
+        const int32_t m0 = __builtin_amdgcn_sbfe((int32_t)u, BLK_HOP_SHIFT, 1);  // hop bit 0
+        if constexpr (NH == 2) {
+            return mask_pick(m0, hw.e1, hw.e0);
+        } else {
+            const int32_t m1 = __builtin_amdgcn_sbfe((int32_t)u, BLK_HOP_SHIFT + 1, 1);  // hop bit 1
+            return mask_pick(m1, mask_pick(m0, hw.e3, hw.e2), mask_pick(m0, hw.e1, hw.e0));
+        }
+    }
+}
+
 template <int B, int NH>
 __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const HopW& hw, const float4& ri,
                                          const float4* s_rec, uint32_t u, uint32_t lmask,
@@ -57,44 +86,40 @@ __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const HopW& hw, c
     const float4 rj = s_rec[u & lmask];
     const float dx = ri.x - rj.x, dy = ri.y - rj.y;
     const float d2 = dx * dx + dy * dy;
-    float eh;
-    if constexpr (NH == 1) {
-        eh = hw.e0;
-    } else if constexpr (NH == 2) {
-        eh = (u >> BLK_HOP_SHIFT) ? hw.e1 : hw.e0;
-    } else {
-        const uint32_t h = u >> BLK_HOP_SHIFT;
-        eh = (h & 2u) ? ((h & 1u) ? hw.e3 : hw.e2) : ((h & 1u) ? hw.e1 : hw.e0);
-    }
+    const float eh = hop_weight<NH>(hw, u);
     const float p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
     const float w = valid ? eh * (ri.z + rj.z) : 0.0f;
     ax += w * clampf(p * dx, a.clip);
     ay += w * clampf(p * dy, a.clip);
 }
 
-// Pair operators of the flat sweep: what one stored pair (record rj, entry u)
-// adds to the lane's partial of its row.  `valid` = 0 masks a slot.
-template <int NH>
-__device__ __forceinline__ float hop_weight(const HopW& hw, uint32_t u) {
-    if constexpr (NH == 1) {
-        return hw.e0;
-    } else if constexpr (NH == 2) {
-        return (u >> BLK_HOP_SHIFT) ? hw.e1 : hw.e0;
-    } else {
-        const uint32_t h = u >> BLK_HOP_SHIFT;
-        return (h & 2u) ? ((h & 1u) ? hw.e3 : hw.e2) : ((h & 1u) ? hw.e1 : hw.e0);
-    }
-}
-
-// the layout step: clipped attraction (weights carry -2b)
-template <int B, int NH>
+// Pair operators of the flat sweep: what one stored pair (row record ri,
+// column record rj, entry u) adds to the lane's partial of its row.
+// `valid` = 0 masks a slot.
+//
+// The layout step: clipped attraction (weights carry -2b).  CLIP = false
+// when the clip cannot bind (|p dx| stays below it for every d, see
+// blk_clip_free): the clamp would return its argument, so it is left out and
+// the weight is folded into p first (one rounding moved, two clamps and a
+// multiply fewer per pair).
+template <int B, int NH, bool CLIP>
 struct LayoutOp {
     const BlockedArgs* a;
     HopW hw;
-    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
-                                               uint32_t lmask, bool valid, float& ax,
-                                               float& ay) const {
-        blk_pair<B, NH>(*a, hw, ri, s_rec, u, lmask, valid, ax, ay);
+    __device__ __forceinline__ void operator()(const float4& ri, const float4& rj, uint32_t u,
+                                               bool valid, float& ax, float& ay) const {
+        const float dx = ri.x - rj.x, dy = ri.y - rj.y;
+        const float d2 = dx * dx + dy * dy;
+        const float p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
+        const float w = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
+        if constexpr (CLIP) {
+            ax += w * clampf(p * dx, a->clip);
+            ay += w * clampf(p * dy, a->clip);
+        } else {
+            const float k = w * p;
+            ax += k * dx;
+            ay += k * dy;
+        }
     }
 };
 
@@ -102,10 +127,8 @@ struct LayoutOp {
 template <int B, int NH>
 struct ObjValOp {
     HopW hw;
-    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
-                                               uint32_t lmask, bool valid, float& ax,
-                                               float& ay) const {
-        const float4 rj = s_rec[u & lmask];
+    __device__ __forceinline__ void operator()(const float4& ri, const float4& rj, uint32_t u,
+                                               bool valid, float& ax, float& ay) const {
         const float dx = ri.x - rj.x, dy = ri.y - rj.y;
         const float d2 = dx * dx + dy * dy;
         const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
@@ -118,10 +141,8 @@ struct ObjValOp {
 template <int B, int NH>
 struct ObjGradOp {
     HopW hw;
-    __device__ __forceinline__ void operator()(const float4& ri, const float4* s_rec, uint32_t u,
-                                               uint32_t lmask, bool valid, float& ax,
-                                               float& ay) const {
-        const float4 rj = s_rec[u & lmask];
+    __device__ __forceinline__ void operator()(const float4& ri, const float4& rj, uint32_t u,
+                                               bool valid, float& ax, float& ay) const {
         const float dx = ri.x - rj.x, dy = ri.y - rj.y;
         const float d2 = dx * dx + dy * dy;
         const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
@@ -327,38 +348,53 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         const int32_t hrow = i;
         bool hopen = true;  // still on the lane's first row
         int32_t qn = nxt - pbase;  // slot where the current row ends
+        // FULL: every slot of every lane of the window is valid (all windows
+        // but those at the ends of an item or of the wave's range)
+        auto entries = [&](auto full_c) {
+            constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
+            for (int k = 0; k < CPL; ++k) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                constexpr int32_t Q0 = 0;
-                const int32_t Q = Q0 + 8 * k + q;
-                const bool valid = Q >= qlo && Q < qhi;
-                if (valid && Q >= qn) {  // the row ends before this slot
-                    const int32_t p = pbase + Q;
-                    if (hopen) {
-                        hx = ax;
-                        hy = ay;
-                        hopen = false;
-                    } else {
-                        close_row(i, ax, ay);  // started and ended inside this lane
+                for (int h = 0; h < 8; h += 4) {
+                    // four column records requested before any is used
+                    float4 rj[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) rj[q] = s_rec[half16(v[k], h + q) & lmask];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int32_t Q = 8 * k + h + q;
+                        const bool valid = FULL || (Q >= qlo && Q < qhi);
+                        if (valid && Q >= qn) {  // the row ends before this slot
+                            const int32_t p = pbase + Q;
+                            if (hopen) {
+                                hx = ax;
+                                hy = ay;
+                                hopen = false;
+                            } else {
+                                close_row(i, ax, ay);  // started and ended inside this lane
+                            }
+                            do {
+                                ++i;
+                                nxt = s_off[i + 1];
+                            } while (p >= nxt);
+                            qn = nxt - pbase;
+                            float4 rt = R[i];
+                            // keeps the reload on this (rare) path: otherwise the load is
+                            // moved past the branch and every entry waits for it
+                            asm volatile("" : "+v"(rt.x), "+v"(rt.y), "+v"(rt.z));
+                            ri = rt;
+                            ax = 0.0f;
+                            ay = 0.0f;
+                        }
+                        op(ri, rj[q], half16(v[k], h + q), valid, ax, ay);
                     }
-                    do {
-                        ++i;
-                        nxt = s_off[i + 1];
-                    } while (p >= nxt);
-                    qn = nxt - pbase;
-                    float4 rt = R[i];
-                    // keeps the reload on this (rare) path: otherwise the load is
-                    // moved past the branch and every entry waits for it
-                    asm volatile("" : "+v"(rt.x), "+v"(rt.y), "+v"(rt.z));
-                    ri = rt;
-                    ax = 0.0f;
-                    ay = 0.0f;
                 }
-                op(ri, s_rec, half16(v[k], q), lmask, valid, ax, ay);
             }
-        }
+        };
+        if (__all(has && qlo == 0 && qhi == EPL))
+            entries(std::true_type{});
+        else
+            entries(std::false_type{});
         // the window's carried row continues into lane 0
         if (lane == 0 && hrow == c_row) {
             if (hopen) {
@@ -446,11 +482,12 @@ __device__ __forceinline__ void blk_stage(const BlockedArgs& a, float4* s_rec, i
     __syncthreads();
 }
 
-// One work item of the layout sweep (block b, rows r0..r1): staging, then the
-// flat form with a.flat chunks per lane, or the row form (a.lanes lanes per
-// segment, 0: chosen from the item's mean segment length).  s_dyn is the
-// workgroup's dynamic LDS (records, row offsets, wave fragments).
-template <int B, int NH>
+// One work item of the layout sweep (block b, rows r0..r1): staging, then
+// the flat form with F chunks per lane (F = 1, 2, 4, 8), or for F = 0 the row
+// form (a.lanes lanes per segment, 0: chosen from the item's mean segment
+// length).  s_dyn is the workgroup's dynamic LDS (records, row offsets, wave
+// fragments).
+template <int B, int NH, int F>
 __device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_dyn, int32_t b,
                                                 int32_t r0, int32_t r1) {
     const int32_t bw = 1 << a.bits;
@@ -458,36 +495,32 @@ __device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_
     int32_t* s_off = reinterpret_cast<int32_t*>(s_dyn + bw);
     WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
     blk_stage(a, s_rec, s_off, b, r0, r1);
-    const LayoutOp<B, NH> op{&a, hop_weights(a)};
-    if (a.flat == 1) {
-        blk_flat<1>(a, op, s_rec, s_off, s_frag, b, r0, r1);
-        return;
+    if constexpr (F > 0) {
+        if (a.noclip)
+            blk_flat<F>(a, LayoutOp<B, NH, false>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b,
+                        r0, r1);
+        else
+            blk_flat<F>(a, LayoutOp<B, NH, true>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b,
+                        r0, r1);
+    } else {
+        int S = a.lanes;
+        if (S == 0) {
+            const int32_t rows = max(1, r1 - r0);
+            const int32_t mean = (s_off[r1 - r0] - s_off[0]) / rows;
+            S = mean >= 320 ? 64 : (mean >= 96 ? 32 : 16);
+        }
+        if (S == 16)
+            blk_rows<B, NH, 16>(a, s_rec, s_off, b, r0, r1);
+        else if (S == 32)
+            blk_rows<B, NH, 32>(a, s_rec, s_off, b, r0, r1);
+        else
+            blk_rows<B, NH, 64>(a, s_rec, s_off, b, r0, r1);
     }
-    if (a.flat == 2) {
-        blk_flat<2>(a, op, s_rec, s_off, s_frag, b, r0, r1);
-        return;
-    }
-    if (a.flat == 4) {
-        blk_flat<4>(a, op, s_rec, s_off, s_frag, b, r0, r1);
-        return;
-    }
-    if (a.flat == 8) {
-        blk_flat<8>(a, op, s_rec, s_off, s_frag, b, r0, r1);
-        return;
-    }
-    int S = a.lanes;
-    if (S == 0) {
-        const int32_t rows = max(1, r1 - r0);
-        const int32_t mean = (s_off[r1 - r0] - s_off[0]) / rows;
-        S = mean >= 320 ? 64 : (mean >= 96 ? 32 : 16);
-    }
-    if (S == 16)
-        blk_rows<B, NH, 16>(a, s_rec, s_off, b, r0, r1);
-    else if (S == 32)
-        blk_rows<B, NH, 32>(a, s_rec, s_off, b, r0, r1);
-    else
-        blk_rows<B, NH, 64>(a, s_rec, s_off, b, r0, r1);
 }
+
+// sweep form as a template argument: the flat form's chunks per lane, 0 for
+// the row form
+inline int blk_form(int flat) { return (flat == 1 || flat == 2 || flat == 4 || flat == 8) ? flat : 0; }
 
 // dynamic LDS of a blocked-sweep workgroup
 inline size_t blk_lds_bytes(int bits) {

@@ -118,7 +118,8 @@ void build_blocked(drg_ctx* ctx, drg_sim* s);
 void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp,
                         const uint32_t* colhop, int32_t col_base, BlkLayout& L);
 int blk_flat_cpl();  // chunks per lane of the flat form (env DRG_BLK_FLAT; 0: row form)
-int blk_lanes();     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
+int blk_lanes();
+bool blk_clip_free(int b, float clip_over_2b);  // the attraction clip cannot bind     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
 // One FP32 sync sweep on the blocked layout: the one-sided steps into g.
 void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
                    uint64_t seed, uint64_t iter, float2* g, hipEvent_t e0, hipEvent_t e1);
