@@ -24,6 +24,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 
 #include "drg_blocked.hpp"
 #include "drg_forces.hpp"
@@ -37,7 +38,8 @@ struct BGraph {              // constants of graph c
     int32_t gbits, guide_off, lv_off, blk;  // blk: swept on its column-blocked copy
     uint64_t S, Cbase;       // sampling total and C[base]
     uint64_t seed;
-    float clip, pad2;
+    float clip;
+    int32_t noclip;          // the attraction clip cannot bind (attract_clip_free)
 };
 
 struct BLevel {              // graph c at level l
@@ -232,10 +234,10 @@ struct BSweepArgs {
     HalfE<float> eh;
 };
 
-template <int B>
+template <int B, bool CLIP>
 __device__ __forceinline__ float2 b_row(const BSweepArgs& a, const BGraph& g, int64_t i,
                                         int32_t v, int lane, float gamma) {
-    return sweep_row<float, B>(a.rec[i], a.prp[i], a.prp[i + 1], lane, g.G, a.colhop, a.rec, a.eh,
+    return sweep_row<float, B, CLIP>(a.rec[i], a.prp[i], a.prp[i + 1], lane, g.G, a.colhop, a.rec, a.eh,
                                g.clip, g.M, g.seed, (uint64_t)a.t, v,
                                [&](uint64_t w) {
                                    return g.base + draw_in_graph(w, a.C, a.guide, g);
@@ -261,12 +263,21 @@ __global__ __launch_bounds__(256) void k_b_sweep(BSweepArgs a) {
     const int64_t i = (int64_t)g.base + v;
     float2 gi = make_float2(0.0f, 0.0f);
     if (a.prp[i] < a.prp[i + 1]) {
-        if (g.b == 1)
-            gi = b_row<1>(a, g, i, v, lane, sc.gamma);
-        else if (g.b == 2)
-            gi = b_row<2>(a, g, i, v, lane, sc.gamma);
-        else
-            gi = b_row<3>(a, g, i, v, lane, sc.gamma);
+        if (g.noclip) {
+            if (g.b == 1)
+                gi = b_row<1, false>(a, g, i, v, lane, sc.gamma);
+            else if (g.b == 2)
+                gi = b_row<2, false>(a, g, i, v, lane, sc.gamma);
+            else
+                gi = b_row<3, false>(a, g, i, v, lane, sc.gamma);
+        } else {
+            if (g.b == 1)
+                gi = b_row<1, true>(a, g, i, v, lane, sc.gamma);
+            else if (g.b == 2)
+                gi = b_row<2, true>(a, g, i, v, lane, sc.gamma);
+            else
+                gi = b_row<3, true>(a, g, i, v, lane, sc.gamma);
+        }
     }
     if (lane == 0) a.g[i] = gi;
 }
@@ -297,18 +308,28 @@ __global__ __launch_bounds__(WIN_BLOCK) void k_b_sweep_win(BWinArgs a) {
     if (g.blk) return;  // swept by k_b_sweep_blocked
     auto draw = [&](uint64_t w) { return g.base + draw_in_graph(w, a.C, a.guide, g); };
     auto key = [&](int64_t i) { return (int32_t)(i - g.base); };
-    if (g.b == 1)
-        window_item<1, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
-                                       g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
-                                       a.g);
-    else if (g.b == 2)
-        window_item<2, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
-                                       g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
-                                       a.g);
-    else
-        window_item<3, RPL, WIN_BLOCK>(it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh,
-                                       g.clip, g.M, g.seed, (uint64_t)a.t, sc.gamma, draw, key,
-                                       a.g);
+    auto item = [&](auto b_c, auto clip_c) {
+        window_item<decltype(b_c)::value, decltype(clip_c)::value, RPL, WIN_BLOCK>(
+            it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh, g.clip, g.M, g.seed,
+            (uint64_t)a.t, sc.gamma, draw, key, a.g);
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    if (g.noclip) {
+        if (g.b == 1)
+            item(std::integral_constant<int, 1>{}, no{});
+        else if (g.b == 2)
+            item(std::integral_constant<int, 2>{}, no{});
+        else
+            item(std::integral_constant<int, 3>{}, no{});
+    } else {
+        if (g.b == 1)
+            item(std::integral_constant<int, 1>{}, yes{});
+        else if (g.b == 2)
+            item(std::integral_constant<int, 2>{}, yes{});
+        else
+            item(std::integral_constant<int, 3>{}, yes{});
+    }
 }
 
 // Graphs whose single-graph sweep runs on the column-blocked copy (large
@@ -322,12 +343,13 @@ struct BBlkView {
     int32_t nb, bits;
     float eh0, eh1, eh2, eh3;  // -b e_d per hop
     float clip;                // clip / (2b)
-    int32_t noclip;            // the clip cannot bind (blk_clip_free)
+    int32_t noclip;            // the clip cannot bind (attract_clip_free)
 };
 
 struct BBlkArgs {
     int32_t count, t, flat, lanes;
-    const int4* items;  // (block, first row, end row, graph)
+    const int4* items;   // (block, first row, end row, graph)
+    const int4* groups;  // (first item, items, graph, -): consecutive items of one block
     const BBlkView* views;
     const BGraph* gt;
     const BSched* sched;
@@ -337,9 +359,11 @@ struct BBlkArgs {
 template <int NH, int F>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
     extern __shared__ float4 s_dyn[];
-    const int4 it = a.items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
-    const int32_t c = it.w;
+    const int4 gr = a.groups[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
+    const int32_t c = gr.z;
     if (a.sched[(int64_t)a.t * a.count + c].level < 0) return;  // the whole workgroup leaves
+    const int4* its = a.items + gr.x;
+    const int32_t blk = its[0].x;
     const BGraph g = a.gt[c];
     const BBlkView v = a.views[c];
     BlockedArgs la{};
@@ -359,11 +383,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
     la.lanes = a.lanes;
     la.flat = a.flat;
     if (g.b == 1)
-        blk_layout_item<1, NH, F>(la, s_dyn, it.x, it.y, it.z);
+        blk_layout_items<1, NH, F>(la, s_dyn, blk, its, gr.y);
     else if (g.b == 2)
-        blk_layout_item<2, NH, F>(la, s_dyn, it.x, it.y, it.z);
+        blk_layout_items<2, NH, F>(la, s_dyn, blk, its, gr.y);
     else
-        blk_layout_item<3, NH, F>(la, s_dyn, it.x, it.y, it.z);
+        blk_layout_items<3, NH, F>(la, s_dyn, blk, its, gr.y);
 }
 
 template <int NH>
@@ -479,9 +503,10 @@ struct drg_batch {
     drg::DevBuf<drg::WinItem> win_items;        // items of the chosen windowed form
     std::vector<std::unique_ptr<drg::BlkLayout>> blk;  // column-blocked copies (large graphs)
     drg::DevBuf<int4> blk_items;
+    drg::DevBuf<int4> blk_groups;
     drg::DevBuf<drg::BBlkView> blk_views;
     drg::DevBuf<int32_t> blk_off, blk_graph;
-    int32_t blk_nitems = 0, blk_count = 0, blk_nodes = 0;
+    int32_t blk_ngroups = 0, blk_count = 0, blk_nodes = 0;
     drg::SweepForm form;                        // chosen sweep form
     std::vector<std::pair<drg::SweepForm, float>> tune;  // candidates and their times
     drg::DevBuf<int2> pro_ops;
@@ -640,6 +665,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         g.lv_off = (int32_t)lt.size();
         g.seed = p.seed;
         g.clip = p.clip;
+        g.noclip = attract_clip_free(p.b, p.clip) ? 1 : 0;
         const int64_t w = g.blk ? 0 : ((int64_t)n + WAVE / g.G - 1) / (WAVE / g.G);
         if ((int64_t)woff[c] + w >= ((int64_t)1 << 31))
             throw Error(DRG_E_INVALID, "batched layout: too many rows");
@@ -762,7 +788,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
     size_t blk_lds = 0;
     {
         std::vector<BBlkView> views(count);
-        std::vector<int4> bitems;
+        std::vector<int4> bitems, bgroups;
         std::vector<int32_t> boff(1, 0), bgraph;
         int bits = 0;
         for (int32_t c = 0; c < count; ++c) {
@@ -783,13 +809,22 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             v.eh2 = (float)(-p.b * s->e[2]);
             v.eh3 = (float)(-p.b * s->e[3]);
             v.clip = p.clip / (float)(2 * p.b);
-            v.noclip = blk_clip_free(p.b, v.clip) ? 1 : 0;
+            v.noclip = attract_clip_free(p.b, p.clip) ? 1 : 0;
             bits = L->bits;
             std::vector<int4> h(L->nitems);
             DRG_HIP(hipMemcpy(h.data(), L->items.get(), sizeof(int4) * L->nitems,
                               hipMemcpyDeviceToHost));
+            // a workgroup takes up to `per` consecutive items of one block
+            // (about 2^18 entries), staging the block's records once
+            const int32_t per = (int32_t)std::max<int64_t>(1, ((int64_t)1 << 18) / L->chunk);
             for (int4 it : h) {
                 it.w = c;
+                const int4 last = bgroups.empty() ? make_int4(0, 0, -1, 0) : bgroups.back();
+                const bool extend = last.z == c && last.y < per && bitems[last.x].x == it.x;
+                if (extend)
+                    bgroups.back().y += 1;
+                else
+                    bgroups.push_back(make_int4((int32_t)bitems.size(), 1, c, 0));
                 bitems.push_back(it);
             }
             bgraph.push_back(c);
@@ -797,11 +832,12 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             b->blk.push_back(std::move(L));
         }
         b->blk_count = (int32_t)bgraph.size();
-        b->blk_nitems = (int32_t)bitems.size();
+        b->blk_ngroups = (int32_t)bgroups.size();
         b->blk_nodes = boff.back();
         if (b->blk_count > 0) {
             upload(b->blk_views, views, st);
             upload(b->blk_items, bitems, st);
+            upload(b->blk_groups, bgroups, st);
             upload(b->blk_off, boff, st);
             upload(b->blk_graph, bgraph, st);
             blk_lds = blk_lds_bytes(bits);
@@ -819,12 +855,13 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         ba.flat = blk_cpl;
         ba.lanes = blk_ln;
         ba.items = b->blk_items.get();
+        ba.groups = b->blk_groups.get();
         ba.views = b->blk_views.get();
         ba.gt = b->gt.get();
         ba.sched = b->sched.get();
         ba.rec = s->rec.get();
         auto fn = b_blk_kernel(NH, blk_form(blk_cpl));
-        hipLaunchKernelGGL(fn, dim3(b->blk_nitems), dim3(STREAM_BLOCK), blk_lds, stream, ba);
+        hipLaunchKernelGGL(fn, dim3(b->blk_ngroups), dim3(STREAM_BLOCK), blk_lds, stream, ba);
         DRG_LAUNCH_CHECK();
         BFinArgs fa{};
         fa.nblk = b->blk_count;

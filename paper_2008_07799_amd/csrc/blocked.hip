@@ -136,7 +136,8 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_obj_blocked(BlockedArgs a) {
     WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
     const int4 it = a.items[blockIdx.x];
     const int32_t b = it.x, r0 = it.y, r1 = it.z;
-    blk_stage(a, s_rec, s_off, b, r0, r1);
+    blk_stage_rec(a, s_rec, b);
+    blk_stage_off(a, s_off, b, r0, r1);
     if constexpr (KIND == 0)
         blk_flat<4>(a, ObjValOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
     else
@@ -190,12 +191,14 @@ bool blocked_wanted_for(drg_ctx* ctx, int32_t n, int64_t nnz) {
     const int force = env_int("DRG_SWEEP_BLOCKED", -1);  // 1 force on, 0 force off
     if (force == 0) return false;
     const int bits = block_bits();
-    if ((int64_t)(16u << bits) + 4 * (ROWCAP + 1) + 1024 > (int64_t)ctx->max_lds) return false;
+    if (blk_lds_bytes(bits) > (size_t)ctx->max_lds) return false;
     if (force == 1) return nnz > 0;
     const int64_t nb = ((int64_t)n + (1 << bits) - 1) >> bits;
-    // records of at least half an L2 slice or a large pattern, and rows long
-    // enough to amortise the per-block partials
-    const bool big = (int64_t)n * 16 >= ((int64_t)2 << 20) || nnz >= ((int64_t)1 << 25);
+    // records of at least half an L2 slice or a pattern of 2^22 entries
+    // (env DRG_BLK_MIN_BITS), and rows long enough to amortise the
+    // per-block partials
+    const int64_t min_nnz = (int64_t)1 << env_int("DRG_BLK_MIN_BITS", 22);
+    const bool big = (int64_t)n * 16 >= ((int64_t)2 << 20) || nnz >= min_nnz;
     return big && nnz > 32 * nb * (int64_t)n;
 }
 
@@ -241,10 +244,19 @@ void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp
                        L.ent.get());
     DRG_LAUNCH_CHECK();
     // work items: about `chunk` units of work each (entries + rc per row),
-    // at most ROWCAP rows each
+    // at most ROWCAP rows each; a small pattern gets about 256 items
+    // (env DRG_BLK_ITEMS) of 2^15 .. 2^18 entries, so that it still fills
+    // the device, a large one items of 1/16 of a CU's share
+    // (env DRG_BLK_CHUNK_BITS fixes the floor).  The rule depends only on
+    // the graph, so a graph gets the same items alone and in a batch.
+    const int cbits = env_int("DRG_BLK_CHUNK_BITS", 0);
+    const int64_t floor_chunk =
+        cbits > 0 ? (int64_t)1 << cbits
+                  : std::min<int64_t>((int64_t)1 << 18,
+                                      std::max<int64_t>((int64_t)1 << 15,
+                                                        nnz / std::max(1, env_int("DRG_BLK_ITEMS", 256))));
     const int64_t want_items = std::max<int64_t>((int64_t)ctx->num_cu * 16, nb);
-    const int64_t chunk = std::max<int64_t>((int64_t)1 << env_int("DRG_BLK_CHUNK_BITS", 18),
-                                            (nnz + 16 * (int64_t)n * nb) / want_items);
+    const int64_t chunk = std::max<int64_t>(floor_chunk, (nnz + 16 * (int64_t)n * nb) / want_items);
     const int64_t rc = std::max<int64_t>(16, (chunk + ROWCAP - 1) / ROWCAP);
     std::vector<int32_t> first(nb + 1);
     first[0] = 0;
@@ -276,6 +288,7 @@ void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp
     L.nb = nb;
     L.bits = bits;
     L.nitems = first[nb];
+    L.chunk = chunk;
     DRG_HIP(hipStreamSynchronize(st));
 }
 
@@ -302,19 +315,19 @@ int blk_flat_cpl() {
     return (f == 1 || f == 2 || f == 4 || f == 8) ? f : 0;
 }
 
-// True when clip(p dx, c) with c = clip / (2b) can never bind: for an
-// offset of length d, |p dx| <= d^{2b-1} / (1 + d^{2b}), whose maximum over d
-// (at d^{2b} = 2b - 1) is (2b-1)^{(2b-1)/(2b)} / (2b).  A 1% margin covers
-// the FP32 rounding of p and d^2.
-bool blk_clip_free(int b, float clip_over_2b) {
-    const double m = std::pow(2.0 * b - 1.0, (2.0 * b - 1.0) / (2.0 * b)) / (2.0 * b);
-    return (double)clip_over_2b >= 1.01 * m;
+// True when the per-pair clip of the attraction can never bind: for an
+// offset of length d the clipped quantity is at most
+// 2b d^{2b-1} / (1 + d^{2b}) in magnitude, whose maximum over d (at
+// d^{2b} = 2b - 1) is (2b-1)^{(2b-1)/(2b)}.  A 1% margin covers the
+// rounding of the coefficient and of d^2.
+bool attract_clip_free(int b, double clip) {
+    const double m = std::pow(2.0 * b - 1.0, (2.0 * b - 1.0) / (2.0 * b));
+    return clip >= 1.01 * m;
 }
 
 template <int B, int NH>
 static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
-    const size_t lds = ((size_t)16 << a.bits) + 16 * ((ROWCAP + 4) / 4) +
-                       sizeof(WaveFrag) * STREAM_WAVES;
+    const size_t lds = blk_lds_bytes(a.bits);
     const int form = blk_form(a.flat);
     auto fn = form == 4   ? k_sweep_blocked<B, NH, 4>
               : form == 8 ? k_sweep_blocked<B, NH, 8>
@@ -329,8 +342,7 @@ static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
 
 template <int B, int NH, int KIND>
 static void launch_obj_blocked(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
-    const size_t lds = ((size_t)16 << a.bits) + 16 * ((ROWCAP + 4) / 4) +
-                       sizeof(WaveFrag) * STREAM_WAVES;
+    const size_t lds = blk_lds_bytes(a.bits);
     auto fn = k_obj_blocked<B, NH, KIND>;
     DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
@@ -387,7 +399,7 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
     a.eh2 = (float)(-b * s->e[2]);
     a.eh3 = (float)(-b * s->e[3]);
     a.clip = clip / (float)(2 * b);
-    a.noclip = blk_clip_free(b, a.clip) ? 1 : 0;
+    a.noclip = attract_clip_free(b, clip) ? 1 : 0;
     a.lanes = blk_lanes();
     a.flat = blk_flat_cpl();
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));

@@ -25,7 +25,7 @@ struct BlockedArgs {
     float clip;                 // clip / (2b)
     int32_t lanes;              // lanes per row segment (16, 32, 64; 0: per item)
     int32_t flat;               // chunks per lane of the flat (merge-path) form; 0: row form
-    int32_t noclip;             // 1: the clip cannot bind (blk_clip_free), flat form skips it
+    int32_t noclip;             // 1: the clip cannot bind (attract_clip_free), flat form skips it
 };
 
 template <int B>
@@ -99,7 +99,7 @@ __device__ __forceinline__ void blk_pair(const BlockedArgs& a, const HopW& hw, c
 //
 // The layout step: clipped attraction (weights carry -2b).  CLIP = false
 // when the clip cannot bind (|p dx| stays below it for every d, see
-// blk_clip_free): the clamp would return its argument, so it is left out and
+// attract_clip_free): the clamp would return its argument, so it is left out and
 // the weight is folded into p first (one rounding moved, two clamps and a
 // multiply fewer per pair).
 template <int B, int NH, bool CLIP>
@@ -155,6 +155,7 @@ struct ObjGradOp {
 // Workgroups of 1024 threads; an entry chunk is 16 bytes (eight 16-bit words).
 constexpr int STREAM_BLOCK = 1024;
 constexpr int STREAM_WAVES = STREAM_BLOCK / WAVE;
+constexpr int ROW_CACHE = WAVE;  // row records per wave cached by the flat form
 
 __device__ __forceinline__ uint32_t half16(const uint4& v, int q) {
     const uint32_t w = q < 2 ? v.x : (q < 4 ? v.y : (q < 6 ? v.z : v.w));
@@ -311,7 +312,34 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
     };
     int32_t c_row = -1;  // row carried from the previous window (wave-uniform)
     float c_x = 0.0f, c_y = 0.0f;
-    int32_t ilo = max(w_first, 0);
+    // rows [i0, i1] spanned by the window starting at chunk w (wave-uniform),
+    // searched from row lo
+    auto win_rows = [&](int64_t w, int32_t lo, int32_t& i0, int32_t& i1) {
+        const int32_t wp0 = max((int32_t)(8 * w - bbase), e0);
+        const int32_t wp1 = min((int32_t)(8 * min(w + WCH, wc1) - bbase), e1) - 1;
+        i0 = row_from(s_off, lo, nr - 1, wp0);
+        i1 = row_from(s_off, i0, nr - 1, wp1);
+    };
+    // The records of the first ROW_CACHE rows of a window sit in the wave's
+    // LDS cache (x, y, z arrays), so a lane that moves on to the next row
+    // reads its record there instead of waiting on a global load.  Each
+    // window's records are requested one window ahead.
+    float* cx = reinterpret_cast<float*>(s_frag + STREAM_WAVES) + wid * (3 * ROW_CACHE);
+    float* cy = cx + ROW_CACHE;
+    float* cz = cy + ROW_CACHE;
+    auto row_rec = [&](int32_t i0, int32_t i1, float& x, float& y, float& z) {
+        const int32_t r = i0 + lane;
+        const float4 t = r <= i1 ? R[r] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        x = t.x;
+        y = t.y;
+        z = t.z;
+    };
+    int32_t ni0 = 0, ni1 = -1;  // rows of the next window
+    float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+    if (wc0 < wc1) {
+        win_rows(wc0, max(w_first, 0), ni0, ni1);
+        row_rec(ni0, ni1, nx, ny, nz);
+    }
     // chunk loads are unconditional, clamped to the wave's last chunk (slots
     // past the range are masked), so the counters of outstanding loads stay
     // exact and a wait for one load does not drain the prefetches
@@ -320,6 +348,29 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
 #pragma unroll
     for (int k = 0; k < CPL; ++k) vn[k] = E4[min(wc0 + (int64_t)lane * CPL + k, clast)];
     for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
+        // this window's rows and their cached records
+        const int32_t i0 = ni0, i1 = ni1;
+        cx[lane] = nx;
+        cy[lane] = ny;
+        cz[lane] = nz;
+        if (w0 + WCH < wc1) {
+            win_rows(w0 + WCH, i1, ni0, ni1);
+            row_rec(ni0, ni1, nx, ny, nz);
+        }
+        // record of row i of this window: cached, or from global memory
+        auto load_row = [&](int32_t i) {
+            const int32_t k = i - i0;
+            float4 t;
+            if (k < ROW_CACHE) {
+                t = make_float4(cx[k], cy[k], cz[k], 0.0f);
+            } else {
+                t = R[i];
+                // keeps the load on this (rare) path: otherwise it is moved
+                // past the branch and every entry waits for it
+                asm volatile("" : "+v"(t.x), "+v"(t.y), "+v"(t.z));
+            }
+            return t;
+        };
         const int64_t c = w0 + (int64_t)lane * CPL;  // the lane's first chunk
         const int32_t nl = (int32_t)min((int64_t)WAVE, (wc1 - w0 + CPL - 1) / CPL);
         const bool has = lane < nl;
@@ -328,16 +379,10 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         const int32_t pl = min(min(pbase + EPL, (int32_t)(8 * wc1 - bbase)), e1);  // end of valid slots
         // the same bounds relative to the lane's first slot (none valid without a chunk)
         const int32_t qlo = pf - pbase, qhi = has ? pl - pbase : 0;
-        // rows spanned by the window, then the lane's first row
-        const int32_t wp0 = max((int32_t)(8 * w0 - bbase), e0);
-        const int32_t wp1 = min((int32_t)(8 * min(w0 + WCH, wc1) - bbase), e1) - 1;
-        const int32_t i0 = row_from(s_off, ilo, nr - 1, wp0);
-        const int32_t i1 = row_from(s_off, i0, nr - 1, wp1);
+        // the lane's first row
         int32_t i = has ? row_of(s_off, i0, i1, pf) : i1;
         int32_t nxt = s_off[i + 1];
-        // the row record is requested before the next window's chunks, so
-        // waiting for it does not wait for them
-        float4 ri = R[i];
+        float4 ri = load_row(i);
         uint4 v[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
@@ -378,11 +423,7 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                                 nxt = s_off[i + 1];
                             } while (p >= nxt);
                             qn = nxt - pbase;
-                            float4 rt = R[i];
-                            // keeps the reload on this (rare) path: otherwise the load is
-                            // moved past the branch and every entry waits for it
-                            asm volatile("" : "+v"(rt.x), "+v"(rt.y), "+v"(rt.z));
-                            ri = rt;
+                            ri = load_row(i);
                             ax = 0.0f;
                             ay = 0.0f;
                         }
@@ -436,7 +477,6 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         c_row = lcont ? lrow : -1;
         c_x = lcont ? lx : 0.0f;
         c_y = lcont ? ly : 0.0f;
-        ilo = i1;
     }
     // the wave's open tail (its last row goes on into the next wave)
     if (c_row >= 0 && lane == 0) {
@@ -465,36 +505,65 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
 }
 
 // One workgroup per item (block b, rows r0..r1): the block's records and the
-// item's row offsets go to LDS, then the rows are swept with the lanes per
-// segment that suit the item's mean segment length.  Lane sums run in a
+// item's row offsets go to LDS, then the rows are swept.  Lane sums run in a
 // fixed order and the group reductions are fixed, so the result is
 // repeatable.
-// Stages block b's records and the item's row offsets into LDS.
-__device__ __forceinline__ void blk_stage(const BlockedArgs& a, float4* s_rec, int32_t* s_off,
-                                          int32_t b, int32_t r0, int32_t r1) {
+// Stages block b's records into LDS (callers synchronise before use).
+// Each thread requests all its records before writing any, so the staging
+// costs one memory round trip instead of one per record.
+__device__ __forceinline__ void blk_stage_rec(const BlockedArgs& a, float4* s_rec, int32_t b) {
+    constexpr int RU = 8;  // records per thread per pass (8192-record blocks: one pass)
     const int32_t bw = 1 << a.bits;
     const int32_t j0 = b * bw;
     const int32_t cnt = min(bw, a.n0 - j0);
-    const int32_t* O = a.off + (int64_t)b * (a.n0 + 1);
-    for (int32_t t = threadIdx.x; t < bw; t += STREAM_BLOCK)
-        s_rec[t] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int32_t t = threadIdx.x; t <= r1 - r0; t += STREAM_BLOCK) s_off[t] = O[r0 + t];
+    for (int32_t t0 = 0; t0 < bw; t0 += STREAM_BLOCK * RU) {
+        float4 v[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int32_t t = t0 + u * STREAM_BLOCK + (int32_t)threadIdx.x;
+            v[u] = t < cnt ? a.rec[j0 + t] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int32_t t = t0 + u * STREAM_BLOCK + (int32_t)threadIdx.x;
+            if (t < bw) s_rec[t] = v[u];
+        }
+    }
+}
+
+// Stages the row offsets of rows r0..r1 in block b (all requests first),
+// then synchronises.
+__device__ __forceinline__ void blk_stage_off(const BlockedArgs& a, int32_t* s_off, int32_t b,
+                                              int32_t r0, int32_t r1) {
+    constexpr int OU = (ROWCAP + STREAM_BLOCK) / STREAM_BLOCK;  // covers ROWCAP + 1 offsets
+    const int32_t* O = a.off + (int64_t)b * (a.n0 + 1) + r0;
+    const int32_t nr = r1 - r0;
+    int32_t v[OU];
+#pragma unroll
+    for (int u = 0; u < OU; ++u) {
+        const int32_t t = u * STREAM_BLOCK + (int32_t)threadIdx.x;
+        v[u] = t <= nr ? O[t] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < OU; ++u) {
+        const int32_t t = u * STREAM_BLOCK + (int32_t)threadIdx.x;
+        if (t <= nr) s_off[t] = v[u];
+    }
     __syncthreads();
 }
 
-// One work item of the layout sweep (block b, rows r0..r1): staging, then
-// the flat form with F chunks per lane (F = 1, 2, 4, 8), or for F = 0 the row
-// form (a.lanes lanes per segment, 0: chosen from the item's mean segment
-// length).  s_dyn is the workgroup's dynamic LDS (records, row offsets, wave
-// fragments).
+// The sweep of one work item (block b, rows r0..r1) once the block's records
+// and the item's row offsets are in LDS: the flat form with F chunks per
+// lane (F = 1, 2, 4, 8), or for F = 0 the row form (a.lanes lanes per
+// segment, 0: chosen from the item's mean segment length).  s_dyn is the
+// workgroup's dynamic LDS (records, row offsets, wave fragments).
 template <int B, int NH, int F>
-__device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_dyn, int32_t b,
-                                                int32_t r0, int32_t r1) {
+__device__ __forceinline__ void blk_sweep_staged(const BlockedArgs& a, float4* s_dyn, int32_t b,
+                                                 int32_t r0, int32_t r1) {
     const int32_t bw = 1 << a.bits;
     float4* s_rec = s_dyn;
     int32_t* s_off = reinterpret_cast<int32_t*>(s_dyn + bw);
     WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
-    blk_stage(a, s_rec, s_off, b, r0, r1);
     if constexpr (F > 0) {
         if (a.noclip)
             blk_flat<F>(a, LayoutOp<B, NH, false>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b,
@@ -518,13 +587,42 @@ __device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_
     }
 }
 
+// One work item of the layout sweep: staging, then the sweep.
+template <int B, int NH, int F>
+__device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_dyn, int32_t b,
+                                                int32_t r0, int32_t r1) {
+    const int32_t bw = 1 << a.bits;
+    blk_stage_rec(a, s_dyn, b);
+    blk_stage_off(a, reinterpret_cast<int32_t*>(s_dyn + bw), b, r0, r1);
+    blk_sweep_staged<B, NH, F>(a, s_dyn, b, r0, r1);
+}
+
+// Consecutive work items items[0..cnt) of one block b: the records are
+// staged once, then every item is swept exactly as alone (its own row
+// offsets, wave ranges and lane order), so the result is the same bit for
+// bit as one workgroup per item.
+template <int B, int NH, int F>
+__device__ __forceinline__ void blk_layout_items(const BlockedArgs& a, float4* s_dyn, int32_t b,
+                                                 const int4* __restrict__ items, int32_t cnt) {
+    const int32_t bw = 1 << a.bits;
+    blk_stage_rec(a, s_dyn, b);
+    for (int32_t k = 0; k < cnt; ++k) {
+        const int4 it = items[k];
+        __syncthreads();  // the previous item is done with the offsets and fragments
+        blk_stage_off(a, reinterpret_cast<int32_t*>(s_dyn + bw), b, it.y, it.z);
+        blk_sweep_staged<B, NH, F>(a, s_dyn, b, it.y, it.z);
+    }
+}
+
 // sweep form as a template argument: the flat form's chunks per lane, 0 for
 // the row form
 inline int blk_form(int flat) { return (flat == 1 || flat == 2 || flat == 4 || flat == 8) ? flat : 0; }
 
-// dynamic LDS of a blocked-sweep workgroup
+// dynamic LDS of a blocked-sweep workgroup: column records, row offsets,
+// wave fragments, the flat form's row-record caches
 inline size_t blk_lds_bytes(int bits) {
-    return ((size_t)16 << bits) + 16 * ((ROWCAP + 4) / 4) + sizeof(WaveFrag) * STREAM_WAVES;
+    return ((size_t)16 << bits) + 16 * ((ROWCAP + 4) / 4) + sizeof(WaveFrag) * STREAM_WAVES +
+           sizeof(float) * 3 * ROW_CACHE * STREAM_WAVES;
 }
 
 // g_i of one finest node on the blocked layout: its block partials added in

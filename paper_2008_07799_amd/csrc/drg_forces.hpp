@@ -125,8 +125,10 @@ struct HalfE {
 // added to the lane's partial (ax, ay).  Coincident nodes contribute nothing;
 // no test is needed for that: at d2 = 0 the coefficient is finite (-2b for
 // b = 1, -0 otherwise) and dx = dy = +0, so both terms are zeros, which leave
-// the partial's value unchanged.
-template <typename T, int B>
+// the partial's value unchanged.  CLIP = false when the clip cannot bind
+// (|k dx| stays below it for every offset): the clamp would return its
+// argument, so it is left out and the weight is folded into k first.
+template <typename T, int B, bool CLIP = true>
 __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
                                              const typename VT<T>::v4& rj, const HalfE<T>& eh,
                                              T clip, T& ax, T& ay) {
@@ -134,8 +136,14 @@ __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint3
     const T d2 = dx * dx + dy * dy;
     const T k = attract_coef<B>(d2);
     const T w = eh(e >> 30) * (ri.z + rj.z);
-    ax += w * clampT2(k * dx, clip);
-    ay += w * clampT2(k * dy, clip);
+    if constexpr (CLIP) {
+        ax += w * clampT2(k * dx, clip);
+        ay += w * clampT2(k * dy, clip);
+    } else {
+        const T wk = w * k;
+        ax += wk * dx;
+        ay += wk * dy;
+    }
 }
 
 // Repulsion partial of lane `lane` of G: negative slots lane, lane+G, ...
@@ -175,7 +183,7 @@ __device__ __forceinline__ typename VT<T>::v2 row_total(T ax, T ay, T rx, T ry, 
 // the group.  Returns g_i (valid in every lane) = attraction + gq *
 // repulsion, where `key` is the node's own id for the negative words and
 // draw(w) turns a word into the record index of the drawn node.
-template <typename T, int B, typename Draw>
+template <typename T, int B, bool CLIP, typename Draw>
 __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
     const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
@@ -206,7 +214,7 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
 #pragma unroll
         for (int q = 0; q < U; ++q) en[q] = colhop[max(xl + (int64_t)q * G, x)];
 #pragma unroll
-        for (int q = 0; q < U; ++q) attract_pair<T, B>(ri, e[q], rj[q], eh, clip, ax, ay);
+        for (int q = 0; q < U; ++q) attract_pair<T, B, CLIP>(ri, e[q], rj[q], eh, clip, ax, ay);
 #pragma unroll
         for (int q = 0; q < U; ++q) e[q] = en[q];
         x = xn;
@@ -214,7 +222,7 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     }
     for (; x < re; x += G) {
         const uint32_t e = colhop[x];
-        attract_pair<T, B>(ri, e, rec[e & COL_MASK], eh, clip, ax, ay);
+        attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, ax, ay);
     }
     T rx, ry;
     repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, rx, ry);
@@ -237,7 +245,7 @@ struct WinItem {
     int32_t pad[3];
 };
 
-template <int B, int RPL, int BLOCK, typename Draw, typename Key>
+template <int B, bool CLIP, int RPL, int BLOCK, typename Draw, typename Key>
 __device__ __forceinline__ void window_item(
     const WinItem& it, int G, float4* __restrict__ lds, int CH,
     const int64_t* __restrict__ prp, const uint32_t* __restrict__ colhop,
@@ -287,7 +295,7 @@ __device__ __forceinline__ void window_item(
                 for (; q < U; ++q) {
                     const int32_t c = (int32_t)(e[q] & COL_MASK);
                     if (c >= b1) break;
-                    attract_pair<float, B>(ri[k], e[q], lds[c - b0], eh, clip, sx, sy);
+                    attract_pair<float, B, CLIP>(ri[k], e[q], lds[c - b0], eh, clip, sx, sy);
                 }
                 x += (int64_t)q * G;
                 if (q < U) break;

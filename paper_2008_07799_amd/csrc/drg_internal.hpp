@@ -105,6 +105,7 @@ void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, 
 // Column-blocked copy of a pattern (see blocked.hip).
 struct BlkLayout {
     int32_t nb = 0, bits = 0, nitems = 0;
+    int64_t chunk = 0;        // work per item the items were cut for
     DevBuf<int64_t> base;     // [nb+1] first entry of each block
     DevBuf<int32_t> off;      // [nb][n+1] row offsets inside a block
     DevBuf<uint16_t> ent;     // [nnz+8] block-local col | (hop-1) << 13
@@ -119,7 +120,7 @@ void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp
                         const uint32_t* colhop, int32_t col_base, BlkLayout& L);
 int blk_flat_cpl();  // chunks per lane of the flat form (env DRG_BLK_FLAT; 0: row form)
 int blk_lanes();
-bool blk_clip_free(int b, float clip_over_2b);  // the attraction clip cannot bind     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
+bool attract_clip_free(int b, double clip);  // the attraction clip cannot bind     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
 // One FP32 sync sweep on the blocked layout: the one-sided steps into g.
 void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
                    uint64_t seed, uint64_t iter, float2* g, hipEvent_t e0, hipEvent_t e1);

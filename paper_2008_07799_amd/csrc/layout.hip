@@ -19,6 +19,8 @@
 //
 // Every kernel is templated on the coordinate type: float is the product
 // path; the double instance runs the same arithmetic for trajectory checks.
+#include <type_traits>
+
 #include "drg_forces.hpp"
 #include "drg_internal.hpp"
 
@@ -65,6 +67,7 @@ struct SweepArgs {
     uint64_t S;
     T eh0, eh1, eh2, eh3;  // e_d / 2
     T gamma, clip;
+    int32_t noclip;        // the attraction clip cannot bind (attract_clip_free)
     uint64_t seed, iter;
     // async only
     v2* y;
@@ -85,18 +88,25 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
     const HalfE<T> eh{a.eh0, a.eh1, a.eh2, a.eh3};
-    for (int64_t i = grp; i < a.n0; i += ngrp) {
-        const int64_t rs = a.prp[i], re = a.prp[i + 1];
-        typename VT<T>::v2 gi = mk2<T>(T(0), T(0));
-        if (rs < re)
-            gi = sweep_row<T, B>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh, a.clip, a.M,
-                                 a.seed, a.iter, (int32_t)i,
-                                 [&](uint64_t w) {
-                                     return draw_node(w, a.C, a.guide, a.gbits, a.S);
-                                 },
-                                 a.gamma * a.qt[i]);
-        if (lane == 0) a.g[i] = gi;
-    }
+    auto rows = [&](auto clip_c) {
+        constexpr bool CLIP = decltype(clip_c)::value;
+        for (int64_t i = grp; i < a.n0; i += ngrp) {
+            const int64_t rs = a.prp[i], re = a.prp[i + 1];
+            typename VT<T>::v2 gi = mk2<T>(T(0), T(0));
+            if (rs < re)
+                gi = sweep_row<T, B, CLIP>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh, a.clip,
+                                           a.M, a.seed, a.iter, (int32_t)i,
+                                           [&](uint64_t w) {
+                                               return draw_node(w, a.C, a.guide, a.gbits, a.S);
+                                           },
+                                           a.gamma * a.qt[i]);
+            if (lane == 0) a.g[i] = gi;
+        }
+    };
+    if (a.noclip)
+        rows(std::false_type{});
+    else
+        rows(std::true_type{});
 }
 
 // Windowed form of k_sweep (same result bit for bit): one workgroup per item.
@@ -106,10 +116,16 @@ __global__ __launch_bounds__(WIN_BLOCK) void k_sweep_win(const WinItem* __restri
     extern __shared__ float4 s_rec[];
     const HalfE<float> eh{a.eh0, a.eh1, a.eh2, a.eh3};
     const WinItem it = items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
-    window_item<B, RPL, WIN_BLOCK>(
-        it, G, s_rec, CH, a.prp, a.colhop, a.rec, a.qt, eh, a.clip, a.M, a.seed, a.iter, a.gamma,
-        [&](uint64_t w) { return draw_node(w, a.C, a.guide, a.gbits, a.S); },
-        [&](int64_t i) { return (int32_t)i; }, a.g);
+    auto draw = [&](uint64_t w) { return draw_node(w, a.C, a.guide, a.gbits, a.S); };
+    auto key = [&](int64_t i) { return (int32_t)i; };
+    if (a.noclip)
+        window_item<B, false, RPL, WIN_BLOCK>(it, G, s_rec, CH, a.prp, a.colhop, a.rec, a.qt, eh,
+                                              a.clip, a.M, a.seed, a.iter, a.gamma, draw, key,
+                                              a.g);
+    else
+        window_item<B, true, RPL, WIN_BLOCK>(it, G, s_rec, CH, a.prp, a.colhop, a.rec, a.qt, eh,
+                                             a.clip, a.M, a.seed, a.iter, a.gamma, draw, key,
+                                             a.g);
 }
 
 template <int B, int RPL>
@@ -341,6 +357,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.eh3 = (T)(0.5 * s->e[3]);
     a.gamma = (T)p->gamma;
     a.clip = (T)p->clip;
+    a.noclip = attract_clip_free(p->b, p->clip) ? 1 : 0;
     a.seed = p->seed;
     a.iter = p->iter;
     a.y = reinterpret_cast<v2*>(y);
