@@ -450,25 +450,29 @@ __global__ void k_b_finish(BFinArgs a) {
     a.g[i] = gi;
 }
 
-// One thread per node of each graph's current level (off: this phase's prefix).
+// One lane per node of each graph's current level (off: this phase's
+// prefix); coarse-level nodes with many members are summed by the whole wave,
+// as in the single-graph kernel.
 __global__ void k_b_apply(int32_t total, int32_t count, int32_t t, const int32_t* __restrict__ off,
                           const BGraph* __restrict__ gt, const BLevel* __restrict__ lt,
                           const BSched* __restrict__ sched, const float2* __restrict__ g,
                           const float* __restrict__ qt, float2* __restrict__ y) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= total) return;
+    const int64_t x0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (__ballot(x0 < total) == 0) return;  // the whole wave leaves
+    const bool in = x0 < total;
+    const int64_t x = in ? x0 : total - 1;
     const int32_t c = find_owner(off, count, x);
     const BSched sc = sched[(int64_t)t * count + c];
     const BGraph gg = gt[c];
     const BLevel d = lt[gg.lv_off + sc.level];
     const int32_t v = (int32_t)(x - off[c]);
-    if (sc.level == 0) {
+    if (sc.level == 0 && in) {
         const int64_t i = (int64_t)gg.base + v;
         apply_node<float>(g[i], qt[i], y + d.yoff + v, sc.eta);
-    } else {
-        apply_group<float>(d.seg[v], d.seg[v + 1], d.perm, d.pbase, g, qt, y + d.yoff + v,
-                           sc.eta);
     }
+    const bool coarse = in && sc.level > 0;
+    apply_level_wave<float>(coarse, coarse ? d.seg[v] : 0, coarse ? d.seg[v + 1] : 0, d.perm,
+                            d.pbase, g, qt, y + d.yoff + v, sc.eta);
 }
 
 // y_{l-1}[u] = y_l[map_l[u]] for the graphs of one prolongation round.

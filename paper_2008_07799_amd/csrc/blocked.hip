@@ -244,17 +244,13 @@ void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp
                        L.ent.get());
     DRG_LAUNCH_CHECK();
     // work items: about `chunk` units of work each (entries + rc per row),
-    // at most ROWCAP rows each; a small pattern gets about 256 items
-    // (env DRG_BLK_ITEMS) of 2^15 .. 2^18 entries, so that it still fills
-    // the device, a large one items of 1/16 of a CU's share
-    // (env DRG_BLK_CHUNK_BITS fixes the floor).  The rule depends only on
-    // the graph, so a graph gets the same items alone and in a batch.
-    const int cbits = env_int("DRG_BLK_CHUNK_BITS", 0);
-    const int64_t floor_chunk =
-        cbits > 0 ? (int64_t)1 << cbits
-                  : std::min<int64_t>((int64_t)1 << 18,
-                                      std::max<int64_t>((int64_t)1 << 15,
-                                                        nnz / std::max(1, env_int("DRG_BLK_ITEMS", 256))));
+    // at most ROWCAP rows each: at least 2^18 entries (env
+    // DRG_BLK_CHUNK_BITS), which keeps the per-item setup small against the
+    // sweep; a large pattern gets items of 1/16 of a CU's share.  The rule
+    // depends only on the graph, so a graph gets the same items alone and
+    // in a batch.  (Smaller items would let a small graph alone use more of
+    // the device, at the cost of batches of such graphs.)
+    const int64_t floor_chunk = (int64_t)1 << std::min(24, std::max(10, env_int("DRG_BLK_CHUNK_BITS", 18)));
     const int64_t want_items = std::max<int64_t>((int64_t)ctx->num_cu * 16, nb);
     const int64_t chunk = std::max<int64_t>(floor_chunk, (nnz + 16 * (int64_t)n * nb) / want_items);
     const int64_t rc = std::max<int64_t>(16, (chunk + ROWCAP - 1) / ROWCAP);

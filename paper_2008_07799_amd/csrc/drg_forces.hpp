@@ -354,4 +354,55 @@ __device__ __forceinline__ void apply_group(int32_t xb, int32_t xe, const int32_
     }
 }
 
+// Coarse-level steps of the level nodes held by the lanes of one wave (all
+// 64 lanes call it; valid = the lane holds a node).  A node with at most
+// APPLY_SEQ members is summed by its own lane (apply_group); a larger one by
+// the whole wave: lane l adds members l, l+64, ... in ascending order, then
+// a fixed butterfly, and the node's lane applies the step.  So a node with
+// many members (the centre of a large star) does not hold up its wave for
+// thousands of serial steps, and the order of the sums is fixed by the data.
+constexpr int APPLY_SEQ = 64;
+
+template <typename T>
+__device__ __forceinline__ void apply_level_wave(bool valid, int32_t xb, int32_t xe,
+                                                 const int32_t* perm, int64_t pbase,
+                                                 const typename VT<T>::v2* __restrict__ g,
+                                                 const T* __restrict__ qt,
+                                                 typename VT<T>::v2* yp, T eta) {
+    const bool big = valid && xe - xb > APPLY_SEQ;
+    if (valid && !big) apply_group<T>(xb, xe, perm, pbase, g, qt, yp, eta);
+    uint64_t m = __ballot(big);
+    const int lane = __lane_id();
+    while (m) {
+        const int src = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int32_t b0 = __builtin_amdgcn_readlane(xb, src);
+        const int32_t b1 = __builtin_amdgcn_readlane(xe, src);
+        const uint64_t pp = (uint64_t)(uintptr_t)perm;
+        const uint64_t pu = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)pp, src) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(pp >> 32), src) << 32);
+        const int32_t* P = reinterpret_cast<const int32_t*>((uintptr_t)pu);
+        const int64_t pb = (int64_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)pbase, src) |
+                                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                                          (int32_t)((uint64_t)pbase >> 32), src) << 32));
+        T sx = T(0), sy = T(0), sw = T(0);
+        for (int32_t x = b0 + lane; x < b1; x += WAVE) {
+            const int64_t i = pb + P[x];
+            const typename VT<T>::v2 v = g[i];
+            sx += v.x;
+            sy += v.y;
+            sw += qt[i];
+        }
+        sx = group_sum<WAVE>(sx);
+        sy = group_sum<WAVE>(sy);
+        sw = group_sum<WAVE>(sw);
+        if (lane == src && sw > T(0)) {
+            typename VT<T>::v2 p = *yp;
+            p.x += eta * (sx / sw);
+            p.y += eta * (sy / sw);
+            *yp = p;
+        }
+    }
+}
+
 }  // namespace drg

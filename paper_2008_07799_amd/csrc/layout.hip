@@ -157,8 +157,8 @@ __global__ void k_apply0(int32_t n, const typename VT<T>::v2* __restrict__ g,
     if (i < n) apply_node<T>(g[i], qt[i], y + i, eta);
 }
 
-// One thread per level node: the members' steps and anchor weights summed in
-// ascending member id.
+// One lane per level node: the members' steps and anchor weights summed in
+// ascending member id, by the whole wave for nodes with many members.
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply_level(int32_t nl, const int32_t* __restrict__ seg,
                                                      const int32_t* __restrict__ perm,
@@ -166,7 +166,11 @@ __global__ __launch_bounds__(256) void k_apply_level(int32_t nl, const int32_t* 
                                                      const T* __restrict__ qt,
                                                      typename VT<T>::v2* __restrict__ y, T eta) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < nl) apply_group<T>(seg[a], seg[a + 1], perm, 0, g, qt, y + a, eta);
+    const bool valid = a < nl;
+    const int64_t v = valid ? a : 0;
+    if (__ballot(valid) == 0) return;  // the whole wave leaves
+    apply_level_wave<T>(valid, valid ? seg[v] : 0, valid ? seg[v + 1] : 0, perm, 0, g, qt, y + v,
+                        eta);
 }
 
 template <typename T>

@@ -55,11 +55,14 @@ def _check_batch(graphs, params):
 @pytest.mark.parametrize("k,blocked", [(1, False), (2, False), (3, False), (2, True), (3, True)])
 def test_mixed_batch_equals_single_graph_layouts(monkeypatch, k, blocked):
     """blocked=True forces the column-blocked sweep (small blocks, so every
-    graph spans several) on every graph with edges, alone and in the batch."""
+    graph spans several, and small work items, so that the batch sweeps runs
+    of several items per workgroup) on every graph with edges, alone and in
+    the batch."""
     say("batch mixed k", k, "blocked" if blocked else "")
     if blocked:
         monkeypatch.setenv("DRG_SWEEP_BLOCKED", "1")
         monkeypatch.setenv("DRG_BLOCK_BITS", "8")
+        monkeypatch.setenv("DRG_BLK_CHUNK_BITS", "12")
     graphs = [
         gen.grid_deleted(700, 0.05, 0, sub=0),
         gen.ba(1500, 3, 0, sub=1),
