@@ -80,6 +80,26 @@ def _traffic(workload: str, kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def _copy_bandwidth(mib: int = 4096) -> float:
+    """Bandwidth of a plain device-to-device copy (bytes read + written per
+    second, GB/s), HIP events around 8 copies of a `mib` MiB buffer."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(8):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 8 * 2 * n * 4 / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(cfg: dict) -> dict:
     """The oracle (FP64, one thread) on a bounded sample: an R-MAT of the same
     generator at scale 14 (edge factor 16) with the workload's k, M and b;
@@ -381,18 +401,26 @@ def main():
                              seed=0, mode=mode)
     y = torch.zeros((g.n, 2), dtype=torch.float32, device="cuda")
 
+    phase_s = {"similarity": 0.0, "hierarchy": 0.0, "layout": 0.0}
+
     def step():
         t = time.perf_counter()
         sim = d.drg_build_similarity(ctx, rp, col, cfg["k"])
-        print(f"[bench]   similarity nnz={sim.nnz} ({time.perf_counter() - t:.2f} s)",
-              file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        print(f"[bench]   similarity nnz={sim.nnz} ({t1 - t:.2f} s)", file=sys.stderr, flush=True)
         hier = d.drg_coarsen(ctx, rp, col, seed=0, rho=0.8, min_nodes=cfg["min_nodes"],
                              max_levels=cfg["max_levels"])
-        print(f"[bench]   hierarchy {hier.sizes} ({time.perf_counter() - t:.2f} s)",
-              file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(f"[bench]   hierarchy {hier.sizes} ({t2 - t:.2f} s)", file=sys.stderr, flush=True)
         d.drg_layout_run(ctx, sim, hier, params, y)
-        print(f"[bench]   layout done ({time.perf_counter() - t:.2f} s)", file=sys.stderr,
-              flush=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        print(f"[bench]   layout done ({t3 - t:.2f} s)", file=sys.stderr, flush=True)
+        phase_s["similarity"] += t1 - t
+        phase_s["hierarchy"] += t2 - t1
+        phase_s["layout"] += t3 - t2
         info = (sim.nnz, sim.n_active, hier.sizes, sim.blocked)
         sim.close()
         hier.close()
@@ -401,6 +429,8 @@ def main():
     for w in range(args.warmup):
         print(f"[bench] warmup step {w}", file=sys.stderr, flush=True)
         step()
+    for key in phase_s:
+        phase_s[key] = 0.0
     torch.cuda.synchronize()
     ctx.set_profiling(True)
     t0 = time.perf_counter()
@@ -420,6 +450,7 @@ def main():
     alg_bytes = 16.0 * nnz + 16.0 * M * n_active + 28.0 * n
     kernel = "k_sweep_blocked" if blocked else "k_sweep"
     achieved = alg_bytes / (avg_ms / 1000.0) / 1e9
+    copy_gbs = _copy_bandwidth()
     rec = {
         "metric": "pair-updates/s + time-to-layout, 1M-node R-MAT; batched/autograd vs plain",
         "value": value,
@@ -437,12 +468,15 @@ def main():
                    "undirected_edges": g.nnz // 2, "k": cfg["k"], "M": M, "b": cfg["b"],
                    "T": T, "levels": sizes, "nnz_P": nnz, "n_active": n_active,
                    "mode": args.mode, "time_to_layout_s": ms_per_step / 1000.0,
+                   "layout_only_s": phase_s["layout"] / args.steps,
+                   "phases_s": {k: v / args.steps for k, v in phase_s.items()},
                    "iteration_sweep_pair_updates_per_s": pairs / (avg_ms / 1000.0)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _traffic(args.workload, kernel),
                      "kernel": kernel, "launches": launches, "avg_launch_ms": avg_ms,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

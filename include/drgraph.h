@@ -148,6 +148,17 @@ drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_a
  * W[n] (uint64 sampling weights), e[k] (FP64), invZ[n] (FP64). */
 drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop,
                           double* P, double* qt, uint64_t* W, double* e, double* invZ);
+/* Copies the rows rows[0..nrows) of the similarity to host arrays (each
+ * nullable; synchronises), for graphs whose whole pattern is too large to
+ * copy: row_len[nrows] entries per row; col, hop (1..k) and P (FP64 P~_ij)
+ * of the rows one after another in the order of `rows`, each row in
+ * ascending column order; qt[nrows], W[nrows], invZ[nrows] of the rows.
+ * cap = capacity of col/hop/P in entries.  DRG_E_INVALID when a row index is
+ * out of range or the rows hold more than cap entries (row_len is still
+ * written). */
+drg_status drg_sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows,
+                               int64_t cap, int64_t* row_len, int32_t* col, uint8_t* hop,
+                               double* P, double* qt, uint64_t* W, double* invZ);
 void drg_sim_destroy(drg_sim* s);
 
 /* Multilevel coarsening (Sec. 3.2.3, Fig. 3): repeatedly groups a randomly

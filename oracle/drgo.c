@@ -167,6 +167,84 @@ void drgo_similarity(int32_t n, int32_t k, double sigma, const int64_t* prp, con
 }
 
 /* ------------------------------------------------------------------------ */
+/* The same similarity for a list of rows only, for graphs too large to take */
+/* whole: row s is NNG(s, k) by the bounded BFS above, ascending; Z of every */
+/* node involved is its own hop histogram weighted by e (each node's BFS run */
+/* once); P~, qt and W of the listed rows follow the operations and order of */
+/* drgo_similarity.  out_rp[r] .. out_rp[r+1] are the entries of srcs[r].    */
+/* Returns the number of entries; with out_col == NULL only out_rp is set.   */
+/* ------------------------------------------------------------------------ */
+static double z_of(const int32_t* rp, const int32_t* col, int32_t k, const double* e, int32_t v,
+                   int32_t* dist, int32_t* q, int64_t* cnt) {
+    int32_t t = bfs_bounded(rp, col, k, v, dist, q);
+    for (int32_t d = 0; d < k; ++d) cnt[d] = 0;
+    for (int32_t x = 1; x < t; ++x) cnt[dist[q[x]] - 1] += 1;
+    for (int32_t x = 0; x < t; ++x) dist[q[x]] = -1;
+    double z = 0.0;
+    for (int32_t d = 0; d < k; ++d) {
+        double term = (double)cnt[d] * e[d];
+        z = z + term;
+    }
+    return z;
+}
+
+int64_t drgo_similarity_rows(int32_t n, const int32_t* rp, const int32_t* col, int32_t k,
+                             double sigma, int32_t nsrc, const int32_t* srcs, int64_t* out_rp,
+                             int32_t* out_col, uint8_t* out_hop, double* out_P, double* out_invZ,
+                             double* out_qt, uint64_t* out_W) {
+    double e[8];
+    if (k < 1 || k > 8) return -1;
+    for (int32_t d = 1; d <= k; ++d) e[d - 1] = exp(-(double)(d * d) / (2.0 * sigma * sigma));
+    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* cnt = (int64_t*)calloc((size_t)(k > 0 ? k : 1), sizeof(int64_t));
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    out_rp[0] = 0;
+    for (int32_t r = 0; r < nsrc; ++r) {
+        int32_t t = bfs_bounded(rp, col, k, srcs[r], dist, q);
+        out_rp[r + 1] = out_rp[r] + (t - 1);
+        for (int32_t x = 0; x < t; ++x) dist[q[x]] = -1;
+    }
+    if (out_col) {
+        double* Zc = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        for (int32_t v = 0; v < n; ++v) Zc[v] = -1.0;
+        for (int32_t r = 0; r < nsrc; ++r) {
+            int32_t s = srcs[r];
+            int32_t t = bfs_bounded(rp, col, k, s, dist, q);
+            int64_t o = out_rp[r];
+            qsort(q + 1, (size_t)(t - 1), sizeof(int32_t), cmp_i32);
+            for (int32_t x = 1; x < t; ++x) {
+                out_col[o + x - 1] = q[x];
+                out_hop[o + x - 1] = (uint8_t)dist[q[x]];
+            }
+            for (int32_t x = 0; x < t; ++x) dist[q[x]] = -1;
+            if (Zc[s] < 0.0) Zc[s] = z_of(rp, col, k, e, s, dist, q, cnt);
+            double izs = (out_rp[r + 1] > o) ? 1.0 / Zc[s] : 0.0;
+            out_invZ[r] = izs;
+            double qs = 0.0;
+            uint64_t w = 0;
+            for (int64_t x = o; x < out_rp[r + 1]; ++x) {
+                int32_t j = out_col[x];
+                if (Zc[j] < 0.0) Zc[j] = z_of(rp, col, k, e, j, dist, q, cnt);
+                double sm = izs + 1.0 / Zc[j];
+                double tt = e[out_hop[x] - 1] * sm;
+                double p = tt * 0.5;
+                out_P[x] = p;
+                qs = qs + p;
+                w += (uint64_t)(p * 4294967296.0);
+            }
+            out_qt[r] = qs;
+            out_W[r] = w;
+        }
+        free(Zc);
+    }
+    free(cnt);
+    free(dist);
+    free(q);
+    return out_rp[nsrc];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Negative sampling by node weight (Sec. 3.2.2): inverse of the integer   */
 /* cumulative weight table.                                                  */
 /* ------------------------------------------------------------------------ */

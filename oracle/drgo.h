@@ -52,6 +52,14 @@ void drgo_similarity(int32_t n, int32_t k, double sigma, const int64_t* prp, con
                      const uint8_t* phop, double* e, double* Z, double* invZ, double* P, double* qt,
                      uint64_t* W, uint64_t* C);
 
+/* The same similarity for the rows srcs[0..nsrc) only (k <= 8): out_rp[nsrc+1]
+ * row offsets; with out_col non-NULL also the rows' columns (ascending), hops,
+ * P~ values, and per row 1/Z, qt and W.  Returns the number of entries. */
+int64_t drgo_similarity_rows(int32_t n, const int32_t* rp, const int32_t* col, int32_t k,
+                             double sigma, int32_t nsrc, const int32_t* srcs, int64_t* out_rp,
+                             int32_t* out_col, uint8_t* out_hop, double* out_P, double* out_invZ,
+                             double* out_qt, uint64_t* out_W);
+
 /* Negative-sample draw from a 64-bit uniform word (node weight sampling). */
 int32_t drgo_draw(const uint64_t* C, int32_t n, uint64_t w);
 /* The word for slot m of node i at iteration it. */

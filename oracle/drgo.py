@@ -52,6 +52,10 @@ def lib():
     L.drgo_khop_fill.argtypes = [C.c_int32, _i32p, _i32p, C.c_int32, _i64p, _i32p, _u8p]
     L.drgo_similarity.argtypes = [C.c_int32, C.c_int32, C.c_double, _i64p, _i32p, _u8p,
                                   _f64p, _f64p, _f64p, _f64p, _f64p, _u64p, _u64p]
+    L.drgo_similarity_rows.argtypes = [C.c_int32, _i32p, _i32p, C.c_int32, C.c_double,
+                                       C.c_int32, _i32p, _i64p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.drgo_similarity_rows.restype = C.c_int64
     L.drgo_draw.argtypes = [_u64p, C.c_int32, C.c_uint64]
     L.drgo_draw.restype = C.c_int32
     L.drgo_neg_word.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_int32]
@@ -155,6 +159,33 @@ def similarity_from_pattern(n, k, sigma, rp, col, hop) -> Sim:
                           e, Z, invZ, P, qt, W, Cc)
     return Sim(n, k, float(sigma), _c(rp, np.int64), colc[:nnz], hopc[:nnz], e, Z, invZ,
                P[:nnz], qt, W, Cc)
+
+
+def similarity_rows(csr, k: int, sources, sigma: float = 1.0) -> dict:
+    """P~ restricted to the rows `sources` (Sec. 3.2.1, as `similarity`), for
+    graphs too large to take whole: per row its columns (ascending), hops,
+    values, and 1/Z, qt, W of the row."""
+    L = lib()
+    n = int(csr.n)
+    rp = _c(csr.row_ptr, np.int32)
+    col = _c(csr.col, np.int32)
+    src = _c(sources, np.int32)
+    out_rp = np.zeros(len(src) + 1, np.int64)
+    nnz = L.drgo_similarity_rows(n, rp, col, int(k), float(sigma), len(src), src, out_rp,
+                                 None, None, None, None, None, None)
+    if nnz < 0:
+        raise ValueError("k out of range")
+    out_col = np.zeros(max(nnz, 1), np.int32)
+    out_hop = np.zeros(max(nnz, 1), np.uint8)
+    out_P = np.zeros(max(nnz, 1), np.float64)
+    invZ = np.zeros(len(src), np.float64)
+    qt = np.zeros(len(src), np.float64)
+    W = np.zeros(len(src), np.uint64)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    L.drgo_similarity_rows(n, rp, col, int(k), float(sigma), len(src), src, out_rp, ptr(out_col),
+                           ptr(out_hop), ptr(out_P), ptr(invZ), ptr(qt), ptr(W))
+    return {"row_ptr": out_rp, "col": out_col[:nnz], "hop": out_hop[:nnz], "P": out_P[:nnz],
+            "invZ": invZ, "qt": qt, "W": W}
 
 
 def draw(sim: Sim, w: int) -> int:

@@ -174,6 +174,15 @@ drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint
     });
 }
 
+drg_status drg_sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows,
+                               int64_t cap, int64_t* row_len, int32_t* col, uint8_t* hop,
+                               double* P, double* qt, uint64_t* W, double* invZ) {
+    return guarded([&] {
+        need(s, "sim");
+        drg::sim_export_rows(s, nrows, rows, cap, row_len, col, hop, P, qt, W, invZ);
+    });
+}
+
 void drg_sim_destroy(drg_sim* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);

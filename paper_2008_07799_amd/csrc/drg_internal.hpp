@@ -99,6 +99,9 @@ inline int sweep_group(double mean_len) {
 drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
                           UnionInfo* u = nullptr);
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
+void sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows, int64_t cap,
+                     int64_t* row_len, int32_t* col, uint8_t* hop, double* P, double* qt,
+                     uint64_t* W, double* invZ);
 void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,
                 double* qt, uint64_t* W, double* e, double* invZ);
 // blocked.hip

@@ -12,6 +12,7 @@
 // Two passes: count (hop histogram per row) -> prefix sum -> fill.
 #include <cmath>
 #include <memory>
+#include <vector>
 
 #include "drg_bitmap.hpp"
 #include "drg_internal.hpp"
@@ -440,6 +441,19 @@ __global__ void k_materialise_P(int32_t n, const int64_t* __restrict__ prp,
     }
 }
 
+// P~ of the entries x0 .. x1-1 of row i (same operations as k_materialise_P)
+__global__ void k_materialise_row(int32_t i, int64_t x0, int64_t x1,
+                                  const uint32_t* __restrict__ ch, const double* __restrict__ invZ,
+                                  ECoef ec, double* __restrict__ P) {
+#pragma clang fp contract(off)
+    const int64_t x = x0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= x1) return;
+    const uint32_t e = ch[x];
+    const double s = invZ[i] + invZ[e & COL_MASK];
+    const double t = pick_e(ec.e, e >> 30) * s;
+    P[x - x0] = t * 0.5;
+}
+
 static int pick_group(double mean_len) {
     if (mean_len <= 4) return 4;
     if (mean_len <= 8) return 8;
@@ -648,6 +662,57 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     DRG_HIP(hipStreamSynchronize(st));
     if (blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
     return s.release();
+}
+
+void sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows, int64_t cap,
+                     int64_t* row_len, int32_t* col, uint8_t* hop, double* P, double* qt,
+                     uint64_t* W, double* invZ) {
+    if (nrows < 0 || (nrows > 0 && !rows)) throw Error(DRG_E_INVALID, "rows");
+    DRG_HIP(hipSetDevice(s->device));
+    DRG_HIP(hipDeviceSynchronize());
+    std::vector<int64_t> a(nrows), b(nrows);
+    int64_t total = 0;
+    for (int32_t r = 0; r < nrows; ++r) {
+        const int32_t i = rows[r];
+        if (i < 0 || i >= s->n) throw Error(DRG_E_INVALID, "row index out of range");
+        int64_t se[2];
+        DRG_HIP(hipMemcpy(se, s->row_ptr.get() + i, sizeof(se), hipMemcpyDeviceToHost));
+        a[r] = se[0];
+        b[r] = se[1];
+        total += se[1] - se[0];
+    }
+    if (row_len)
+        for (int32_t r = 0; r < nrows; ++r) row_len[r] = b[r] - a[r];
+    if ((col || hop || P) && total > cap)
+        throw Error(DRG_E_INVALID, "the rows hold more entries than cap");
+    ECoef ec{};
+    for (int d = 0; d < 4; ++d) ec.e[d] = s->e[d];
+    int64_t o = 0;
+    for (int32_t r = 0; r < nrows; ++r) {
+        const int32_t i = rows[r];
+        const int64_t len = b[r] - a[r];
+        if (len > 0 && (col || hop)) {
+            std::vector<uint32_t> ch(len);
+            DRG_HIP(hipMemcpy(ch.data(), s->colhop.get() + a[r], sizeof(uint32_t) * len,
+                              hipMemcpyDeviceToHost));
+            for (int64_t x = 0; x < len; ++x) {
+                if (col) col[o + x] = (int32_t)(ch[x] & COL_MASK);
+                if (hop) hop[o + x] = (uint8_t)((ch[x] >> 30) + 1);
+            }
+        }
+        if (len > 0 && P) {
+            DevBuf<double> dP(len);
+            hipLaunchKernelGGL(k_materialise_row, dim3(ceil_div(len, 256)), dim3(256), 0, nullptr,
+                               i, a[r], b[r], s->colhop.get(), s->invZ.get(), ec, dP.get());
+            DRG_LAUNCH_CHECK();
+            DRG_HIP(hipMemcpy(P + o, dP.get(), sizeof(double) * len, hipMemcpyDeviceToHost));
+        }
+        if (qt) DRG_HIP(hipMemcpy(qt + r, s->qt.get() + i, sizeof(double), hipMemcpyDeviceToHost));
+        if (W) DRG_HIP(hipMemcpy(W + r, s->W.get() + i, sizeof(uint64_t), hipMemcpyDeviceToHost));
+        if (invZ)
+            DRG_HIP(hipMemcpy(invZ + r, s->invZ.get() + i, sizeof(double), hipMemcpyDeviceToHost));
+        o += len;
+    }
 }
 
 void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, double* P,

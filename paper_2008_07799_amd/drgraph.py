@@ -89,6 +89,7 @@ def lib():
         "drg_sim_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                           C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
         "drg_sim_export": ([_P] + [_P] * 8, st),
+        "drg_sim_export_rows": ([_P, C.c_int32, _P, C.c_int64] + [_P] * 7, st),
         "drg_sim_destroy": ([_P], None),
         "drg_coarsen": ([_P, C.POINTER(Csr), C.c_uint64, C.c_double, C.c_int32, C.c_int32,
                          C.POINTER(_P)], st),
@@ -220,22 +221,55 @@ class Similarity:
 
     __del__ = close
 
-    def export(self, values: bool = True) -> dict:
+    def export(self, values: bool = True, pattern: bool = True) -> dict:
+        """The whole similarity as host numpy arrays; pattern=False leaves out
+        the per-entry arrays (columns, hops, values) and copies the per-node
+        ones only."""
         n, nnz, k = self.n, self.nnz, self.k
-        out = {"row_ptr": np.zeros(n + 1, np.int64), "col": np.zeros(max(nnz, 1), np.int32),
-               "hop": np.zeros(max(nnz, 1), np.uint8), "qt": np.zeros(n, np.float64),
+        m = max(nnz, 1) if pattern else 0
+        out = {"row_ptr": np.zeros(n + 1, np.int64),
+               "col": np.zeros(m, np.int32) if pattern else None,
+               "hop": np.zeros(m, np.uint8) if pattern else None, "qt": np.zeros(n, np.float64),
                "W": np.zeros(n, np.uint64), "e": np.zeros(max(k, 1), np.float64),
                "invZ": np.zeros(n, np.float64)}
-        out["P"] = np.zeros(max(nnz, 1), np.float64) if values else None
+        out["P"] = np.zeros(m, np.float64) if values and pattern else None
         _check(lib().drg_sim_export(self.h, _np_ptr(out["row_ptr"]), _np_ptr(out["col"]),
                                     _np_ptr(out["hop"]), _np_ptr(out["P"]), _np_ptr(out["qt"]),
                                     _np_ptr(out["W"]), _np_ptr(out["e"]),
                                     _np_ptr(out["invZ"])))
-        out["col"] = out["col"][:nnz]
-        out["hop"] = out["hop"][:nnz]
-        if values:
-            out["P"] = out["P"][:nnz]
+        if pattern:
+            out["col"] = out["col"][:nnz]
+            out["hop"] = out["hop"][:nnz]
+            if values:
+                out["P"] = out["P"][:nnz]
         out["e"] = out["e"][:k]
+        return out
+
+    def export_rows(self, rows, values: bool = True) -> dict:
+        """Rows `rows` only (host numpy): per-row lengths, then the rows'
+        columns, hops and (with values) FP64 P~ one after another; qt, W, invZ of
+        the rows."""
+        r = np.ascontiguousarray(rows, np.int32)
+        m = len(r)
+        lens = np.zeros(max(m, 1), np.int64)
+        _check(lib().drg_sim_export_rows(self.h, m, _np_ptr(r), 0, _np_ptr(lens), None, None,
+                                         None, None, None, None))
+        tot = int(lens[:m].sum())
+        out = {"row_len": lens[:m], "col": np.zeros(max(tot, 1), np.int32),
+               "hop": np.zeros(max(tot, 1), np.uint8),
+               "P": np.zeros(max(tot, 1), np.float64) if values else None,
+               "qt": np.zeros(max(m, 1), np.float64), "W": np.zeros(max(m, 1), np.uint64),
+               "invZ": np.zeros(max(m, 1), np.float64)}
+        _check(lib().drg_sim_export_rows(self.h, m, _np_ptr(r), tot, _np_ptr(lens),
+                                         _np_ptr(out["col"]), _np_ptr(out["hop"]), _np_ptr(out["P"]),
+                                         _np_ptr(out["qt"]), _np_ptr(out["W"]),
+                                         _np_ptr(out["invZ"])))
+        out["col"] = out["col"][:tot]
+        out["hop"] = out["hop"][:tot]
+        if values:
+            out["P"] = out["P"][:tot]
+        for key in ("qt", "W", "invZ"):
+            out[key] = out[key][:m]
         return out
 
 

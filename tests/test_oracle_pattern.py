@@ -116,3 +116,31 @@ def test_isolated_nodes_have_empty_rows(oracle_lib):
     sim = oracle_lib.similarity(g, 2)
     assert [int(x) for x in np.diff(sim.row_ptr)] == [2, 3, 3, 2, 0, 0, 0, 0]
     assert np.all(sim.qt[4:] == 0) and np.all(sim.W[4:] == 0) and np.all(sim.invZ[4:] == 0)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_similarity_rows_pinned(oracle_lib, k):
+    """The rows-only similarity (for graphs too large to take whole): its rows
+    are NNG(v, k) with hop = SPD (all-pairs BFS), and its values, 1/Z, qt and
+    W equal the whole-graph similarity's rows bit for bit, for a subset of
+    sources in any order (isolated nodes included)."""
+    g = gen.random_graph(150, 0.02, seed=13, sub=k)
+    D = _spd(g)
+    full = oracle_lib.similarity(g, k)
+    rng = np.random.default_rng(k)
+    src = rng.choice(g.n, size=40, replace=False)
+    iso = np.nonzero(np.diff(g.row_ptr) == 0)[0]
+    if len(iso):
+        src = np.concatenate([src, iso[:2]])
+    rows = oracle_lib.similarity_rows(g, k, src)
+    rp = rows["row_ptr"]
+    for r, v in enumerate(src):
+        want = np.nonzero((D[v] >= 1) & (D[v] <= k))[0]
+        a, b = rp[r], rp[r + 1]
+        assert np.array_equal(rows["col"][a:b], want)
+        assert np.array_equal(rows["hop"][a:b], D[v, want].astype(np.uint8))
+        fa, fb = full.row_ptr[v], full.row_ptr[v + 1]
+        assert np.array_equal(rows["P"][a:b], full.P[fa:fb])
+        assert rows["invZ"][r] == full.invZ[v]
+        assert rows["qt"][r] == full.qt[v]
+        assert rows["W"][r] == full.W[v]
