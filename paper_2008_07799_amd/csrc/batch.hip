@@ -393,9 +393,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
 template <int NH>
 static auto b_blk_kernel_nh(int form) {
     return form == 4   ? k_b_sweep_blocked<NH, 4>
-           : form == 8 ? k_b_sweep_blocked<NH, 8>
            : form == 2 ? k_b_sweep_blocked<NH, 2>
-           : form == 1 ? k_b_sweep_blocked<NH, 1>
                        : k_b_sweep_blocked<NH, 0>;
 }
 

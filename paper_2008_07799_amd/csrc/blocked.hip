@@ -139,9 +139,9 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_obj_blocked(BlockedArgs a) {
     blk_stage_rec(a, s_rec, b);
     blk_stage_off(a, s_off, b, r0, r1);
     if constexpr (KIND == 0)
-        blk_flat<4>(a, ObjValOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
+        blk_flat<2>(a, ObjValOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
     else
-        blk_flat<4>(a, ObjGradOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
+        blk_flat<2>(a, ObjGradOp<B, NH>{hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
 }
 
 __global__ void k_stage_y(int32_t n, const float2* __restrict__ y, const float* __restrict__ invZ,
@@ -308,7 +308,7 @@ int blk_lanes() {
 
 int blk_flat_cpl() {
     const int f = env_int("DRG_BLK_FLAT", 4);
-    return (f == 1 || f == 2 || f == 4 || f == 8) ? f : 0;
+    return (f == 2 || f == 4) ? f : 0;
 }
 
 // True when the per-pair clip of the attraction can never bind: for an
@@ -326,9 +326,7 @@ static void launch_blocked_b(drg_ctx* ctx, const BlockedArgs& a, int nitems) {
     const size_t lds = blk_lds_bytes(a.bits);
     const int form = blk_form(a.flat);
     auto fn = form == 4   ? k_sweep_blocked<B, NH, 4>
-              : form == 8 ? k_sweep_blocked<B, NH, 8>
               : form == 2 ? k_sweep_blocked<B, NH, 2>
-              : form == 1 ? k_sweep_blocked<B, NH, 1>
                           : k_sweep_blocked<B, NH, 0>;
     DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));

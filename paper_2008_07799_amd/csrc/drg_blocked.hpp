@@ -24,7 +24,7 @@ struct BlockedArgs {
     float eh0, eh1, eh2, eh3;   // -2b * e_d / 2 per hop
     float clip;                 // clip / (2b)
     int32_t lanes;              // lanes per row segment (16, 32, 64; 0: per item)
-    int32_t flat;               // chunks per lane of the flat (merge-path) form; 0: row form
+    int32_t flat;               // chunks per lane and batch of the flat (merge-path) form (2, 4); 0: row form
     int32_t noclip;             // 1: the clip cannot bind (attract_clip_free), flat form skips it
 };
 
@@ -232,9 +232,10 @@ __device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_r
 // ------------------------------------------------------------------ flat form
 // The entries of an item (rows r0..r1 of block b) are contiguous, so the
 // item is swept as one stream regardless of row boundaries: wave w takes a
-// contiguous range of its 16-byte chunks, lane l the chunk w0 + l of each
-// 64-chunk window; every lane walks its 8 entries, tracking the row through
-// the LDS row offsets.  A row that starts and ends inside one lane is
+// contiguous range of its 16-byte chunks, lane l the chunks w0 + 2 CPL l ..
+// w0 + 2 CPL (l+1) - 1 of each window of 128 CPL chunks; every lane walks
+// its entries in order, tracking the row through the LDS row offsets.  A row
+// that starts and ends inside one lane is
 // complete there.  A row that crosses lanes is summed by a keyed segmented
 // scan over the lanes' last-row partials (in lane order), a row that crosses
 // windows is carried by the wave, and a row that crosses waves is closed by
@@ -272,8 +273,13 @@ template <int CPL, typename Op>
 __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, const float4* s_rec,
                                          const int32_t* s_off, WaveFrag* s_frag, int32_t b,
                                          int32_t r0, int32_t r1) {
-    constexpr int EPL = 8 * CPL;          // entries per lane per window
-    constexpr int WCH = WAVE * CPL;       // chunks per window
+    // A lane takes 2 CPL consecutive chunks per window, loaded as two
+    // batches of CPL: the second batch is requested when the window starts,
+    // the next window's first batch once this window's first batch is used,
+    // so 2 CPL chunks of registers cover a window of 2 CPL chunks per lane.
+    constexpr int CPW = 2 * CPL;          // chunks per lane per window
+    constexpr int EPL = 8 * CPW;          // entries per lane per window
+    constexpr int WCH = WAVE * CPW;       // chunks per window
     const int lane = __lane_id();
     const int wid = threadIdx.x / WAVE;
     const int32_t nr = r1 - r0;
@@ -344,9 +350,9 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
     // past the range are masked), so the counters of outstanding loads stay
     // exact and a wait for one load does not drain the prefetches
     const int64_t clast = max(wc1 - 1, wc0);
-    uint4 vn[CPL];
+    uint4 va[CPL], vb[CPL];
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) vn[k] = E4[min(wc0 + (int64_t)lane * CPL + k, clast)];
+    for (int k = 0; k < CPL; ++k) va[k] = E4[min(wc0 + (int64_t)lane * CPW + k, clast)];
     for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
         // this window's rows and their cached records
         const int32_t i0 = ni0, i1 = ni1;
@@ -371,8 +377,8 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
             }
             return t;
         };
-        const int64_t c = w0 + (int64_t)lane * CPL;  // the lane's first chunk
-        const int32_t nl = (int32_t)min((int64_t)WAVE, (wc1 - w0 + CPL - 1) / CPL);
+        const int64_t c = w0 + (int64_t)lane * CPW;  // the lane's first chunk
+        const int32_t nl = (int32_t)min((int64_t)WAVE, (wc1 - w0 + CPW - 1) / CPW);
         const bool has = lane < nl;
         const int32_t pbase = (int32_t)(8 * c - bbase);
         const int32_t pf = max(pbase, e0);                                  // first valid slot
@@ -383,59 +389,79 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         int32_t i = has ? row_of(s_off, i0, i1, pf) : i1;
         int32_t nxt = s_off[i + 1];
         float4 ri = load_row(i);
-        uint4 v[CPL];
+        // FULL: every slot of every lane of the window is valid (all windows
+        // but those at the ends of an item or of the wave's range)
+        const bool full = __all(has && qlo == 0 && qhi == EPL);
+        if (full) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            v[k] = vn[k];
-            vn[k] = E4[min(c + WCH + k, clast)];
+            for (int k = 0; k < CPL; ++k) vb[k] = E4[min(c + CPL + k, clast)];
         }
         float ax = 0.0f, ay = 0.0f, hx = 0.0f, hy = 0.0f;
         const int32_t hrow = i;
         bool hopen = true;  // still on the lane's first row
         int32_t qn = nxt - pbase;  // slot where the current row ends
-        // FULL: every slot of every lane of the window is valid (all windows
-        // but those at the ends of an item or of the wave's range)
-        auto entries = [&](auto full_c) {
-            constexpr bool FULL = decltype(full_c)::value;
+        // the pair of slot Q (entry u, column record rj), after closing the
+        // rows that end before it
+        auto slot = [&](int32_t Q, bool valid, uint32_t u, const float4& rj) {
+            if (valid && Q >= qn) {  // the row ends before this slot
+                const int32_t p = pbase + Q;
+                if (hopen) {
+                    hx = ax;
+                    hy = ay;
+                    hopen = false;
+                } else {
+                    close_row(i, ax, ay);  // started and ended inside this lane
+                }
+                do {
+                    ++i;
+                    nxt = s_off[i + 1];
+                } while (p >= nxt);
+                qn = nxt - pbase;
+                ri = load_row(i);
+                ax = 0.0f;
+                ay = 0.0f;
+            }
+            op(ri, rj, u, valid, ax, ay);
+        };
+        if (full) {
+            // the slots of one batch, chunks v[0..CPL) at slots Q0 .., unrolled
+            auto batch = [&](auto q0_c, const uint4* v) {
+                constexpr int32_t Q0 = decltype(q0_c)::value;
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) {
+                for (int k = 0; k < CPL; ++k) {
 #pragma unroll
-                for (int h = 0; h < 8; h += 4) {
-                    // four column records requested before any is used
-                    float4 rj[4];
+                    for (int h = 0; h < 8; h += 4) {
+                        // four column records requested before any is used
+                        float4 rj[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) rj[q] = s_rec[half16(v[k], h + q) & lmask];
+                        for (int q = 0; q < 4; ++q) rj[q] = s_rec[half16(v[k], h + q) & lmask];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int32_t Q = 8 * k + h + q;
-                        const bool valid = FULL || (Q >= qlo && Q < qhi);
-                        if (valid && Q >= qn) {  // the row ends before this slot
-                            const int32_t p = pbase + Q;
-                            if (hopen) {
-                                hx = ax;
-                                hy = ay;
-                                hopen = false;
-                            } else {
-                                close_row(i, ax, ay);  // started and ended inside this lane
-                            }
-                            do {
-                                ++i;
-                                nxt = s_off[i + 1];
-                            } while (p >= nxt);
-                            qn = nxt - pbase;
-                            ri = load_row(i);
-                            ax = 0.0f;
-                            ay = 0.0f;
-                        }
-                        op(ri, rj[q], half16(v[k], h + q), valid, ax, ay);
+                        for (int q = 0; q < 4; ++q)
+                            slot(Q0 + 8 * k + h + q, true, half16(v[k], h + q), rj[q]);
                     }
                 }
+            };
+            batch(std::integral_constant<int32_t, 0>{}, va);
+            // the next window's first batch
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) va[k] = E4[min(c + WCH + k, clast)];
+            batch(std::integral_constant<int32_t, 8 * CPL>{}, vb);
+        } else {
+            // a window at the end of the item or of the wave's range: the
+            // chunks are read again one at a time (they are cached), every
+            // slot tested
+            for (int k = 0; k < CPW; ++k) {
+                const uint4 ck = E4[min(c + k, clast)];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int32_t Q = 8 * k + q;
+                    const uint32_t u = half16(ck, q);
+                    slot(Q, Q >= qlo && Q < qhi, u, s_rec[u & lmask]);
+                }
             }
-        };
-        if (__all(has && qlo == 0 && qhi == EPL))
-            entries(std::true_type{});
-        else
-            entries(std::false_type{});
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) va[k] = E4[min(c + WCH + k, clast)];
+        }
         // the window's carried row continues into lane 0
         if (lane == 0 && hrow == c_row) {
             if (hopen) {
@@ -614,9 +640,9 @@ __device__ __forceinline__ void blk_layout_items(const BlockedArgs& a, float4* s
     }
 }
 
-// sweep form as a template argument: the flat form's chunks per lane, 0 for
+// sweep form as a template argument: the flat form's chunks per lane and batch, 0 for
 // the row form
-inline int blk_form(int flat) { return (flat == 1 || flat == 2 || flat == 4 || flat == 8) ? flat : 0; }
+inline int blk_form(int flat) { return (flat == 2 || flat == 4) ? flat : 0; }
 
 // dynamic LDS of a blocked-sweep workgroup: column records, row offsets,
 // wave fragments, the flat form's row-record caches

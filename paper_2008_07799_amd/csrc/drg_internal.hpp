@@ -121,7 +121,7 @@ void build_blocked(drg_ctx* ctx, drg_sim* s);
 // rows prp[0..n] of a pattern whose columns are col_base .. col_base+n-1
 void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp,
                         const uint32_t* colhop, int32_t col_base, BlkLayout& L);
-int blk_flat_cpl();  // chunks per lane of the flat form (env DRG_BLK_FLAT; 0: row form)
+int blk_flat_cpl();  // chunks per lane and batch of the flat form (env DRG_BLK_FLAT: 2, 4; 0: row form)
 int blk_lanes();
 bool attract_clip_free(int b, double clip);  // the attraction clip cannot bind     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
 // One FP32 sync sweep on the blocked layout: the one-sided steps into g.

@@ -294,7 +294,7 @@ def test_full_layout_statistics(oracle_lib, mode):
     assert abs(np_g - np_r) <= 0.01
 
 
-@pytest.mark.parametrize("bits,form", [(8, "flat2"), (10, "flat1"), (10, "flat4"), (12, "flat8"),
+@pytest.mark.parametrize("bits,form", [(8, "flat2"), (10, "flat2"), (10, "flat4"), (12, "flat4"),
                                        (8, "rows0"), (8, "rows16"), (10, "rows32"),
                                        (10, "rows64")])
 def test_blocked_sweep_every_level(oracle_lib, monkeypatch, bits, form):
