@@ -273,10 +273,12 @@ template <int CPL, typename Op>
 __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, const float4* s_rec,
                                          const int32_t* s_off, WaveFrag* s_frag, int32_t b,
                                          int32_t r0, int32_t r1) {
-    // A lane takes 2 CPL consecutive chunks per window, loaded as two
-    // batches of CPL: the second batch is requested when the window starts,
-    // the next window's first batch once this window's first batch is used,
-    // so 2 CPL chunks of registers cover a window of 2 CPL chunks per lane.
+    // A lane takes 2 CPL consecutive chunks per window, held as two batches
+    // of CPL: once this window's first batch is used, both batches of the
+    // next window are requested together (so the two halves of a lane's
+    // cache lines are fetched together, not a half window apart, when one
+    // could be evicted in between), and the second batch waits in a third
+    // buffer until this window's second batch is used.
     constexpr int CPW = 2 * CPL;          // chunks per lane per window
     constexpr int EPL = 8 * CPW;          // entries per lane per window
     constexpr int WCH = WAVE * CPW;       // chunks per window
@@ -350,9 +352,12 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
     // past the range are masked), so the counters of outstanding loads stay
     // exact and a wait for one load does not drain the prefetches
     const int64_t clast = max(wc1 - 1, wc0);
-    uint4 va[CPL], vb[CPL];
+    uint4 va[CPL], vb[CPL], vn[CPL];
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) va[k] = E4[min(wc0 + (int64_t)lane * CPW + k, clast)];
+    for (int k = 0; k < CPL; ++k) {
+        va[k] = E4[min(wc0 + (int64_t)lane * CPW + k, clast)];
+        vb[k] = E4[min(wc0 + (int64_t)lane * CPW + CPL + k, clast)];
+    }
     for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
         // this window's rows and their cached records
         const int32_t i0 = ni0, i1 = ni1;
@@ -392,10 +397,6 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         // FULL: every slot of every lane of the window is valid (all windows
         // but those at the ends of an item or of the wave's range)
         const bool full = __all(has && qlo == 0 && qhi == EPL);
-        if (full) {
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) vb[k] = E4[min(c + CPL + k, clast)];
-        }
         float ax = 0.0f, ay = 0.0f, hx = 0.0f, hy = 0.0f;
         const int32_t hrow = i;
         bool hopen = true;  // still on the lane's first row
@@ -442,10 +443,15 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                 }
             };
             batch(std::integral_constant<int32_t, 0>{}, va);
-            // the next window's first batch
+            // the next window's two batches
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) va[k] = E4[min(c + WCH + k, clast)];
+            for (int k = 0; k < CPL; ++k) {
+                va[k] = E4[min(c + WCH + k, clast)];
+                vn[k] = E4[min(c + WCH + CPL + k, clast)];
+            }
             batch(std::integral_constant<int32_t, 8 * CPL>{}, vb);
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) vb[k] = vn[k];
         } else {
             // a window at the end of the item or of the wave's range: the
             // chunks are read again one at a time (they are cached), every
@@ -460,7 +466,10 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                 }
             }
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) va[k] = E4[min(c + WCH + k, clast)];
+            for (int k = 0; k < CPL; ++k) {
+                va[k] = E4[min(c + WCH + k, clast)];
+                vb[k] = E4[min(c + WCH + CPL + k, clast)];
+            }
         }
         // the window's carried row continues into lane 0
         if (lane == 0 && hrow == c_row) {
