@@ -52,10 +52,10 @@ WORKLOADS = {
 # sources that make up each profiled kernel (the counter summaries hold
 # their hash; a summary taken on other sources is not used)
 KERNEL_SOURCES = {
-    "k_sweep_blocked": ("blocked.hip", "drg_common.hpp", "drg_forces.hpp"),
+    "k_sweep_blocked": ("blocked.hip", "drg_blocked.hpp", "drg_common.hpp", "drg_forces.hpp"),
     "k_sweep": ("layout.hip", "drg_common.hpp", "drg_forces.hpp"),
-    "k_b_sweep_win": ("batch.hip", "drg_common.hpp", "drg_forces.hpp"),
-    "k_b_sweep": ("batch.hip", "drg_common.hpp", "drg_forces.hpp"),
+    "k_b_sweep_win": ("batch.hip", "drg_blocked.hpp", "drg_common.hpp", "drg_forces.hpp"),
+    "k_b_sweep": ("batch.hip", "drg_blocked.hpp", "drg_common.hpp", "drg_forces.hpp"),
 }
 
 

@@ -356,7 +356,9 @@ struct BBlkArgs {
     const float4* rec;
 };
 
-template <int NH, int F>
+// One launch per exponent b (the groups of the graphs with that b), so
+// each kernel holds the code of one b, as the single-graph kernel does.
+template <int NH, int F, int B>
 __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
     extern __shared__ float4 s_dyn[];
     const int4 gr = a.groups[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
@@ -382,25 +384,26 @@ __global__ __launch_bounds__(STREAM_BLOCK) void k_b_sweep_blocked(BBlkArgs a) {
     la.noclip = v.noclip;
     la.lanes = a.lanes;
     la.flat = a.flat;
-    if (g.b == 1)
-        blk_layout_items<1, NH, F>(la, s_dyn, blk, its, gr.y);
-    else if (g.b == 2)
-        blk_layout_items<2, NH, F>(la, s_dyn, blk, its, gr.y);
-    else
-        blk_layout_items<3, NH, F>(la, s_dyn, blk, its, gr.y);
+    blk_layout_items<B, NH, F>(la, s_dyn, blk, its, gr.y);
+}
+
+template <int NH, int B>
+static auto b_blk_kernel_nhb(int form) {
+    return form == 4   ? k_b_sweep_blocked<NH, 4, B>
+           : form == 2 ? k_b_sweep_blocked<NH, 2, B>
+                       : k_b_sweep_blocked<NH, 0, B>;
 }
 
 template <int NH>
-static auto b_blk_kernel_nh(int form) {
-    return form == 4   ? k_b_sweep_blocked<NH, 4>
-           : form == 2 ? k_b_sweep_blocked<NH, 2>
-                       : k_b_sweep_blocked<NH, 0>;
+static auto b_blk_kernel_nh(int form, int b) {
+    return b == 1 ? b_blk_kernel_nhb<NH, 1>(form)
+                  : (b == 2 ? b_blk_kernel_nhb<NH, 2>(form) : b_blk_kernel_nhb<NH, 3>(form));
 }
 
-// the batch's blocked-sweep kernel for NH hop weights and sweep form F
-static auto b_blk_kernel(int NH, int form) {
-    return NH == 1 ? b_blk_kernel_nh<1>(form)
-                   : (NH == 2 ? b_blk_kernel_nh<2>(form) : b_blk_kernel_nh<4>(form));
+// the batch's blocked-sweep kernel for NH hop weights, sweep form F and exponent b
+static auto b_blk_kernel(int NH, int form, int b) {
+    return NH == 1 ? b_blk_kernel_nh<1>(form, b)
+                   : (NH == 2 ? b_blk_kernel_nh<2>(form, b) : b_blk_kernel_nh<4>(form, b));
 }
 
 struct BFinArgs {
@@ -509,6 +512,7 @@ struct drg_batch {
     drg::DevBuf<drg::BBlkView> blk_views;
     drg::DevBuf<int32_t> blk_off, blk_graph;
     int32_t blk_ngroups = 0, blk_count = 0, blk_nodes = 0;
+    int32_t blk_b_first[3] = {0, 0, 0}, blk_b_count[3] = {0, 0, 0};  // groups per exponent
     drg::SweepForm form;                        // chosen sweep form
     std::vector<std::pair<drg::SweepForm, float>> tune;  // candidates and their times
     drg::DevBuf<int2> pro_ops;
@@ -834,6 +838,15 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             b->blk.push_back(std::move(L));
         }
         b->blk_count = (int32_t)bgraph.size();
+        // groups ordered by exponent (stable), one launch per exponent
+        std::vector<int4> sorted;
+        for (int bb = 1; bb <= 3; ++bb) {
+            b->blk_b_first[bb - 1] = (int32_t)sorted.size();
+            for (const int4& gq : bgroups)
+                if (gt[gq.z].b == bb) sorted.push_back(gq);
+            b->blk_b_count[bb - 1] = (int32_t)sorted.size() - b->blk_b_first[bb - 1];
+        }
+        bgroups.swap(sorted);
         b->blk_ngroups = (int32_t)bgroups.size();
         b->blk_nodes = boff.back();
         if (b->blk_count > 0) {
@@ -843,9 +856,12 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             upload(b->blk_off, boff, st);
             upload(b->blk_graph, bgraph, st);
             blk_lds = blk_lds_bytes(bits);
-            auto fn = b_blk_kernel(NH, blk_form(blk_cpl));
-            DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)blk_lds));
+            for (int bb = 1; bb <= 3; ++bb) {
+                auto fn = b_blk_kernel(NH, blk_form(blk_cpl), bb);
+                DRG_HIP(hipFuncSetAttribute((const void*)fn,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)blk_lds));
+            }
             DRG_HIP(hipStreamSynchronize(st));
         }
     }
@@ -862,9 +878,15 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         ba.gt = b->gt.get();
         ba.sched = b->sched.get();
         ba.rec = s->rec.get();
-        auto fn = b_blk_kernel(NH, blk_form(blk_cpl));
-        hipLaunchKernelGGL(fn, dim3(b->blk_ngroups), dim3(STREAM_BLOCK), blk_lds, stream, ba);
-        DRG_LAUNCH_CHECK();
+        for (int bb = 1; bb <= 3; ++bb) {
+            if (b->blk_b_count[bb - 1] == 0) continue;
+            BBlkArgs bx = ba;
+            bx.groups = b->blk_groups.get() + b->blk_b_first[bb - 1];
+            auto fn = b_blk_kernel(NH, blk_form(blk_cpl), bb);
+            hipLaunchKernelGGL(fn, dim3(b->blk_b_count[bb - 1]), dim3(STREAM_BLOCK), blk_lds,
+                               stream, bx);
+            DRG_LAUNCH_CHECK();
+        }
         BFinArgs fa{};
         fa.nblk = b->blk_count;
         fa.count = count;

@@ -269,7 +269,10 @@ __device__ __forceinline__ int32_t row_from(const int32_t* off, int32_t lo, int3
     return row_of(off, lo, min(lo + step - 1, hi), p);
 }
 
-template <int CPL, typename Op>
+// TOGETHER = false: the next window's second batch is requested only when
+// it starts (no third buffer: for kernels short of registers).  The loads'
+// timing does not change any result.
+template <int CPL, typename Op, bool TOGETHER = true>
 __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, const float4* s_rec,
                                          const int32_t* s_off, WaveFrag* s_frag, int32_t b,
                                          int32_t r0, int32_t r1) {
@@ -352,11 +355,11 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
     // past the range are masked), so the counters of outstanding loads stay
     // exact and a wait for one load does not drain the prefetches
     const int64_t clast = max(wc1 - 1, wc0);
-    uint4 va[CPL], vb[CPL], vn[CPL];
+    uint4 va[CPL], vb[CPL], vn[TOGETHER ? CPL : 1];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         va[k] = E4[min(wc0 + (int64_t)lane * CPW + k, clast)];
-        vb[k] = E4[min(wc0 + (int64_t)lane * CPW + CPL + k, clast)];
+        if constexpr (TOGETHER) vb[k] = E4[min(wc0 + (int64_t)lane * CPW + CPL + k, clast)];
     }
     for (int64_t w0 = wc0; w0 < wc1; w0 += WCH) {
         // this window's rows and their cached records
@@ -397,6 +400,12 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         // FULL: every slot of every lane of the window is valid (all windows
         // but those at the ends of an item or of the wave's range)
         const bool full = __all(has && qlo == 0 && qhi == EPL);
+        if constexpr (!TOGETHER) {
+            if (full) {
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) vb[k] = E4[min(c + CPL + k, clast)];
+            }
+        }
         float ax = 0.0f, ay = 0.0f, hx = 0.0f, hy = 0.0f;
         const int32_t hrow = i;
         bool hopen = true;  // still on the lane's first row
@@ -443,15 +452,17 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                 }
             };
             batch(std::integral_constant<int32_t, 0>{}, va);
-            // the next window's two batches
+            // the next window's batches
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
                 va[k] = E4[min(c + WCH + k, clast)];
-                vn[k] = E4[min(c + WCH + CPL + k, clast)];
+                if constexpr (TOGETHER) vn[k] = E4[min(c + WCH + CPL + k, clast)];
             }
             batch(std::integral_constant<int32_t, 8 * CPL>{}, vb);
+            if constexpr (TOGETHER) {
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) vb[k] = vn[k];
+                for (int k = 0; k < CPL; ++k) vb[k] = vn[k];
+            }
         } else {
             // a window at the end of the item or of the wave's range: the
             // chunks are read again one at a time (they are cached), every
@@ -468,7 +479,7 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
                 va[k] = E4[min(c + WCH + k, clast)];
-                vb[k] = E4[min(c + WCH + CPL + k, clast)];
+                if constexpr (TOGETHER) vb[k] = E4[min(c + WCH + CPL + k, clast)];
             }
         }
         // the window's carried row continues into lane 0
@@ -592,7 +603,7 @@ __device__ __forceinline__ void blk_stage_off(const BlockedArgs& a, int32_t* s_o
 // lane (F = 1, 2, 4, 8), or for F = 0 the row form (a.lanes lanes per
 // segment, 0: chosen from the item's mean segment length).  s_dyn is the
 // workgroup's dynamic LDS (records, row offsets, wave fragments).
-template <int B, int NH, int F>
+template <int B, int NH, int F, bool TOGETHER = true>
 __device__ __forceinline__ void blk_sweep_staged(const BlockedArgs& a, float4* s_dyn, int32_t b,
                                                  int32_t r0, int32_t r1) {
     const int32_t bw = 1 << a.bits;
@@ -601,11 +612,11 @@ __device__ __forceinline__ void blk_sweep_staged(const BlockedArgs& a, float4* s
     WaveFrag* s_frag = reinterpret_cast<WaveFrag*>(s_dyn + bw + (ROWCAP + 4) / 4);
     if constexpr (F > 0) {
         if (a.noclip)
-            blk_flat<F>(a, LayoutOp<B, NH, false>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b,
-                        r0, r1);
+            blk_flat<F, LayoutOp<B, NH, false>, TOGETHER>(
+                a, LayoutOp<B, NH, false>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
         else
-            blk_flat<F>(a, LayoutOp<B, NH, true>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b,
-                        r0, r1);
+            blk_flat<F, LayoutOp<B, NH, true>, TOGETHER>(
+                a, LayoutOp<B, NH, true>{&a, hop_weights(a)}, s_rec, s_off, s_frag, b, r0, r1);
     } else {
         int S = a.lanes;
         if (S == 0) {
@@ -635,7 +646,8 @@ __device__ __forceinline__ void blk_layout_item(const BlockedArgs& a, float4* s_
 // Consecutive work items items[0..cnt) of one block b: the records are
 // staged once, then every item is swept exactly as alone (its own row
 // offsets, wave ranges and lane order), so the result is the same bit for
-// bit as one workgroup per item.
+// bit as one workgroup per item (the next window's second batch is
+// requested late: this loop leaves too few registers for a third buffer).
 template <int B, int NH, int F>
 __device__ __forceinline__ void blk_layout_items(const BlockedArgs& a, float4* s_dyn, int32_t b,
                                                  const int4* __restrict__ items, int32_t cnt) {
@@ -645,7 +657,7 @@ __device__ __forceinline__ void blk_layout_items(const BlockedArgs& a, float4* s
         const int4 it = items[k];
         __syncthreads();  // the previous item is done with the offsets and fragments
         blk_stage_off(a, reinterpret_cast<int32_t*>(s_dyn + bw), b, it.y, it.z);
-        blk_sweep_staged<B, NH, F>(a, s_dyn, b, it.y, it.z);
+        blk_sweep_staged<B, NH, F, false>(a, s_dyn, b, it.y, it.z);
     }
 }
 
