@@ -402,8 +402,9 @@ def main():
     y = torch.zeros((g.n, 2), dtype=torch.float32, device="cuda")
 
     phase_s = {"similarity": 0.0, "hierarchy": 0.0, "layout": 0.0}
+    kept = {}
 
-    def step():
+    def step(keep=False):
         t = time.perf_counter()
         sim = d.drg_build_similarity(ctx, rp, col, cfg["k"])
         torch.cuda.synchronize()
@@ -422,7 +423,10 @@ def main():
         phase_s["hierarchy"] += t2 - t1
         phase_s["layout"] += t3 - t2
         info = (sim.nnz, sim.n_active, hier.sizes, sim.blocked)
-        sim.close()
+        if keep:
+            kept["sim"] = sim
+        else:
+            sim.close()
         hier.close()
         return info
 
@@ -436,13 +440,24 @@ def main():
     t0 = time.perf_counter()
     for s in range(args.steps):
         print(f"[bench] timed step {s}", file=sys.stderr, flush=True)
-        nnz, n_active, sizes, blocked = step()
+        nnz, n_active, sizes, blocked = step(keep=(s == args.steps - 1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, sweep_ms = ctx.kernel_stats()
     ctx.set_profiling(False)
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
 
+    # layout quality of the result (outside the timed region): NP (Sec. 4.1)
+    # of 1000 sampled non-isolated nodes, graph neighbourhoods = the rows of
+    # the workload's own similarity (k_eval = k)
+    sim = kept.pop("sim")
+    deg = np.diff(g.row_ptr)
+    sample = np.random.default_rng(0).choice(np.nonzero(deg > 0)[0], size=1000, replace=False)
+    t_np = time.perf_counter()
+    np_vals = d.drg_neighbourhood_preservation(
+        ctx, sim, y, torch.from_numpy(np.sort(sample).astype(np.int32)).cuda()).cpu().numpy()
+    t_np = time.perf_counter() - t_np
+    sim.close()
     M, T, n = cfg["M"], cfg["T"], g.n
     pairs = nnz + M * n_active
     value = T * pairs / (ms_per_step / 1000.0)
@@ -469,6 +484,8 @@ def main():
                    "T": T, "levels": sizes, "nnz_P": nnz, "n_active": n_active,
                    "mode": args.mode, "time_to_layout_s": ms_per_step / 1000.0,
                    "layout_only_s": phase_s["layout"] / args.steps,
+                   "np_sampled": {"value": float(np_vals[np_vals >= 0].mean()), "nodes": 1000,
+                                  "k_eval": cfg["k"], "seconds": t_np},
                    "phases_s": {k: v / args.steps for k, v in phase_s.items()},
                    "iteration_sweep_pair_updates_per_s": pairs / (avg_ms / 1000.0)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -159,6 +159,18 @@ drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint
 drg_status drg_sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows,
                                int64_t cap, int64_t* row_len, int32_t* col, uint8_t* hop,
                                double* P, double* qt, uint64_t* W, double* invZ);
+/* Layout quality: neighbourhood preservation (Sec. 4.1, Eq. NP) of the nodes
+ * nodes[0..count) (device int32).  For node v with graph neighbourhood
+ * N_G(v) = NNG(v, k) -- the rows of `s`, so build it with k = k_eval -- and
+ * m = |N_G(v)| > 0, N_L(v) is the set of the m nodes u != v nearest to y_v
+ * (squared distance in FP64 from the FP32 coordinates y [n][2], device;
+ * ties by smaller id), and np_out[t] (device double) = |N_G & N_L| /
+ * |N_G | N_L| for v = nodes[t]; -1 when m = 0.  Exact selection, one
+ * workgroup per node, O(n) work per node.  Enqueued on the context's stream
+ * (asynchronous; np_out is ready after drg_ctx_synchronize).  DRG_E_INVALID
+ * for a node id out of range, DRG_E_UNSUPPORTED for n >= 2^24. */
+drg_status drg_neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const float* y,
+                                          int32_t count, const int32_t* nodes, double* np_out);
 void drg_sim_destroy(drg_sim* s);
 
 /* Multilevel coarsening (Sec. 3.2.3, Fig. 3): repeatedly groups a randomly

@@ -4,6 +4,8 @@
   Jaccard index between NNG(v, k_eval) in the graph and the |NNG(v, k_eval)|
   nearest layout neighbours of y_v, with k_eval = 2.  Ties among layout
   distances are broken by node id.  Isolated nodes (empty NNG) are skipped.
+  `np_per_node` computes it per node by brute force (every distance), the
+  mean version with a k-d tree.
 * objective_eval: the sampled objective with a fixed evaluation seed and
   M_eval negatives per node, rescaled to M negatives.
 """
@@ -12,6 +14,35 @@ from __future__ import annotations
 import numpy as np
 
 from . import drgo
+
+
+def np_per_node(y, rp, col, nodes) -> np.ndarray:
+    """NP_v (Sec. 4.1, Eq. NP) of each node in `nodes` by brute force: the
+    squared layout distance to every other node in FP64 (dx*dx + dy*dy),
+    N_L(v) = the m = |N_G(v)| smallest (distance, id) pairs, N_G(v) = row v
+    of the pattern (rp, col); NP_v = |N_G & N_L| / |N_G | N_L|, -1 for m = 0."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    ids = np.arange(n)
+    out = np.zeros(len(nodes), np.float64)
+    for t, v in enumerate(nodes):
+        v = int(v)
+        m = int(rp[v + 1] - rp[v])
+        if m == 0:
+            out[t] = -1.0
+            continue
+        dx = y[v, 0] - y[:, 0]
+        dy = y[v, 1] - y[:, 1]
+        d2 = dx * dx + dy * dy
+        d2[v] = np.inf
+        thr = np.partition(d2, m - 1)[m - 1]
+        less = d2 < thr
+        eq = np.nonzero(d2 == thr)[0]  # ascending ids
+        take = m - int(less.sum())
+        layout = np.concatenate([ids[less], eq[:take]])
+        inter = np.intersect1d(layout, col[rp[v]:rp[v + 1]], assume_unique=True).size
+        out[t] = inter / (2.0 * m - inter)
+    return out
 
 
 def neighbourhood_preservation(csr, y, k_eval: int = 2, sample: int | None = None,

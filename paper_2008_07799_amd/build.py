@@ -14,7 +14,7 @@ LIB = os.path.join(OUT_DIR, "libdrgraph.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["prims.hip", "similarity.hip", "blocked.hip", "coarsen.hip", "layout.hip",
-           "objective.hip", "window.hip", "batch.hip", "capi.hip"]
+           "objective.hip", "window.hip", "batch.hip", "evaluate.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DRG_OFFLOAD_ARCH", "gfx950")

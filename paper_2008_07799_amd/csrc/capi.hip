@@ -183,6 +183,16 @@ drg_status drg_sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* r
     });
 }
 
+drg_status drg_neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const float* y,
+                                          int32_t count, const int32_t* nodes, double* np_out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(s, "sim");
+        use_device(ctx->device);
+        drg::neighbourhood_preservation(ctx, s, y, count, nodes, np_out);
+    });
+}
+
 void drg_sim_destroy(drg_sim* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);

@@ -90,6 +90,7 @@ def lib():
                           C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
         "drg_sim_export": ([_P] + [_P] * 8, st),
         "drg_sim_export_rows": ([_P, C.c_int32, _P, C.c_int64] + [_P] * 7, st),
+        "drg_neighbourhood_preservation": ([_P, _P, _P, C.c_int32, _P, _P], st),
         "drg_sim_destroy": ([_P], None),
         "drg_coarsen": ([_P, C.POINTER(Csr), C.c_uint64, C.c_double, C.c_int32, C.c_int32,
                          C.POINTER(_P)], st),
@@ -280,6 +281,20 @@ def drg_build_similarity(ctx: Context, row_ptr, col, k: int, sigma: float = 1.0,
     _check(lib().drg_build_similarity(ctx.h, C.byref(g), int(k), float(sigma),
                                       DRG_VALIDATE if validate else 0, C.byref(h)))
     return Similarity(h)
+
+
+def drg_neighbourhood_preservation(ctx: Context, sim: Similarity, y, nodes):
+    """NP of `nodes` (Sec. 4.1, Eq. NP) for the layout y [n, 2] (FP32, device),
+    with graph neighbourhoods = the rows of `sim`: a float64 device tensor,
+    -1 where a node has no neighbourhood."""
+    import torch
+    yp = _dev(y, torch.float32, "y", (sim.n, 2))
+    np_ = _dev(nodes, torch.int32, "nodes")
+    out = torch.empty(nodes.numel(), dtype=torch.float64, device=y.device)
+    _check(lib().drg_neighbourhood_preservation(ctx.h, sim.h, yp, int(nodes.numel()), np_,
+                                                C.c_void_p(out.data_ptr())))
+    ctx.synchronize()
+    return out
 
 
 # ------------------------------------------------------------------ hierarchy

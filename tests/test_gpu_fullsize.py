@@ -109,6 +109,13 @@ def test_rmat20_k2_sampled_rows_and_invariants(oracle_lib):
     say("  sampled-row step err", err)
     assert err < 2e-6
     assert np.array_equal(y1[src[-1]], y0[src[-1]])  # the isolated node stays
+    # neighbourhood preservation of the sampled rows at full size (k_eval = 2)
+    from oracle import evaluate
+    nodes = torch.from_numpy(src).cuda()
+    np_gpu = d.drg_neighbourhood_preservation(c, sim, to_y(y0), nodes).cpu().numpy()
+    np_ref = evaluate.np_per_node(y0.astype(np.float64), prp, pc, src)
+    say("  NP of the sampled rows", np_gpu.tolist())
+    assert np.array_equal(np_gpu, np_ref)
     # all rows: zero net attraction force and torque
     qf = per["qt"].astype(np.float32).astype(np.float64)
     gvec = (y1.astype(np.float64) - y0.astype(np.float64)) * qf[:, None] / np.float64(np.float32(eta))
@@ -147,3 +154,12 @@ def test_rmat20_k1_whole_similarity_and_step(oracle_lib):
     err = normwise_rel(y.cpu().numpy(), yr)
     say("  whole step err", err)
     assert err < 2e-6
+    # neighbourhood preservation (k_eval = 1 here: the rows of this
+    # similarity) of 64 nodes at full size
+    import torch
+    from oracle import evaluate
+    nodes = np.random.default_rng(5).choice(g.n, size=64, replace=False).astype(np.int32)
+    y1 = y.cpu().numpy()
+    np_gpu = d.drg_neighbourhood_preservation(c, sim, y, torch.from_numpy(nodes).cuda())
+    np_ref = evaluate.np_per_node(y1.astype(np.float64), rsim.row_ptr, rsim.col, nodes)
+    assert np.array_equal(np_gpu.cpu().numpy(), np_ref)

@@ -198,3 +198,32 @@ def test_grid17_quality_band(oracle_lib):
         g, oracle_lib.layout(g, k=3, M=5, b=3, gamma=0.1, T=400, eta0=1.0, clip=4.0,
                              min_nodes=1000, seed=s)) for s in range(5)]
     assert np.median(vals) > 0.75
+
+
+def test_np_per_node_brute_force_matches_kdtree(oracle_lib):
+    """The brute-force NP per node (used against the GPU evaluator) agrees with
+    the k-d tree route on layouts without distance ties, and an isolated node
+    gets -1."""
+    from oracle import evaluate
+    for sub, k in ((0, 2), (1, 1), (2, 3)):
+        g = gen.random_graph(160, 0.03, seed=21, sub=sub)
+        rp, col, _ = oracle_lib.khop(g, k)
+        y = np.random.default_rng(sub).uniform(-1, 1, size=(g.n, 2))
+        nodes = np.arange(g.n)
+        per = evaluate.np_per_node(y, rp, col, nodes)
+        act = np.diff(rp) > 0
+        assert np.all(per[~act] == -1.0)
+        whole = evaluate.neighbourhood_preservation(g, y, k_eval=k, pattern=(rp, col))
+        assert abs(per[act].mean() - whole) < 1e-12
+
+
+def test_np_per_node_ties_by_id(oracle_lib):
+    """Coincident layout points: the nearest are taken in id order."""
+    from oracle import evaluate
+    # node 0 with neighbours {1, 2}; nodes 1..4 all at the same point
+    rp = np.array([0, 2, 2, 2, 2, 2])
+    col = np.array([1, 2])
+    y = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 0.0], [1.0, 0.0], [1.0, 0.0]])
+    assert evaluate.np_per_node(y, rp, col, [0])[0] == 1.0      # takes ids 1, 2
+    col2 = np.array([3, 4])
+    assert evaluate.np_per_node(y, rp, col2, [0])[0] == 0.0     # takes 1, 2: no overlap
