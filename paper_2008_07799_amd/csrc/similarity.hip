@@ -173,10 +173,36 @@ __global__ __launch_bounds__(BFS_BLOCK) void k_khop(BfsArgs a) {
             const int32_t* F = from_adj ? a.col + rs : q + fb;
             const int32_t flen = from_adj ? (re - rs) : (fe - fb);
             const bool keep = d < a.k;
-            for (int32_t fi = tid / G; fi < flen; fi += BFS_BLOCK / G) {
+            // the next frontier node's adjacency range is requested while
+            // the current one is expanded
+            int32_t fi = tid / G;
+            int32_t us_n = 0, ue_n = 0;
+            if (fi < flen) {
                 const int32_t u = F[fi];
-                const int32_t us = a.rp[u], ue = a.rp[u + 1];
-                for (int32_t x = us + (tid % G); x < ue; x += G) {
+                us_n = a.rp[u];
+                ue_n = a.rp[u + 1];
+            }
+            for (; fi < flen; fi += BFS_BLOCK / G) {
+                const int32_t us = us_n, ue = ue_n;
+                const int32_t fn = fi + BFS_BLOCK / G;
+                if (fn < flen) {
+                    const int32_t un = F[fn];
+                    us_n = a.rp[un];
+                    ue_n = a.rp[un + 1];
+                }
+                int32_t x = us + (tid % G);
+                if (!keep) {
+                    // last hop: only marks; four neighbour ids requested
+                    // before their bits are set
+                    for (; x + 3 * G < ue; x += 4 * G) {
+                        int32_t w[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) w[q] = a.col[x + q * G] - base;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) atomicOr(&bm[w[q] >> 5], 1u << (w[q] & 31));
+                    }
+                }
+                for (; x < ue; x += G) {
                     const int32_t v = a.col[x];
                     const int32_t vb = v - base;
                     const uint32_t bit = 1u << (vb & 31);
