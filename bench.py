@@ -458,6 +458,12 @@ def main():
         ctx, sim, y, torch.from_numpy(np.sort(sample).astype(np.int32)).cuda()).cpu().numpy()
     t_np = time.perf_counter() - t_np
     sim.close()
+    # and the sampled stress (Sec. 4.1): whole-graph searches from 64 sources
+    t_st = time.perf_counter()
+    src = np.sort(np.random.default_rng(1).choice(np.nonzero(deg > 0)[0], size=64,
+                                                  replace=False)).astype(np.int32)
+    _, stress_est = d.drg_stress_sampled(ctx, rp, col, y, torch.from_numpy(src).cuda())
+    t_st = time.perf_counter() - t_st
     M, T, n = cfg["M"], cfg["T"], g.n
     pairs = nnz + M * n_active
     value = T * pairs / (ms_per_step / 1000.0)
@@ -486,6 +492,7 @@ def main():
                    "layout_only_s": phase_s["layout"] / args.steps,
                    "np_sampled": {"value": float(np_vals[np_vals >= 0].mean()), "nodes": 1000,
                                   "k_eval": cfg["k"], "seconds": t_np},
+                   "stress_sampled": {"value": stress_est, "sources": 64, "seconds": t_st},
                    "phases_s": {k: v / args.steps for k, v in phase_s.items()},
                    "iteration_sweep_pair_updates_per_s": pairs / (avg_ms / 1000.0)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

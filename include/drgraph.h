@@ -171,6 +171,20 @@ drg_status drg_sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* r
  * for a node id out of range, DRG_E_UNSUPPORTED for n >= 2^24. */
 drg_status drg_neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const float* y,
                                           int32_t count, const int32_t* nodes, double* np_out);
+/* Layout quality: sampled normalised stress (Sec. 4.1).  The stress with
+ * weights 1/SPD^2 and the best scale alpha is (P - A^2/B) / |V|^2, with
+ * A = sum L/D, B = sum L^2/D^2 over the P pairs summed (L = layout distance,
+ * D = shortest-path distance; unreachable pairs carry weight 0).  For each
+ * source sources[t] (device int32, count of them) this writes, over the
+ * pairs (source, j) with j reachable and j != source, sums_out[3t..3t+2] =
+ * (A, B, P) (device double); the sampled estimate of the stress is then
+ * (n / count) (sum P - (sum A)^2 / sum B) / n^2.  Distances by breadth-first
+ * search over the whole graph g (device CSR, as for drg_build_similarity);
+ * y [n][2] FP32 device coordinates, L in FP64.  Sums in ascending node id:
+ * repeatable.  Scratch: 8 n bytes per concurrently searched source.
+ * Synchronises.  DRG_E_INVALID for a source id out of range. */
+drg_status drg_stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
+                              const int32_t* sources, double* sums_out);
 void drg_sim_destroy(drg_sim* s);
 
 /* Multilevel coarsening (Sec. 3.2.3, Fig. 3): repeatedly groups a randomly

@@ -6,6 +6,8 @@
   distances are broken by node id.  Isolated nodes (empty NNG) are skipped.
   `np_per_node` computes it per node by brute force (every distance), the
   mean version with a k-d tree.
+* stress (Sec. 4.1): weights 1/SPD^2, best scale alpha in closed form;
+  `stress_terms` gives the per-source sums a sampled estimate is made of.
 * objective_eval: the sampled objective with a fixed evaluation seed and
   M_eval negatives per node, rescaled to M negatives.
 """
@@ -77,6 +79,37 @@ def neighbourhood_preservation(csr, y, k_eval: int = 2, sample: int | None = Non
         union = len(layout_nb | graph_nb)
         total += inter / union
     return total / max(1, nodes.size)
+
+
+def stress_terms(csr, y, sources) -> np.ndarray:
+    """Per source s: (A, B, P) = (sum L/D, sum L^2/D^2, number of pairs) over
+    the nodes j != s reachable from s, L = ||y_s - y_j|| (FP64), D = the
+    shortest-path distance (Sec. 4.1, stress with weights 1/D^2)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+    y = np.asarray(y, dtype=np.float64)
+    A = sp.csr_matrix((np.ones(len(csr.col)), csr.col, csr.row_ptr), shape=(csr.n, csr.n))
+    D = shortest_path(A, method="D", unweighted=True, directed=False,
+                      indices=np.asarray(sources))
+    out = np.zeros((len(sources), 3))
+    for t, s in enumerate(sources):
+        ok = np.isfinite(D[t]) & (D[t] > 0)
+        L = np.sqrt(((y[ok] - y[s]) ** 2).sum(axis=1))
+        r = L / D[t][ok]
+        out[t] = (r.sum(), (r * r).sum(), ok.sum())
+    return out
+
+
+def stress(csr, y, sources=None) -> float:
+    """Normalised stress min_alpha (1/|V|^2) sum w (alpha L - D)^2, w = 1/D^2
+    (Sec. 4.1): (P - A^2/B) / |V|^2, over all sources or scaled up from a
+    sample of them."""
+    n = int(csr.n)
+    src = np.arange(n) if sources is None else np.asarray(sources)
+    t = stress_terms(csr, y, src).sum(axis=0)
+    if t[1] <= 0:
+        return 0.0
+    return (n / len(src)) * (t[2] - t[0] * t[0] / t[1]) / (n * n)
 
 
 def objective_eval(sim, y, M: int, b: int, gamma: float, M_eval: int = 50,

@@ -193,6 +193,16 @@ drg_status drg_neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const 
     });
 }
 
+drg_status drg_stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
+                              const int32_t* sources, double* sums_out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(g, "graph");
+        use_device(ctx->device);
+        drg::stress_sampled(ctx, g, y, count, sources, sums_out);
+    });
+}
+
 void drg_sim_destroy(drg_sim* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);

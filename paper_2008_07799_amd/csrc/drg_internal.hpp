@@ -99,6 +99,9 @@ inline int sweep_group(double mean_len) {
 drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
                           UnionInfo* u = nullptr);
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
+void validate_csr_impl(drg_ctx* ctx, const drg_csr* g, bool full);
+void stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
+                    const int32_t* sources, double* out);
 void neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const float* y, int32_t count,
                                 const int32_t* nodes, double* out);
 void sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows, int64_t cap,

@@ -13,6 +13,8 @@
 // eight 8-bit digits of d^2, then the id); then every entry of the row is
 // tested against that key.  Exact, so it matches a plain sort of all
 // distances.
+#include <algorithm>
+
 #include "drg_internal.hpp"
 
 namespace drg {
@@ -158,6 +160,166 @@ void neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const float* y, 
     hipLaunchKernelGGL(k_np, dim3(count), dim3(NP_BLOCK), 0, ctx->stream, s->n, s->row_ptr.get(),
                        s->colhop.get(), reinterpret_cast<const float2*>(y), nodes, out);
     DRG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ stress
+// Normalised stress (Sec. 4.1) needs shortest-path distances D_sj; with the
+// optimal scale alpha it is (P - A^2 / B) / |V|^2 over the pairs summed, where
+// A = sum L/D, B = sum L^2/D^2, P = number of pairs (L = layout distance,
+// weight 1/D^2).  A sampled estimate takes the pairs (s, j) of chosen
+// sources s with all nodes j reachable from them.  One workgroup per source:
+// breadth-first search over the whole graph (visited set as a bitmap, LDS or
+// global), the distance of every node recorded, then the sums in ascending
+// node id (fixed order: repeatable).
+
+constexpr int ST_BLOCK = 1024;
+
+struct StressArgs {
+    int32_t n, nwords;
+    const int32_t* rp;
+    const int32_t* col;
+    const float2* y;
+    const int32_t* src;
+    int32_t* dist;     // [grid][n], zero on entry, left zero
+    int32_t* queue;    // [grid][n]
+    uint32_t* gbm;     // [grid][nwords] when the bitmap is not in LDS
+    double* out;       // [count][3]: A, B, P
+};
+
+template <bool LDS_BM>
+__global__ __launch_bounds__(ST_BLOCK) void k_stress(StressArgs a) {
+#pragma clang fp contract(off)
+    extern __shared__ uint32_t s_bm[];
+    __shared__ int32_t s_tail;
+    __shared__ double s_red[3][ST_BLOCK / WAVE];
+    uint32_t* bm = LDS_BM ? s_bm : a.gbm + (size_t)blockIdx.x * (size_t)a.nwords;
+    int32_t* dist = a.dist + (size_t)blockIdx.x * (size_t)a.n;
+    int32_t* q = a.queue + (size_t)blockIdx.x * (size_t)a.n;
+    const int tid = threadIdx.x;
+    const int32_t s = a.src[blockIdx.x];
+    for (int w = tid; w < a.nwords; w += ST_BLOCK) bm[w] = 0;
+    if (tid == 0) {
+        q[0] = s;
+        s_tail = 1;
+    }
+    __syncthreads();
+    if (tid == 0) atomicOr(&bm[s >> 5], 1u << (s & 31));
+    __syncthreads();
+    // level by level: frontier q[fb..fe) at distance d, G = 64 lanes per node
+    int32_t fb = 0, fe = 1;
+    for (int32_t d = 1; fb < fe; ++d) {
+        for (int32_t fi = fb + tid / WAVE; fi < fe; fi += ST_BLOCK / WAVE) {
+            const int32_t u = q[fi];
+            for (int32_t x = a.rp[u] + __lane_id(); x < a.rp[u + 1]; x += WAVE) {
+                const int32_t v = a.col[x];
+                const uint32_t bit = 1u << (v & 31);
+                const uint32_t old = atomicOr(&bm[v >> 5], bit);
+                const bool fresh = !(old & bit);
+                if (fresh) dist[v] = d;
+                const uint64_t act = __ballot(1);
+                const uint64_t fm = __ballot(fresh);
+                if (fm) {
+                    const int leader = __ffsll((unsigned long long)act) - 1;
+                    int qpos = 0;
+                    if (__lane_id() == leader) qpos = atomicAdd(&s_tail, __popcll(fm));
+                    qpos = __shfl(qpos, leader);
+                    if (fresh) q[qpos + __popcll(fm & lanemask_lt())] = v;
+                }
+            }
+        }
+        __syncthreads();
+        fb = fe;
+        fe = s_tail;
+        __syncthreads();
+    }
+    // the sums, in ascending node id per thread, then a fixed tree
+    const float2 ps = a.y[s];
+    const double sx = ps.x, sy = ps.y;
+    double A = 0.0, B = 0.0, P = 0.0;
+    for (int32_t j = tid; j < a.n; j += ST_BLOCK) {
+        const int32_t dj = dist[j];
+        if (dj > 0) {
+            dist[j] = 0;
+            const float2 p = a.y[j];
+            const double dx = sx - (double)p.x;
+            const double dy = sy - (double)p.y;
+            const double e = dx * dx;
+            const double f = dy * dy;
+            const double L = sqrt(e + f);
+            const double D = (double)dj;
+            const double r = L / D;
+            A = A + r;
+            B = B + r * r;
+            P = P + 1.0;
+        }
+    }
+    A = group_sum<WAVE>(A);
+    B = group_sum<WAVE>(B);
+    P = group_sum<WAVE>(P);
+    if (__lane_id() == 0) {
+        s_red[0][tid / WAVE] = A;
+        s_red[1][tid / WAVE] = B;
+        s_red[2][tid / WAVE] = P;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double t = 0.0;
+        for (int w = 0; w < ST_BLOCK / WAVE; ++w) t = t + s_red[tid][w];
+        a.out[(size_t)blockIdx.x * 3 + tid] = t;
+    }
+}
+
+void stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
+                    const int32_t* sources, double* out) {
+    if (count < 0) throw Error(DRG_E_INVALID, "count >= 0");
+    if (count == 0) return;
+    if (!y || !sources || !out) throw Error(DRG_E_INVALID, "y, sources and out are required");
+    validate_csr_impl(ctx, g, false);
+    hipStream_t st = ctx->stream;
+    const int32_t n = g->n;
+    DevBuf<int> bad(1);
+    DRG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_check_ids, dim3(ceil_div(count, 256)), dim3(256), 0, st, count, sources,
+                       n, bad.get());
+    DRG_LAUNCH_CHECK();
+    int h = 0;
+    DRG_HIP(hipMemcpyAsync(&h, bad.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    DRG_HIP(hipStreamSynchronize(st));
+    if (h) throw Error(DRG_E_INVALID, "source id out of range");
+    const int nwords = (n + 31) / 32;
+    const size_t lds = (size_t)nwords * 4;
+    const bool in_lds = lds + 4096 <= (size_t)ctx->max_lds;
+    // sources in rounds of at most `per` workgroups (scratch: distances and
+    // queue of n ints each per workgroup)
+    const int32_t per = std::max<int32_t>(1, std::min<int32_t>(ctx->num_cu, count));
+    DevBuf<int32_t> dist((int64_t)per * n);
+    DevBuf<int32_t> queue((int64_t)per * n);
+    DevBuf<uint32_t> gbm;
+    if (!in_lds) gbm.alloc((int64_t)per * nwords);
+    DRG_HIP(hipMemsetAsync(dist.get(), 0, sizeof(int32_t) * (size_t)per * n, st));
+    for (int32_t c0 = 0; c0 < count; c0 += per) {
+        const int32_t m = std::min(per, count - c0);
+        StressArgs a{};
+        a.n = n;
+        a.nwords = nwords;
+        a.rp = g->row_ptr;
+        a.col = g->col;
+        a.y = reinterpret_cast<const float2*>(y);
+        a.src = sources + c0;
+        a.dist = dist.get();
+        a.queue = queue.get();
+        a.gbm = gbm.get();
+        a.out = out + (size_t)c0 * 3;
+        if (in_lds) {
+            DRG_HIP(hipFuncSetAttribute((const void*)k_stress<true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_stress<true>, dim3(m), dim3(ST_BLOCK), lds, st, a);
+        } else {
+            hipLaunchKernelGGL(k_stress<false>, dim3(m), dim3(ST_BLOCK), 0, st, a);
+        }
+        DRG_LAUNCH_CHECK();
+    }
+    DRG_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace drg

@@ -91,6 +91,7 @@ def lib():
         "drg_sim_export": ([_P] + [_P] * 8, st),
         "drg_sim_export_rows": ([_P, C.c_int32, _P, C.c_int64] + [_P] * 7, st),
         "drg_neighbourhood_preservation": ([_P, _P, _P, C.c_int32, _P, _P], st),
+        "drg_stress_sampled": ([_P, C.POINTER(Csr), _P, C.c_int32, _P, _P], st),
         "drg_sim_destroy": ([_P], None),
         "drg_coarsen": ([_P, C.POINTER(Csr), C.c_uint64, C.c_double, C.c_int32, C.c_int32,
                          C.POINTER(_P)], st),
@@ -295,6 +296,22 @@ def drg_neighbourhood_preservation(ctx: Context, sim: Similarity, y, nodes):
                                                 C.c_void_p(out.data_ptr())))
     ctx.synchronize()
     return out
+
+
+def drg_stress_sampled(ctx: Context, row_ptr, col, y, sources):
+    """Per-source stress sums (A, B, P) (Sec. 4.1; see drgraph.h) as a
+    [count, 3] float64 device tensor, and the sampled stress estimate."""
+    import torch
+    g = _csr(row_ptr, col)
+    yp = _dev(y, torch.float32, "y", (g.n, 2))
+    sp = _dev(sources, torch.int32, "sources")
+    out = torch.empty((sources.numel(), 3), dtype=torch.float64, device=y.device)
+    _check(lib().drg_stress_sampled(ctx.h, C.byref(g), yp, int(sources.numel()), sp,
+                                    C.c_void_p(out.data_ptr())))
+    s = out.sum(dim=0).cpu().numpy()
+    n = g.n
+    est = (n / max(1, sources.numel())) * (s[2] - s[0] * s[0] / s[1]) / (n * n) if s[1] > 0 else 0.0
+    return out, float(est)
 
 
 # ------------------------------------------------------------------ hierarchy

@@ -71,3 +71,32 @@ def test_np_bad_nodes_rejected():
     with pytest.raises(d.DrgError) as e:
         d.drg_neighbourhood_preservation(c, sim, y, bad)
     assert e.value.status == d.DRG_E_INVALID
+
+
+@pytest.mark.parametrize("name", ["grid32", "er300", "rmat12", "isolated"])
+def test_stress_sums_match_oracle(oracle_lib, name):
+    """Per-source stress sums (A, B, P) of the GPU search against the
+    oracle's shortest paths: P exact, A and B within 1e-12."""
+    import torch
+    from oracle import evaluate
+    from paper_2008_07799_amd import drgraph as d
+    graphs = {
+        "grid32": gen.grid(32, 32),
+        "er300": gen.random_graph(300, 0.02, seed=1),   # several components
+        "rmat12": gen.rmat(12, 8, seed=3),
+        "isolated": gen.canonical_csr(50, np.array([0, 1, 2, 10, 11]), np.array([1, 2, 3, 11, 12])),
+    }
+    g = graphs[name]
+    say("stress", name)
+    c = ctx()
+    rp, col = dev_graph(g)
+    y = np.random.default_rng(9).uniform(-2, 2, size=(g.n, 2)).astype(np.float32)
+    src = np.random.default_rng(1).choice(g.n, size=min(g.n, 40), replace=False).astype(np.int32)
+    got, est = d.drg_stress_sampled(c, rp, col, to_y(y), torch.from_numpy(src).cuda())
+    got = got.cpu().numpy()
+    want = evaluate.stress_terms(g, y.astype(np.float64), src)
+    assert np.array_equal(got[:, 2], want[:, 2])
+    np.testing.assert_allclose(got[:, :2], want[:, :2], rtol=1e-12, atol=0)
+    ref = evaluate.stress(g, y.astype(np.float64), src)
+    say("  sampled stress", est, ref)
+    assert abs(est - ref) <= 1e-10 * max(1e-30, abs(ref))

@@ -227,3 +227,31 @@ def test_np_per_node_ties_by_id(oracle_lib):
     assert evaluate.np_per_node(y, rp, col, [0])[0] == 1.0      # takes ids 1, 2
     col2 = np.array([3, 4])
     assert evaluate.np_per_node(y, rp, col2, [0])[0] == 0.0     # takes 1, 2: no overlap
+
+
+def test_stress_pins():
+    """Stress (Sec. 4.1): zero for a path laid out on a line at any spacing
+    (the best scale absorbs it); on a random layout the closed form equals a
+    direct minimisation of the paper's sum over alpha."""
+    from scipy.optimize import minimize_scalar
+    from scipy.sparse.csgraph import shortest_path
+    import scipy.sparse as sp
+    from oracle import evaluate
+    n = 12
+    path = gen.canonical_csr(n, np.arange(n - 1), np.arange(1, n), "path")
+    for spacing in (1.0, 2.5):
+        y = np.stack([np.arange(n) * spacing, np.zeros(n)], axis=1)
+        assert abs(evaluate.stress(path, y)) < 1e-12
+    g = gen.random_graph(60, 0.08, seed=3)
+    y = np.random.default_rng(2).uniform(-1, 1, size=(g.n, 2))
+    A = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    D = shortest_path(A, method="D", unweighted=True, directed=False)
+    L = np.sqrt(((y[:, None, :] - y[None, :, :]) ** 2).sum(axis=2))
+    ok = np.isfinite(D) & (D > 0)
+
+    def full(alpha):
+        return (((alpha * L[ok] - D[ok]) ** 2) / D[ok] ** 2).sum() / g.n ** 2
+
+    best = minimize_scalar(full, bounds=(1e-6, 100), method="bounded",
+                           options={"xatol": 1e-12}).fun
+    assert abs(evaluate.stress(g, y) - best) < 1e-9 * max(1.0, best)
