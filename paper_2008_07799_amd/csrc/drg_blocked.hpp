@@ -600,7 +600,7 @@ __device__ __forceinline__ void blk_stage_off(const BlockedArgs& a, int32_t* s_o
 
 // The sweep of one work item (block b, rows r0..r1) once the block's records
 // and the item's row offsets are in LDS: the flat form with F chunks per
-// lane (F = 1, 2, 4, 8), or for F = 0 the row form (a.lanes lanes per
+// lane and batch (F = 2, 4), or for F = 0 the row form (a.lanes lanes per
 // segment, 0: chosen from the item's mean segment length).  s_dyn is the
 // workgroup's dynamic LDS (records, row offsets, wave fragments).
 template <int B, int NH, int F, bool TOGETHER = true>
