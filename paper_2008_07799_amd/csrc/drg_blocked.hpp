@@ -132,7 +132,7 @@ struct ObjValOp {
         const float dx = ri.x - rj.x, dy = ri.y - rj.y;
         const float d2 = dx * dx + dy * dy;
         const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
-        ax += pw * (-log1pf(powi<B>(d2)));
+        ax += pw * (-log1p_fast(powi<B>(d2)));
         (void)ay;
     }
 };

@@ -73,7 +73,7 @@ __device__ __forceinline__ T oh(const ObjArgs<T>& a, uint32_t h) {
 
 template <typename T>
 __device__ __forceinline__ T log1pT(T x) {
-    if constexpr (std::is_same<T, float>::value) return log1pf(x);
+    if constexpr (std::is_same<T, float>::value) return log1p_fast(x);
     else return log1p(x);
 }
 template <typename T>
@@ -211,7 +211,7 @@ __global__ void k_obj_finish(ObjArgs<float> a, int32_t nb, const float2* __restr
         const float d2 = dx * dx + dy * dy;
         if (!(d2 > 0.0f)) continue;
         if constexpr (KIND == 0) {
-            rx += (float)B * logf(d2) - log1pf(opow<B>(d2));
+            rx += (float)B * logf(d2) - log1p_fast(opow<B>(d2));
         } else {
             const float k = (float)(2 * B) / (d2 * (1.0f + opow<B>(d2)));
             rx += k * dx;
