@@ -29,10 +29,6 @@ struct BlockedArgs {
 };
 
 template <int B>
-__device__ __forceinline__ float blk_attract_coef(float d2) {
-    return -2.0f * (float)B * powi<B - 1>(d2) / (1.0f + powi<B>(d2));
-}
-template <int B>
 __device__ __forceinline__ float blk_repel_coef(float d2) {
     return 2.0f * (float)B * rcp_fast(d2 * (1.0f + powi<B>(d2)));
 }
@@ -146,7 +142,7 @@ struct ObjGradOp {
         const float dx = ri.x - rj.x, dy = ri.y - rj.y;
         const float d2 = dx * dx + dy * dy;
         const float pw = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
-        const float k = pw * (float)(-2 * B) * powi<B - 1>(d2) / (1.0f + powi<B>(d2));
+        const float k = pw * (float)(-2 * B) * powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
         ax += k * dx;
         ay += k * dy;
     }

@@ -37,6 +37,13 @@ __device__ __forceinline__ typename OV<T>::v2 mk2o(T a, T b) {
     return r;
 }
 
+// 1/x: the hardware reciprocal in FP32 (1 ulp), division in FP64
+template <typename T>
+__device__ __forceinline__ T orcp(T x) {
+    if constexpr (std::is_same<T, float>::value) return rcp_fast(x);
+    else return T(1) / x;
+}
+
 template <int B, typename T>
 __device__ __forceinline__ T opow(T x) {
     if constexpr (B == 0) return T(1);
@@ -151,7 +158,7 @@ __global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
                 const T dx = yi.x - yj.x, dy = yi.y - yj.y;
                 const T d2 = dx * dx + dy * dy;
                 const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
-                const T k = p * T(-2 * B) * opow<B - 1>(d2) / (T(1) + opow<B>(d2));
+                const T k = p * T(-2 * B) * opow<B - 1>(d2) * orcp(T(1) + opow<B>(d2));
                 ax += k * dx;
                 ay += k * dy;
             }
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
                 const T dx = yi.x - yv.x, dy = yi.y - yv.y;
                 const T d2 = dx * dx + dy * dy;
                 if (d2 > T(0)) {
-                    const T k = T(2 * B) / (d2 * (T(1) + opow<B>(d2)));
+                    const T k = T(2 * B) * orcp(d2 * (T(1) + opow<B>(d2)));
                     rx += k * dx;
                     ry += k * dy;
                 }
@@ -213,7 +220,7 @@ __global__ void k_obj_finish(ObjArgs<float> a, int32_t nb, const float2* __restr
         if constexpr (KIND == 0) {
             rx += (float)B * logf(d2) - log1p_fast(opow<B>(d2));
         } else {
-            const float k = (float)(2 * B) / (d2 * (1.0f + opow<B>(d2)));
+            const float k = (float)(2 * B) * rcp_fast(d2 * (1.0f + opow<B>(d2)));
             rx += k * dx;
             ry += k * dy;
         }
