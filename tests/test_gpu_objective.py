@@ -210,3 +210,45 @@ def test_objective_on_blocked_layout_matches_oracle(oracle_lib, monkeypatch, nam
     grad_r = d.drg_objective_bwd(ctx(), sim, y, **kw).cpu().numpy().astype(np.float64)
     assert abs(loss - loss_r) <= 1e-6 * abs(loss_r)
     assert normwise_rel(grad, grad_r) < 1e-6
+
+
+def test_dynamic_graph_with_temporal_coherence():
+    """A dynamic graph through the autograd form (the paper's Sec. 5 names a
+    temporal-coherence term as the way to handle one): the graph at time t
+    gains edges; starting from the layout of time t-1, Adam on
+    -L^/N_a + lam * mean ||Y^t - Y^{t-1}||^2 (one fixed draw of negatives)
+    keeps the new layout closer to the old one than lam = 0 does, while L^
+    still improves in both runs."""
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    say("dynamic graph")
+    g1 = gen.ba(3000, 3, 0, sub=4)
+    # time t: the same nodes plus 300 random new edges
+    rng = np.random.default_rng(8)
+    u = rng.integers(0, g1.n, 300)
+    v = rng.integers(0, g1.n, 300)
+    rows = np.repeat(np.arange(g1.n), np.diff(g1.row_ptr))
+    g2 = gen.canonical_csr(g1.n, np.concatenate([rows, u]), np.concatenate([g1.col, v]), "ba+")
+    c = ctx()
+    rp1, col1 = dev_graph(g1)
+    y_prev = torch.empty((g1.n, 2), dtype=torch.float32, device="cuda")
+    d.drg_layout(c, rp1, col1, d.layout_params(k=2, M=5, b=1, T=200, seed=1), y_prev)
+    sim2 = _sim(g2, 2)
+    out = {}
+    for lam in (0.0, 10.0):
+        y = y_prev.clone().requires_grad_(True)
+        opt = torch.optim.Adam([y], lr=0.01)
+        # one fixed draw of negatives, so the objective is one smooth function
+        L0 = float(d.objective(y.detach(), c, sim2, M=5, b=1, gamma=0.1, seed=0, iter=0))
+        for it in range(60):
+            opt.zero_grad()
+            L = d.objective(y, c, sim2, M=5, b=1, gamma=0.1, seed=0, iter=0)
+            loss = -L / sim2.n_active + lam * ((y - y_prev) ** 2).sum(dim=1).mean()
+            loss.backward()
+            opt.step()
+        L1 = float(d.objective(y.detach(), c, sim2, M=5, b=1, gamma=0.1, seed=0, iter=0))
+        drift = float(((y.detach() - y_prev) ** 2).sum(dim=1).mean())
+        say("  lam", lam, "objective", L0, "->", L1, "drift", drift)
+        assert L1 > L0
+        out[lam] = drift
+    assert out[10.0] < 0.5 * out[0.0]
