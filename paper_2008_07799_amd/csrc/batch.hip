@@ -137,12 +137,6 @@ __global__ void k_check_union_cols(int32_t N, const int32_t* __restrict__ gid,
     }
 }
 
-__global__ void k_count_active(int32_t N, const int32_t* __restrict__ gid,
-                               const int64_t* __restrict__ prp, int32_t* __restrict__ cnt) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < N && prp[j + 1] > prp[j]) atomicAdd(&cnt[gid[j]], 1);
-}
-
 // ------------------------------------------------------------------ sampling guides
 // Per graph: guide[b] = draw result of the smallest word of bucket b, and
 // guide[2^gbits] that of the largest word (as the single-graph table).
@@ -630,10 +624,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
     std::vector<uint64_t> Cb(count + 1, 0);
     {
         DevBuf<int32_t> cnt(count);
-        DRG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * count, st));
-        hipLaunchKernelGGL(k_count_active, dim3(ceil_div(N, 256)), dim3(256), 0, st, N,
-                           b->gid.get(), s->row_ptr.get(), cnt.get());
-        DRG_LAUNCH_CHECK();
+        count_nonempty_by_group<int64_t>(s->row_ptr.get(), b->gid.get(), N, cnt.get(), count, st);
         DRG_HIP(hipMemcpyAsync(nact.data(), cnt.get(), sizeof(int32_t) * count,
                                hipMemcpyDeviceToHost, st));
         for (int32_t c = 0; c <= count; ++c)

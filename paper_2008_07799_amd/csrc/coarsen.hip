@@ -447,12 +447,6 @@ drg_hier* build_hierarchy(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double 
 }
 
 // ------------------------------------------------------------------ unions
-__global__ void k_count_active_i32(int32_t n, const int32_t* __restrict__ gid,
-                                   const int32_t* __restrict__ rp, int32_t* __restrict__ cnt) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n && rp[v + 1] > rp[v]) atomicAdd(&cnt[gid[v]], 1);
-}
-
 // Keeps the graphs with nb[c] >= 0: node v of graph c becomes nb[c] + (v -
 // ob[c]), its row moves by ne[c] - oe[c] and its columns by nb[c] - ob[c].
 __global__ void k_compact(int32_t n, const int32_t* __restrict__ gid,
@@ -592,10 +586,7 @@ void build_hierarchy_union(drg_ctx* ctx, const drg_csr* g, const int32_t* gid,
             DRG_HIP(hipMemcpyAsync(&rpb[c], g->row_ptr + base[c], sizeof(int32_t),
                                    hipMemcpyDeviceToHost, st));
         DevBuf<int32_t> cnt(count);
-        DRG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * count, st));
-        hipLaunchKernelGGL(k_count_active_i32, dim3(ceil_div(N0, 256)), dim3(256), 0, st, N0, gid,
-                           g->row_ptr, cnt.get());
-        DRG_LAUNCH_CHECK();
+        count_nonempty_by_group<int32_t>(g->row_ptr, gid, N0, cnt.get(), count, st);
         DRG_HIP(hipMemcpyAsync(na.data(), cnt.get(), sizeof(int32_t) * count,
                                hipMemcpyDeviceToHost, st));
         DRG_HIP(hipStreamSynchronize(st));
@@ -676,12 +667,8 @@ void build_hierarchy_union(drg_ctx* ctx, const drg_csr* g, const int32_t* gid,
         std::vector<int32_t> nna(count, 0);
         {
             DevBuf<int32_t> cnt(count);
-            DRG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * count, st));
-            if (nxt.n > 0) {
-                hipLaunchKernelGGL(k_count_active_i32, dim3(ceil_div(nxt.n, 256)), dim3(256), 0,
-                                   st, nxt.n, u.cgid.get(), nxt.rp.get(), cnt.get());
-                DRG_LAUNCH_CHECK();
-            }
+            count_nonempty_by_group<int32_t>(nxt.rp.get(), u.cgid.get(), nxt.n, cnt.get(), count,
+                                             st);
             DRG_HIP(hipMemcpyAsync(nna.data(), cnt.get(), sizeof(int32_t) * count,
                                    hipMemcpyDeviceToHost, st));
         }

@@ -211,4 +211,43 @@ int64_t count_nonempty_rows(const T* rp, int64_t n, hipStream_t s) {
 template int64_t count_nonempty_rows<int32_t>(const int32_t*, int64_t, hipStream_t);
 template int64_t count_nonempty_rows<int64_t>(const int64_t*, int64_t, hipStream_t);
 
+// Lanes of a wave whose rows share a group id add their count with one
+// atomic per run of equal ids (the ids of a union are sorted by graph, so a
+// wave touches one or two counters instead of 64 atomics on one address).
+template <typename T>
+__global__ void k_count_nonempty_by_group(const T* __restrict__ rp, const int32_t* __restrict__ gid,
+                                          int64_t n, int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)__lane_id();
+    const bool in = i < n;
+    const bool ne = in && rp[i + 1] > rp[i];
+    const int32_t g = in ? gid[i] : -1;
+    const int32_t gp = __shfl_up(g, 1);
+    const bool head = in && (lane == 0 || gp != g);
+    const uint64_t heads = __ballot(head);
+    const uint64_t flags = __ballot(ne);
+    if (head) {
+        const uint64_t above = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+        const uint64_t upto = above ? (above & (0ull - above)) - 1ull : ~0ull;
+        const int c = __popcll(flags & upto & (~0ull << lane));
+        if (c) atomicAdd(&cnt[g], c);
+    }
+}
+
+template <typename T>
+void count_nonempty_by_group(const T* rp, const int32_t* gid, int64_t n, int32_t* cnt,
+                             int32_t groups, hipStream_t s) {
+    DRG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(groups, 0), s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_count_nonempty_by_group<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s,
+                           rp, gid, n, cnt);
+        DRG_LAUNCH_CHECK();
+    }
+}
+
+template void count_nonempty_by_group<int32_t>(const int32_t*, const int32_t*, int64_t, int32_t*,
+                                               int32_t, hipStream_t);
+template void count_nonempty_by_group<int64_t>(const int64_t*, const int32_t*, int64_t, int32_t*,
+                                               int32_t, hipStream_t);
+
 }  // namespace drg
