@@ -80,6 +80,30 @@ def _traffic(workload: str, kernel: str):
     return rec.get("bytes_per_launch")
 
 
+# Lane-operation issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz (one wave64 VALU instruction per CU per cycle).
+VALU_LANE_PEAK = 256 * 64 * 2.4e9
+
+
+def _valu_issue(workload: str, kernel: str, avg_ms: float):
+    """VALU issue rate of the launch: wave64 VALU instructions per dispatch
+    from a committed rocprofv3 SQ counter summary (if taken on the current
+    kernel source) x 64 lanes / the launch time measured in this run."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_valu.json")
+    if not os.path.exists(path) or avg_ms <= 0:
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != _kernel_source_hash(kernel):
+        return None
+    lane_ops = rec["counters_per_dispatch"]["SQ_INSTS_VALU"] * 64
+    achieved = lane_ops / (avg_ms / 1000.0)
+    return {"achieved": achieved, "peak": VALU_LANE_PEAK, "unit": "lane-ops/s",
+            "frac": achieved / VALU_LANE_PEAK,
+            "lane_slots_per_pair": rec["valu_lane_slots_per_pair"],
+            "counter_issue_per_cu_cycle": rec["valu_insts_per_cu_cycle"]}
+
+
 def _copy_bandwidth(mib: int = 4096) -> float:
     """Bandwidth of a plain device-to-device copy (bytes read + written per
     second, GB/s), HIP events around 8 copies of a `mib` MiB buffer."""
@@ -498,6 +522,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _traffic(args.workload, kernel),
+                     "valu_issue": _valu_issue(args.workload, kernel, avg_ms),
                      "kernel": kernel, "launches": launches, "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
