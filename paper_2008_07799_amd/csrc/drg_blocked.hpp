@@ -105,8 +105,14 @@ struct LayoutOp {
     __device__ __forceinline__ void operator()(const float4& ri, const float4& rj, uint32_t u,
                                                bool valid, float& ax, float& ay) const {
         const float dx = ri.x - rj.x, dy = ri.y - rj.y;
-        const float d2 = dx * dx + dy * dy;
-        const float p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
+        float p;
+        if constexpr (B == 1) {
+            // 1 + d^2 as two FMAs: d^2 alone is not needed
+            p = rcp_fast(fmaf(dx, dx, fmaf(dy, dy, 1.0f)));
+        } else {
+            const float d2 = dx * dx + dy * dy;
+            p = powi<B - 1>(d2) * rcp_fast(1.0f + powi<B>(d2));
+        }
         const float w = valid ? hop_weight<NH>(hw, u) * (ri.z + rj.z) : 0.0f;
         if constexpr (CLIP) {
             ax += w * clampf(p * dx, a->clip);
@@ -416,7 +422,11 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                     hy = ay;
                     hopen = false;
                 } else {
-                    close_row(i, ax, ay);  // started and ended inside this lane
+                    // started and ended inside this lane, so it is not the
+                    // wave's open first row: stored directly (32-bit offset)
+                    *reinterpret_cast<float2*>(reinterpret_cast<char*>(P) +
+                                               (uint32_t)i * (uint32_t)sizeof(float2)) =
+                        make_float2(ax, ay);
                 }
                 do {
                     ++i;
