@@ -14,7 +14,10 @@ Prints one JSON line.  Extra objects:
   roofline     -- the iteration sweep kernel against the HBM peak, with the
                   algorithmic bytes 16 nnz + 16 M N_a + 28 N per launch and the
                   launch duration measured with HIP events on the library's
-                  stream over the timed region;
+                  stream over the timed region; `traffic` (HBM bytes per launch)
+                  and `valu_issue` (VALU lane-operations per second against the
+                  issue peak) come from committed rocprofv3 counter summaries
+                  and are null unless those were taken on the current sources;
   cpu_baseline -- the FP64 oracle, single-threaded, timed on a bounded sample
                   of the same workload family.
 """
