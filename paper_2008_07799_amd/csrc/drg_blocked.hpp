@@ -231,6 +231,24 @@ __device__ __forceinline__ void blk_rows(const BlockedArgs& a, const float4* s_r
     }
 }
 
+// Lane moves by DPP (register crossbar, no LDS): a lane reads the value of
+// another lane of the wave; a lane with no source lane, or outside the rows
+// enabled by RM, reads 0.
+constexpr int DPP_ROW_SHR = 0x110;      // + d: lane - d of the same 16-lane row
+constexpr int DPP_WAVE_SHR1 = 0x138;    // lane - 1 of the wave
+constexpr int DPP_ROW_BCAST15 = 0x142;  // lane 15 of the previous row (rows 1, 3: RM 0xA)
+constexpr int DPP_ROW_BCAST31 = 0x143;  // lane 31 (rows 2, 3: RM 0xC)
+
+template <int CTRL, int RM>
+__device__ __forceinline__ int32_t lane_dpp(int32_t v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, RM, 0xF, false);
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ float lane_dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, 0xF, false));
+}
+
 // ------------------------------------------------------------------ flat form
 // The entries of an item (rows r0..r1 of block b) are contiguous, so the
 // item is swept as one stream regardless of row boundaries: wave w takes a
@@ -498,23 +516,31 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                 hy = c_y + hy;
             }
         }
-        // keyed inclusive scan of the lanes' last-row partials
-        const int32_t tk = has ? i : -2 - lane;
+        // keyed inclusive scan of the lanes' last-row partials (keys are
+        // row + 1, or a distinct negative value for a lane without entries;
+        // never 0, the key a lane reads when it has no source lane)
+        const int32_t tk = has ? i + 1 : -1 - lane;
         float sx = ax, sy = ay;
-#pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1) {
-            const float ox = __shfl_up(sx, d), oy = __shfl_up(sy, d);
-            const int32_t ok = __shfl_up(tk, d);
-            if (lane >= d && ok == tk) {
+        auto scan_step = [&](auto ctrl_c, auto rows_c) {
+            constexpr int C = decltype(ctrl_c)::value, RM = decltype(rows_c)::value;
+            const int32_t ok = lane_dpp<C, RM>(tk);
+            const float ox = lane_dpp<C, RM>(sx), oy = lane_dpp<C, RM>(sy);
+            if (ok == tk) {
                 sx = ox + sx;
                 sy = oy + sy;
             }
-        }
+        };
+        scan_step(std::integral_constant<int, DPP_ROW_SHR + 1>{}, std::integral_constant<int, 0xF>{});
+        scan_step(std::integral_constant<int, DPP_ROW_SHR + 2>{}, std::integral_constant<int, 0xF>{});
+        scan_step(std::integral_constant<int, DPP_ROW_SHR + 4>{}, std::integral_constant<int, 0xF>{});
+        scan_step(std::integral_constant<int, DPP_ROW_SHR + 8>{}, std::integral_constant<int, 0xF>{});
+        scan_step(std::integral_constant<int, DPP_ROW_BCAST15>{}, std::integral_constant<int, 0xA>{});
+        scan_step(std::integral_constant<int, DPP_ROW_BCAST31>{}, std::integral_constant<int, 0xC>{});
         // a first row that ended inside the lane: add what earlier lanes hold
-        const float px = __shfl_up(sx, 1), py = __shfl_up(sy, 1);
-        const int32_t pk = __shfl_up(tk, 1);
+        const float px = lane_dpp<DPP_WAVE_SHR1, 0xF>(sx), py = lane_dpp<DPP_WAVE_SHR1, 0xF>(sy);
+        const int32_t pk = lane_dpp<DPP_WAVE_SHR1, 0xF>(tk);
         if (has && !hopen) {
-            const bool cin = lane > 0 && pk == hrow;
+            const bool cin = lane > 0 && pk == hrow + 1;
             close_row(hrow, cin ? px + hx : hx, cin ? py + hy : hy);
         }
         // the last row: complete unless it goes on past this lane (into the
@@ -522,10 +548,11 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         const bool cont = has && nxt > pl;
         if (has && !cont) close_row(i, sx, sy);
         // carry of the window's last lane
-        const int32_t L = nl - 1;
-        const bool lcont = __shfl(cont ? 1 : 0, L) != 0;
-        const int32_t lrow = __shfl(i, L);
-        const float lx = __shfl(sx, L), ly = __shfl(sy, L);
+        const int32_t L = __builtin_amdgcn_readfirstlane(nl - 1);  // wave-uniform
+        const bool lcont = __builtin_amdgcn_readlane(cont ? 1 : 0, L) != 0;
+        const int32_t lrow = __builtin_amdgcn_readlane(i, L);
+        const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), L));
+        const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), L));
         c_row = lcont ? lrow : -1;
         c_x = lcont ? lx : 0.0f;
         c_y = lcont ? ly : 0.0f;
