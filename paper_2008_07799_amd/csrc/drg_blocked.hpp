@@ -278,15 +278,20 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t lo, int32_
     return lo;
 }
 
-// largest i in [lo, hi] with off[i] <= p, given off[lo] <= p: doubling steps
-// from lo, then bisection (cheap when the answer is near lo)
-__device__ __forceinline__ int32_t row_from(const int32_t* off, int32_t lo, int32_t hi, int32_t p) {
-    int32_t step = 1;
-    while (lo + step <= hi && off[lo + step] <= p) {
-        lo += step;
-        step <<= 1;
+// largest i in [lo, hi] with off[i] <= p, given off[lo] <= p, for
+// wave-uniform lo, hi, p (all lanes active): the wave tests the next 64
+// offsets at once; as off is non-decreasing, those at most p form a prefix,
+// so the answer is lo plus its length (one LDS read per 64 rows)
+__device__ __forceinline__ int32_t row_from_wave(const int32_t* off, int32_t lo, int32_t hi,
+                                                 int32_t p) {
+    const int lane = __lane_id();
+    while (true) {
+        const int32_t j = lo + 1 + lane;
+        const bool le = j <= hi && off[j] <= p;
+        const int c = __popcll(__ballot(le));
+        if (c < WAVE) return lo + c;
+        lo += WAVE;
     }
-    return row_of(off, lo, min(lo + step - 1, hi), p);
 }
 
 // TOGETHER = false: the next window's second batch is requested only when
@@ -348,8 +353,8 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
     auto win_rows = [&](int64_t w, int32_t lo, int32_t& i0, int32_t& i1) {
         const int32_t wp0 = max((int32_t)(8 * w - bbase), e0);
         const int32_t wp1 = min((int32_t)(8 * min(w + WCH, wc1) - bbase), e1) - 1;
-        i0 = row_from(s_off, lo, nr - 1, wp0);
-        i1 = row_from(s_off, i0, nr - 1, wp1);
+        i0 = row_from_wave(s_off, lo, nr - 1, wp0);
+        i1 = row_from_wave(s_off, i0, nr - 1, wp1);
     };
     // The records of the first ROW_CACHE rows of a window sit in the wave's
     // LDS cache (x, y, z arrays), so a lane that moves on to the next row
