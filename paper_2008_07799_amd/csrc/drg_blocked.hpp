@@ -435,11 +435,24 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
         const int32_t hrow = i;
         bool hopen = true;  // still on the lane's first row
         int32_t qn = nxt - pbase;  // slot where the current row ends
+        // If the first row ends inside the lane's slots, the row that follows
+        // (the one holding position nxt) and its record are found now, by all
+        // such lanes together, so that the first row change in the slots
+        // below only moves registers (a later one, rare, searches itself).
+        bool pre = has && nxt < pl;
+        int32_t i2 = i, nxt2 = nxt;
+        float4 r2 = ri;
+        if (pre) {
+            do {
+                ++i2;
+                nxt2 = s_off[i2 + 1];
+            } while (nxt >= nxt2);
+            r2 = load_row(i2);
+        }
         // the pair of slot Q (entry u, column record rj), after closing the
         // rows that end before it
         auto slot = [&](int32_t Q, bool valid, uint32_t u, const float4& rj) {
             if (valid && Q >= qn) {  // the row ends before this slot
-                const int32_t p = pbase + Q;
                 if (hopen) {
                     hx = ax;
                     hy = ay;
@@ -451,12 +464,22 @@ __device__ __forceinline__ void blk_flat(const BlockedArgs& a, const Op& op, con
                                                (uint32_t)i * (uint32_t)sizeof(float2)) =
                         make_float2(ax, ay);
                 }
-                do {
-                    ++i;
-                    nxt = s_off[i + 1];
-                } while (p >= nxt);
+                if (pre) {
+                    // valid slots are consecutive, so this slot is at
+                    // position nxt: the row found above
+                    i = i2;
+                    nxt = nxt2;
+                    ri = r2;
+                    pre = false;
+                } else {
+                    const int32_t p = pbase + Q;
+                    do {
+                        ++i;
+                        nxt = s_off[i + 1];
+                    } while (p >= nxt);
+                    ri = load_row(i);
+                }
                 qn = nxt - pbase;
-                ri = load_row(i);
                 ax = 0.0f;
                 ay = 0.0f;
             }
