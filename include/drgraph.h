@@ -48,10 +48,14 @@ typedef int32_t drg_status;
 #define DRG_VALIDATE 1u      /* flag: validate the input CSR on the device */
 
 #define DRG_MODE_SYNC 0      /* Jacobi: all steps from one snapshot, deterministic */
-#define DRG_MODE_ASYNC 1     /* Hogwild: steps applied in place while others read;
-                                on a similarity with the column-blocked copy
-                                (drg_sim_info's `blocked`) the FP32 step runs
-                                the synchronous sweep in both modes */
+#define DRG_MODE_ASYNC 1     /* Hogwild: steps applied in place while others read */
+
+/* Sweep forms of the FP32 layout step (drg_ctx_last_sweep) */
+#define DRG_SWEEP_ROW 0           /* a group of lanes per row, gathered records */
+#define DRG_SWEEP_WINDOW 1        /* same sums, records staged in LDS windows */
+#define DRG_SWEEP_BLOCKED 2       /* column-blocked copy, LDS-staged blocks */
+#define DRG_SWEEP_ROW_ASYNC 3     /* Hogwild, a group of lanes per row */
+#define DRG_SWEEP_BLOCKED_ASYNC 4 /* Hogwild on the column-blocked copy */
 
 typedef struct drg_ctx drg_ctx;
 typedef struct drg_sim drg_sim;
@@ -127,6 +131,9 @@ drg_status drg_ctx_synchronize(drg_ctx* ctx);
  * summed duration in milliseconds since the last reset. */
 drg_status drg_ctx_set_profiling(drg_ctx* ctx, int32_t on);
 drg_status drg_ctx_kernel_stats(drg_ctx* ctx, int64_t* launches, double* total_ms);
+/* *form = the DRG_SWEEP_* form that the latest drg_layout_step (or layout
+ * run) on this context launched, -1 before the first. */
+drg_status drg_ctx_last_sweep(const drg_ctx* ctx, int32_t* form);
 
 /* Sparse distance matrix and node similarity (Sec. 3.2.1, Eq. NS):
  * for every node i the set NNG(i, k) = {j != i : SPD(i, j) <= k} with hop

@@ -200,7 +200,8 @@ __global__ void k_b_init(int32_t total, int32_t count, const int32_t* __restrict
 __global__ void k_b_stage(int32_t N, int32_t count, int32_t t, const int32_t* __restrict__ gid,
                           const BGraph* __restrict__ gt, const BLevel* __restrict__ lt,
                           const BSched* __restrict__ sched, const float* __restrict__ invZ,
-                          const float2* __restrict__ y, float4* __restrict__ rec) {
+                          const float* __restrict__ invZlo, const float2* __restrict__ y,
+                          float4* __restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int32_t c = gid[j];
@@ -210,7 +211,7 @@ __global__ void k_b_stage(int32_t N, int32_t count, int32_t t, const int32_t* __
     const BLevel d = lt[g.lv_off + l];
     const int32_t v = (int32_t)j - g.base;
     const float2 p = y[d.yoff + (l == 0 ? v : d.cmap[v])];
-    rec[j] = mk4<float>(p.x, p.y, invZ[j], 0.0f);
+    rec[j] = mk4<float>(p.x, p.y, invZ[j], invZlo[j]);
 }
 
 struct BSweepArgs {
@@ -225,7 +226,7 @@ struct BSweepArgs {
     const uint64_t* C;
     const int32_t* guide;
     float2* g;
-    HalfE<float> eh;
+    HalfE<double> eh;
 };
 
 template <int B, bool CLIP>
@@ -236,7 +237,7 @@ __device__ __forceinline__ float2 b_row(const BSweepArgs& a, const BGraph& g, in
                                [&](uint64_t w) {
                                    return g.base + draw_in_graph(w, a.C, a.guide, g);
                                },
-                               gamma * a.qt[i]);
+                               (double)gamma * (double)a.qt[i]);
 }
 
 // Graph c owns waves woff[c] .. woff[c+1]-1; each handles 64/G consecutive
@@ -289,7 +290,7 @@ struct BWinArgs {
     const uint64_t* C;
     const int32_t* guide;
     float2* g;
-    HalfE<float> eh;
+    HalfE<double> eh;
 };
 
 template <int RPL>
@@ -912,8 +913,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
     sa.C = s->C.get();
     sa.guide = b->guide.get();
     sa.g = s->g.get();
-    sa.eh = HalfE<float>{(float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]), (float)(0.5 * s->e[2]),
-                         (float)(0.5 * s->e[3])};
+    sa.eh = HalfE<double>{0.5 * s->e[0], 0.5 * s->e[1], 0.5 * s->e[2], 0.5 * s->e[3]};
     const int64_t sweep_blocks = std::max<int64_t>(1, ((int64_t)woff[count] + 3) / 4);
     BWinArgs wa{};
     wa.count = count;
@@ -984,7 +984,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         DRG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_b_stage, dim3(ceil_div(N, 256)), dim3(256), 0, st, N, count, 0,
                            b->gid.get(), b->gt.get(), b->lt.get(), b->sched.get(), s->invZf.get(),
-                           b->y.get(), s->rec.get());
+                           s->invZlo.get(), b->y.get(), s->rec.get());
         DRG_LAUNCH_CHECK();
         hipEvent_t e0, e1;
         DRG_HIP(hipEventCreate(&e0));
@@ -1039,7 +1039,7 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             prolong_rounds(t);
             hipLaunchKernelGGL(k_b_stage, dim3(ceil_div(N, 256)), dim3(256), 0, cap, N, count, t,
                                b->gid.get(), b->gt.get(), b->lt.get(), b->sched.get(),
-                               s->invZf.get(), b->y.get(), s->rec.get());
+                               s->invZf.get(), s->invZlo.get(), b->y.get(), s->rec.get());
             DRG_LAUNCH_CHECK();
             if (b->blk_count < count) launch_form(b->form, t, cap);
             launch_blocked(t, cap);

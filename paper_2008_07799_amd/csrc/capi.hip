@@ -143,6 +143,14 @@ drg_status drg_ctx_kernel_stats(drg_ctx* ctx, int64_t* launches, double* total_m
     });
 }
 
+drg_status drg_ctx_last_sweep(const drg_ctx* ctx, int32_t* form) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(form, "form");
+        *form = ctx->last_sweep;
+    });
+}
+
 drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, double sigma,
                                 uint32_t flags, drg_sim** out) {
     return guarded([&] {

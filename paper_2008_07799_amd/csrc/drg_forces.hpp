@@ -122,7 +122,11 @@ struct HalfE {
 };
 
 // Attraction of one pattern entry e (record rj) on the node with record ri,
-// added to the lane's partial (ax, ay).  Coincident nodes contribute nothing;
+// added to the lane's partial (ax, ay).  Records hold (x, y, 1/Z high part,
+// 1/Z low part) in the coordinate type T; the pair's arithmetic and the
+// partials are FP64 whatever T is: these row forms are bound by the gathers,
+// not by arithmetic, and FP64 terms keep the FP32 trajectory within the
+// rounding of its stored coordinates.  Coincident nodes contribute nothing;
 // no test is needed for that: at d2 = 0 the coefficient is finite (-2b for
 // b = 1, -0 otherwise) and dx = dy = +0, so both terms are zeros, which leave
 // the partial's value unchanged.  CLIP = false when the clip cannot bind
@@ -130,17 +134,18 @@ struct HalfE {
 // argument, so it is left out and the weight is folded into k first.
 template <typename T, int B, bool CLIP = true>
 __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
-                                             const typename VT<T>::v4& rj, const HalfE<T>& eh,
-                                             T clip, T& ax, T& ay) {
-    const T dx = ri.x - rj.x, dy = ri.y - rj.y;
-    const T d2 = dx * dx + dy * dy;
-    const T k = attract_coef<B>(d2);
-    const T w = eh(e >> 30) * (ri.z + rj.z);
+                                             const typename VT<T>::v4& rj, const HalfE<double>& eh,
+                                             double clip, double& ax, double& ay) {
+    const double dx = (double)ri.x - (double)rj.x, dy = (double)ri.y - (double)rj.y;
+    const double d2 = dx * dx + dy * dy;
+    const double k = attract_coef<B, double>(d2);
+    const double zi = (double)ri.z + (double)ri.w, zj = (double)rj.z + (double)rj.w;
+    const double w = eh(e >> 30) * (zi + zj);
     if constexpr (CLIP) {
         ax += w * clampT2(k * dx, clip);
         ay += w * clampT2(k * dy, clip);
     } else {
-        const T wk = w * k;
+        const double wk = w * k;
         ax += wk * dx;
         ay += wk * dy;
     }
@@ -151,30 +156,32 @@ template <typename T, int B, typename Draw>
 __device__ __forceinline__ void repel_lane(const typename VT<T>::v4& ri,
                                            const typename VT<T>::v4* __restrict__ rec, int lane,
                                            int G, int M, uint64_t seed, uint64_t iter, int32_t key,
-                                           Draw draw, T clip, T& rx, T& ry) {
-    rx = T(0);
-    ry = T(0);
+                                           Draw draw, double clip, double& rx, double& ry) {
+    rx = 0.0;
+    ry = 0.0;
     for (int m = lane; m < M; m += G) {
         const uint64_t w = neg_word(seed, iter, key, m);
         const typename VT<T>::v4 rv = rec[draw(w)];
-        const T dx = ri.x - rv.x, dy = ri.y - rv.y;
-        const T d2 = dx * dx + dy * dy;
-        if (d2 > T(0)) {
-            const T k = repel_coef<B>(d2);
-            rx += repelT(k, dx, clip);
-            ry += repelT(k, dy, clip);
+        const double dx = (double)ri.x - (double)rv.x, dy = (double)ri.y - (double)rv.y;
+        const double d2 = dx * dx + dy * dy;
+        if (d2 > 0.0) {
+            const double k = repel_coef<B, double>(d2);
+            rx += clampT2(k * dx, clip);
+            ry += clampT2(k * dy, clip);
         }
     }
 }
 
-// Butterfly sums over the group, then g_i = attraction + gq * repulsion.
+// Butterfly sums over the group, then g_i = attraction + gq * repulsion,
+// rounded once to the coordinate type.
 template <typename T>
-__device__ __forceinline__ typename VT<T>::v2 row_total(T ax, T ay, T rx, T ry, int G, T gq) {
+__device__ __forceinline__ typename VT<T>::v2 row_total(double ax, double ay, double rx,
+                                                        double ry, int G, double gq) {
     ax = group_sum_rt(ax, G);
     ay = group_sum_rt(ay, G);
     rx = group_sum_rt(rx, G);
     ry = group_sum_rt(ry, G);
-    return mk2<T>(ax + gq * rx, ay + gq * ry);
+    return mk2<T>((T)(ax + gq * rx), (T)(ay + gq * ry));
 }
 
 // One row of the sweep, computed by the G lanes of a group (lane = 0..G-1):
@@ -187,10 +194,10 @@ template <typename T, int B, bool CLIP, typename Draw>
 __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
     const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
-    const HalfE<T>& eh, T clip, int M, uint64_t seed, uint64_t iter, int32_t key, Draw draw,
-    T gq) {
+    const HalfE<double>& eh, double clip, int M, uint64_t seed, uint64_t iter, int32_t key,
+    Draw draw, double gq) {
     using v4 = typename VT<T>::v4;
-    T ax = T(0), ay = T(0);
+    double ax = 0.0, ay = 0.0;
     // U entries per step; the next step's entries are loaded while this
     // step's records are gathered and used (the terms still go in order)
     constexpr int U = 4;
@@ -224,7 +231,7 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
         const uint32_t e = colhop[x];
         attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, ax, ay);
     }
-    T rx, ry;
+    double rx, ry;
     repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, rx, ry);
     return row_total<T>(ax, ay, rx, ry, G, gq);
 }
@@ -249,20 +256,20 @@ template <int B, bool CLIP, int RPL, int BLOCK, typename Draw, typename Key>
 __device__ __forceinline__ void window_item(
     const WinItem& it, int G, float4* __restrict__ lds, int CH,
     const int64_t* __restrict__ prp, const uint32_t* __restrict__ colhop,
-    const float4* __restrict__ rec, const float* __restrict__ qt, const HalfE<float>& eh,
-    float clip, int M, uint64_t seed, uint64_t iter, float gamma, Draw draw, Key key,
+    const float4* __restrict__ rec, const float* __restrict__ qt, const HalfE<double>& eh,
+    double clip, int M, uint64_t seed, uint64_t iter, double gamma, Draw draw, Key key,
     float2* __restrict__ g) {
     const int tid = threadIdx.x;
     const int NG = BLOCK / G;
     const int lane = tid % G, grp = tid / G;
-    float ax[RPL], ay[RPL];
+    double ax[RPL], ay[RPL];
     int64_t xs[RPL], xe[RPL];
     float4 ri[RPL];
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
         const int32_t r = grp + k * NG;
-        ax[k] = 0.0f;
-        ay[k] = 0.0f;
+        ax[k] = 0.0;
+        ay[k] = 0.0;
         xs[k] = 0;
         xe[k] = 0;
         if (r < it.nrows) {
@@ -281,7 +288,7 @@ __device__ __forceinline__ void window_item(
         for (int k = 0; k < RPL; ++k) {
             int64_t x = xs[k];
             const int64_t e_end = xe[k];
-            float sx = ax[k], sy = ay[k];
+            double sx = ax[k], sy = ay[k];
             constexpr int U = 4;  // entry loads in flight; past-the-end slots read a sentinel
             while (x < e_end) {
                 uint32_t e[U];
@@ -312,9 +319,9 @@ __device__ __forceinline__ void window_item(
         const int64_t i = (int64_t)it.r0 + r;
         float2 gi = make_float2(0.0f, 0.0f);
         if (prp[i] < prp[i + 1]) {
-            float rx, ry;
+            double rx, ry;
             repel_lane<float, B>(ri[k], rec, lane, G, M, seed, iter, key(i), draw, clip, rx, ry);
-            gi = row_total<float>(ax[k], ay[k], rx, ry, G, gamma * qt[i]);
+            gi = row_total<float>(ax[k], ay[k], rx, ry, G, gamma * (double)qt[i]);
         }
         if (lane == 0) g[i] = gi;
     }

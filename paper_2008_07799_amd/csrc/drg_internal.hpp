@@ -16,6 +16,7 @@ struct drg_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     int64_t launches = 0;
     double total_ms = 0.0;
+    int32_t last_sweep = -1;  // DRG_SWEEP_* form of the latest layout step
 };
 
 // Sparse similarity P~ over the finest graph plus the sampling table.
@@ -35,6 +36,7 @@ struct drg_sim {
     int gbits = 1;
     uint64_t S = 0;                  // = C[n]
     drg::DevBuf<float> invZf;        // [n]
+    drg::DevBuf<float> invZlo;       // [n] 1/Z - invZf (so hi + lo holds 1/Z to ~48 bits)
     drg::DevBuf<float> qtf;          // [n]
     // per-iteration workspace of the layout step
     drg::DevBuf<float4> rec;         // [n] staged (y_c(j), invZ_j)
@@ -49,6 +51,10 @@ struct drg_sim {
     drg::DevBuf<uint16_t> blk_ent;   // [nnz] local col | (hop-1) << 13
     drg::DevBuf<int4> blk_items;     // (block, first row, end row)
     drg::DevBuf<float2> blk_partial; // [nb][n] partial attraction
+    // Hogwild form on the blocked layout (built on first use)
+    int32_t blk_nwin = 0;
+    drg::DevBuf<int32_t> blk_async_order;  // launch slot -> item, in window order
+    drg::DevBuf<uint32_t> blk_wneed, blk_wcnt;  // per row window: items touching it, counted
     // work items of the windowed sweep (built on first use)
     drg::DevBuf<drg::WinItem> win_items;
     int32_t win_n = 0, win_rpl = 0;
@@ -134,6 +140,9 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
                    uint64_t seed, uint64_t iter, float2* g, hipEvent_t e0, hipEvent_t e1);
 // The objective's attraction terms per (block, row) into s->blk_partial from
 // coordinates y: kind 0 = row values, 1 = attraction gradients.
+void sweep_blocked_async(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
+                         float eta, uint64_t seed, uint64_t iter, float* y, const int32_t* cmap,
+                         const float* w, hipEvent_t e0, hipEvent_t e1);
 void sweep_blocked_objective(drg_ctx* ctx, drg_sim* s, int b, const float* y, int kind);
 // objective.hip
 template <typename T>

@@ -40,14 +40,16 @@ __global__ void k_prolong(int32_t n, const int32_t* __restrict__ map,
     if (u < n) yf[u] = yl[map[u]];
 }
 
+// invZlo (FP32 records only, else NULL): 1/Z_j - (float)(1/Z_j), so the
+// record carries 1/Z_j to about 48 bits for the FP64 pair arithmetic.
 template <typename T>
 __global__ void k_stage(int32_t n0, const int32_t* __restrict__ cmap,
                         const typename VT<T>::v2* __restrict__ y, const T* __restrict__ invZ,
-                        typename VT<T>::v4* __restrict__ rec) {
+                        const float* __restrict__ invZlo, typename VT<T>::v4* __restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n0) return;
     const typename VT<T>::v2 p = y[cmap ? cmap[j] : (int32_t)j];
-    rec[j] = mk4<T>(p.x, p.y, invZ[j], T(0));
+    rec[j] = mk4<T>(p.x, p.y, invZ[j], invZlo ? (T)invZlo[j] : T(0));
 }
 
 template <typename T>
@@ -65,7 +67,7 @@ struct SweepArgs {
     const int32_t* guide;
     int32_t gbits;
     uint64_t S;
-    T eh0, eh1, eh2, eh3;  // e_d / 2
+    double eh0, eh1, eh2, eh3;  // e_d / 2
     T gamma, clip;
     int32_t noclip;        // the attraction clip cannot bind (attract_clip_free)
     uint64_t seed, iter;
@@ -79,7 +81,7 @@ struct SweepArgs {
 
 template <typename T>
 __device__ __forceinline__ T half_e(const SweepArgs<T>& a, uint32_t h) {
-    return h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
+    return (T)(h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3)));
 }
 
 template <typename T, int B, int G>
@@ -87,19 +89,20 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
     const int lane = threadIdx.x % G;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
-    const HalfE<T> eh{a.eh0, a.eh1, a.eh2, a.eh3};
+    const HalfE<double> eh{a.eh0, a.eh1, a.eh2, a.eh3};
     auto rows = [&](auto clip_c) {
         constexpr bool CLIP = decltype(clip_c)::value;
         for (int64_t i = grp; i < a.n0; i += ngrp) {
             const int64_t rs = a.prp[i], re = a.prp[i + 1];
             typename VT<T>::v2 gi = mk2<T>(T(0), T(0));
             if (rs < re)
-                gi = sweep_row<T, B, CLIP>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh, a.clip,
+                gi = sweep_row<T, B, CLIP>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh,
+                                           (double)a.clip,
                                            a.M, a.seed, a.iter, (int32_t)i,
                                            [&](uint64_t w) {
                                                return draw_node(w, a.C, a.guide, a.gbits, a.S);
                                            },
-                                           a.gamma * a.qt[i]);
+                                           (double)a.gamma * (double)a.qt[i]);
             if (lane == 0) a.g[i] = gi;
         }
     };
@@ -114,7 +117,7 @@ template <int B, int RPL>
 __global__ __launch_bounds__(WIN_BLOCK) void k_sweep_win(const WinItem* __restrict__ items, int G,
                                                          int CH, SweepArgs<float> a) {
     extern __shared__ float4 s_rec[];
-    const HalfE<float> eh{a.eh0, a.eh1, a.eh2, a.eh3};
+    const HalfE<double> eh{a.eh0, a.eh1, a.eh2, a.eh3};
     const WinItem it = items[xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x)];
     auto draw = [&](uint64_t w) { return draw_node(w, a.C, a.guide, a.gbits, a.S); };
     auto key = [&](int64_t i) { return (int32_t)i; };
@@ -355,10 +358,10 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.guide = s->guide.get();
     a.gbits = s->gbits;
     a.S = s->S;
-    a.eh0 = (T)(0.5 * s->e[0]);
-    a.eh1 = (T)(0.5 * s->e[1]);
-    a.eh2 = (T)(0.5 * s->e[2]);
-    a.eh3 = (T)(0.5 * s->e[3]);
+    a.eh0 = 0.5 * s->e[0];
+    a.eh1 = 0.5 * s->e[1];
+    a.eh2 = 0.5 * s->e[2];
+    a.eh3 = 0.5 * s->e[3];
     a.gamma = (T)p->gamma;
     a.clip = (T)p->clip;
     a.noclip = attract_clip_free(p->b, p->clip) ? 1 : 0;
@@ -369,12 +372,11 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.invZ = invZ;
     a.eta = (T)p->eta;
     const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
-    // On the column-blocked layout both modes run the synchronous sweep: the
-    // snapshot it stages costs well under 1% of an iteration there, and the
-    // Hogwild kernel's global gathers and atomics are an order of magnitude
-    // slower than the LDS-staged sweep.
+    // Both modes stage the records on the column-blocked layout: its Hogwild
+    // form reads neighbours from LDS copies of the records and updates them
+    // in place as windows of rows finish.
     const bool blocked = F32 && s->blk_nb > 0;
-    const bool async = p->mode == DRG_MODE_ASYNC && !blocked;
+    const bool async = p->mode == DRG_MODE_ASYNC;
     if (async) {
         if (level == 0) {
             a.w = qt;
@@ -386,9 +388,11 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
             DRG_LAUNCH_CHECK();
             a.w = reinterpret_cast<const T*>(s->wlev.get());
         }
-    } else {
+    }
+    if (!async || blocked) {
         hipLaunchKernelGGL(k_stage<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, cmap,
-                           reinterpret_cast<const v2*>(y), invZ, rec);
+                           reinterpret_cast<const v2*>(y), invZ, F32 ? s->invZlo.get() : nullptr,
+                           rec);
         DRG_LAUNCH_CHECK();
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -397,8 +401,16 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
         DRG_HIP(hipEventCreate(&e1));
     }
     if constexpr (F32) {
+        if (blocked && async) {
+            sweep_blocked_async(ctx, s, p->b, a.M, a.gamma, a.clip, a.eta, a.seed, a.iter, y,
+                                cmap, a.w, e0, e1);
+            if (ctx->profiling) ctx->events.emplace_back(e0, e1);
+            ctx->last_sweep = DRG_SWEEP_BLOCKED_ASYNC;
+            return;
+        }
         if (blocked) {
             // LDS-staged sweep over the column-blocked pattern
+            ctx->last_sweep = DRG_SWEEP_BLOCKED;
             sweep_blocked(ctx, s, p->b, a.M, a.gamma, a.clip, a.seed, a.iter, g, e0, e1);
             if (ctx->profiling) ctx->events.emplace_back(e0, e1);
             if (level == 0) {
@@ -426,6 +438,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
             win = s->win_n > 0;
         }
     }
+    ctx->last_sweep = async ? DRG_SWEEP_ROW_ASYNC : (win ? DRG_SWEEP_WINDOW : DRG_SWEEP_ROW);
     if (ctx->profiling) DRG_HIP(hipEventRecord(e0, st));
     if (win) {
         if constexpr (F32) {

@@ -339,7 +339,8 @@ struct ECoef {
 // Z_i = sum_d cnt_i(d) e_d accumulated from zero in hop order, every
 // operation rounded on its own; invZ_i = 1 / Z_i (0 for an isolated node).
 __global__ void k_normalise(int32_t n, int32_t k, const int32_t* __restrict__ cnt, ECoef ec,
-                            double* __restrict__ invZ, float* __restrict__ invZf) {
+                            double* __restrict__ invZ, float* __restrict__ invZf,
+                            float* __restrict__ invZlo) {
 #pragma clang fp contract(off)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -351,7 +352,9 @@ __global__ void k_normalise(int32_t n, int32_t k, const int32_t* __restrict__ cn
     }
     const double iz = z > 0.0 ? 1.0 / z : 0.0;
     invZ[i] = iz;
-    invZf[i] = (float)iz;
+    const float hi = (float)iz;
+    invZf[i] = hi;
+    invZlo[i] = (float)(iz - (double)hi);  // exact difference, rounded once
 }
 
 // P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2.  Per row: W_i = sum_j trunc(P~_ij 2^32)
@@ -648,12 +651,13 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     }
     s->invZ.alloc(n);
     s->invZf.alloc(n);
+    s->invZlo.alloc(n);
     s->qt.alloc(n);
     s->qtf.alloc(n);
     s->W.alloc(n);
     s->C.alloc((int64_t)n + 1);
     hipLaunchKernelGGL(k_normalise, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k, cnt.get(), ec,
-                       s->invZ.get(), s->invZf.get());
+                       s->invZ.get(), s->invZf.get(), s->invZlo.get());
     DRG_LAUNCH_CHECK();
     const double mean_len = (double)s->nnz / (double)n;
     if (u) {

@@ -25,6 +25,11 @@ DRG_E_UNSUPPORTED = -5
 DRG_VALIDATE = 1
 DRG_MODE_SYNC = 0
 DRG_MODE_ASYNC = 1
+DRG_SWEEP_ROW = 0
+DRG_SWEEP_WINDOW = 1
+DRG_SWEEP_BLOCKED = 2
+DRG_SWEEP_ROW_ASYNC = 3
+DRG_SWEEP_BLOCKED_ASYNC = 4
 
 
 class DrgError(RuntimeError):
@@ -84,6 +89,7 @@ def lib():
         "drg_ctx_synchronize": ([_P], st),
         "drg_ctx_set_profiling": ([_P, C.c_int32], st),
         "drg_ctx_kernel_stats": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)], st),
+        "drg_ctx_last_sweep": ([_P, C.POINTER(C.c_int32)], st),
         "drg_build_similarity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double, C.c_uint32,
                                   C.POINTER(_P)], st),
         "drg_sim_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -183,6 +189,12 @@ class Context:
         ms = C.c_double()
         _check(lib().drg_ctx_kernel_stats(self.h, C.byref(n), C.byref(ms)))
         return int(n.value), float(ms.value)
+
+    def last_sweep(self) -> int:
+        """DRG_SWEEP_* form launched by the latest layout step (-1: none yet)."""
+        f = C.c_int32()
+        _check(lib().drg_ctx_last_sweep(self.h, C.byref(f)))
+        return int(f.value)
 
 
 def _csr(row_ptr, col) -> Csr:

@@ -205,17 +205,24 @@ def test_fp64_instance_one_step_is_tight(oracle_lib):
     assert err < 1e-12
 
 
+# Step size of the 32x32 grid workload (k=3, M=5, b=3, T=300, one level): the
+# largest of 1, 1/2, 1/3, 1/4 at which the oracle's own 50-iteration
+# trajectory moves by less than a fifth of the 1e-4 bar when its state is
+# rounded to FP32 after every iteration (tests/test_oracle_forces.py measures
+# this on the CPU: 0.78 at 1, 1e-5 at 1/4).
+C1_ETA0 = 0.25
+
+
 @pytest.mark.parametrize("case", ["grid32", "rgg_multilevel", "rmat_multilevel"])
 def test_sync_50_iterations_fp64_instance(oracle_lib, case):
     """50 synchronous iterations of the schedule, FP64 instance vs oracle:
-    grid32 (k=3, M=5, b=3, single level); RGG (k=3, M=10, b=2, three levels,
-    60 iterations so two refinements happen); R-MAT (k=2, M=5, b=1).  On the
-    grid with b=3 a step size of 1 makes the iteration expansive (the radial
-    stiffness of the b=3 force is about 2b), so that case uses eta0 = 1/b."""
+    grid32 (k=3, M=5, b=3, single level, the grid workload's step size); RGG
+    (k=3, M=10, b=2, three levels, 60 iterations so two refinements happen);
+    R-MAT (k=2, M=5, b=1)."""
     say("sync50 fp64", case)
     if case == "grid32":
         y, yr, *_ = _run_steps(oracle_lib, gen.grid(32, 32), 3, 5, 3, 0.1, 50, 300, f64=True,
-                               eta0=1.0 / 3.0)
+                               eta0=C1_ETA0)
     elif case == "rgg_multilevel":
         y, yr, sim, h, *_ = _run_steps(oracle_lib, gen.rgg(20000, 0.0125, seed=4), 3, 10, 2, 0.1,
                                        60, 60, max_levels=3, f64=True)
@@ -230,12 +237,16 @@ def test_sync_50_iterations_fp64_instance(oracle_lib, case):
 
 
 def test_sync_50_iterations_fp32_grid32(oracle_lib):
-    """32x32 grid, k=3, M=5, b=3, single level, eta0 = 1/(2b): FP32 kernels
-    vs the FP64 oracle after 50 iterations.  (At eta0 = 1/b the FP64 run
-    above still tracks the oracle, but the iteration is close to neutral and
-    FP32 rounding grows to a few 1e-4.)"""
+    """The 32x32 grid workload itself (k=3, M=5, b=3, T=300, one level, seed
+    0, sync) on the FP32 product path, at the same step size as the FP64
+    test: within 1e-4 of the FP64 oracle after 50 iterations.  The row-form
+    sweep computes every pair in FP64 from the FP32 records, so the FP32
+    trajectory differs from the oracle's by the rounding of the stored
+    coordinates only."""
+    from paper_2008_07799_amd import drgraph as d
     say("sync50 fp32 grid32")
-    y, yr, *_ = _run_steps(oracle_lib, gen.grid(32, 32), 3, 5, 3, 0.1, 50, 300, eta0=1.0 / 6.0)
+    y, yr, *_ = _run_steps(oracle_lib, gen.grid(32, 32), 3, 5, 3, 0.1, 50, 300, eta0=C1_ETA0)
+    assert ctx().last_sweep() == d.DRG_SWEEP_ROW
     err = normwise_rel(y, yr)
     say("  err", err)
     assert err < 1e-4
@@ -266,27 +277,40 @@ def test_sync_is_deterministic():
     assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy())
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_full_layout_statistics(oracle_lib, mode):
+@pytest.mark.parametrize("case,mode", [("grid32", 0), ("grid32", 1), ("rmat13", 0),
+                                       ("rmat13", 1)])
+def test_full_layout_statistics(oracle_lib, case, mode):
     """End to end (FP32 sync, FP32 async) vs the oracle's sync layout with the
     same parameters: final sampled objective within 1% and NP within 0.01.
-    R-MAT 2^13, edge factor 16, k=2, M=5, b=1, T=300, coarsened until < 1000
-    nodes; across seeds the oracle's own final objective varies by about 0.1%
-    and NP by about 0.0015 on this family, so the bars measure the method."""
+    grid32 is the grid workload (k=3, M=5, b=3, T=300, one level, its step
+    size); its async run is the Hogwild row sweep.  R-MAT 2^13, edge factor
+    16, k=2, M=5, b=1, T=300, coarsened until < 1000 nodes, is above the
+    column-blocked threshold: its async run is the Hogwild form of the
+    blocked sweep.  Across seeds the oracle's own final objective varies by
+    about 0.1% and NP by about 0.0015 on that family.  The form that ran is
+    checked through drg_ctx_last_sweep."""
     from oracle import evaluate
     from paper_2008_07799_amd import drgraph as d
-    say("full layout stats, mode", mode)
-    g = gen.rmat(13, 16, seed=1)
+    say("full layout stats", case, "mode", mode)
+    if case == "grid32":
+        g = gen.grid(32, 32)
+        kw = dict(k=3, M=5, b=3, T=300, max_levels=1, eta0=C1_ETA0)
+        want = d.DRG_SWEEP_ROW_ASYNC if mode else d.DRG_SWEEP_ROW
+    else:
+        g = gen.rmat(13, 16, seed=1)
+        kw = dict(k=2, M=5, b=1, T=300, min_nodes=1000)
+        want = d.DRG_SWEEP_BLOCKED_ASYNC if mode else d.DRG_SWEEP_BLOCKED
     c = ctx()
     rp, col = dev_graph(g)
-    p = d.layout_params(k=2, M=5, b=1, T=300, min_nodes=1000, seed=0, mode=mode)
+    p = d.layout_params(seed=0, mode=mode, **kw)
     y = zeros_y(g.n)
     d.drg_layout(c, rp, col, p, y)
+    assert c.last_sweep() == want
     yg = y.cpu().numpy().astype(np.float64)
-    yr, rsim, _ = oracle_lib.layout(g, k=2, M=5, b=1, T=300, min_nodes=1000, seed=0,
-                                    return_all=True)
-    obj_g = evaluate.objective_eval(rsim, yg, M=5, b=1, gamma=0.1)
-    obj_r = evaluate.objective_eval(rsim, yr, M=5, b=1, gamma=0.1)
+    yr, rsim, _ = oracle_lib.layout(g, seed=0, return_all=True, **kw)
+    M, b = kw["M"], kw["b"]
+    obj_g = evaluate.objective_eval(rsim, yg, M=M, b=b, gamma=0.1)
+    obj_r = evaluate.objective_eval(rsim, yr, M=M, b=b, gamma=0.1)
     np_g = evaluate.neighbourhood_preservation(g, yg)
     np_r = evaluate.neighbourhood_preservation(g, yr)
     say("  objective", obj_g, obj_r, "NP", np_g, np_r)
