@@ -262,6 +262,21 @@ drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h
  * objective, not the step). */
 drg_status drg_objective_fwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
                              const float* y_dev, float* loss_dev, float* rows_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the loss of
+ * drg_objective_fwd (same kernels, same fixed-order sum, so the same bits)
+ * with no allocation of any kind.  Its scratch -- the n row values and the
+ * block sums of the reduction, 4 (2^20 + 2048) bytes -- is a static device
+ * array that each GPU the library runs on holds until the process ends;
+ * every call on a GPU reuses that GPU's array, so calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  The array needs no clearing: every value in it is written before
+ * it is read.  Enqueued on the context's stream, no synchronisation: the
+ * loss is in loss_dev (one device float) once the stream reaches it.
+ * DRG_E_INVALID when the similarity has more than 2^20 nodes (the size of
+ * the static scratch), or for a NULL argument, M < 0 or b outside 1..3. */
+drg_status drg_objective_fwd_noalloc(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                                     const float* y_dev, float* loss_dev);
 /* dy_dev[n][2] = dloss * dL^/dY (exact gradient of the sampled objective).
  * The negatives are drawn again from their counters (nothing is stored by
  * the forward); contributions to a drawn node are summed in a fixed order,

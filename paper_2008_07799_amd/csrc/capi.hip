@@ -330,6 +330,15 @@ drg_status drg_objective_fwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_param
     });
 }
 
+drg_status drg_objective_fwd_noalloc(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
+                                     const float* y_dev, float* loss_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        use_device(ctx->device);
+        drg::objective_fwd_noalloc(ctx, const_cast<drg_sim*>(s), p, y_dev, loss_dev);
+    });
+}
+
 drg_status drg_objective_bwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_params* p,
                              const float* y_dev, const float* dloss_dev, float* dy_dev) {
     return guarded([&] {

@@ -140,6 +140,10 @@ void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float cl
                    uint64_t seed, uint64_t iter, float2* g, hipEvent_t e0, hipEvent_t e1);
 // The objective's attraction terms per (block, row) into s->blk_partial from
 // coordinates y: kind 0 = row values, 1 = attraction gradients.
+// largest similarity (nodes) of the allocation-free objective forward
+constexpr int64_t OBJ_NOALLOC_MAX_N = (int64_t)1 << 20;
+void objective_fwd_noalloc(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const float* y,
+                           float* loss);
 void sweep_blocked_async(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
                          float eta, uint64_t seed, uint64_t iter, float* y, const int32_t* cmap,
                          const float* w, hipEvent_t e0, hipEvent_t e1);

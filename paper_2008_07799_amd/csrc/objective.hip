@@ -14,6 +14,9 @@
 // so the gradient is deterministic.
 #include <cstdlib>
 
+#include <mutex>
+#include <string>
+
 #include "drg_internal.hpp"
 
 namespace drg {
@@ -490,6 +493,64 @@ void objective_bwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T*
     }
     DRG_LAUNCH_CHECK();
     DRG_HIP(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------ no-allocation forward
+// The FP32 forward with its scratch (row values, then the block sums of the
+// fixed-order reduction) in a file-scope device array instead of library
+// allocations.  Host code reaches the array only through the address that
+// hipGetSymbolAddress returns for the current device (kept per device):
+// the array's own name is not a device address in host code.
+constexpr int64_t OBJ_NA_SUMS = (OBJ_NOALLOC_MAX_N + 1023) / 1024;
+static __device__ __align__(256) float scratch[OBJ_NOALLOC_MAX_N + 2 * OBJ_NA_SUMS];
+
+static float* obj_scratch(int device) {
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static float* addr[MAXDEV] = {};
+    if (device < 0 || device >= MAXDEV) throw Error(DRG_E_UNSUPPORTED, "objective: device id >= 64");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t rc = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (rc != hipSuccess || !p)
+            throw Error(DRG_E_DEVICE, std::string("objective: hipGetSymbolAddress: ") +
+                                          hipGetErrorString(rc));
+        addr[device] = static_cast<float*>(p);
+    }
+    return addr[device];
+}
+
+void objective_fwd_noalloc(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const float* y,
+                           float* loss) {
+    check_obj(s, p, y);
+    if (!loss) throw Error(DRG_E_INVALID, "objective: loss is NULL");
+    if ((int64_t)s->n > OBJ_NOALLOC_MAX_N)
+        throw Error(DRG_E_INVALID, "objective (no allocation): n = " + std::to_string(s->n) +
+                                       " exceeds the static scratch of " +
+                                       std::to_string(OBJ_NOALLOC_MAX_N) + " nodes");
+    float* base = obj_scratch(ctx->device);  // ctx->device is current
+    hipStream_t st = ctx->stream;
+    ObjArgs<float> a = obj_args<float>(s, p, y);
+    a.row_val = base;  // every row is written, isolated rows with 0
+    obj_rows<float>(ctx, s, p, a, false);
+    // the same fixed-order reduction as objective_fwd_t, ping-ponging
+    // between the two block-sum areas after the row values
+    float* buf1 = base + OBJ_NOALLOC_MAX_N;
+    float* buf2 = buf1 + OBJ_NA_SUMS;
+    int64_t m = s->n;
+    const float* src = a.row_val;
+    float* dst = buf1;
+    while (true) {
+        const int64_t nb = (m + 1023) / 1024;
+        hipLaunchKernelGGL(k_sum_blocks<float>, dim3((unsigned)nb), dim3(1024), 0, st, m, src,
+                           nb == 1 ? loss : dst);
+        DRG_LAUNCH_CHECK();
+        if (nb == 1) break;
+        src = dst;
+        dst = (dst == buf1) ? buf2 : buf1;
+        m = nb;
+    }
 }
 
 template void objective_fwd_t<float>(drg_ctx*, drg_sim*, const drg_obj_params*, const float*, float*, float*);

@@ -113,6 +113,7 @@ def lib():
         "drg_layout_run": ([_P, _P, _P, C.POINTER(LayoutParams), _P], st),
         "drg_objective_fwd": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
         "drg_objective_bwd": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
+        "drg_objective_fwd_noalloc": ([_P, _P, C.POINTER(ObjParams), _P, _P], st),
         "drg_objective_fwd_f64": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
         "drg_objective_bwd_f64": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
         "drg_sample_negatives": ([_P, _P, C.c_int32, C.c_uint64, C.c_uint64, _P], st),
@@ -511,6 +512,18 @@ def drg_objective_fwd(ctx: Context, sim: Similarity, y, *, M=5, b=1, gamma=0.1, 
     optr = C.c_void_p(out.data_ptr())
     _check(fn(ctx.h, sim.h, C.byref(p), ptr, None if rows else optr, optr if rows else None))
     return out
+
+
+def drg_objective_fwd_noalloc(ctx: Context, sim: Similarity, y, loss, *, M=5, b=1, gamma=0.1,
+                              seed=0, iter=0):
+    """The FP32 loss of drg_objective_fwd written into the caller's 0-d float32
+    device tensor `loss`, with no allocation in the library (static scratch,
+    at most 2^20 nodes); enqueued only: synchronise before reading it."""
+    import torch
+    yp = _dev(y, torch.float32, "y", (sim.n, 2))
+    lp = _dev(loss, torch.float32, "loss", ())
+    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter))
+    _check(lib().drg_objective_fwd_noalloc(ctx.h, sim.h, C.byref(p), yp, lp))
 
 
 def drg_objective_bwd(ctx: Context, sim: Similarity, y, dloss=None, *, M=5, b=1, gamma=0.1,
