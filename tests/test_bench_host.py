@@ -52,3 +52,22 @@ def test_valu_issue_rate(monkeypatch):
     monkeypatch.setattr(bench, "_kernel_source_hash", lambda k: "changed")
     assert bench._valu_issue("rmat20_k2", "k_sweep_blocked", 20.0) is None
 
+
+
+def test_roofline_is_a_fraction_of_the_binding_roof(monkeypatch):
+    """The blocked sweep is priced at its 15 VALU lane-instructions per stored
+    pair against 256 CUs x 64 lanes x 2.4 GHz; the 16-bytes-per-pair
+    convention is kept apart, since it exceeds the HBM peak by design.  A
+    row-form sweep is priced against HBM with the algorithmic bytes."""
+    monkeypatch.setattr(bench, "_kernel_source_hash", lambda k: "none")
+    nnz, na, n, M = 23762699968, 646140, 1048576, 5
+    r = bench.roofline("rmat20_k2", "k_sweep_blocked", 18.7, 500, nnz, na, n, M, 1, 4500.0)
+    assert r["bound"] == "alu" and r["traffic"] is None
+    assert r["achieved"] == pytest.approx(15 * nnz / 0.0187 / 1e12)
+    assert r["peak"] == pytest.approx(256 * 64 * 2.4e9 / 1e12)
+    assert 0.0 < r["frac"] < 1.0
+    assert r["convention"]["frac_of_8TBs"] > 1.0
+    r = bench.roofline("rmat20_k1", "k_sweep", 0.79, 500, 31_400_000, na, n, M, 1, 4500.0)
+    assert r["bound"] == "hbm"
+    want = (16.0 * 31_400_000 + 16.0 * M * na + 28.0 * n) / 0.00079 / 1e9
+    assert r["achieved"] == pytest.approx(want) and r["frac"] == pytest.approx(want / 8000.0)
