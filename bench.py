@@ -573,7 +573,7 @@ def main():
     alg_bytes = 16.0 * nnz + 16.0 * M * n_active + 28.0 * n
     form = ctx.last_sweep()
     kernel = {d.DRG_SWEEP_BLOCKED: "k_sweep_blocked",
-              d.DRG_SWEEP_BLOCKED_ASYNC: "k_sweep_blocked_async",
+              d.DRG_SWEEP_BLOCKED_ASYNC: "k_sweep_blocked+k_finish_inplace (async stages)",
               d.DRG_SWEEP_ROW_ASYNC: "k_sweep_async",
               d.DRG_SWEEP_WINDOW: "k_sweep_win"}.get(form, "k_sweep")
     ran_mode = "async" if form in (d.DRG_SWEEP_BLOCKED_ASYNC, d.DRG_SWEEP_ROW_ASYNC) else "sync"

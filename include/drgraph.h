@@ -55,7 +55,7 @@ typedef int32_t drg_status;
 #define DRG_SWEEP_WINDOW 1        /* same sums, records staged in LDS windows */
 #define DRG_SWEEP_BLOCKED 2       /* column-blocked copy, LDS-staged blocks */
 #define DRG_SWEEP_ROW_ASYNC 3     /* Hogwild, a group of lanes per row */
-#define DRG_SWEEP_BLOCKED_ASYNC 4 /* Hogwild on the column-blocked copy */
+#define DRG_SWEEP_BLOCKED_ASYNC 4 /* column-blocked copy, rows moved per row stage */
 
 typedef struct drg_ctx drg_ctx;
 typedef struct drg_sim drg_sim;
@@ -234,7 +234,11 @@ drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const flo
  *   sync : y_a += eta * (sum_{c(i)=a} g_i) / (sum_{c(i)=a} qt_i), all g_i from
  *          one snapshot (deterministic, bit-for-bit repeatable);
  *   async: eta * g_i / (sum_{c(j)=c(i)} qt_j) is added to y_c(i) as soon as g_i
- *          is computed, while other nodes read y (Hogwild-style).
+ *          is computed, while other nodes read y (Hogwild-style: not
+ *          repeatable).  On a similarity with the column-blocked copy the
+ *          rows are cut into DRG_ASYNC_STAGES (environment, default 4)
+ *          equal ranges, moved range by range once all their pairs are
+ *          summed; later ranges see the moves of earlier ones.
  * h may be NULL for level 0.  y_level_dev: [n_level][2], in/out. */
 drg_status drg_layout_step(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                            const drg_step_params* p, float* y_level_dev);

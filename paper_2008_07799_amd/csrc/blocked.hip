@@ -179,97 +179,64 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
     a.g[i] = gi;
 }
 
-// ------------------------------------------------------------------ Hogwild form
+// ------------------------------------------------------------------ asynchronous form
 // Asynchronous iteration on the blocked layout.  The rows are cut into
-// windows of ASYNC_WIN rows; the work items are launched in window order
-// (every item of window w before any item whose first row lies in a later
-// window), and each window counts the items that touch it.  The workgroup
-// whose item completes a window finishes that window's rows on the spot:
-// partials summed in block order, negatives drawn from the live records,
-// and the step applied in place to the coordinates and to the records that
-// items launched later stage into LDS.  Later windows thus see the earlier
-// windows' new positions within the same iteration (Gauss-Seidel across
-// windows, Hogwild within one: which updates a workgroup sees depends on
-// timing, so runs are not repeatable).
-constexpr int32_t ASYNC_WIN = ROWCAP;  // an item spans at most two windows
-
-struct AsyncArgs {
-    const int32_t* order;      // launch slot -> item
-    uint32_t* wcnt;            // per window: items counted so far (0 between launches)
-    const uint32_t* wneed;     // per window: items that touch it
-    int32_t nb, M;
-    const int64_t* prp;
+// ASYNC_STAGES equal ranges; the work items run stage by stage (an item
+// belongs to the stage of its first row), and after the items of stage s
+// the rows of stage s are finished and moved at once: their partials are
+// complete (every item that holds part of them belongs to stage s or an
+// earlier one), the negatives are gathered from the live records, and the
+// new positions go straight into the coordinates and into the records that
+// the following stages stage into LDS.  Later stages therefore see the
+// moves of earlier ones within the same iteration, and the rows finished
+// together read and write each other's records without order (Hogwild).
+// Finishing per work item instead needs a device-wide cache write-back
+// and invalidate per item to pass partials between XCDs, which cost more
+// than half an iteration on R-MAT 2^20.
+struct FinishInPlaceArgs {
+    FinishArgs f;
+    int32_t r0, r1;            // rows of the stage
     float4* rec;               // live records (x, y, 1/Z, 1/Z low part)
-    const float* qt;
-    const uint64_t* C;
-    const int32_t* guide;
-    int32_t gbits;
-    uint64_t S;
-    float gamma, clip, eta;
-    uint64_t seed, iter;
     float2* y;                 // level coordinates, updated in place
     const int32_t* cmap;       // finest node -> level node (NULL at level 0)
     const float* w;            // anchor weight of each level node
+    float eta;
 };
 
 template <int B>
-__device__ void blk_async_window(const BlockedArgs& a, const AsyncArgs& h, int32_t win) {
-    __threadfence();  // acquire: the other items' partials of this window
-    const int32_t r0 = win * ASYNC_WIN, r1 = min(a.n0, r0 + ASYNC_WIN);
-    auto draw = [&](uint64_t w) { return draw_node(w, h.C, h.guide, h.gbits, h.S); };
-    for (int32_t i = r0 + (int32_t)threadIdx.x; i < r1; i += STREAM_BLOCK) {
-        if (h.prp[i + 1] == h.prp[i]) continue;  // isolated: never moves
-        const float4 ri = h.rec[i];
-        const float2 gi = blk_finish_row<B>(a.partial, h.nb, a.n0, i, h.rec, ri, h.M, h.seed,
-                                            h.iter, i, draw, h.gamma * h.qt[i], h.clip);
-        if (!h.cmap) {
-            const float wi = h.qt[i];
-            const float nx = ri.x + h.eta * (gi.x / wi), ny = ri.y + h.eta * (gi.y / wi);
-            h.y[i] = make_float2(nx, ny);
-            h.rec[i] = make_float4(nx, ny, ri.z, ri.w);
-        } else {
-            const int32_t c = h.cmap[i];
-            const float wc = h.w[c];
-            if (wc > 0.0f) {
-                atomicAdd(&h.y[c].x, h.eta * (gi.x / wc));
-                atomicAdd(&h.y[c].y, h.eta * (gi.y / wc));
-            }
+__global__ __launch_bounds__(256) void k_finish_inplace(FinishInPlaceArgs a) {
+    const int64_t i = (int64_t)a.r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.r1 || a.f.prp[i + 1] == a.f.prp[i]) return;  // isolated: never moves
+    const FinishArgs& f = a.f;
+    const float4 ri = a.rec[i];
+    const float2 gi =
+        blk_finish_row<B>(f.partial, f.nb, f.n0, (int32_t)i, a.rec, ri, f.M, f.seed, f.iter,
+                          (int32_t)i,
+                          [&](uint64_t w) { return draw_node(w, f.C, f.guide, f.gbits, f.S); },
+                          f.gamma * f.qt[i], f.clip);
+    if (!a.cmap) {
+        const float wi = f.qt[i];
+        const float nx = ri.x + a.eta * (gi.x / wi), ny = ri.y + a.eta * (gi.y / wi);
+        a.y[i] = make_float2(nx, ny);
+        a.rec[i] = make_float4(nx, ny, ri.z, ri.w);
+    } else {
+        const int32_t c = a.cmap[i];
+        const float wc = a.w[c];
+        if (wc > 0.0f) {
+            atomicAdd(&a.y[c].x, a.eta * (gi.x / wc));
+            atomicAdd(&a.y[c].y, a.eta * (gi.y / wc));
         }
     }
-    if (h.cmap) {
-        // the window's records follow their level nodes as they stand now
-        __syncthreads();
-        __threadfence();
-        for (int32_t i = r0 + (int32_t)threadIdx.x; i < r1; i += STREAM_BLOCK) {
-            const float4 ri = h.rec[i];
-            const float2 p = h.y[h.cmap[i]];
-            h.rec[i] = make_float4(p.x, p.y, ri.z, ri.w);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) h.wcnt[win] = 0u;  // ready for the next launch
 }
 
-template <int B, int NH, int F>
-__global__ __launch_bounds__(STREAM_BLOCK) void k_sweep_blocked_async(BlockedArgs a, AsyncArgs h) {
-    extern __shared__ float4 s_dyn[];
-    __shared__ int32_t s_fin[2];
-    const int4 it = a.items[h.order[blockIdx.x]];
-    blk_layout_item<B, NH, F>(a, s_dyn, it.x, it.y, it.z);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_fin[0] = -1;
-        s_fin[1] = -1;
-        if (it.z > it.y) {
-            __threadfence();  // release this item's partials
-            const int32_t w0 = it.y / ASYNC_WIN, w1 = (it.z - 1) / ASYNC_WIN;
-            for (int32_t w = w0; w <= w1; ++w)
-                if (atomicAdd(&h.wcnt[w], 1u) + 1u == h.wneed[w]) s_fin[w - w0] = w;
-        }
-    }
-    __syncthreads();
-    for (int q = 0; q < 2; ++q)
-        if (s_fin[q] >= 0) blk_async_window<B>(a, h, s_fin[q]);
+// records of every finest node from its level node's current position
+__global__ void k_restage_xy(int32_t n0, const int32_t* __restrict__ cmap,
+                             const float2* __restrict__ y, float4* __restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n0) return;
+    const float2 p = y[cmap[j]];
+    const float4 r = rec[j];
+    rec[j] = make_float4(p.x, p.y, r.z, r.w);
 }
 
 // ------------------------------------------------------------------ host
@@ -468,58 +435,34 @@ void sweep_blocked_objective(drg_ctx* ctx, drg_sim* s, int b, const float* y, in
     throw Error(DRG_E_INVALID, "objective: b in 1..3");
 }
 
-// Launch order and window counts of the Hogwild form, built on first use:
-// items sorted by (window of their first row, block, first row).
+// Work items of the asynchronous form, built on first use: the items
+// sorted by (stage of their first row, block, first row), and where each
+// stage's items begin.
+static int async_stages() { return std::min(64, std::max(1, env_int("DRG_ASYNC_STAGES", 4))); }
+
 static void build_async_order(drg_ctx* ctx, drg_sim* s) {
+    const int S = async_stages();
     std::vector<int4> items(s->blk_nitems);
     DRG_HIP(hipMemcpyAsync(items.data(), s->blk_items.get(), sizeof(int4) * items.size(),
                            hipMemcpyDeviceToHost, ctx->stream));
     DRG_HIP(hipStreamSynchronize(ctx->stream));
-    const int32_t nwin = ceil_div(s->n, ASYNC_WIN);
-    std::vector<int32_t> order(items.size());
-    for (size_t t = 0; t < order.size(); ++t) order[t] = (int32_t)t;
-    auto win_of = [&](const int4& it) { return it.y / ASYNC_WIN; };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
-        const int4 &A = items[p], &Bq = items[q];
-        if (win_of(A) != win_of(Bq)) return win_of(A) < win_of(Bq);
-        if (A.x != Bq.x) return A.x < Bq.x;
-        return A.y < Bq.y;
+    auto stage_of = [&](int32_t row) { return (int32_t)(((int64_t)row * S) / s->n); };
+    std::stable_sort(items.begin(), items.end(), [&](const int4& p, const int4& q) {
+        const int32_t sp = stage_of(p.y), sq = stage_of(q.y);
+        if (sp != sq) return sp < sq;
+        if (p.x != q.x) return p.x < q.x;
+        return p.y < q.y;
     });
-    std::vector<uint32_t> need(nwin, 0u);
-    for (const int4& it : items) {
-        if (it.z <= it.y) continue;
-        const int32_t w1 = (it.z - 1) / ASYNC_WIN;
-        if (w1 - it.y / ASYNC_WIN > 1) throw Error(DRG_E_DEVICE, "async sweep: item spans > 2 windows");
-        for (int32_t w = it.y / ASYNC_WIN; w <= w1; ++w) ++need[w];
-    }
-    s->blk_async_order.alloc((int64_t)order.size());
-    s->blk_wneed.alloc(nwin);
-    s->blk_wcnt.alloc(nwin);
-    DRG_HIP(hipMemcpyAsync(s->blk_async_order.get(), order.data(), sizeof(int32_t) * order.size(),
+    s->blk_stage_first.assign(S + 1, 0);
+    for (const int4& it : items) ++s->blk_stage_first[stage_of(it.y) + 1];
+    for (int t = 0; t < S; ++t) s->blk_stage_first[t + 1] += s->blk_stage_first[t];
+    s->blk_items_async.alloc((int64_t)items.size());
+    DRG_HIP(hipMemcpyAsync(s->blk_items_async.get(), items.data(), sizeof(int4) * items.size(),
                            hipMemcpyHostToDevice, ctx->stream));
-    DRG_HIP(hipMemcpyAsync(s->blk_wneed.get(), need.data(), sizeof(uint32_t) * nwin,
-                           hipMemcpyHostToDevice, ctx->stream));
-    DRG_HIP(hipMemsetAsync(s->blk_wcnt.get(), 0, sizeof(uint32_t) * nwin, ctx->stream));
     DRG_HIP(hipStreamSynchronize(ctx->stream));
-    s->blk_nwin = nwin;
+    s->blk_stages = S;
 }
 
-template <int B, int NH>
-static void launch_blocked_async_b(drg_ctx* ctx, const BlockedArgs& a, const AsyncArgs& h,
-                                   int nitems) {
-    const size_t lds = blk_lds_bytes(a.bits);
-    const int form = blk_form(a.flat);
-    auto fn = form == 4   ? k_sweep_blocked_async<B, NH, 4>
-              : form == 2 ? k_sweep_blocked_async<B, NH, 2>
-                          : k_sweep_blocked_async<B, NH, 0>;
-    DRG_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    hipLaunchKernelGGL(fn, dim3(nitems), dim3(STREAM_BLOCK), lds, ctx->stream, a, h);
-    DRG_LAUNCH_CHECK();
-}
-
-// The sweep and finish of one synchronous FP32 iteration on the blocked
-// layout.  `g` non-null: write the steps (coarse level); else update y.
 static BlockedArgs layout_args(drg_sim* s, int b, float clip) {
     BlockedArgs a{};
     a.n0 = s->n;
@@ -541,48 +484,73 @@ static BlockedArgs layout_args(drg_sim* s, int b, float clip) {
     return a;
 }
 
-// One Hogwild iteration on the blocked layout (records already staged from
-// y): the sweep finishes every window in place, no further launch.
+// One asynchronous iteration on the blocked layout (records already staged
+// from y): per stage, the sweep of its work items, then its rows finished
+// and moved in place; at a coarse level the records of all finest nodes then
+// follow their level nodes.
 void sweep_blocked_async(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
                          float eta, uint64_t seed, uint64_t iter, float* y, const int32_t* cmap,
                          const float* w, hipEvent_t e0, hipEvent_t e1) {
-    if (s->blk_nwin == 0) build_async_order(ctx, s);
-    const BlockedArgs a = layout_args(s, b, clip);
-    AsyncArgs h{};
-    h.order = s->blk_async_order.get();
-    h.wcnt = s->blk_wcnt.get();
-    h.wneed = s->blk_wneed.get();
-    h.nb = s->blk_nb;
-    h.M = s->S > 0 ? M : 0;
-    h.prp = s->row_ptr.get();
-    h.rec = s->rec.get();
-    h.qt = s->qtf.get();
-    h.C = s->C.get();
-    h.guide = s->guide.get();
-    h.gbits = s->gbits;
-    h.S = s->S;
-    h.gamma = gamma;
-    h.clip = clip;
-    h.eta = eta;
-    h.seed = seed;
-    h.iter = iter;
-    h.y = reinterpret_cast<float2*>(y);
-    h.cmap = cmap;
-    h.w = w;
+    if (s->blk_stages == 0) build_async_order(ctx, s);
+    BlockedArgs a = layout_args(s, b, clip);
+    FinishInPlaceArgs fa{};
+    fa.f.n0 = s->n;
+    fa.f.nb = s->blk_nb;
+    fa.f.M = s->S > 0 ? M : 0;
+    fa.f.prp = s->row_ptr.get();
+    fa.f.partial = s->blk_partial.get();
+    fa.f.rec = s->rec.get();
+    fa.f.qt = s->qtf.get();
+    fa.f.C = s->C.get();
+    fa.f.guide = s->guide.get();
+    fa.f.gbits = s->gbits;
+    fa.f.S = s->S;
+    fa.f.gamma = gamma;
+    fa.f.clip = clip;
+    fa.f.seed = seed;
+    fa.f.iter = iter;
+    fa.rec = s->rec.get();
+    fa.y = reinterpret_cast<float2*>(y);
+    fa.cmap = cmap;
+    fa.w = w;
+    fa.eta = eta;
+    const int S = s->blk_stages;
     if (e0) DRG_HIP(hipEventRecord(e0, ctx->stream));
-#define DRG_BLKA(BB)                                                                   \
+    for (int t = 0; t < S; ++t) {
+        const int32_t i0 = s->blk_stage_first[t], i1 = s->blk_stage_first[t + 1];
+        a.items = s->blk_items_async.get() + i0;
+        if (i1 > i0) {
+#define DRG_BLK(BB)                                                                    \
     case BB:                                                                           \
-        if (s->k == 1) launch_blocked_async_b<BB, 1>(ctx, a, h, s->blk_nitems);        \
-        else if (s->k == 2) launch_blocked_async_b<BB, 2>(ctx, a, h, s->blk_nitems);   \
-        else launch_blocked_async_b<BB, 4>(ctx, a, h, s->blk_nitems);                  \
+        if (s->k == 1) launch_blocked_b<BB, 1>(ctx, a, i1 - i0);                       \
+        else if (s->k == 2) launch_blocked_b<BB, 2>(ctx, a, i1 - i0);                  \
+        else launch_blocked_b<BB, 4>(ctx, a, i1 - i0);                                 \
         break;
-    switch (b) {
-        DRG_BLKA(1)
-        DRG_BLKA(2)
-        default:
-        DRG_BLKA(3)
+            switch (b) {
+                DRG_BLK(1)
+                DRG_BLK(2)
+                default:
+                DRG_BLK(3)
+            }
+#undef DRG_BLK
+        }
+        fa.r0 = (int32_t)(((int64_t)t * s->n) / S);
+        fa.r1 = (int32_t)(((int64_t)(t + 1) * s->n) / S);
+        if (fa.r1 > fa.r0) {
+            const dim3 grid(ceil_div(fa.r1 - fa.r0, 256));
+            switch (b) {
+                case 1: hipLaunchKernelGGL(k_finish_inplace<1>, grid, dim3(256), 0, ctx->stream, fa); break;
+                case 2: hipLaunchKernelGGL(k_finish_inplace<2>, grid, dim3(256), 0, ctx->stream, fa); break;
+                default: hipLaunchKernelGGL(k_finish_inplace<3>, grid, dim3(256), 0, ctx->stream, fa); break;
+            }
+            DRG_LAUNCH_CHECK();
+        }
+        if (cmap && t + 1 < S) {
+            hipLaunchKernelGGL(k_restage_xy, dim3(ceil_div(s->n, 256)), dim3(256), 0, ctx->stream,
+                               s->n, cmap, fa.y, s->rec.get());
+            DRG_LAUNCH_CHECK();
+        }
     }
-#undef DRG_BLKA
     if (e1) DRG_HIP(hipEventRecord(e1, ctx->stream));
 }
 

@@ -51,10 +51,11 @@ struct drg_sim {
     drg::DevBuf<uint16_t> blk_ent;   // [nnz] local col | (hop-1) << 13
     drg::DevBuf<int4> blk_items;     // (block, first row, end row)
     drg::DevBuf<float2> blk_partial; // [nb][n] partial attraction
-    // Hogwild form on the blocked layout (built on first use)
-    int32_t blk_nwin = 0;
-    drg::DevBuf<int32_t> blk_async_order;  // launch slot -> item, in window order
-    drg::DevBuf<uint32_t> blk_wneed, blk_wcnt;  // per row window: items touching it, counted
+    // asynchronous form on the blocked layout (built on first use): the work
+    // items sorted by row stage, and the first item of each stage
+    int32_t blk_stages = 0;
+    drg::DevBuf<int4> blk_items_async;
+    std::vector<int32_t> blk_stage_first;
     // work items of the windowed sweep (built on first use)
     drg::DevBuf<drg::WinItem> win_items;
     int32_t win_n = 0, win_rpl = 0;

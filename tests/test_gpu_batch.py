@@ -180,3 +180,60 @@ def test_bad_batches_are_rejected():
     y = torch.empty((g1.n + g2.n, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(ValueError):
         d.drg_layout_batched(ctx(), devs, d.layout_params(k=2), y[:-1])
+
+
+def test_batch_matches_oracle_layouts(oracle_lib):
+    """Every graph of a mixed batch against the oracle's own layout of that
+    graph (drgo.layout, FP64) with the same parameters: one-level and
+    multilevel graphs, exponents 1..3, different seeds and iteration counts,
+    an isolated node.  Coordinates within 1e-4 normwise on the graphs whose
+    trajectory is conditioned for it (grids and random geometric graphs:
+    the oracle's own FP32-rounded run stays within ~1e-5); the power-law
+    graph (Barabasi-Albert, b = 1), whose trajectory amplifies rounding to
+    O(0.05) within 30 iterations, by final objective within 1% and NP within
+    0.01."""
+    import torch
+    from oracle import evaluate
+    from paper_2008_07799_amd import drgraph as d
+    f32 = lambda v: float(np.float32(v))  # noqa: E731  (parameters cross the ABI as FP32)
+    cases = [  # graph, k, b, T, eta0, min_nodes, seed, compare
+        (gen.grid_deleted(700, 0.05, 0, sub=0), 3, 3, 30, 0.25, 200, 101, "coords"),
+        (gen.rgg(3000, 0.04, seed=1), 3, 2, 30, 0.5, 200, 102, "coords"),
+        (gen.grid(32, 32), 3, 3, 20, 0.25, 1 << 30, 103, "coords"),
+        (gen.canonical_csr(40, np.arange(0, 38), np.arange(1, 39)), 2, 2, 25, 0.5, 10, 104,
+         "coords"),
+        (gen.ba(1500, 3, 0, sub=1), 2, 1, 150, 1.0, 200, 105, "stats"),
+    ]
+    devs, params = [], []
+    for g, k, b, T, eta0, mn, seed, _ in cases:
+        devs.append(dev_graph(g))
+        params.append(d.layout_params(k=k, M=5, b=b, T=T, eta0=eta0, min_nodes=mn, seed=seed))
+    ks = {c[1] for c in cases}
+    batches = []
+    for k in sorted(ks):  # k is one per batch (one union similarity)
+        idx = [i for i, c in enumerate(cases) if c[1] == k]
+        batch = d.drg_batch_create(ctx(), [devs[i] for i in idx], [params[i] for i in idx])
+        y = torch.empty((batch.n_total, 2), dtype=torch.float32, device="cuda")
+        batch.run(ctx(), y)
+        batches.append((idx, batch, y.cpu().numpy()))
+    for idx, batch, got in batches:
+        for pos, i in enumerate(idx):
+            g, k, b, T, eta0, mn, seed, how = cases[i]
+            part = got[batch.base[pos]:batch.base[pos + 1]].astype(np.float64)
+            yr, rsim, rh = oracle_lib.layout(g, k=k, M=5, b=b, T=T, eta0=f32(eta0),
+                                             gamma=f32(0.1), gamma_coarsest=f32(0.01),
+                                             min_nodes=mn, seed=seed, return_all=True)
+            assert batch.levels[pos] == rh.levels
+            if how == "coords":
+                err = float(np.abs(part - yr).max() / np.abs(yr).max())
+                say("  batch graph", i, g.name, "levels", rh.levels, "err", err)
+                assert err < 1e-4
+            else:
+                o_g = evaluate.objective_eval(rsim, part, M=5, b=b, gamma=0.1)
+                o_r = evaluate.objective_eval(rsim, yr, M=5, b=b, gamma=0.1)
+                np_g = evaluate.neighbourhood_preservation(g, part)
+                np_r = evaluate.neighbourhood_preservation(g, yr)
+                say("  batch graph", i, g.name, "objective", o_g, o_r, "NP", np_g, np_r)
+                assert abs(o_g - o_r) <= 0.01 * abs(o_r)
+                assert abs(np_g - np_r) <= 0.01
+        batch.close()

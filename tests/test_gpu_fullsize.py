@@ -163,3 +163,46 @@ def test_rmat20_k1_whole_similarity_and_step(oracle_lib):
     np_gpu = d.drg_neighbourhood_preservation(c, sim, y, torch.from_numpy(nodes).cuda())
     np_ref = evaluate.np_per_node(y1.astype(np.float64), rsim.row_ptr, rsim.col, nodes)
     assert np.array_equal(np_gpu.cpu().numpy(), np_ref)
+
+
+def test_rmat16_k2_whole_step_default_blocks(oracle_lib):
+    """R-MAT 2^16 (edge factor 16), k = 2: 3.6e8 pattern entries, rows up to
+    45k entries, so at the default 8192-column blocks every long row spans
+    eight blocks and, inside a block, several windows and waves of the flat
+    sweep.  One whole synchronous FP32 step with negatives from a seeded state
+    on the column-blocked path vs the FP64 oracle over all rows, and the same
+    at the coarse level of a two-level hierarchy."""
+    from paper_2008_07799_amd import drgraph as d
+    say("rmat16 k=2 whole step")
+    g = gen.rmat(16, 16, seed=2)
+    c = ctx()
+    rp, col = dev_graph(g)
+    sim = d.drg_build_similarity(c, rp, col, 2)
+    assert sim.blocked
+    rsim = oracle_lib.similarity(g, 2)
+    assert sim.nnz == rsim.nnz
+    say("  nnz", sim.nnz, "longest row", int(np.diff(rsim.row_ptr).max()))
+    y0 = np.random.default_rng(6).uniform(-3, 3, size=(g.n, 2)).astype(np.float32)
+    y = to_y(y0)
+    d.drg_layout_step(c, sim, None, y, M=5, b=1, gamma=0.1, eta=0.9, clip=4.0, level=0,
+                      seed=4, iter=11)
+    assert c.last_sweep() == d.DRG_SWEEP_BLOCKED
+    yr = y0.astype(np.float64)
+    oracle_lib.iter_sync(rsim, yr, None, 5, 1, float(np.float32(0.1)), float(np.float32(0.9)),
+                         4.0, 4, 11)
+    err = normwise_rel(y.cpu().numpy(), yr)
+    say("  level 0 err", err)
+    assert err < 2e-6
+    h = d.drg_coarsen(c, rp, col, seed=0, rho=0.8, min_nodes=1000, max_levels=2)
+    rh = oracle_lib.hierarchy(g, 0, 0.8, 1000, 2)
+    assert h.sizes == rh.sizes and h.levels == 2
+    y1 = np.random.default_rng(7).uniform(-3, 3, size=(h.sizes[1], 2)).astype(np.float32)
+    y = to_y(y1)
+    d.drg_layout_step(c, sim, h, y, M=5, b=1, gamma=0.1, eta=0.9, clip=4.0, level=1,
+                      seed=4, iter=12)
+    yr = y1.astype(np.float64)
+    oracle_lib.iter_sync(rsim, yr, rh.cmaps[1], 5, 1, float(np.float32(0.1)),
+                         float(np.float32(0.9)), 4.0, 4, 12)
+    err = normwise_rel(y.cpu().numpy(), yr)
+    say("  level 1 err", err)
+    assert err < 2e-6
