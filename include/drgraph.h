@@ -30,6 +30,7 @@
  */
 #ifndef DRGRAPH_H
 #define DRGRAPH_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -120,9 +121,26 @@ const char* drg_version(void);
  * max_levels=64, sync mode, seed 0 (Sec. 4 "Parameters", Sec. 3.2.3). */
 drg_status drg_layout_params_default(drg_layout_params* p);
 
+/* Source of device memory: alloc(bytes, user) returns device memory of the
+ * context's device, at least `bytes` bytes, 256-byte aligned, or NULL when it
+ * cannot; free(ptr, user) releases what alloc returned.  Both are called on
+ * the thread of the drg_* call that needs them (destroy calls included). */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} drg_allocator;
+
 /* Creates a context on `device` that enqueues on `hip_stream` (a hipStream_t;
- * NULL = the null stream).  The stream is borrowed and must outlive ctx. */
-drg_status drg_ctx_create(int32_t device, void* hip_stream, drg_ctx** out);
+ * NULL = the null stream).  The stream is borrowed and must outlive ctx.
+ * alloc (nullable; copied): every device buffer that calls on this context
+ * create -- similarities, hierarchies, batches and per-call scratch -- comes
+ * from it and goes back to it, also when the object is destroyed after the
+ * context; NULL = hipMalloc / hipFree.  When it returns NULL the call fails
+ * with DRG_E_OOM after freeing what it had allocated.  DRG_E_INVALID when
+ * alloc lacks a function. */
+drg_status drg_ctx_create(int32_t device, void* hip_stream, const drg_allocator* alloc,
+                          drg_ctx** out);
 void drg_ctx_destroy(drg_ctx* ctx);
 drg_status drg_ctx_synchronize(drg_ctx* ctx);
 /* Kernel timing: when on, the library brackets every launch of the layout
@@ -188,10 +206,12 @@ drg_status drg_neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const 
  * (n / count) (sum P - (sum A)^2 / sum B) / n^2.  Distances by breadth-first
  * search over the whole graph g (device CSR, as for drg_build_similarity);
  * y [n][2] FP32 device coordinates, L in FP64.  Sums in ascending node id:
- * repeatable.  Scratch: 8 n bytes per concurrently searched source.
- * Synchronises.  DRG_E_INVALID for a source id out of range. */
+ * repeatable.  *estimate (host, nullable) receives that sampled estimate,
+ * the sums added over the sources in the order given.  Scratch: 8 n bytes
+ * per concurrently searched source.  Synchronises.  DRG_E_INVALID for a
+ * source id out of range. */
 drg_status drg_stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
-                              const int32_t* sources, double* sums_out);
+                              const int32_t* sources, double* sums_out, double* estimate);
 void drg_sim_destroy(drg_sim* s);
 
 /* Multilevel coarsening (Sec. 3.2.3, Fig. 3): repeatedly groups a randomly
@@ -211,6 +231,10 @@ drg_status drg_hier_info(const drg_hier* h, int32_t* levels, int32_t* sizes_host
  * contracted graph G^level.  coarse_nnz (nullable) receives nnz_level. */
 drg_status drg_hier_export(const drg_hier* h, int32_t level, int32_t* map, int32_t* cmap,
                            int32_t* coarse_rp, int32_t* coarse_col, int64_t* coarse_nnz);
+/* fine_to_level[n_0] (host): the node of `level` that each finest node
+ * belongs to (the composed grouping of Sec. 3.2.3); level 0 is refused
+ * (DRG_E_INVALID), its map being the identity.  Synchronises. */
+drg_status drg_hier_export_map(const drg_hier* h, int32_t level, int32_t* fine_to_level);
 void drg_hier_destroy(drg_hier* h);
 
 /* Random layout of a level (Sec. 3.2.3): y[v] = (2u-1, 2u-1) with 24-bit
@@ -302,15 +326,34 @@ drg_status drg_sample_negatives(drg_ctx* ctx, const drg_sim* s, int32_t M, uint6
 drg_status drg_sim_coo(drg_ctx* ctx, const drg_sim* s, int32_t* rows_dev, int32_t* cols_dev,
                        float* P_dev);
 
-/* The whole schedule on a built similarity and hierarchy: random layout of the
- * coarsest level, T iterations split evenly over levels (the finest takes the
- * remainder) with eta_t = eta0 (1 - t/T_l) restarting per level and
- * gamma_coarsest on the coarsest level, refinement between levels.
- * Negatives use the global iteration index.  y_out_dev: [n][2]. */
+/* The multilevel layout of Sec. 3.2.3 on a built similarity and hierarchy:
+ * random layout of the coarsest level, the iterations of Sec. 3.2.2 level by
+ * level from the coarsest down, each level's result copied to the next finer
+ * level (refinement).  T (Sec. 4.2: iteration number) is the total over the
+ * levels, split evenly, the finest taking the remainder; the step is
+ * eta0 (1 - t/T_l), restarting per level; the coarsest of two or more levels
+ * uses gamma_coarsest (Sec. 4.2, weight of negative samples).  Iteration t of
+ * level l has the global index (iterations of the coarser levels) + t, which
+ * keys its negatives.  y_out_dev: [n][2].  Synchronises. */
 drg_status drg_layout_run(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                           const drg_layout_params* p, float* y_out_dev);
+/* Checkpoint and resume of that schedule.  drg_layout_run_until runs it from
+ * the start until t iterations of `level` are done (0 <= t <= T_level; t =
+ * T_level is before the refinement to level-1) and writes that level's
+ * coordinates to y_level_dev [n_level][2].  drg_layout_resume continues from
+ * such a state (level, t, y_level_dev) to the end and writes the finest
+ * coordinates to y_out_dev [n][2].  In sync mode a run cut anywhere and
+ * resumed gives the same bits as drg_layout_run.  DRG_E_INVALID for a point
+ * outside the schedule.  Both synchronise. */
+drg_status drg_layout_run_until(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                                const drg_layout_params* p, int32_t level, int32_t t,
+                                float* y_level_dev);
+drg_status drg_layout_resume(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                             const drg_layout_params* p, int32_t level, int32_t t,
+                             const float* y_level_dev, float* y_out_dev);
 
-/* End to end: drg_build_similarity + drg_coarsen + drg_layout_run. */
+/* End to end (Sec. 3.1: undirected graph in, positions out; Sec. 3.2 stages
+ * in order): drg_build_similarity + drg_coarsen + drg_layout_run. */
 drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p,
                       float* y_out_dev);
 

@@ -38,6 +38,20 @@ static drg_status guarded(F&& f) {
 
 static void use_device(int dev) { DRG_HIP(hipSetDevice(dev)); }
 
+// For the duration of a call on a context: its device is current and the
+// device memory of whatever the call builds comes from its allocator.
+struct CtxScope {
+    drg::Allocator saved;
+    explicit CtxScope(const drg_ctx* c) {
+        use_device(c->device);
+        saved = drg::thread_allocator();
+        drg::thread_allocator() = c->alloc;
+    }
+    ~CtxScope() { drg::thread_allocator() = saved; }
+    CtxScope(const CtxScope&) = delete;
+    CtxScope& operator=(const CtxScope&) = delete;
+};
+
 static void need(const void* p, const char* what) {
     if (!p) throw Error(DRG_E_INVALID, std::string(what) + " is NULL");
 }
@@ -69,10 +83,13 @@ drg_status drg_layout_params_default(drg_layout_params* p) {
     });
 }
 
-drg_status drg_ctx_create(int32_t device, void* hip_stream, drg_ctx** out) {
+drg_status drg_ctx_create(int32_t device, void* hip_stream, const drg_allocator* alloc,
+                          drg_ctx** out) {
     return guarded([&] {
         need(out, "out");
         *out = nullptr;
+        if (alloc && (!alloc->alloc || !alloc->free))
+            throw Error(DRG_E_INVALID, "allocator needs both alloc and free");
         int count = 0;
         DRG_HIP(hipGetDeviceCount(&count));
         if (device < 0 || device >= count) throw Error(DRG_E_INVALID, "no such device");
@@ -89,6 +106,11 @@ drg_status drg_ctx_create(int32_t device, void* hip_stream, drg_ctx** out) {
             lds_optin = 0;
         }
         c->max_lds = std::max(lds, lds_optin);
+        if (alloc) {
+            c->alloc.alloc = alloc->alloc;
+            c->alloc.free = alloc->free;
+            c->alloc.user = alloc->user;
+        }
         *out = c.release();
     });
 }
@@ -105,7 +127,7 @@ void drg_ctx_destroy(drg_ctx* ctx) {
 drg_status drg_ctx_synchronize(drg_ctx* ctx) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         DRG_HIP(hipStreamSynchronize(ctx->stream));
     });
 }
@@ -127,7 +149,7 @@ drg_status drg_ctx_set_profiling(drg_ctx* ctx, int32_t on) {
 drg_status drg_ctx_kernel_stats(drg_ctx* ctx, int64_t* launches, double* total_ms) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         DRG_HIP(hipStreamSynchronize(ctx->stream));
         for (auto& e : ctx->events) {
             float ms = 0.0f;
@@ -157,7 +179,7 @@ drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, doubl
         need(ctx, "ctx");
         need(out, "out");
         *out = nullptr;
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         *out = drg::build_similarity(ctx, g, k, sigma, flags);
     });
 }
@@ -196,18 +218,18 @@ drg_status drg_neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const 
     return guarded([&] {
         need(ctx, "ctx");
         need(s, "sim");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::neighbourhood_preservation(ctx, s, y, count, nodes, np_out);
     });
 }
 
 drg_status drg_stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
-                              const int32_t* sources, double* sums_out) {
+                              const int32_t* sources, double* sums_out, double* estimate) {
     return guarded([&] {
         need(ctx, "ctx");
         need(g, "graph");
-        use_device(ctx->device);
-        drg::stress_sampled(ctx, g, y, count, sources, sums_out);
+        CtxScope scope(ctx);
+        drg::stress_sampled(ctx, g, y, count, sources, sums_out, estimate);
     });
 }
 
@@ -224,7 +246,7 @@ drg_status drg_coarsen(drg_ctx* ctx, const drg_csr* g, uint64_t seed, double rho
         need(ctx, "ctx");
         need(out, "out");
         *out = nullptr;
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         *out = drg::build_hierarchy(ctx, g, seed, rho, min_nodes, max_levels);
     });
 }
@@ -236,6 +258,10 @@ drg_status drg_hier_info(const drg_hier* h, int32_t* levels, int32_t* sizes_host
         if (sizes_host)
             for (size_t l = 0; l < h->lv.size(); ++l) sizes_host[l] = h->lv[l].n;
     });
+}
+
+drg_status drg_hier_export_map(const drg_hier* h, int32_t level, int32_t* fine_to_level) {
+    return drg_hier_export(h, level, nullptr, fine_to_level, nullptr, nullptr, nullptr);
 }
 
 drg_status drg_hier_export(const drg_hier* h, int32_t level, int32_t* map, int32_t* cmap,
@@ -271,7 +297,7 @@ void drg_hier_destroy(drg_hier* h) {
 drg_status drg_init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::init_layout(ctx, n, seed, level, y_dev);
     });
 }
@@ -280,7 +306,7 @@ drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const flo
                        float* y_finer_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::prolong(ctx, h, level, y_level_dev, y_finer_dev);
     });
 }
@@ -289,7 +315,7 @@ drg_status drg_layout_step(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                            const drg_step_params* p, float* y_level_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::layout_step(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
     });
 }
@@ -298,7 +324,7 @@ drg_status drg_init_layout_f64(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t l
                                double* y_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::init_layout_t<double>(ctx, n, seed, level, y_dev);
     });
 }
@@ -307,7 +333,7 @@ drg_status drg_prolong_f64(drg_ctx* ctx, const drg_hier* h, int32_t level,
                            const double* y_level_dev, double* y_finer_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::prolong_t<double>(ctx, h, level, y_level_dev, y_finer_dev);
     });
 }
@@ -316,7 +342,7 @@ drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h
                                const drg_step_params* p, double* y_level_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::layout_step_t<double>(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
     });
 }
@@ -325,7 +351,7 @@ drg_status drg_objective_fwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_param
                              const float* y_dev, float* loss_dev, float* rows_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::objective_fwd_t<float>(ctx, const_cast<drg_sim*>(s), p, y_dev, loss_dev, rows_dev);
     });
 }
@@ -334,7 +360,7 @@ drg_status drg_objective_fwd_noalloc(drg_ctx* ctx, const drg_sim* s, const drg_o
                                      const float* y_dev, float* loss_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::objective_fwd_noalloc(ctx, const_cast<drg_sim*>(s), p, y_dev, loss_dev);
     });
 }
@@ -343,7 +369,7 @@ drg_status drg_objective_bwd(drg_ctx* ctx, const drg_sim* s, const drg_obj_param
                              const float* y_dev, const float* dloss_dev, float* dy_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::objective_bwd_t<float>(ctx, const_cast<drg_sim*>(s), p, y_dev, dloss_dev, dy_dev);
     });
 }
@@ -352,7 +378,7 @@ drg_status drg_objective_fwd_f64(drg_ctx* ctx, const drg_sim* s, const drg_obj_p
                                  const double* y_dev, double* loss_dev, double* rows_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::objective_fwd_t<double>(ctx, const_cast<drg_sim*>(s), p, y_dev, loss_dev, rows_dev);
     });
 }
@@ -361,7 +387,7 @@ drg_status drg_objective_bwd_f64(drg_ctx* ctx, const drg_sim* s, const drg_obj_p
                                  const double* y_dev, const double* dloss_dev, double* dy_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::objective_bwd_t<double>(ctx, const_cast<drg_sim*>(s), p, y_dev, dloss_dev, dy_dev);
     });
 }
@@ -370,7 +396,7 @@ drg_status drg_sample_negatives(drg_ctx* ctx, const drg_sim* s, int32_t M, uint6
                                 uint64_t iter, int32_t* out_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::sample_negatives(ctx, const_cast<drg_sim*>(s), M, seed, iter, out_dev);
     });
 }
@@ -379,32 +405,70 @@ drg_status drg_sim_coo(drg_ctx* ctx, const drg_sim* s, int32_t* rows_dev, int32_
                        float* P_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::sim_coo(ctx, const_cast<drg_sim*>(s), rows_dev, cols_dev, P_dev);
     });
 }
 
 using drg::check_layout_params;
 
+// A point of the schedule: `t` iterations of level `level` done (levels run
+// from the coarsest down to 0).
+struct SchedPoint {
+    int32_t level, t;
+};
+
+static int32_t level_iters(const drg_layout_params* p, int32_t Lc, int32_t l) {
+    const int32_t base = p->T / Lc;
+    return base + (l == 0 ? p->T - base * Lc : 0);
+}
+
+static void check_point(const drg_layout_params* p, int32_t Lc, const SchedPoint& q) {
+    if (q.level < 0 || q.level >= Lc || q.t < 0 || q.t > level_iters(p, Lc, q.level))
+        throw Error(DRG_E_INVALID, "schedule point: level in [0, levels), t in [0, T_level]");
+}
+
+// The schedule of Sec. 3.2.3 / Sec. 4.2 on a built similarity and hierarchy:
+// from `from` (coordinates y_from of that level; NULL: the random layout of
+// the coarsest level at its first iteration) to `to` (the level's
+// coordinates copied to y_to; NULL: to the end, the finest coordinates in
+// y_out).  Iteration t of level l has step eta0 (1 - t/T_l) and global index
+// (iterations of the coarser levels) + t, which keys its negatives; a split
+// run therefore equals the whole one.
 static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_layout_params* p,
-                         float* y_out) {
+                         const SchedPoint* from, const float* y_from, const SchedPoint* to,
+                         float* y_to, float* y_out) {
     check_layout_params(p);
     need(s, "sim");
     need(h, "hier");
-    need(y_out, "y_out");
     if (h->n0 != s->n) throw Error(DRG_E_INVALID, "hierarchy is of another graph");
     const int32_t Lc = (int32_t)h->lv.size();
-    // level buffers: the finest level is y_out, coarser ones are scratch
+    const SchedPoint start = from ? *from : SchedPoint{Lc - 1, 0};
+    const SchedPoint stop = to ? *to : SchedPoint{0, level_iters(p, Lc, 0)};
+    check_point(p, Lc, start);
+    check_point(p, Lc, stop);
+    if (start.level < stop.level || (start.level == stop.level && start.t > stop.t))
+        throw Error(DRG_E_INVALID, "schedule point: the stop lies before the start");
+    if (from) need(y_from, "y_from");
+    if (to) need(y_to, "y_to");
+    else need(y_out, "y_out");
+    // level buffers: the finest level of a run to the end is y_out, the others scratch
     std::vector<drg::DevBuf<float2>> ybuf(Lc);
     auto ylev = [&](int32_t l) -> float* {
-        return l == 0 ? y_out : reinterpret_cast<float*>(ybuf[l].get());
+        return (l == 0 && !to) ? y_out : reinterpret_cast<float*>(ybuf[l].get());
     };
-    for (int32_t l = 1; l < Lc; ++l) ybuf[l].alloc(h->lv[l].n);
-    drg::init_layout(ctx, h->lv[Lc - 1].n, p->seed, Lc - 1, ylev(Lc - 1));
-    const int32_t base = p->T / Lc;
+    for (int32_t l = stop.level; l <= start.level; ++l)
+        if (!(l == 0 && !to)) ybuf[l].alloc(h->lv[l].n);
+    if (from)
+        DRG_HIP(hipMemcpyAsync(ylev(start.level), y_from, sizeof(float2) * h->lv[start.level].n,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    else
+        drg::init_layout(ctx, h->lv[Lc - 1].n, p->seed, Lc - 1, ylev(Lc - 1));
     uint64_t git = 0;
-    for (int32_t l = Lc - 1; l >= 0; --l) {
-        const int32_t Tl = base + (l == 0 ? p->T - base * Lc : 0);
+    for (int32_t l = Lc - 1; l > start.level; --l) git += (uint64_t)level_iters(p, Lc, l);
+    git += (uint64_t)start.t;
+    for (int32_t l = start.level; l >= stop.level; --l) {
+        const int32_t Tl = level_iters(p, Lc, l);
         const float gam = (l == Lc - 1 && Lc > 1) ? p->gamma_coarsest : p->gamma;
         drg_step_params sp{};
         sp.M = p->M;
@@ -414,13 +478,19 @@ static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_
         sp.level = l;
         sp.mode = p->mode;
         sp.seed = p->seed;
-        for (int32_t t = 0; t < Tl; ++t) {
+        const int32_t t0 = l == start.level ? start.t : 0;
+        const int32_t t1 = l == stop.level ? stop.t : Tl;
+        for (int32_t t = t0; t < t1; ++t) {
             sp.eta = (float)((double)p->eta0 * (1.0 - (double)t / (double)Tl));
             sp.iter = git++;
             drg::layout_step(ctx, s, h, &sp, ylev(l));
         }
-        if (l > 0) drg::prolong(ctx, h, l, ylev(l), ylev(l - 1));
+        if (l == stop.level) break;
+        drg::prolong(ctx, h, l, ylev(l), ylev(l - 1));
     }
+    if (to)
+        DRG_HIP(hipMemcpyAsync(y_to, ylev(stop.level), sizeof(float2) * h->lv[stop.level].n,
+                               hipMemcpyDeviceToDevice, ctx->stream));
     DRG_HIP(hipStreamSynchronize(ctx->stream));
 }
 
@@ -428,8 +498,33 @@ drg_status drg_layout_run(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                           const drg_layout_params* p, float* y_out_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
-        run_schedule(ctx, const_cast<drg_sim*>(s), h, p, y_out_dev);
+        CtxScope scope(ctx);
+        run_schedule(ctx, const_cast<drg_sim*>(s), h, p, nullptr, nullptr, nullptr, nullptr,
+                     y_out_dev);
+    });
+}
+
+drg_status drg_layout_run_until(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                                const drg_layout_params* p, int32_t level, int32_t t,
+                                float* y_level_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        CtxScope scope(ctx);
+        const SchedPoint to{level, t};
+        run_schedule(ctx, const_cast<drg_sim*>(s), h, p, nullptr, nullptr, &to, y_level_dev,
+                     nullptr);
+    });
+}
+
+drg_status drg_layout_resume(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
+                             const drg_layout_params* p, int32_t level, int32_t t,
+                             const float* y_level_dev, float* y_out_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        CtxScope scope(ctx);
+        const SchedPoint from{level, t};
+        run_schedule(ctx, const_cast<drg_sim*>(s), h, p, &from, y_level_dev, nullptr, nullptr,
+                     y_out_dev);
     });
 }
 
@@ -439,13 +534,13 @@ drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p
         need(ctx, "ctx");
         need(g, "graph");
         check_layout_params(p);
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         std::unique_ptr<drg_sim, void (*)(drg_sim*)> s(
             drg::build_similarity(ctx, g, p->k, p->sigma, 0), drg_sim_destroy);
         std::unique_ptr<drg_hier, void (*)(drg_hier*)> h(
             drg::build_hierarchy(ctx, g, p->seed, p->rho, p->min_nodes, p->max_levels),
             drg_hier_destroy);
-        run_schedule(ctx, s.get(), h.get(), p, y_out_dev);
+        run_schedule(ctx, s.get(), h.get(), p, nullptr, nullptr, nullptr, nullptr, y_out_dev);
     });
 }
 
@@ -455,7 +550,7 @@ drg_status drg_batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         need(ctx, "ctx");
         need(out, "out");
         *out = nullptr;
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         *out = drg::batch_create(ctx, graphs, count, params);
     });
 }
@@ -473,7 +568,7 @@ drg_status drg_batch_tuning(const drg_batch* b, int32_t cap, int32_t* n, int32_t
 drg_status drg_batch_run(drg_ctx* ctx, drg_batch* b, float* y_out_dev) {
     return guarded([&] {
         need(ctx, "ctx");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         drg::batch_run(ctx, b, y_out_dev);
     });
 }
@@ -485,7 +580,7 @@ drg_status drg_layout_batched(drg_ctx* ctx, const drg_csr* graphs, int32_t count
     return guarded([&] {
         need(ctx, "ctx");
         need(y_out_dev, "y_out");
-        use_device(ctx->device);
+        CtxScope scope(ctx);
         std::unique_ptr<drg_batch, void (*)(drg_batch*)> b(
             drg::batch_create(ctx, graphs, count, params), drg_batch_destroy);
         drg::batch_run(ctx, b.get(), y_out_dev);

@@ -17,6 +17,7 @@ struct drg_ctx {
     int64_t launches = 0;
     double total_ms = 0.0;
     int32_t last_sweep = -1;  // DRG_SWEEP_* form of the latest layout step
+    drg::Allocator alloc;     // device memory of every object built on this context
 };
 
 // Sparse similarity P~ over the finest graph plus the sampling table.
@@ -108,7 +109,7 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
 void validate_csr_impl(drg_ctx* ctx, const drg_csr* g, bool full);
 void stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
-                    const int32_t* sources, double* out);
+                    const int32_t* sources, double* out, double* estimate);
 void neighbourhood_preservation(drg_ctx* ctx, const drg_sim* s, const float* y, int32_t count,
                                 const int32_t* nodes, double* out);
 void sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows, int64_t cap,

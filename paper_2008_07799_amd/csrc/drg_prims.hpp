@@ -6,16 +6,31 @@
 
 namespace drg {
 
-// RAII device buffer (hipMalloc / hipFree).
+// Where device memory comes from: a caller's allocator (set on the context,
+// see drg_allocator) or, when alloc is NULL, hipMalloc / hipFree.
+struct Allocator {
+    void* (*alloc)(size_t bytes, void* user) = nullptr;
+    void (*free)(void* ptr, void* user) = nullptr;
+    void* user = nullptr;
+};
+
+// The allocator of the entry point running on this thread: the context's,
+// for the duration of a call on a context; else the default.
+Allocator& thread_allocator();
+
+void* dev_alloc_bytes(int64_t bytes, const Allocator& al);
+
+// RAII device buffer; freed with the allocator it came from.
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
     int64_t n = 0;
+    Allocator al;
     DevBuf() = default;
     explicit DevBuf(int64_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), al(o.al) {
         o.p = nullptr;
         o.n = 0;
     }
@@ -24,6 +39,7 @@ struct DevBuf {
             reset();
             p = o.p;
             n = o.n;
+            al = o.al;
             o.p = nullptr;
             o.n = 0;
         }
@@ -32,19 +48,24 @@ struct DevBuf {
     ~DevBuf() { reset(); }
     void alloc(int64_t count);
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al.free)
+                al.free(p, al.user);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
     }
     T* get() const { return p; }
 };
 
-void* dev_alloc_bytes(int64_t bytes);
-
 template <typename T>
 void DevBuf<T>::alloc(int64_t count) {
     reset();
-    p = static_cast<T*>(dev_alloc_bytes((count > 0 ? count : 1) * (int64_t)sizeof(T)));
+    const Allocator use = thread_allocator();
+    p = static_cast<T*>(dev_alloc_bytes((count > 0 ? count : 1) * (int64_t)sizeof(T), use));
+    al = use;
     n = count;
 }
 

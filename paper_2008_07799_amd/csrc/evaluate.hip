@@ -15,6 +15,8 @@
 // distances.
 #include <algorithm>
 
+#include <vector>
+
 #include "drg_internal.hpp"
 
 namespace drg {
@@ -270,8 +272,9 @@ __global__ __launch_bounds__(ST_BLOCK) void k_stress(StressArgs a) {
 }
 
 void stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
-                    const int32_t* sources, double* out) {
+                    const int32_t* sources, double* out, double* estimate) {
     if (count < 0) throw Error(DRG_E_INVALID, "count >= 0");
+    if (estimate) *estimate = 0.0;
     if (count == 0) return;
     if (!y || !sources || !out) throw Error(DRG_E_INVALID, "y, sources and out are required");
     validate_csr_impl(ctx, g, false);
@@ -318,6 +321,22 @@ void stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t coun
             hipLaunchKernelGGL(k_stress<false>, dim3(m), dim3(ST_BLOCK), 0, st, a);
         }
         DRG_LAUNCH_CHECK();
+    }
+    if (estimate) {
+        // (n / count) (sum P - (sum A)^2 / sum B) / n^2, the sums taken over
+        // the sources in the order given
+        std::vector<double> h((size_t)count * 3);
+        DRG_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                               st));
+        DRG_HIP(hipStreamSynchronize(st));
+        double A = 0.0, B = 0.0, P = 0.0;
+        for (int32_t t = 0; t < count; ++t) {
+            A += h[3 * (size_t)t];
+            B += h[3 * (size_t)t + 1];
+            P += h[3 * (size_t)t + 2];
+        }
+        const double nn = (double)n;
+        *estimate = B > 0.0 ? (nn / (double)count) * (P - A * A / B) / (nn * nn) : 0.0;
     }
     DRG_HIP(hipStreamSynchronize(st));
 }

@@ -4,8 +4,19 @@
 
 namespace drg {
 
-void* dev_alloc_bytes(int64_t bytes) {
+Allocator& thread_allocator() {
+    static thread_local Allocator a;
+    return a;
+}
+
+void* dev_alloc_bytes(int64_t bytes, const Allocator& al) {
     void* p = nullptr;
+    if (al.alloc) {
+        p = al.alloc((size_t)bytes, al.user);
+        if (!p)
+            throw Error(-3, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        return p;
+    }
     hipError_t e = hipMalloc(&p, (size_t)bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -54,6 +54,14 @@ class ObjParams(C.Structure):
                 ("iter", C.c_uint64)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 class LayoutParams(C.Structure):
     _fields_ = [("k", C.c_int32), ("M", C.c_int32), ("b", C.c_int32), ("T", C.c_int32),
                 ("sigma", C.c_double), ("gamma", C.c_float), ("gamma_coarsest", C.c_float),
@@ -84,7 +92,7 @@ def lib():
         "drg_last_error": ([], C.c_char_p),
         "drg_version": ([], C.c_char_p),
         "drg_layout_params_default": ([C.POINTER(LayoutParams)], st),
-        "drg_ctx_create": ([C.c_int32, _P, C.POINTER(_P)], st),
+        "drg_ctx_create": ([C.c_int32, _P, C.POINTER(Allocator), C.POINTER(_P)], st),
         "drg_ctx_destroy": ([_P], None),
         "drg_ctx_synchronize": ([_P], st),
         "drg_ctx_set_profiling": ([_P, C.c_int32], st),
@@ -97,12 +105,14 @@ def lib():
         "drg_sim_export": ([_P] + [_P] * 8, st),
         "drg_sim_export_rows": ([_P, C.c_int32, _P, C.c_int64] + [_P] * 7, st),
         "drg_neighbourhood_preservation": ([_P, _P, _P, C.c_int32, _P, _P], st),
-        "drg_stress_sampled": ([_P, C.POINTER(Csr), _P, C.c_int32, _P, _P], st),
+        "drg_stress_sampled": ([_P, C.POINTER(Csr), _P, C.c_int32, _P, _P,
+                                C.POINTER(C.c_double)], st),
         "drg_sim_destroy": ([_P], None),
         "drg_coarsen": ([_P, C.POINTER(Csr), C.c_uint64, C.c_double, C.c_int32, C.c_int32,
                          C.POINTER(_P)], st),
         "drg_hier_info": ([_P, C.POINTER(C.c_int32), _P], st),
         "drg_hier_export": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int64)], st),
+        "drg_hier_export_map": ([_P, C.c_int32, _P], st),
         "drg_hier_destroy": ([_P], None),
         "drg_init_layout": ([_P, C.c_int32, C.c_uint64, C.c_int32, _P], st),
         "drg_prolong": ([_P, _P, C.c_int32, _P, _P], st),
@@ -111,6 +121,10 @@ def lib():
         "drg_prolong_f64": ([_P, _P, C.c_int32, _P, _P], st),
         "drg_layout_step_f64": ([_P, _P, _P, C.POINTER(StepParams), _P], st),
         "drg_layout_run": ([_P, _P, _P, C.POINTER(LayoutParams), _P], st),
+        "drg_layout_run_until": ([_P, _P, _P, C.POINTER(LayoutParams), C.c_int32, C.c_int32,
+                                  _P], st),
+        "drg_layout_resume": ([_P, _P, _P, C.POINTER(LayoutParams), C.c_int32, C.c_int32, _P,
+                               _P], st),
         "drg_objective_fwd": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
         "drg_objective_bwd": ([_P, _P, C.POINTER(ObjParams), _P, _P, _P], st),
         "drg_objective_fwd_noalloc": ([_P, _P, C.POINTER(ObjParams), _P, _P], st),
@@ -161,14 +175,21 @@ def _np_ptr(a):
 
 # ------------------------------------------------------------------ context
 class Context:
-    def __init__(self, device: int = 0, stream=None):
+    """A library context on `device`; `allocator` (optional) is a drgraph
+    Allocator structure whose callbacks provide all device memory of the
+    objects built through this context (it must outlive them)."""
+
+    def __init__(self, device: int = 0, stream=None, allocator: Allocator | None = None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.device = device
         self.stream = stream
+        self.allocator = allocator
         h = C.c_void_p()
-        _check(lib().drg_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        _check(lib().drg_ctx_create(device, C.c_void_p(stream.cuda_stream),
+                                    C.byref(allocator) if allocator is not None else None,
+                                    C.byref(h)))
         self._free = lib().drg_ctx_destroy  # kept: module globals are gone at exit
         self.h = h
 
@@ -313,18 +334,17 @@ def drg_neighbourhood_preservation(ctx: Context, sim: Similarity, y, nodes):
 
 def drg_stress_sampled(ctx: Context, row_ptr, col, y, sources):
     """Per-source stress sums (A, B, P) (Sec. 4.1; see drgraph.h) as a
-    [count, 3] float64 device tensor, and the sampled stress estimate."""
+    [count, 3] float64 device tensor, and the library's sampled stress
+    estimate."""
     import torch
     g = _csr(row_ptr, col)
     yp = _dev(y, torch.float32, "y", (g.n, 2))
     sp = _dev(sources, torch.int32, "sources")
     out = torch.empty((sources.numel(), 3), dtype=torch.float64, device=y.device)
+    est = C.c_double()
     _check(lib().drg_stress_sampled(ctx.h, C.byref(g), yp, int(sources.numel()), sp,
-                                    C.c_void_p(out.data_ptr())))
-    s = out.sum(dim=0).cpu().numpy()
-    n = g.n
-    est = (n / max(1, sources.numel())) * (s[2] - s[0] * s[0] / s[1]) / (n * n) if s[1] > 0 else 0.0
-    return out, float(est)
+                                    C.c_void_p(out.data_ptr()), C.byref(est)))
+    return out, float(est.value)
 
 
 # ------------------------------------------------------------------ hierarchy
@@ -356,6 +376,12 @@ class Hierarchy:
         _check(lib().drg_hier_export(self.h, level, _np_ptr(out["map"]), _np_ptr(out["cmap"]),
                                      _np_ptr(out["row_ptr"]), _np_ptr(out["col"]), C.byref(nnz)))
         out["col"] = out["col"][: nnz.value]
+        return out
+
+    def export_map(self, level: int, n0: int) -> np.ndarray:
+        """Finest node -> node of `level` (host int32 [n0])."""
+        out = np.zeros(n0, np.int32)
+        _check(lib().drg_hier_export_map(self.h, level, _np_ptr(out)))
         return out
 
 
@@ -416,6 +442,27 @@ def drg_layout_run(ctx: Context, sim: Similarity, hier: Hierarchy, params: Layou
     import torch
     _check(lib().drg_layout_run(ctx.h, sim.h, hier.h, C.byref(params),
                                 _dev(y_out, torch.float32, "y_out", (sim.n, 2))))
+
+
+def drg_layout_run_until(ctx: Context, sim: Similarity, hier: Hierarchy, params: LayoutParams,
+                         level: int, t: int, y_level):
+    """Runs the schedule until t iterations of `level` are done; writes that
+    level's coordinates into y_level [n_level, 2] (float32, device)."""
+    import torch
+    _check(lib().drg_layout_run_until(ctx.h, sim.h, hier.h, C.byref(params), int(level), int(t),
+                                      _dev(y_level, torch.float32, "y_level",
+                                           (hier.sizes[level], 2))))
+
+
+def drg_layout_resume(ctx: Context, sim: Similarity, hier: Hierarchy, params: LayoutParams,
+                      level: int, t: int, y_level, y_out):
+    """Continues the schedule from (level, t, y_level) to the end; finest
+    coordinates into y_out [n, 2]."""
+    import torch
+    _check(lib().drg_layout_resume(ctx.h, sim.h, hier.h, C.byref(params), int(level), int(t),
+                                   _dev(y_level, torch.float32, "y_level",
+                                        (hier.sizes[level], 2)),
+                                   _dev(y_out, torch.float32, "y_out", (sim.n, 2))))
 
 
 def drg_layout(ctx: Context, row_ptr, col, params: LayoutParams, y_out):

@@ -46,7 +46,7 @@ def test_defaults_and_argument_errors(lib):
     assert lib.drg_sim_info(None, None, None, None, None, None) == d.DRG_E_INVALID
     assert lib.drg_hier_info(None, None, None) == d.DRG_E_INVALID
     assert lib.drg_layout_step(None, None, None, None, None) == d.DRG_E_INVALID
-    assert lib.drg_ctx_create(0, None, None) == d.DRG_E_INVALID
+    assert lib.drg_ctx_create(0, None, None, None) == d.DRG_E_INVALID
     # destroy calls are NULL-safe
     lib.drg_sim_destroy(None)
     lib.drg_hier_destroy(None)

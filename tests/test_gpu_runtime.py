@@ -1,0 +1,163 @@
+"""The runtime around the kernels (marked gpu): device memory from a
+caller's allocator, with a simulated allocation failure returning
+DRG_E_OOM after everything allocated so far is freed; checkpoint and resume
+of the layout schedule giving the same bits as an uninterrupted run; the
+hierarchy's composed maps exported on their own (Sec. 3.2.3)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2008_07799_amd import gen
+from tests.gpu_util import ctx, dev_graph, say, zeros_y
+
+pytestmark = pytest.mark.gpu
+
+
+def _loaded_hip_runtime() -> str:
+    """Path of the HIP runtime already in the process (the one the library
+    and torch use), so the callbacks allocate through the same runtime."""
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1]
+            if "libamdhip64.so" in path:
+                return path
+    raise RuntimeError("no HIP runtime loaded")
+
+
+class CountingAllocator:
+    """hipMalloc / hipFree behind the library's allocator callbacks; refuses
+    every request after `fail_after` successful ones (None: never)."""
+
+    def __init__(self, fail_after=None):
+        from paper_2008_07799_amd import drgraph as d
+        d.lib()  # loads torch's HIP runtime and binds the library to it
+        self.hip = C.CDLL(_loaded_hip_runtime())
+        self.hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        self.hip.hipFree.argtypes = [C.c_void_p]
+        self.fail_after = fail_after
+        self.done = 0
+        self.refused = 0
+        self.live = {}
+        self._a = d.ALLOC_FN(self._alloc)
+        self._f = d.FREE_FN(self._free)
+        self.struct = d.Allocator(self._a, self._f, None)
+
+    def _alloc(self, nbytes, user):
+        if self.fail_after is not None and self.done >= self.fail_after:
+            self.refused += 1
+            return None
+        p = C.c_void_p()
+        if self.hip.hipMalloc(C.byref(p), nbytes) != 0:
+            return None
+        self.done += 1
+        self.live[p.value] = nbytes
+        return p.value
+
+    def _free(self, ptr, user):
+        assert ptr in self.live, "freed memory the allocator did not give out"
+        del self.live[ptr]
+        self.hip.hipFree(C.c_void_p(ptr))
+
+
+def _ctx_with(al):
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    return d.Context(0, torch.cuda.current_stream(0), allocator=al.struct)
+
+
+def test_allocator_serves_every_buffer_and_gets_it_back():
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    g = gen.rmat(12, 8, seed=3)
+    rp, col = dev_graph(g)
+    al = CountingAllocator()
+    c = _ctx_with(al)
+    p = d.layout_params(k=2, M=5, b=1, T=30, min_nodes=100, seed=1)
+    y = zeros_y(g.n)
+    d.drg_layout(c, rp, col, p, y)
+    say("  allocations", al.done, "live after the call", len(al.live))
+    assert al.done > 10 and not al.live  # the call's objects are gone again
+    sim = d.drg_build_similarity(c, rp, col, 2)
+    h = d.drg_coarsen(c, rp, col, seed=1, rho=0.8, min_nodes=100, max_levels=64)
+    assert al.live
+    c.close()  # objects outlive their context and still free through it
+    sim.close()
+    h.close()
+    assert not al.live
+    # the same layout with the library's own allocations
+    y2 = zeros_y(g.n)
+    d.drg_layout(ctx(), rp, col, p, y2)
+    assert torch.equal(y, y2)
+
+
+@pytest.mark.parametrize("what", ["similarity", "coarsen", "layout"])
+def test_allocation_failure_returns_oom_and_frees_everything(what):
+    from paper_2008_07799_amd import drgraph as d
+    g = gen.rmat(12, 8, seed=3)
+    rp, col = dev_graph(g)
+    p = d.layout_params(k=2, M=5, b=1, T=10, min_nodes=100, seed=1)
+
+    def call(c):
+        if what == "similarity":
+            d.drg_build_similarity(c, rp, col, 2).close()
+        elif what == "coarsen":
+            d.drg_coarsen(c, rp, col, seed=1, rho=0.8, min_nodes=100, max_levels=64).close()
+        else:
+            d.drg_layout(c, rp, col, p, zeros_y(g.n))
+
+    probe = CountingAllocator()
+    c = _ctx_with(probe)
+    call(c)
+    c.close()
+    total = probe.done
+    assert total > 1 and not probe.live
+    for k in sorted({0, 1, total // 2, total - 1}):
+        al = CountingAllocator(fail_after=k)
+        c = _ctx_with(al)
+        with pytest.raises(d.DrgError) as e:
+            call(c)
+        say(" ", what, "fail after", k, "of", total, "->", e.value.status)
+        assert e.value.status == d.DRG_E_OOM
+        assert al.refused == 1 and not al.live
+        c.close()
+
+
+def test_checkpoint_and_resume_give_the_same_bits():
+    """A three-level RGG schedule (T = 90: 30 per level) cut at the start of
+    a level, inside a level, at the end of a level (before its refinement)
+    and inside the finest level, then resumed, equals the uninterrupted run
+    bit for bit."""
+    import torch
+    from paper_2008_07799_amd import drgraph as d
+    g = gen.rgg(6000, 0.03, seed=2)
+    c = ctx()
+    rp, col = dev_graph(g)
+    sim = d.drg_build_similarity(c, rp, col, 2)
+    h = d.drg_coarsen(c, rp, col, seed=3, rho=0.8, min_nodes=100, max_levels=3)
+    assert h.levels == 3
+    p = d.layout_params(k=2, M=5, b=2, T=90, min_nodes=100, max_levels=3, seed=3, eta0=0.5)
+    want = zeros_y(g.n)
+    d.drg_layout_run(c, sim, h, p, want)
+    for level, t in ((2, 0), (2, 13), (2, 30), (1, 29), (0, 0), (0, 17), (0, 30)):
+        yl = zeros_y(h.sizes[level])
+        d.drg_layout_run_until(c, sim, h, p, level, t, yl)
+        got = zeros_y(g.n)
+        d.drg_layout_resume(c, sim, h, p, level, t, yl, got)
+        say("  cut at", level, t)
+        assert torch.equal(got, want), (level, t)
+    with pytest.raises(d.DrgError):
+        d.drg_layout_run_until(c, sim, h, p, 1, 31, zeros_y(h.sizes[1]))
+
+
+def test_export_map_matches_composed_map():
+    from paper_2008_07799_amd import drgraph as d
+    g = gen.ba(3000, 3, seed=4)
+    c = ctx()
+    rp, col = dev_graph(g)
+    h = d.drg_coarsen(c, rp, col, seed=2, rho=0.8, min_nodes=50, max_levels=64)
+    assert h.levels >= 2
+    for level in range(1, h.levels):
+        assert np.array_equal(h.export_map(level, g.n), h.export(level, g.n)["cmap"])
+    with pytest.raises(d.DrgError):
+        h.export_map(0, g.n)
