@@ -184,13 +184,15 @@ void build_hierarchy_union(drg_ctx* ctx, const drg_csr* g, const int32_t* gid,
 void init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, float* y);
 void prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* yl, float* yf);
 void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p,
-                 float* y);
+                 float* y, bool staged = false, bool restage = false);
+void prepare_sync_step(drg_ctx* ctx, drg_sim* s);
 template <typename T>
 void init_layout_t(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, T* y);
 template <typename T>
 void prolong_t(drg_ctx* ctx, const drg_hier* h, int32_t level, const T* yl, T* yf);
 template <typename T>
-void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y);
+void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y,
+                   bool staged = false, bool restage = false);
 // window.hip
 // Items of rows_per_item[c] consecutive rows of graph c (rows base[c] ..
 // base[c+1]-1 of s) with the column window of their entries; returns the

@@ -153,11 +153,20 @@ static void launch_win(drg_ctx* ctx, drg_sim* s, const SweepArgs<float>& a, int 
     }
 }
 
+// rec (nullable): the records of the next iteration at this level take the
+// new positions here, so that iteration needs no staging pass.
 template <typename T>
 __global__ void k_apply0(int32_t n, const typename VT<T>::v2* __restrict__ g,
-                         const T* __restrict__ qt, typename VT<T>::v2* __restrict__ y, T eta) {
+                         const T* __restrict__ qt, typename VT<T>::v2* __restrict__ y, T eta,
+                         typename VT<T>::v4* __restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) apply_node<T>(g[i], qt[i], y + i, eta);
+    if (i >= n) return;
+    apply_node<T>(g[i], qt[i], y + i, eta);
+    if (rec) {
+        const typename VT<T>::v2 p = y[i];
+        rec[i].x = p.x;
+        rec[i].y = p.y;
+    }
 }
 
 // One lane per level node: the members' steps and anchor weights summed in
@@ -308,7 +317,8 @@ void prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* yl, fl
 }
 
 template <typename T>
-void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y) {
+void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y,
+                   bool staged, bool restage) {
     constexpr bool F32 = std::is_same<T, float>::value;
     if (!s || !p || !y) throw Error(DRG_E_INVALID, "layout_step: NULL argument");
     if (p->M < 0 || p->b < 1 || p->b > 3)
@@ -389,7 +399,10 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
             a.w = reinterpret_cast<const T*>(s->wlev.get());
         }
     }
-    if (!async || blocked) {
+    // staged: the records already hold y (the previous level-0 sync step of
+    // a schedule wrote them); restage: this level-0 sync step writes them
+    if (async || level != 0) staged = restage = false;
+    if ((!async || blocked) && !staged) {
         hipLaunchKernelGGL(k_stage<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, cmap,
                            reinterpret_cast<const v2*>(y), invZ, F32 ? s->invZlo.get() : nullptr,
                            rec);
@@ -415,7 +428,8 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
             if (ctx->profiling) ctx->events.emplace_back(e0, e1);
             if (level == 0) {
                 hipLaunchKernelGGL(k_apply0<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, g,
-                                   qt, reinterpret_cast<v2*>(y), (T)p->eta);
+                                   qt, reinterpret_cast<v2*>(y), (T)p->eta,
+                                   restage ? rec : nullptr);
             } else {
                 const drg_level& L = h->lv[level];
                 hipLaunchKernelGGL(k_apply_level<T>, dim3(ceil_div(nl, 256)), dim3(256), 0, st, nl,
@@ -462,7 +476,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     if (!async) {
         if (level == 0) {
             hipLaunchKernelGGL(k_apply0<T>, dim3(ceil_div(n0, 256)), dim3(256), 0, st, n0, g, qt,
-                               reinterpret_cast<v2*>(y), (T)p->eta);
+                               reinterpret_cast<v2*>(y), (T)p->eta, restage ? rec : nullptr);
         } else {
             const drg_level& L = h->lv[level];
             hipLaunchKernelGGL(k_apply_level<T>, dim3(ceil_div(nl, 256)), dim3(256), 0, st, nl,
@@ -474,13 +488,25 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
 }
 
 template void layout_step_t<float>(drg_ctx*, drg_sim*, const drg_hier*, const drg_step_params*,
-                                   float*);
+                                   float*, bool, bool);
 template void layout_step_t<double>(drg_ctx*, drg_sim*, const drg_hier*, const drg_step_params*,
-                                    double*);
+                                    double*, bool, bool);
 
 void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p,
-                 float* y) {
-    layout_step_t<float>(ctx, s, h, p, y);
+                 float* y, bool staged, bool restage) {
+    layout_step_t<float>(ctx, s, h, p, y, staged, restage);
+}
+
+// Everything a synchronous FP32 step builds on first use, built now (before
+// a step is recorded into a graph).
+void prepare_sync_step(drg_ctx* ctx, drg_sim* s) {
+    if (s->blk_nb > 0 || !window_wanted(s)) return;
+    const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
+    const int rpl = win_rpl();
+    if (s->win_rpl != rpl) {
+        s->win_n = build_window_items(ctx, s, {0, s->n}, {(WIN_BLOCK / G) * rpl}, s->win_items);
+        s->win_rpl = rpl;
+    }
 }
 
 }  // namespace drg

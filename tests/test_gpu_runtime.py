@@ -161,3 +161,48 @@ def test_export_map_matches_composed_map():
         assert np.array_equal(h.export_map(level, g.n), h.export(level, g.n)["cmap"])
     with pytest.raises(d.DrgError):
         h.export_map(0, g.n)
+
+
+@pytest.mark.parametrize("graph_mode", ["0", "1"])
+@pytest.mark.parametrize("name", ["grid32", "rgg_3levels", "rmat13_blocked"])
+def test_schedule_run_equals_step_by_step(monkeypatch, graph_mode, name):
+    """drg_layout_run (recorded into one graph or launched step by step, and
+    with the records of a level-0 step written by the previous step's apply)
+    equals the schedule driven from the host through drg_init_layout,
+    drg_layout_step and drg_prolong, bit for bit."""
+    import numpy as np
+    from paper_2008_07799_amd import drgraph as d
+    monkeypatch.setenv("DRG_RUN_GRAPH", graph_mode)
+    if name == "grid32":
+        g, k, b, T, mn, ml = gen.grid(32, 32), 3, 3, 40, 1 << 30, 1
+    elif name == "rgg_3levels":
+        g, k, b, T, mn, ml = gen.rgg(6000, 0.03, seed=2), 2, 2, 45, 100, 3
+    else:
+        g, k, b, T, mn, ml = gen.rmat(13, 16, seed=1), 2, 1, 12, 1000, 64
+    c = ctx()
+    rp, col = dev_graph(g)
+    sim = d.drg_build_similarity(c, rp, col, k)
+    assert sim.blocked == (name == "rmat13_blocked")
+    h = d.drg_coarsen(c, rp, col, seed=5, rho=0.8, min_nodes=mn, max_levels=ml)
+    p = d.layout_params(k=k, M=5, b=b, T=T, min_nodes=mn, max_levels=ml, seed=5, eta0=0.5)
+    want = zeros_y(g.n)
+    d.drg_layout_run(c, sim, h, p, want)
+    Lc = h.levels
+    y = zeros_y(h.sizes[-1])
+    d.drg_init_layout(c, h.sizes[-1], 5, Lc - 1, y)
+    git = 0
+    base = T // Lc
+    for l in range(Lc - 1, -1, -1):
+        Tl = base + (T - base * Lc if l == 0 else 0)
+        gam = 0.01 if (l == Lc - 1 and Lc > 1) else 0.1
+        for t in range(Tl):
+            eta = float(np.float32(0.5 * (1.0 - t / Tl)))
+            d.drg_layout_step(c, sim, h, y, M=5, b=b, gamma=gam, eta=eta, clip=4.0, level=l,
+                              seed=5, iter=git)
+            git += 1
+        if l > 0:
+            yf = zeros_y(h.sizes[l - 1])
+            d.drg_prolong(c, h, l, y, yf)
+            y = yf
+    say(" ", name, "graph", graph_mode, "levels", Lc)
+    assert np.array_equal(y.cpu().numpy(), want.cpu().numpy())
