@@ -231,6 +231,140 @@ def cpu_baseline(cfg: dict, workload_pairs: float = 0.0, workload_nnz: float = 0
     return out
 
 
+def cpu_plan() -> dict:
+    """The oracle timed on the host (FP64, one thread) over the workloads:
+    the 32x32 grid and the 100k-node RGG in full; R-MAT 2^20 at k = 1 in full;
+    R-MAT 2^16 at k = 2 (similarity and 10 level-0 iterations) with the
+    2^20-node k = 2 layout extrapolated from its rates; 16 graphs of the
+    512-graph batch spanning its size range, with the whole batch
+    extrapolated by pair count; the autograd workload's forward and gradient
+    on R-MAT 2^18.  Extrapolated figures are labelled."""
+    from oracle import drgo
+    from paper_2008_07799_amd import gen
+
+    drgo.build()
+    out = {"kind": "oracle", "cores": 1, "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+
+    def log(*a):
+        print("[cpu-plan]", *a, file=sys.stderr, flush=True)
+
+    def similarity(g, k, tag):
+        """drgo.similarity in its three steps (count, fill, normalise), each
+        reported as it ends."""
+        L = drgo.lib()
+        rp32 = np.ascontiguousarray(g.row_ptr, np.int32)
+        col32 = np.ascontiguousarray(g.col, np.int32)
+        out_rp = np.zeros(g.n + 1, np.int64)
+        nnz = L.drgo_khop_count(g.n, rp32, col32, int(k), out_rp)
+        log(tag, f"pattern counted: {nnz} entries")
+        out_col = np.zeros(max(nnz, 1), np.int32)
+        out_hop = np.zeros(max(nnz, 1), np.uint8)
+        L.drgo_khop_fill(g.n, rp32, col32, int(k), out_rp, out_col, out_hop)
+        log(tag, "pattern filled")
+        sim = drgo.similarity_from_pattern(g.n, k, 1.0, out_rp, out_col[:nnz], out_hop[:nnz])
+        log(tag, "similarity normalised")
+        return sim
+
+    def full_layout(g, k, M, b, T, min_nodes, max_levels, seed=0, tag=""):
+        t0 = time.perf_counter()
+        sim = similarity(g, k, tag)
+        t_sim = time.perf_counter() - t0
+        hier = drgo.hierarchy(g, seed, 0.8, min_nodes, max_levels)
+        t_h = time.perf_counter() - t0 - t_sim
+        Lc = hier.levels
+        y = drgo.init(hier.sizes[-1], seed, Lc - 1)
+        gi, last = 0, time.perf_counter()
+        t1 = time.perf_counter()
+        for (l, Tl, gam) in drgo.schedule(T, Lc, 0.1, 0.01):
+            cm = None if l == 0 else hier.cmaps[l]
+            for t in range(Tl):
+                drgo.iter_sync(sim, y, cm, M, b, gam, drgo.eta_at(1.0, t, Tl), 4.0, seed, gi)
+                gi += 1
+                if time.perf_counter() - last > 20:
+                    last = time.perf_counter()
+                    log(tag, f"iteration {gi}/{T}")
+            if l > 0:
+                y = y[hier.maps[l - 1]].copy()
+        t_it = time.perf_counter() - t1
+        pairs = sim.nnz + M * sim.n_active
+        return {"time_to_layout_s": time.perf_counter() - t0, "similarity_s": t_sim,
+                "hierarchy_s": t_h, "iterations_s": t_it, "levels": hier.sizes, "nnz_P": sim.nnz,
+                "pair_updates_per_s": T * pairs / t_it}
+
+    log("grid32")
+    out["grid32_k3"] = full_layout(gen.grid(32, 32), 3, 5, 3, 300, 1 << 30, 1, tag="grid32")
+    log("rgg100k")
+    out["rgg100k_k3"] = full_layout(gen.named("rgg100k"), 3, 10, 2, 500, 1, 3, tag="rgg100k")
+    log("rmat20 k=1")
+    g20 = gen.named("rmat20")
+    out["rmat20_k1"] = full_layout(g20, 1, 5, 1, 500, 1000, 64, tag="rmat20 k=1")
+    del g20
+    log("rmat16 k=2 sample")
+    g16 = gen.rmat(16, 16, seed=0)
+    t0 = time.perf_counter()
+    sim = similarity(g16, 2, "rmat16")
+    t_sim = time.perf_counter() - t0
+    y = drgo.init(g16.n, 0, 0)
+    t0 = time.perf_counter()
+    for it in range(10):
+        drgo.iter_sync(sim, y, None, 5, 1, 0.1, 1.0, 4.0, 0, it)
+        log("rmat16 iteration", it)
+    t_it = time.perf_counter() - t0
+    pairs16 = sim.nnz + 5 * sim.n_active
+    rate = 10 * pairs16 / t_it
+    # R-MAT 2^20, k = 2: pattern entries and active nodes as the library counts
+    # them (its rows match the oracle rows-only similarity on sampled rows)
+    nnz20, na20 = 23762699968, 646140
+    out["rmat16_k2_sample"] = {
+        "nnz_P": sim.nnz, "similarity_s": t_sim, "iterations": 10, "iterations_s": t_it,
+        "pair_updates_per_s": rate, "similarity_entries_per_s": sim.nnz / t_sim,
+        "extrapolated_rmat20_k2_time_to_layout_s": {
+            "value": 500 * (nnz20 + 5 * na20) / rate + nnz20 / (sim.nnz / t_sim),
+            "note": "EXTRAPOLATED from the 2^16 sample's rates to nnz 2.376e10, 500 "
+                    "iterations; the oracle cannot hold that pattern (about 310 GB)"}}
+    del sim
+    log("batch subset")
+    graphs = gen.batch_graphs(512)
+    order = np.argsort([g.n for g in graphs], kind="stable")
+    pick = [int(order[i]) for i in range(0, 512, 32)]
+    t_sub, work_sub = 0.0, 0.0
+    for c in pick:
+        g = graphs[c]
+        b = 3 if c % 2 == 0 else 1
+        r = full_layout(g, 3, 5, b, 300, 1000, 64, seed=c, tag=f"batch graph {c}")
+        log(f"batch graph {c} (n={g.n}) done")
+        t_sub += r["time_to_layout_s"]
+        work_sub += 300 * (r["nnz_P"] + 5 * int(np.count_nonzero(np.diff(g.row_ptr))))
+    work_all = 0.0
+    for g in graphs:
+        rp = np.zeros(g.n + 1, np.int64)
+        nnz = drgo.lib().drgo_khop_count(g.n, np.ascontiguousarray(g.row_ptr, np.int32),
+                                         np.ascontiguousarray(g.col, np.int32), 3, rp)
+        work_all += 300 * (nnz + 5 * int(np.count_nonzero(np.diff(g.row_ptr))))
+    out["batch512_k3_subset"] = {
+        "graphs": pick, "subset_time_to_layout_s": t_sub,
+        "extrapolated_batch_time_to_layout_s": {
+            "value": t_sub * work_all / work_sub,
+            "note": "EXTRAPOLATED from the 16-graph subset by pair count (T x (nnz + M N_a))"}}
+    del graphs
+    log("autograd rmat18 forward + gradient")
+    g18 = gen.named("rmat18")
+    t0 = time.perf_counter()
+    sim = similarity(g18, 2, "rmat18")
+    t_sim = time.perf_counter() - t0
+    y = np.random.default_rng(0).uniform(-5, 5, size=(g18.n, 2))
+    t0 = time.perf_counter()
+    drgo.objective(sim, y, 5, 1, 0.1, 0, 0)
+    t_f = time.perf_counter() - t0
+    log("rmat18 forward done")
+    t0 = time.perf_counter()
+    drgo.objective_grad(sim, y, 5, 1, 0.1, 0, 0)
+    t_g = time.perf_counter() - t0
+    out["autograd_rmat18_k2"] = {"nnz_P": sim.nnz, "similarity_s": t_sim, "forward_s": t_f,
+                                 "gradient_s": t_g}
+    return out
+
+
 def bench_autograd(args):
     """The differentiable form on R-MAT 2^18 (edge factor 8), k=2, M=5, b=1:
     one step = L^ forward (library) + anchor MSE on 1% of the nodes, backward
@@ -461,7 +595,12 @@ def main():
                     help="only print the source hash of a profiled kernel")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 8 times (counter calibration)")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="only time the CPU oracle over the workloads (about 20 minutes)")
     args = ap.parse_args()
+    if args.cpu_plan:
+        print(json.dumps(cpu_plan()), flush=True)
+        return
     if args.source_hash:
         print(_kernel_source_hash(args.source_hash))
         return
