@@ -231,7 +231,7 @@ def cpu_baseline(cfg: dict, workload_pairs: float = 0.0, workload_nnz: float = 0
     return out
 
 
-def cpu_plan() -> dict:
+def cpu_plan(parts: str = "abcdef") -> dict:
     """The oracle timed on the host (FP64, one thread) over the workloads:
     the 32x32 grid and the 100k-node RGG in full; R-MAT 2^20 at k = 1 in full;
     R-MAT 2^16 at k = 2 (similarity and 10 level-0 iterations) with the
@@ -247,6 +247,10 @@ def cpu_plan() -> dict:
 
     def log(*a):
         print("[cpu-plan]", *a, file=sys.stderr, flush=True)
+
+    def done(key):
+        # each workload's figures as soon as they are measured
+        print(json.dumps({"cpu_plan_part": key, **out[key]}), flush=True)
 
     def similarity(g, k, tag):
         """drgo.similarity in its three steps (count, fill, normalise), each
@@ -291,14 +295,35 @@ def cpu_plan() -> dict:
                 "hierarchy_s": t_h, "iterations_s": t_it, "levels": hier.sizes, "nnz_P": sim.nnz,
                 "pair_updates_per_s": T * pairs / t_it}
 
-    log("grid32")
-    out["grid32_k3"] = full_layout(gen.grid(32, 32), 3, 5, 3, 300, 1 << 30, 1, tag="grid32")
-    log("rgg100k")
-    out["rgg100k_k3"] = full_layout(gen.named("rgg100k"), 3, 10, 2, 500, 1, 3, tag="rgg100k")
-    log("rmat20 k=1")
-    g20 = gen.named("rmat20")
-    out["rmat20_k1"] = full_layout(g20, 1, 5, 1, 500, 1000, 64, tag="rmat20 k=1")
-    del g20
+    if "a" in parts:
+        log("grid32")
+        out["grid32_k3"] = full_layout(gen.grid(32, 32), 3, 5, 3, 300, 1 << 30, 1, tag="grid32")
+        done("grid32_k3")
+    if "b" in parts:
+        log("rgg100k")
+        out["rgg100k_k3"] = full_layout(gen.named("rgg100k"), 3, 10, 2, 500, 1, 3, tag="rgg100k")
+        done("rgg100k_k3")
+    if "c" in parts:
+        log("rmat20 k=1")
+        g20 = gen.named("rmat20")
+        out["rmat20_k1"] = full_layout(g20, 1, 5, 1, 500, 1000, 64, tag="rmat20 k=1")
+        del g20
+        done("rmat20_k1")
+    if "d" in parts:
+        rmat16_part(out, log, similarity)
+        done("rmat16_k2_sample")
+    if "e" in parts:
+        batch_part(out, log, full_layout)
+        done("batch512_k3_subset")
+    if "f" in parts:
+        autograd_part(out, log, similarity)
+        done("autograd_rmat18_k2")
+    return out
+
+
+def rmat16_part(out, log, similarity):
+    from oracle import drgo
+    from paper_2008_07799_amd import gen
     log("rmat16 k=2 sample")
     g16 = gen.rmat(16, 16, seed=0)
     t0 = time.perf_counter()
@@ -323,6 +348,11 @@ def cpu_plan() -> dict:
             "note": "EXTRAPOLATED from the 2^16 sample's rates to nnz 2.376e10, 500 "
                     "iterations; the oracle cannot hold that pattern (about 310 GB)"}}
     del sim
+
+
+def batch_part(out, log, full_layout):
+    from oracle import drgo
+    from paper_2008_07799_amd import gen
     log("batch subset")
     graphs = gen.batch_graphs(512)
     order = np.argsort([g.n for g in graphs], kind="stable")
@@ -347,6 +377,11 @@ def cpu_plan() -> dict:
             "value": t_sub * work_all / work_sub,
             "note": "EXTRAPOLATED from the 16-graph subset by pair count (T x (nnz + M N_a))"}}
     del graphs
+
+
+def autograd_part(out, log, similarity):
+    from oracle import drgo
+    from paper_2008_07799_amd import gen
     log("autograd rmat18 forward + gradient")
     g18 = gen.named("rmat18")
     t0 = time.perf_counter()
@@ -362,7 +397,6 @@ def cpu_plan() -> dict:
     t_g = time.perf_counter() - t0
     out["autograd_rmat18_k2"] = {"nnz_P": sim.nnz, "similarity_s": t_sim, "forward_s": t_f,
                                  "gradient_s": t_g}
-    return out
 
 
 def bench_autograd(args):
@@ -595,11 +629,13 @@ def main():
                     help="only print the source hash of a profiled kernel")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 8 times (counter calibration)")
-    ap.add_argument("--cpu-plan", action="store_true",
-                    help="only time the CPU oracle over the workloads (about 20 minutes)")
+    ap.add_argument("--cpu-plan", default="", metavar="PARTS",
+                    help="only time the CPU oracle over the workloads: a grid32, b rgg100k, "
+                         "c rmat20 k=1, d rmat16 k=2 sample, e batch subset, f autograd "
+                         "(e.g. abcdef; about 20 minutes in all)")
     args = ap.parse_args()
     if args.cpu_plan:
-        print(json.dumps(cpu_plan()), flush=True)
+        print(json.dumps(cpu_plan(args.cpu_plan)), flush=True)
         return
     if args.source_hash:
         print(_kernel_source_hash(args.source_hash))
