@@ -351,17 +351,20 @@ int64_t drgo_contract(int32_t n, const int32_t* rp, const int32_t* col, const in
 
 /* ------------------------------------------------------------------------ */
 /* Layout of the coarsest graph: random initialisation (Sec. 3.2.3), each   */
-/* coordinate uniform on [-1, 1) on a 2^-23 grid.                            */
+/* coordinate uniform on [-1, 1) on a 2^-23 grid.  Positions are points of  */
+/* R^dim, dim = 2 or 3 (Sec. 3.1); coordinate c of node v is word c of the   */
+/* node's Philox block, so the 2-D layout is the first two coordinates of   */
+/* the 3-D one.                                                              */
 /* ------------------------------------------------------------------------ */
-void drgo_init(int32_t nl, uint64_t seed, int32_t level, double* y) {
+void drgo_init(int32_t nl, uint64_t seed, int32_t level, double* y, int32_t dim) {
     for (int32_t v = 0; v < nl; ++v) {
         uint64_t out[4];
         philox_stream(seed, DRGO_TAG_INIT, (uint64_t)(uint32_t)v, (uint64_t)(uint32_t)level, 0,
                       out);
-        double ux = (double)(out[0] >> 40) * (1.0 / 16777216.0);
-        double uy = (double)(out[1] >> 40) * (1.0 / 16777216.0);
-        y[2 * v] = 2.0 * ux - 1.0;
-        y[2 * v + 1] = 2.0 * uy - 1.0;
+        for (int32_t c = 0; c < dim; ++c) {
+            double u = (double)(out[c] >> 40) * (1.0 / 16777216.0);
+            y[(size_t)dim * v + c] = 2.0 * u - 1.0;
+        }
     }
 }
 
@@ -370,7 +373,8 @@ void drgo_init(int32_t nl, uint64_t seed, int32_t level, double* y) {
 /* d = ||y_i - y_j||:                                                        */
 /*   d/dy_i log w       = -2b d^{2b-2} (y_i - y_j) / (1 + d^{2b})  (attract) */
 /*   d/dy_i log(1 - w)  =  2b (y_i - y_j) / (d^2 (1 + d^{2b}))     (repel)   */
-/* A pair at distance exactly zero contributes nothing.                      */
+/* A pair at distance exactly zero contributes nothing.  Both act along the  */
+/* offset, so they are the same in any dimension.                           */
 /* ------------------------------------------------------------------------ */
 static double ipow(double x, int32_t b) {
     double r = 1.0;
@@ -391,39 +395,42 @@ static double repel_coef(double d2, int32_t b) {
     return 2.0 * (double)b / (d2 * (1.0 + D));
 }
 
+/* offset d = y_a - y_c (dim components) and its squared length, summed in
+ * component order */
+static double offset(const double* y, int32_t a, int32_t c, int32_t dim, double* d) {
+    double d2 = 0.0;
+    for (int32_t k = 0; k < dim; ++k) {
+        d[k] = y[(size_t)dim * a + k] - y[(size_t)dim * c + k];
+        d2 += d[k] * d[k];
+    }
+    return d2;
+}
+
 void drgo_step_direction(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                          const double* qt, const uint64_t* C, const int32_t* cmap, const double* y,
                          int32_t M, int32_t b, double gamma, double clip, uint64_t seed,
-                         uint64_t it, double* g) {
+                         uint64_t it, double* g, int32_t dim) {
     for (int32_t i = 0; i < n0; ++i) {
-        g[2 * i] = 0.0;
-        g[2 * i + 1] = 0.0;
+        for (int32_t k = 0; k < dim; ++k) g[(size_t)dim * i + k] = 0.0;
         if (prp[i + 1] == prp[i]) continue; /* isolated: never anchors */
         int32_t a = cmap ? cmap[i] : i;
-        double yx = y[2 * a], yy = y[2 * a + 1];
-        double ax = 0.0, ay = 0.0;
+        double A[3] = {0.0, 0.0, 0.0}, R[3] = {0.0, 0.0, 0.0}, d[3];
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
             int32_t c = cmap ? cmap[pcol[x]] : pcol[x];
-            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, a, c, dim, d);
             if (d2 == 0.0) continue;
             double k = attract_coef(d2, b);
-            ax += P[x] * clipd(k * dx, clip);
-            ay += P[x] * clipd(k * dy, clip);
+            for (int32_t q = 0; q < dim; ++q) A[q] += P[x] * clipd(k * d[q], clip);
         }
-        double rx = 0.0, ry = 0.0;
         for (int32_t m = 0; m < M; ++m) {
             int32_t v = drgo_draw(C, n0, drgo_neg_word(seed, it, i, m));
             int32_t c = cmap ? cmap[v] : v;
-            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, a, c, dim, d);
             if (d2 == 0.0) continue;
             double k = repel_coef(d2, b);
-            rx += clipd(k * dx, clip);
-            ry += clipd(k * dy, clip);
+            for (int32_t q = 0; q < dim; ++q) R[q] += clipd(k * d[q], clip);
         }
-        g[2 * i] = ax + gamma * qt[i] * rx;
-        g[2 * i + 1] = ay + gamma * qt[i] * ry;
+        for (int32_t q = 0; q < dim; ++q) g[(size_t)dim * i + q] = A[q] + gamma * qt[i] * R[q];
     }
 }
 
@@ -445,20 +452,19 @@ static double* level_weights(int32_t n0, const double* qt, const int32_t* cmap, 
 void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                     const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
                     int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
-                    uint64_t it) {
-    double* g = (double*)malloc(sizeof(double) * 2 * (size_t)(n0 > 0 ? n0 : 1));
-    double* G = (double*)calloc(2 * (size_t)(nl > 0 ? nl : 1), sizeof(double));
+                    uint64_t it, int32_t dim) {
+    double* g = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n0 > 0 ? n0 : 1));
+    double* G = (double*)calloc((size_t)dim * (size_t)(nl > 0 ? nl : 1), sizeof(double));
     double* w = level_weights(n0, qt, cmap, nl);
-    drgo_step_direction(n0, prp, pcol, P, qt, C, cmap, y, M, b, gamma, clip, seed, it, g);
+    drgo_step_direction(n0, prp, pcol, P, qt, C, cmap, y, M, b, gamma, clip, seed, it, g, dim);
     for (int32_t i = 0; i < n0; ++i) {
         int32_t a = cmap ? cmap[i] : i;
-        G[2 * a] += g[2 * i];
-        G[2 * a + 1] += g[2 * i + 1];
+        for (int32_t q = 0; q < dim; ++q) G[(size_t)dim * a + q] += g[(size_t)dim * i + q];
     }
     for (int32_t a = 0; a < nl; ++a) {
         if (w[a] <= 0.0) continue;
-        y[2 * a] += eta * (G[2 * a] / w[a]);
-        y[2 * a + 1] += eta * (G[2 * a + 1] / w[a]);
+        for (int32_t q = 0; q < dim; ++q)
+            y[(size_t)dim * a + q] += eta * (G[(size_t)dim * a + q] / w[a]);
     }
     free(w);
     free(g);
@@ -471,35 +477,29 @@ void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const d
 void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                    const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
                    int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
-                   uint64_t it) {
+                   uint64_t it, int32_t dim) {
     double* w = level_weights(n0, qt, cmap, nl);
     for (int32_t i = 0; i < n0; ++i) {
         if (prp[i + 1] == prp[i]) continue;
         int32_t a = cmap ? cmap[i] : i;
-        double yx = y[2 * a], yy = y[2 * a + 1];
-        double ax = 0.0, ay = 0.0;
+        double A[3] = {0.0, 0.0, 0.0}, R[3] = {0.0, 0.0, 0.0}, d[3];
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
             int32_t c = cmap ? cmap[pcol[x]] : pcol[x];
-            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, a, c, dim, d);
             if (d2 == 0.0) continue;
             double k = attract_coef(d2, b);
-            ax += P[x] * clipd(k * dx, clip);
-            ay += P[x] * clipd(k * dy, clip);
+            for (int32_t q = 0; q < dim; ++q) A[q] += P[x] * clipd(k * d[q], clip);
         }
-        double rx = 0.0, ry = 0.0;
         for (int32_t m = 0; m < M; ++m) {
             int32_t v = drgo_draw(C, n0, drgo_neg_word(seed, it, i, m));
             int32_t c = cmap ? cmap[v] : v;
-            double dx = yx - y[2 * c], dy = yy - y[2 * c + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, a, c, dim, d);
             if (d2 == 0.0) continue;
             double k = repel_coef(d2, b);
-            rx += clipd(k * dx, clip);
-            ry += clipd(k * dy, clip);
+            for (int32_t q = 0; q < dim; ++q) R[q] += clipd(k * d[q], clip);
         }
-        y[2 * a] += eta * ((ax + gamma * qt[i] * rx) / w[a]);
-        y[2 * a + 1] += eta * ((ay + gamma * qt[i] * ry) / w[a]);
+        for (int32_t q = 0; q < dim; ++q)
+            y[(size_t)dim * a + q] += eta * ((A[q] + gamma * qt[i] * R[q]) / w[a]);
     }
     free(w);
 }
@@ -513,22 +513,19 @@ void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const do
 /* ------------------------------------------------------------------------ */
 double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                       const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
-                      double gamma, uint64_t seed, uint64_t it) {
-    double L = 0.0;
+                      double gamma, uint64_t seed, uint64_t it, int32_t dim) {
+    double L = 0.0, d[3];
     for (int32_t i = 0; i < n; ++i) {
         if (prp[i + 1] == prp[i]) continue;
         double att = 0.0;
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
-            int32_t j = pcol[x];
-            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, pcol[x], dim, d);
             att += P[x] * (-log1p(ipow(d2, b)));
         }
         double rep = 0.0;
         for (int32_t m = 0; m < M; ++m) {
             int32_t v = drgo_draw(C, n, drgo_neg_word(seed, it, i, m));
-            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, v, dim, d);
             if (v == i || d2 == 0.0) continue;
             rep += (double)b * log(d2) - log1p(ipow(d2, b));
         }
@@ -539,32 +536,31 @@ double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const 
 
 void drgo_objective_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                          const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
-                         double gamma, uint64_t seed, uint64_t it, double* grad) {
-    for (int32_t i = 0; i < 2 * n; ++i) grad[i] = 0.0;
+                         double gamma, uint64_t seed, uint64_t it, double* grad, int32_t dim) {
+    double d[3];
+    for (int64_t t = 0; t < (int64_t)dim * n; ++t) grad[t] = 0.0;
     for (int32_t i = 0; i < n; ++i) {
         if (prp[i + 1] == prp[i]) continue;
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
             int32_t j = pcol[x];
-            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, j, dim, d);
             if (d2 == 0.0) continue;
             double k = attract_coef(d2, b);
             /* the term P~_ij log w_ij depends on both y_i and y_j */
-            grad[2 * i] += P[x] * k * dx;
-            grad[2 * i + 1] += P[x] * k * dy;
-            grad[2 * j] -= P[x] * k * dx;
-            grad[2 * j + 1] -= P[x] * k * dy;
+            for (int32_t q = 0; q < dim; ++q) {
+                grad[(size_t)dim * i + q] += P[x] * k * d[q];
+                grad[(size_t)dim * j + q] -= P[x] * k * d[q];
+            }
         }
         for (int32_t m = 0; m < M; ++m) {
             int32_t v = drgo_draw(C, n, drgo_neg_word(seed, it, i, m));
-            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, v, dim, d);
             if (v == i || d2 == 0.0) continue;
             double k = gamma * qt[i] * repel_coef(d2, b);
-            grad[2 * i] += k * dx;
-            grad[2 * i + 1] += k * dy;
-            grad[2 * v] -= k * dx;
-            grad[2 * v + 1] -= k * dy;
+            for (int32_t q = 0; q < dim; ++q) {
+                grad[(size_t)dim * i + q] += k * d[q];
+                grad[(size_t)dim * v + q] -= k * d[q];
+            }
         }
     }
 }
@@ -576,20 +572,16 @@ static double draw_prob(const uint64_t* C, int32_t n, int32_t v) {
 
 double drgo_objective_exact(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                             const double* qt, const uint64_t* C, const double* y, int32_t M,
-                            int32_t b, double gamma) {
-    double L = 0.0;
+                            int32_t b, double gamma, int32_t dim) {
+    double L = 0.0, d[3];
     for (int32_t i = 0; i < n; ++i) {
         if (prp[i + 1] == prp[i]) continue;
-        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
-            int32_t j = pcol[x];
-            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
-            L += P[x] * (-log1p(ipow(dx * dx + dy * dy, b)));
-        }
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x)
+            L += P[x] * (-log1p(ipow(offset(y, i, pcol[x], dim, d), b)));
         double rep = 0.0;
         for (int32_t v = 0; v < n; ++v) {
             double pv = draw_prob(C, n, v);
-            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, v, dim, d);
             if (v == i || d2 == 0.0 || pv == 0.0) continue;
             rep += pv * ((double)b * log(d2) - log1p(ipow(d2, b)));
         }
@@ -600,62 +592,56 @@ double drgo_objective_exact(int32_t n, const int64_t* prp, const int32_t* pcol, 
 
 void drgo_objective_exact_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                                const double* qt, const uint64_t* C, const double* y, int32_t M,
-                               int32_t b, double gamma, double* grad) {
-    for (int32_t i = 0; i < 2 * n; ++i) grad[i] = 0.0;
+                               int32_t b, double gamma, double* grad, int32_t dim) {
+    double d[3];
+    for (int64_t t = 0; t < (int64_t)dim * n; ++t) grad[t] = 0.0;
     for (int32_t i = 0; i < n; ++i) {
         if (prp[i + 1] == prp[i]) continue;
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
             int32_t j = pcol[x];
-            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, j, dim, d);
             if (d2 == 0.0) continue;
             double k = P[x] * attract_coef(d2, b);
-            grad[2 * i] += k * dx;
-            grad[2 * i + 1] += k * dy;
-            grad[2 * j] -= k * dx;
-            grad[2 * j + 1] -= k * dy;
+            for (int32_t q = 0; q < dim; ++q) {
+                grad[(size_t)dim * i + q] += k * d[q];
+                grad[(size_t)dim * j + q] -= k * d[q];
+            }
         }
         for (int32_t v = 0; v < n; ++v) {
             double pv = draw_prob(C, n, v);
-            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, v, dim, d);
             if (v == i || d2 == 0.0 || pv == 0.0) continue;
             double k = gamma * qt[i] * (double)M * pv * repel_coef(d2, b);
-            grad[2 * i] += k * dx;
-            grad[2 * i + 1] += k * dy;
-            grad[2 * v] -= k * dx;
-            grad[2 * v + 1] -= k * dy;
+            for (int32_t q = 0; q < dim; ++q) {
+                grad[(size_t)dim * i + q] += k * d[q];
+                grad[(size_t)dim * v + q] -= k * d[q];
+            }
         }
     }
 }
 
 void drgo_step_expected(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                         const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
-                        double gamma, double* g) {
+                        double gamma, double* g, int32_t dim) {
+    double d[3];
     for (int32_t i = 0; i < n; ++i) {
-        g[2 * i] = 0.0;
-        g[2 * i + 1] = 0.0;
+        for (int32_t q = 0; q < dim; ++q) g[(size_t)dim * i + q] = 0.0;
         if (prp[i + 1] == prp[i]) continue;
-        double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
+        double A[3] = {0.0, 0.0, 0.0}, R[3] = {0.0, 0.0, 0.0};
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
-            int32_t j = pcol[x];
-            double dx = y[2 * i] - y[2 * j], dy = y[2 * i + 1] - y[2 * j + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, pcol[x], dim, d);
             if (d2 == 0.0) continue;
             double k = attract_coef(d2, b);
-            ax += P[x] * k * dx;
-            ay += P[x] * k * dy;
+            for (int32_t q = 0; q < dim; ++q) A[q] += P[x] * k * d[q];
         }
         for (int32_t v = 0; v < n; ++v) {
             double pv = draw_prob(C, n, v);
-            double dx = y[2 * i] - y[2 * v], dy = y[2 * i + 1] - y[2 * v + 1];
-            double d2 = dx * dx + dy * dy;
+            double d2 = offset(y, i, v, dim, d);
             if (d2 == 0.0 || pv == 0.0) continue;
             double k = repel_coef(d2, b);
-            rx += pv * k * dx;
-            ry += pv * k * dy;
+            for (int32_t q = 0; q < dim; ++q) R[q] += pv * k * d[q];
         }
-        g[2 * i] = ax + gamma * qt[i] * (double)M * rx;
-        g[2 * i + 1] = ay + gamma * qt[i] * (double)M * ry;
+        for (int32_t q = 0; q < dim; ++q)
+            g[(size_t)dim * i + q] = A[q] + gamma * qt[i] * (double)M * R[q];
     }
 }

@@ -64,26 +64,28 @@ def lib():
     L.drgo_coarsen_level.restype = C.c_int32
     L.drgo_contract.argtypes = [C.c_int32, _i32p, _i32p, _i32p, C.c_int32, _i32p, _i32p]
     L.drgo_contract.restype = C.c_int64
-    L.drgo_init.argtypes = [C.c_int32, C.c_uint64, C.c_int32, _f64p]
+    L.drgo_init.argtypes = [C.c_int32, C.c_uint64, C.c_int32, _f64p, C.c_int32]
     cmap_t = C.c_void_p
     step_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, cmap_t, _f64p,
-                 C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_uint64, _f64p]
+                 C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_uint64, _f64p,
+                 C.c_int32]
     L.drgo_step_direction.argtypes = step_args
     it_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, cmap_t, C.c_int32, _f64p,
-               C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64]
+               C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64,
+               C.c_int32]
     L.drgo_iter_sync.argtypes = it_args
     L.drgo_iter_seq.argtypes = it_args
     obj_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, _f64p, C.c_int32, C.c_int32,
                 C.c_double, C.c_uint64, C.c_uint64]
-    L.drgo_objective.argtypes = obj_args
+    L.drgo_objective.argtypes = obj_args + [C.c_int32]
     L.drgo_objective.restype = C.c_double
-    L.drgo_objective_grad.argtypes = obj_args + [_f64p]
+    L.drgo_objective_grad.argtypes = obj_args + [_f64p, C.c_int32]
     ex_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, _f64p, C.c_int32, C.c_int32,
                C.c_double]
-    L.drgo_objective_exact.argtypes = ex_args
+    L.drgo_objective_exact.argtypes = ex_args + [C.c_int32]
     L.drgo_objective_exact.restype = C.c_double
-    L.drgo_objective_exact_grad.argtypes = ex_args + [_f64p]
-    L.drgo_step_expected.argtypes = ex_args + [_f64p]
+    L.drgo_objective_exact_grad.argtypes = ex_args + [_f64p, C.c_int32]
+    L.drgo_step_expected.argtypes = ex_args + [_f64p, C.c_int32]
     _lib = L
     return L
 
@@ -257,10 +259,11 @@ def hierarchy(csr, seed: int = 0, rho: float = 0.8, min_nodes: int = 1000,
     return Hier(graphs, maps, cm)
 
 
-def init(nl: int, seed: int, level: int) -> np.ndarray:
-    y = np.zeros(2 * max(nl, 1), np.float64)
-    lib().drgo_init(int(nl), int(seed), int(level), y)
-    return y[: 2 * nl].reshape(nl, 2)
+def init(nl: int, seed: int, level: int, dim: int = 2) -> np.ndarray:
+    """Coarsest-level layout, [nl, dim] (dim 2 or 3, Sec. 3.1)."""
+    y = np.zeros(dim * max(nl, 1), np.float64)
+    lib().drgo_init(int(nl), int(seed), int(level), y, int(dim))
+    return y[: dim * nl].reshape(nl, dim)
 
 
 def _cm_ptr(cmap):
@@ -270,13 +273,21 @@ def _cm_ptr(cmap):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
+def _dim(y) -> int:
+    d = int(np.shape(y)[1])
+    if d not in (2, 3):
+        raise ValueError("coordinates must be [n, 2] or [n, 3]")
+    return d
+
+
 def step_direction(sim: Sim, y, cmap=None, M=5, b=1, gamma=0.1, clip=math.inf, seed=0, it=0):
     keep, p = _cm_ptr(cmap)
-    g = np.zeros(2 * sim.n, np.float64)
+    d = _dim(y)
+    g = np.zeros(d * sim.n, np.float64)
     yy = _c(y, np.float64).ravel()
     lib().drgo_step_direction(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C, p, yy,
-                              int(M), int(b), float(gamma), float(clip), int(seed), int(it), g)
-    return g.reshape(sim.n, 2)
+                              int(M), int(b), float(gamma), float(clip), int(seed), int(it), g, d)
+    return g.reshape(sim.n, d)
 
 
 def _pcol(sim):
@@ -292,46 +303,50 @@ def iter_sync(sim: Sim, y, cmap=None, M=5, b=1, gamma=0.1, eta=1.0, clip=4.0, se
     """One iteration in place on y (level coordinates [nl, 2])."""
     keep, p = _cm_ptr(cmap)
     nl = y.shape[0]
+    d = _dim(y)
     yy = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
     fn = lib().drgo_iter_seq if seq else lib().drgo_iter_sync
     fn(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C, p, nl, yy, int(M), int(b),
-       float(gamma), float(eta), float(clip), int(seed), int(it))
-    y[...] = yy.reshape(nl, 2)
+       float(gamma), float(eta), float(clip), int(seed), int(it), d)
+    y[...] = yy.reshape(nl, d)
     return y
 
 
 def objective(sim, y, M=5, b=1, gamma=0.1, seed=0, it=0) -> float:
     return float(lib().drgo_objective(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
                                       _c(y, np.float64).ravel(), int(M), int(b), float(gamma),
-                                      int(seed), int(it)))
+                                      int(seed), int(it), _dim(y)))
 
 
 def objective_grad(sim, y, M=5, b=1, gamma=0.1, seed=0, it=0) -> np.ndarray:
-    g = np.zeros(2 * sim.n, np.float64)
+    d = _dim(y)
+    g = np.zeros(d * sim.n, np.float64)
     lib().drgo_objective_grad(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
                               _c(y, np.float64).ravel(), int(M), int(b), float(gamma),
-                              int(seed), int(it), g)
-    return g.reshape(sim.n, 2)
+                              int(seed), int(it), g, d)
+    return g.reshape(sim.n, d)
 
 
 def objective_exact(sim, y, M=5, b=1, gamma=0.1) -> float:
     return float(lib().drgo_objective_exact(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt,
                                             sim.C, _c(y, np.float64).ravel(), int(M), int(b),
-                                            float(gamma)))
+                                            float(gamma), _dim(y)))
 
 
 def objective_exact_grad(sim, y, M=5, b=1, gamma=0.1) -> np.ndarray:
-    g = np.zeros(2 * sim.n, np.float64)
+    d = _dim(y)
+    g = np.zeros(d * sim.n, np.float64)
     lib().drgo_objective_exact_grad(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
-                                    _c(y, np.float64).ravel(), int(M), int(b), float(gamma), g)
-    return g.reshape(sim.n, 2)
+                                    _c(y, np.float64).ravel(), int(M), int(b), float(gamma), g, d)
+    return g.reshape(sim.n, d)
 
 
 def step_expected(sim, y, M=5, b=1, gamma=0.1) -> np.ndarray:
-    g = np.zeros(2 * sim.n, np.float64)
+    d = _dim(y)
+    g = np.zeros(d * sim.n, np.float64)
     lib().drgo_step_expected(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
-                             _c(y, np.float64).ravel(), int(M), int(b), float(gamma), g)
-    return g.reshape(sim.n, 2)
+                             _c(y, np.float64).ravel(), int(M), int(b), float(gamma), g, d)
+    return g.reshape(sim.n, d)
 
 
 # ------------------------------------------------------------- full layout
@@ -355,14 +370,14 @@ def eta_at(eta0: float, t: int, Tl: int) -> float:
 
 def layout(csr, k=1, sigma=1.0, M=5, b=1, gamma=0.1, gamma_coarsest=0.01, T=400, eta0=1.0,
            clip=4.0, rho=0.8, min_nodes=1000, max_levels=64, seed=0, mode="sync",
-           sim: Sim | None = None, hier: Hier | None = None, return_all=False):
-    """Full multilevel layout; returns Y^0 [n, 2] (float64)."""
+           sim: Sim | None = None, hier: Hier | None = None, return_all=False, dim=2):
+    """Full multilevel layout; returns Y^0 [n, dim] (float64)."""
     if sim is None:
         sim = similarity(csr, k, sigma)
     if hier is None:
         hier = hierarchy(csr, seed, rho, min_nodes, max_levels)
     Lc = hier.levels
-    y = init(hier.sizes[-1], seed, Lc - 1)
+    y = init(hier.sizes[-1], seed, Lc - 1, dim)
     gi = 0
     for (l, Tl, g) in schedule(T, Lc, gamma, gamma_coarsest):
         cmap = None if l == 0 else hier.cmaps[l]
