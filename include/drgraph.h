@@ -4,8 +4,11 @@
  * Algorithm for Large-scale Graphs by Dimensionality Reduction").
  *
  * Problem (Sec. 3.1): an undirected, unweighted graph G = (V, E) is mapped to
- * 2-D positions Y.  The library takes the graph as CSR in device memory and
- * writes FP32 coordinates [n][2] into caller-owned device memory.
+ * positions Y in R^2 or R^3.  The library takes the graph as CSR in device
+ * memory and writes FP32 coordinates [n][dim] into caller-owned device
+ * memory.  3-D layouts (dim = 3 in the parameters) run the row-form sweep;
+ * the column-blocked copy, the batched form and the quality evaluators are
+ * 2-D only.
  *
  * General conventions
  *   - Every pointer named *_dev is device memory on the context's device;
@@ -80,7 +83,7 @@ typedef struct {
     float clip;              /* per-pair, per-component force clip, > 0 */
     int32_t level;           /* hierarchy level being laid out (0 = finest) */
     int32_t mode;            /* DRG_MODE_SYNC or DRG_MODE_ASYNC */
-    int32_t _pad;
+    int32_t dim;             /* 2 (or 0): positions in R^2, y [n][2]; 3: R^3, y [n][3] */
     uint64_t seed;
     uint64_t iter;           /* global iteration index; keys the negatives */
 } drg_step_params;
@@ -100,7 +103,7 @@ typedef struct {
     int32_t min_nodes;       /* do not coarsen a level with fewer active nodes */
     int32_t max_levels;      /* at most this many levels (1 = single level) */
     int32_t mode;            /* DRG_MODE_SYNC or DRG_MODE_ASYNC */
-    int32_t _pad;
+    int32_t dim;             /* 2 (or 0) or 3: coordinates [n][dim] (Sec. 3.1) */
     uint64_t seed;
 } drg_layout_params;
 
@@ -111,6 +114,8 @@ typedef struct {
     double gamma;
     uint64_t seed;
     uint64_t iter;           /* keys the negatives like drg_layout_step */
+    int32_t dim;             /* 2 (or 0) or 3: coordinates [n][dim] */
+    int32_t _pad;
 } drg_obj_params;
 
 const char* drg_last_error(void);
@@ -244,6 +249,17 @@ drg_status drg_init_layout(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level
  * of level-1.  level >= 1. */
 drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* y_level_dev,
                        float* y_finer_dev);
+/* The same in R^3 (Sec. 3.1): coordinates [n][3]; coordinate c of node v is
+ * (2u-1) with u from Philox word c of (seed, node v, level), so the first
+ * two are those of drg_init_layout.  FP64 instances for trajectory checks. */
+drg_status drg_init_layout_3d(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level,
+                              float* y_dev);
+drg_status drg_prolong_3d(drg_ctx* ctx, const drg_hier* h, int32_t level,
+                          const float* y_level_dev, float* y_finer_dev);
+drg_status drg_init_layout_3d_f64(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level,
+                                  double* y_dev);
+drg_status drg_prolong_3d_f64(drg_ctx* ctx, const drg_hier* h, int32_t level,
+                              const double* y_level_dev, double* y_finer_dev);
 
 /* One optimisation iteration at level p->level (Sec. 3.2.2 with the
  * gradient sharing of Sec. 3.2.3).  For every non-isolated finest node i,
@@ -263,7 +279,8 @@ drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const flo
  *          rows are cut into DRG_ASYNC_STAGES (environment, default 4)
  *          equal ranges, moved range by range once all their pairs are
  *          summed; later ranges see the moves of earlier ones.
- * h may be NULL for level 0.  y_level_dev: [n_level][2], in/out. */
+ * h may be NULL for level 0.  y_level_dev: [n_level][dim], in/out (p->dim
+ * 3: the same step in R^3, row-form sweep). */
 drg_status drg_layout_step(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                            const drg_step_params* p, float* y_level_dev);
 

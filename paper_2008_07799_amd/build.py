@@ -13,7 +13,7 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libdrgraph.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["prims.hip", "similarity.hip", "blocked.hip", "coarsen.hip", "layout.hip",
+SOURCES = ["prims.hip", "similarity.hip", "blocked.hip", "coarsen.hip", "layout.hip", "layout3d.hip",
            "objective.hip", "window.hip", "batch.hip", "evaluate.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

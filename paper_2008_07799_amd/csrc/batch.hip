@@ -529,6 +529,8 @@ void check_layout_params(const drg_layout_params* p) {
     if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "clip must be > 0");
     if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
         throw Error(DRG_E_INVALID, "unknown mode");
+    if (p->dim != 0 && p->dim != 2 && p->dim != 3)
+        throw Error(DRG_E_INVALID, "dim must be 2 (or 0) or 3");
 }
 
 template <typename T>
@@ -554,6 +556,8 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         check_layout_params(&p);
         if (p.mode != DRG_MODE_SYNC)
             throw Error(DRG_E_UNSUPPORTED, "batched layout: synchronous mode only");
+        if (p.dim == 3)
+            throw Error(DRG_E_UNSUPPORTED, "batched layout: 2-D layouts only");
         if (p.k != params[0].k || p.sigma != params[0].sigma)
             throw Error(DRG_E_INVALID, "batched layout: k and sigma must agree over the batch");
         if (!(p.rho > 0.0 && p.rho <= 1.0) || p.max_levels < 1 || p.min_nodes < 0)

@@ -312,12 +312,59 @@ drg_status drg_prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const flo
     });
 }
 
+// the coordinate dimension of a parameter block: 2 (0 means 2) or 3
+static int32_t dim_of(int32_t d) {
+    if (d == 0 || d == 2) return 2;
+    if (d == 3) return 3;
+    throw Error(DRG_E_INVALID, "dim must be 2 (or 0) or 3");
+}
+
 drg_status drg_layout_step(drg_ctx* ctx, const drg_sim* s, const drg_hier* h,
                            const drg_step_params* p, float* y_level_dev) {
     return guarded([&] {
         need(ctx, "ctx");
+        need(p, "params");
         CtxScope scope(ctx);
-        drg::layout_step(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+        if (dim_of(p->dim) == 3)
+            drg::layout_step3_t<float>(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+        else
+            drg::layout_step(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+    });
+}
+
+drg_status drg_init_layout_3d(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level,
+                              float* y_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        CtxScope scope(ctx);
+        drg::init_layout3_t<float>(ctx, n, seed, level, y_dev);
+    });
+}
+
+drg_status drg_prolong_3d(drg_ctx* ctx, const drg_hier* h, int32_t level,
+                          const float* y_level_dev, float* y_finer_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        CtxScope scope(ctx);
+        drg::prolong3_t<float>(ctx, h, level, y_level_dev, y_finer_dev);
+    });
+}
+
+drg_status drg_init_layout_3d_f64(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level,
+                                  double* y_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        CtxScope scope(ctx);
+        drg::init_layout3_t<double>(ctx, n, seed, level, y_dev);
+    });
+}
+
+drg_status drg_prolong_3d_f64(drg_ctx* ctx, const drg_hier* h, int32_t level,
+                              const double* y_level_dev, double* y_finer_dev) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        CtxScope scope(ctx);
+        drg::prolong3_t<double>(ctx, h, level, y_level_dev, y_finer_dev);
     });
 }
 
@@ -343,8 +390,12 @@ drg_status drg_layout_step_f64(drg_ctx* ctx, const drg_sim* s, const drg_hier* h
                                const drg_step_params* p, double* y_level_dev) {
     return guarded([&] {
         need(ctx, "ctx");
+        need(p, "params");
         CtxScope scope(ctx);
-        drg::layout_step_t<double>(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+        if (dim_of(p->dim) == 3)
+            drg::layout_step3_t<double>(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
+        else
+            drg::layout_step_t<double>(ctx, const_cast<drg_sim*>(s), h, p, y_level_dev);
     });
 }
 
@@ -465,13 +516,12 @@ static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_
     if (from) need(y_from, "y_from");
     if (to) need(y_to, "y_to");
     else need(y_out, "y_out");
+    const int32_t D = dim_of(p->dim);
     // level buffers: the finest level of a run to the end is y_out, the others scratch
-    std::vector<drg::DevBuf<float2>> ybuf(Lc);
-    auto ylev = [&](int32_t l) -> float* {
-        return (l == 0 && !to) ? y_out : reinterpret_cast<float*>(ybuf[l].get());
-    };
+    std::vector<drg::DevBuf<float>> ybuf(Lc);
+    auto ylev = [&](int32_t l) -> float* { return (l == 0 && !to) ? y_out : ybuf[l].get(); };
     for (int32_t l = stop.level; l <= start.level; ++l)
-        if (!(l == 0 && !to)) ybuf[l].alloc(h->lv[l].n);
+        if (!(l == 0 && !to)) ybuf[l].alloc((int64_t)D * h->lv[l].n);
     uint64_t git0 = 0;
     for (int32_t l = Lc - 1; l > start.level; --l) git0 += (uint64_t)level_iters(p, Lc, l);
     git0 += (uint64_t)start.t;
@@ -480,7 +530,12 @@ static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_
     // (after the initial layout, a refinement or a resume) stages them
     const bool sync = p->mode == DRG_MODE_SYNC;
     auto issue = [&] {
-        if (!from) drg::init_layout(ctx, h->lv[Lc - 1].n, p->seed, Lc - 1, ylev(Lc - 1));
+        if (!from) {
+            if (D == 3)
+                drg::init_layout3_t<float>(ctx, h->lv[Lc - 1].n, p->seed, Lc - 1, ylev(Lc - 1));
+            else
+                drg::init_layout(ctx, h->lv[Lc - 1].n, p->seed, Lc - 1, ylev(Lc - 1));
+        }
         uint64_t git = git0;
         for (int32_t l = start.level; l >= stop.level; --l) {
             const int32_t Tl = level_iters(p, Lc, l);
@@ -492,21 +547,29 @@ static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_
             sp.clip = p->clip;
             sp.level = l;
             sp.mode = p->mode;
+            sp.dim = D;
             sp.seed = p->seed;
             const int32_t t0 = l == start.level ? start.t : 0;
             const int32_t t1 = l == stop.level ? stop.t : Tl;
             for (int32_t t = t0; t < t1; ++t) {
                 sp.eta = (float)((double)p->eta0 * (1.0 - (double)t / (double)Tl));
                 sp.iter = git++;
-                drg::layout_step(ctx, s, h, &sp, ylev(l), sync && t > t0, sync);
+                if (D == 3)
+                    drg::layout_step3_t<float>(ctx, s, h, &sp, ylev(l));
+                else
+                    drg::layout_step(ctx, s, h, &sp, ylev(l), sync && t > t0, sync);
             }
             if (l == stop.level) break;
-            drg::prolong(ctx, h, l, ylev(l), ylev(l - 1));
+            if (D == 3)
+                drg::prolong3_t<float>(ctx, h, l, ylev(l), ylev(l - 1));
+            else
+                drg::prolong(ctx, h, l, ylev(l), ylev(l - 1));
         }
     };
     if (from)
-        DRG_HIP(hipMemcpyAsync(ylev(start.level), y_from, sizeof(float2) * h->lv[start.level].n,
-                               hipMemcpyDeviceToDevice, ctx->stream));
+        DRG_HIP(hipMemcpyAsync(ylev(start.level), y_from,
+                               sizeof(float) * D * h->lv[start.level].n, hipMemcpyDeviceToDevice,
+                               ctx->stream));
     if (run_as_graph(ctx, s, p)) {
         // the launches of the whole run recorded into a graph, launched once
         drg::prepare_sync_step(ctx, s);
@@ -545,7 +608,7 @@ static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_
         issue();
     }
     if (to)
-        DRG_HIP(hipMemcpyAsync(y_to, ylev(stop.level), sizeof(float2) * h->lv[stop.level].n,
+        DRG_HIP(hipMemcpyAsync(y_to, ylev(stop.level), sizeof(float) * D * h->lv[stop.level].n,
                                hipMemcpyDeviceToDevice, ctx->stream));
     DRG_HIP(hipStreamSynchronize(ctx->stream));
 }

@@ -45,6 +45,8 @@ struct drg_sim {
     drg::DevBuf<float> wlev;         // [n] anchor weights of level nodes (async)
     drg::DevBuf<double4> rec64;      // FP64 instance workspace (allocated on use)
     drg::DevBuf<double2> g64;
+    drg::DevBuf<float> g3;           // [n][3] steps of a 3-D layout (allocated on use)
+    drg::DevBuf<double> g3_64;
     // column-blocked copy of the pattern for the LDS-staged sweep (blk_nb > 0)
     int32_t blk_nb = 0, blk_bits = 0, blk_nitems = 0;
     drg::DevBuf<int64_t> blk_base;   // [nb+1] first entry of each block
@@ -186,6 +188,13 @@ void prolong(drg_ctx* ctx, const drg_hier* h, int32_t level, const float* yl, fl
 void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p,
                  float* y, bool staged = false, bool restage = false);
 void prepare_sync_step(drg_ctx* ctx, drg_sim* s);
+// layouts in R^3 (coordinates [n][3]; row-form sweep)
+template <typename T>
+void init_layout3_t(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, T* y);
+template <typename T>
+void prolong3_t(drg_ctx* ctx, const drg_hier* h, int32_t level, const T* yl, T* yf);
+template <typename T>
+void layout_step3_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y);
 template <typename T>
 void init_layout_t(drg_ctx* ctx, int32_t n, uint64_t seed, int32_t level, T* y);
 template <typename T>

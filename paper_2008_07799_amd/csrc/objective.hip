@@ -74,6 +74,8 @@ struct ObjArgs {
     const T* dloss;        // backward: scale (NULL = 1)
     T* row_val;            // forward: per-row value
     v2* dy;                // backward: gradient
+    const T* y3;           // 3-D layouts: coordinates [n][3]
+    T* dy3;                // 3-D layouts: gradient [n][3]
 };
 
 template <typename T>
@@ -297,6 +299,127 @@ __global__ void k_other_side(ObjArgs<T> a, const int32_t* __restrict__ seg,
     a.dy[v] = o;
 }
 
+// ------------------------------------------------------------------ 3-D layouts
+// The same objective and gradient with positions in R^3 (Sec. 3.1): the terms
+// depend on the squared distance only, the forces act along the offset.
+template <typename T>
+__device__ __forceinline__ T off3(const T* __restrict__ y, int64_t i, int64_t j, T& dx, T& dy,
+                                  T& dz) {
+    dx = y[3 * i] - y[3 * j];
+    dy = y[3 * i + 1] - y[3 * j + 1];
+    dz = y[3 * i + 2] - y[3 * j + 2];
+    return dx * dx + dy * dy + dz * dz;
+}
+
+template <typename T, int B, int G>
+__global__ __launch_bounds__(256) void k_obj_rows3(ObjArgs<T> a) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t i = grp; i < a.n; i += ngrp) {
+        const int64_t rs = a.prp[i], re = a.prp[i + 1];
+        T val = T(0);
+        if (rs < re) {
+            const T zi = a.invZ[i];
+            T att = T(0), rep = T(0), dx, dy, dz;
+            for (int64_t x = rs + lane; x < re; x += G) {
+                const uint32_t e = a.colhop[x];
+                const int32_t j = (int32_t)(e & COL_MASK);
+                const T d2 = off3(a.y3, i, j, dx, dy, dz);
+                att += oh(a, e >> 30) * (zi + a.invZ[j]) * (-log1pT(opow<B>(d2)));
+            }
+            for (int m = lane; m < a.M; m += G) {
+                const int32_t v =
+                    draw_node(neg_word(a.seed, a.iter, (int32_t)i, m), a.C, a.guide, a.gbits, a.S);
+                if (v == (int32_t)i) continue;
+                const T d2 = off3(a.y3, i, v, dx, dy, dz);
+                if (d2 > T(0)) rep += T(B) * logT(d2) - log1pT(opow<B>(d2));
+            }
+            att = group_sum<G>(att);
+            rep = group_sum<G>(rep);
+            val = att + a.gamma * a.qt[i] * rep;
+        }
+        if (lane == 0) a.row_val[i] = val;
+    }
+}
+
+template <typename T, int B, int G>
+__global__ __launch_bounds__(256) void k_grad_rows3(ObjArgs<T> a) {
+    const int lane = threadIdx.x % G;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    const T dl = a.dloss ? *a.dloss : T(1);
+    for (int64_t i = grp; i < a.n; i += ngrp) {
+        const int64_t rs = a.prp[i], re = a.prp[i + 1];
+        T g0 = T(0), g1 = T(0), g2 = T(0);
+        if (rs < re) {
+            const T zi = a.invZ[i];
+            T ax = T(0), ay = T(0), az = T(0), rx = T(0), ry = T(0), rz = T(0), dx, dy, dz;
+            for (int64_t x = rs + lane; x < re; x += G) {
+                const uint32_t e = a.colhop[x];
+                const int32_t j = (int32_t)(e & COL_MASK);
+                const T d2 = off3(a.y3, i, j, dx, dy, dz);
+                const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
+                const T k = p * T(-2 * B) * opow<B - 1>(d2) * orcp(T(1) + opow<B>(d2));
+                ax += k * dx;
+                ay += k * dy;
+                az += k * dz;
+            }
+            for (int m = lane; m < a.M; m += G) {
+                const int32_t v =
+                    draw_node(neg_word(a.seed, a.iter, (int32_t)i, m), a.C, a.guide, a.gbits, a.S);
+                if (v == (int32_t)i) continue;
+                const T d2 = off3(a.y3, i, v, dx, dy, dz);
+                if (d2 > T(0)) {
+                    const T k = T(2 * B) * orcp(d2 * (T(1) + opow<B>(d2)));
+                    rx += k * dx;
+                    ry += k * dy;
+                    rz += k * dz;
+                }
+            }
+            ax = group_sum<G>(ax);
+            ay = group_sum<G>(ay);
+            az = group_sum<G>(az);
+            rx = group_sum<G>(rx);
+            ry = group_sum<G>(ry);
+            rz = group_sum<G>(rz);
+            const T gq = a.gamma * a.qt[i];
+            g0 = T(2) * ax + gq * rx;
+            g1 = T(2) * ay + gq * ry;
+            g2 = T(2) * az + gq * rz;
+        }
+        if (lane == 0) {
+            a.dy3[3 * i] = dl * g0;
+            a.dy3[3 * i + 1] = dl * g1;
+            a.dy3[3 * i + 2] = dl * g2;
+        }
+    }
+}
+
+template <typename T, int B>
+__global__ void k_other_side3(ObjArgs<T> a, const int32_t* __restrict__ seg,
+                              const int32_t* __restrict__ pairs) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.n) return;
+    const int32_t s = seg[v], e = seg[v + 1];
+    if (s == e) return;
+    const T dl = a.dloss ? *a.dloss : T(1);
+    T g0 = T(0), g1 = T(0), g2 = T(0), dx, dy, dz;
+    for (int32_t x = s; x < e; ++x) {
+        const int32_t u = pairs[x] / a.M;
+        const T d2 = off3(a.y3, v, u, dx, dy, dz);
+        if (d2 > T(0)) {
+            const T k = a.gamma * a.qt[u] * T(2 * B) / (d2 * (T(1) + opow<B>(d2)));
+            g0 += k * dx;
+            g1 += k * dy;
+            g2 += k * dz;
+        }
+    }
+    a.dy3[3 * v] += dl * g0;
+    a.dy3[3 * v + 1] += dl * g1;
+    a.dy3[3 * v + 2] += dl * g2;
+}
+
 __global__ void k_negatives(int32_t n, int32_t M, const int64_t* __restrict__ prp,
                             const uint64_t* __restrict__ C, const int32_t* __restrict__ guide,
                             int32_t gbits, uint64_t S, uint64_t seed, uint64_t iter,
@@ -343,6 +466,7 @@ static ObjArgs<T> obj_args(drg_sim* s, const drg_obj_params* p, const T* y) {
         a.qt = s->qt.get();
     }
     a.y = reinterpret_cast<const typename OV<T>::v2*>(y);
+    a.y3 = y;
     a.C = s->C.get();
     a.guide = s->guide.get();
     a.gbits = s->gbits;
@@ -360,6 +484,8 @@ static ObjArgs<T> obj_args(drg_sim* s, const drg_obj_params* p, const T* y) {
 static void check_obj(const drg_sim* s, const drg_obj_params* p, const void* y) {
     if (!s || !p || !y) throw Error(DRG_E_INVALID, "objective: NULL argument");
     if (p->M < 0 || p->b < 1 || p->b > 3) throw Error(DRG_E_INVALID, "objective: M >= 0, b in 1..3");
+    if (p->dim != 0 && p->dim != 2 && p->dim != 3)
+        throw Error(DRG_E_INVALID, "objective: dim must be 2 (or 0) or 3");
 }
 
 static int obj_group(const drg_sim* s) {
@@ -368,21 +494,27 @@ static int obj_group(const drg_sim* s) {
 }
 
 template <typename T, int B, int G>
-static void launch_obj(hipStream_t st, const ObjArgs<T>& a, bool grad) {
+static void launch_obj(hipStream_t st, const ObjArgs<T>& a, bool grad, bool three) {
     const int grid = (int)std::max<int64_t>(
         1, std::min<int64_t>(((int64_t)a.n * G + 255) / 256, (int64_t)1 << 22));
-    if (grad)
+    if (three) {
+        if (grad)
+            hipLaunchKernelGGL((k_grad_rows3<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_obj_rows3<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+    } else if (grad) {
         hipLaunchKernelGGL((k_grad_rows<T, B, G>), dim3(grid), dim3(256), 0, st, a);
-    else
+    } else {
         hipLaunchKernelGGL((k_obj_rows<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+    }
     DRG_LAUNCH_CHECK();
 }
 
 template <typename T, int B>
-static void launch_obj_g(hipStream_t st, const ObjArgs<T>& a, int G, bool grad) {
-    if (G == 8) launch_obj<T, B, 8>(st, a, grad);
-    else if (G == 32) launch_obj<T, B, 32>(st, a, grad);
-    else launch_obj<T, B, 64>(st, a, grad);
+static void launch_obj_g(hipStream_t st, const ObjArgs<T>& a, int G, bool grad, bool three) {
+    if (G == 8) launch_obj<T, B, 8>(st, a, grad, three);
+    else if (G == 32) launch_obj<T, B, 32>(st, a, grad, three);
+    else launch_obj<T, B, 64>(st, a, grad, three);
 }
 
 static bool obj_blocked_wanted() {
@@ -391,13 +523,14 @@ static bool obj_blocked_wanted() {
 }
 
 // Attraction and own-side terms of every row: the blocked flat sweep when the
-// similarity has the column-blocked copy (FP32), else the row kernels.
+// similarity has the column-blocked copy (FP32, 2-D), else the row kernels.
 template <typename T>
 static void obj_rows(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const ObjArgs<T>& a,
                      bool grad) {
     hipStream_t st = ctx->stream;
+    const bool three = p->dim == 3;
     if constexpr (std::is_same<T, float>::value) {
-        if (s->blk_nb > 0 && obj_blocked_wanted()) {
+        if (!three && s->blk_nb > 0 && obj_blocked_wanted()) {
             sweep_blocked_objective(ctx, s, p->b, reinterpret_cast<const float*>(a.y), grad ? 1 : 0);
             const float2* part = s->blk_partial.get();
 #define DRG_FIN(BB)                                                                          \
@@ -422,9 +555,9 @@ static void obj_rows(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const Ob
     }
     const int G = obj_group(s);
     switch (p->b) {
-        case 1: launch_obj_g<T, 1>(st, a, G, grad); break;
-        case 2: launch_obj_g<T, 2>(st, a, G, grad); break;
-        default: launch_obj_g<T, 3>(st, a, G, grad); break;
+        case 1: launch_obj_g<T, 1>(st, a, G, grad, three); break;
+        case 2: launch_obj_g<T, 2>(st, a, G, grad, three); break;
+        default: launch_obj_g<T, 3>(st, a, G, grad, three); break;
     }
 }
 
@@ -470,6 +603,8 @@ void objective_bwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T*
     ObjArgs<T> a = obj_args<T>(s, p, y);
     a.dloss = dloss;
     a.dy = reinterpret_cast<typename OV<T>::v2*>(dy);
+    a.dy3 = dy;
+    const bool three = p->dim == 3;
     obj_rows<T>(ctx, s, p, a, true);
     if (a.M == 0) return;
     const int64_t np = (int64_t)s->n * a.M;
@@ -486,10 +621,19 @@ void objective_bwd_t(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const T*
     hipLaunchKernelGGL(k_key_bounds, dim3(ceil_div((int64_t)s->n + 1, 256)), dim3(256), 0, st, np,
                        s->n, keys.get(), seg.get());
     DRG_LAUNCH_CHECK();
-    switch (p->b) {
-        case 1: hipLaunchKernelGGL((k_other_side<T, 1>), dim3(ceil_div(s->n, 256)), dim3(256), 0, st, a, seg.get(), pairs.get()); break;
-        case 2: hipLaunchKernelGGL((k_other_side<T, 2>), dim3(ceil_div(s->n, 256)), dim3(256), 0, st, a, seg.get(), pairs.get()); break;
-        default: hipLaunchKernelGGL((k_other_side<T, 3>), dim3(ceil_div(s->n, 256)), dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+    const dim3 og(ceil_div(s->n, 256));
+    if (three) {
+        switch (p->b) {
+            case 1: hipLaunchKernelGGL((k_other_side3<T, 1>), og, dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+            case 2: hipLaunchKernelGGL((k_other_side3<T, 2>), og, dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+            default: hipLaunchKernelGGL((k_other_side3<T, 3>), og, dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+        }
+    } else {
+        switch (p->b) {
+            case 1: hipLaunchKernelGGL((k_other_side<T, 1>), og, dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+            case 2: hipLaunchKernelGGL((k_other_side<T, 2>), og, dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+            default: hipLaunchKernelGGL((k_other_side<T, 3>), og, dim3(256), 0, st, a, seg.get(), pairs.get()); break;
+        }
     }
     DRG_LAUNCH_CHECK();
     DRG_HIP(hipStreamSynchronize(st));

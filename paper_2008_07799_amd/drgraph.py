@@ -46,12 +46,12 @@ class Csr(C.Structure):
 class StepParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("b", C.c_int32), ("gamma", C.c_float), ("eta", C.c_float),
                 ("clip", C.c_float), ("level", C.c_int32), ("mode", C.c_int32),
-                ("_pad", C.c_int32), ("seed", C.c_uint64), ("iter", C.c_uint64)]
+                ("dim", C.c_int32), ("seed", C.c_uint64), ("iter", C.c_uint64)]
 
 
 class ObjParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("b", C.c_int32), ("gamma", C.c_double), ("seed", C.c_uint64),
-                ("iter", C.c_uint64)]
+                ("iter", C.c_uint64), ("dim", C.c_int32), ("_pad", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -67,7 +67,7 @@ class LayoutParams(C.Structure):
                 ("sigma", C.c_double), ("gamma", C.c_float), ("gamma_coarsest", C.c_float),
                 ("eta0", C.c_float), ("clip", C.c_float), ("rho", C.c_double),
                 ("min_nodes", C.c_int32), ("max_levels", C.c_int32), ("mode", C.c_int32),
-                ("_pad", C.c_int32), ("seed", C.c_uint64)]
+                ("dim", C.c_int32), ("seed", C.c_uint64)]
 
 
 _lib = None
@@ -118,6 +118,10 @@ def lib():
         "drg_prolong": ([_P, _P, C.c_int32, _P, _P], st),
         "drg_layout_step": ([_P, _P, _P, C.POINTER(StepParams), _P], st),
         "drg_init_layout_f64": ([_P, C.c_int32, C.c_uint64, C.c_int32, _P], st),
+        "drg_init_layout_3d": ([_P, C.c_int32, C.c_uint64, C.c_int32, _P], st),
+        "drg_init_layout_3d_f64": ([_P, C.c_int32, C.c_uint64, C.c_int32, _P], st),
+        "drg_prolong_3d": ([_P, _P, C.c_int32, _P, _P], st),
+        "drg_prolong_3d_f64": ([_P, _P, C.c_int32, _P, _P], st),
         "drg_prolong_f64": ([_P, _P, C.c_int32, _P, _P], st),
         "drg_layout_step_f64": ([_P, _P, _P, C.POINTER(StepParams), _P], st),
         "drg_layout_run": ([_P, _P, _P, C.POINTER(LayoutParams), _P], st),
@@ -403,27 +407,45 @@ def _coords(y, name, shape):
     return _dev(y, torch.float32, name, shape), False
 
 
+def _dim(y) -> int:
+    """Coordinate dimension of a [n, 2] or [n, 3] tensor (Sec. 3.1)."""
+    d = int(y.shape[1]) if y.dim() == 2 else 0
+    if d not in (2, 3):
+        raise ValueError("coordinates must be [n, 2] or [n, 3]")
+    return d
+
+
 def drg_init_layout(ctx: Context, n: int, seed: int, level: int, y):
-    ptr, f64 = _coords(y, "y", (n, 2))
-    fn = lib().drg_init_layout_f64 if f64 else lib().drg_init_layout
+    """Random layout of a level into y [n, 2] or [n, 3]."""
+    d = _dim(y)
+    ptr, f64 = _coords(y, "y", (n, d))
+    if d == 3:
+        fn = lib().drg_init_layout_3d_f64 if f64 else lib().drg_init_layout_3d
+    else:
+        fn = lib().drg_init_layout_f64 if f64 else lib().drg_init_layout
     _check(fn(ctx.h, int(n), int(seed), int(level), ptr))
 
 
 def drg_prolong(ctx: Context, hier: Hierarchy, level: int, y_level, y_finer):
-    a, f64 = _coords(y_level, "y_level", (hier.sizes[level], 2))
-    b, f64b = _coords(y_finer, "y_finer", (hier.sizes[level - 1], 2))
+    d = _dim(y_level)
+    a, f64 = _coords(y_level, "y_level", (hier.sizes[level], d))
+    b, f64b = _coords(y_finer, "y_finer", (hier.sizes[level - 1], d))
     if f64 != f64b:
         raise TypeError("y_level and y_finer must have the same dtype")
-    fn = lib().drg_prolong_f64 if f64 else lib().drg_prolong
+    if d == 3:
+        fn = lib().drg_prolong_3d_f64 if f64 else lib().drg_prolong_3d
+    else:
+        fn = lib().drg_prolong_f64 if f64 else lib().drg_prolong
     _check(fn(ctx.h, hier.h, int(level), a, b))
 
 
 def drg_layout_step(ctx: Context, sim: Similarity, hier, y, *, M=5, b=1, gamma=0.1, eta=1.0,
                     clip=4.0, level=0, mode=DRG_MODE_SYNC, seed=0, iter=0):
     nl = sim.n if level == 0 else hier.sizes[level]
+    d = _dim(y)
     p = StepParams(int(M), int(b), float(gamma), float(eta), float(clip), int(level), int(mode),
-                   0, int(seed), int(iter))
-    ptr, f64 = _coords(y, "y", (nl, 2))
+                   d, int(seed), int(iter))
+    ptr, f64 = _coords(y, "y", (nl, d))
     fn = lib().drg_layout_step_f64 if f64 else lib().drg_layout_step
     _check(fn(ctx.h, sim.h, hier.h if hier is not None else None, C.byref(p), ptr))
 
@@ -438,38 +460,45 @@ def layout_params(**kw) -> LayoutParams:
     return p
 
 
+def _pdim(params: LayoutParams) -> int:
+    return 3 if params.dim == 3 else 2
+
+
 def drg_layout_run(ctx: Context, sim: Similarity, hier: Hierarchy, params: LayoutParams, y_out):
+    """The whole schedule; y_out [n, 2] (or [n, 3] with params.dim = 3)."""
     import torch
     _check(lib().drg_layout_run(ctx.h, sim.h, hier.h, C.byref(params),
-                                _dev(y_out, torch.float32, "y_out", (sim.n, 2))))
+                                _dev(y_out, torch.float32, "y_out", (sim.n, _pdim(params)))))
 
 
 def drg_layout_run_until(ctx: Context, sim: Similarity, hier: Hierarchy, params: LayoutParams,
                          level: int, t: int, y_level):
     """Runs the schedule until t iterations of `level` are done; writes that
-    level's coordinates into y_level [n_level, 2] (float32, device)."""
+    level's coordinates into y_level [n_level, dim] (float32, device)."""
     import torch
     _check(lib().drg_layout_run_until(ctx.h, sim.h, hier.h, C.byref(params), int(level), int(t),
                                       _dev(y_level, torch.float32, "y_level",
-                                           (hier.sizes[level], 2))))
+                                           (hier.sizes[level], _pdim(params)))))
 
 
 def drg_layout_resume(ctx: Context, sim: Similarity, hier: Hierarchy, params: LayoutParams,
                       level: int, t: int, y_level, y_out):
     """Continues the schedule from (level, t, y_level) to the end; finest
-    coordinates into y_out [n, 2]."""
+    coordinates into y_out [n, dim]."""
     import torch
+    d = _pdim(params)
     _check(lib().drg_layout_resume(ctx.h, sim.h, hier.h, C.byref(params), int(level), int(t),
                                    _dev(y_level, torch.float32, "y_level",
-                                        (hier.sizes[level], 2)),
-                                   _dev(y_out, torch.float32, "y_out", (sim.n, 2))))
+                                        (hier.sizes[level], d)),
+                                   _dev(y_out, torch.float32, "y_out", (sim.n, d))))
 
 
 def drg_layout(ctx: Context, row_ptr, col, params: LayoutParams, y_out):
+    """End to end; y_out [n, 2] (or [n, 3] with params.dim = 3)."""
     import torch
     g = _csr(row_ptr, col)
     _check(lib().drg_layout(ctx.h, C.byref(g), C.byref(params),
-                            _dev(y_out, torch.float32, "y_out", (g.n, 2))))
+                            _dev(y_out, torch.float32, "y_out", (g.n, _pdim(params)))))
 
 
 # ------------------------------------------------------------------ batches
@@ -552,8 +581,9 @@ def drg_objective_fwd(ctx: Context, sim: Similarity, y, *, M=5, b=1, gamma=0.1, 
     """The sampled objective L^ at y ([n,2], float32 or float64).  Returns a
     0-d tensor, or with rows=True the per-row values [n]."""
     import torch
-    ptr, f64 = _coords(y, "y", (sim.n, 2))
-    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter))
+    d = _dim(y)
+    ptr, f64 = _coords(y, "y", (sim.n, d))
+    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter), d, 0)
     out = torch.empty((sim.n,) if rows else (), dtype=y.dtype, device=y.device)
     fn = lib().drg_objective_fwd_f64 if f64 else lib().drg_objective_fwd
     optr = C.c_void_p(out.data_ptr())
@@ -567,9 +597,10 @@ def drg_objective_fwd_noalloc(ctx: Context, sim: Similarity, y, loss, *, M=5, b=
     device tensor `loss`, with no allocation in the library (static scratch,
     at most 2^20 nodes); enqueued only: synchronise before reading it."""
     import torch
-    yp = _dev(y, torch.float32, "y", (sim.n, 2))
+    d = _dim(y)
+    yp = _dev(y, torch.float32, "y", (sim.n, d))
     lp = _dev(loss, torch.float32, "loss", ())
-    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter))
+    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter), d, 0)
     _check(lib().drg_objective_fwd_noalloc(ctx.h, sim.h, C.byref(p), yp, lp))
 
 
@@ -577,8 +608,9 @@ def drg_objective_bwd(ctx: Context, sim: Similarity, y, dloss=None, *, M=5, b=1,
                       seed=0, iter=0):
     """dloss * dL^/dy as a tensor like y; dloss is a 0-d device tensor or None."""
     import torch
-    ptr, f64 = _coords(y, "y", (sim.n, 2))
-    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter))
+    d = _dim(y)
+    ptr, f64 = _coords(y, "y", (sim.n, d))
+    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter), d, 0)
     dy = torch.empty_like(y)
     dl = None
     if dloss is not None:

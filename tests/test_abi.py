@@ -54,12 +54,33 @@ def test_defaults_and_argument_errors(lib):
     assert lib.drg_version().startswith(b"drgraph")
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the size and field offsets that
+    a C compiler gives the header's structures."""
+    import subprocess
     from paper_2008_07799_amd import drgraph as d
-    assert C.sizeof(d.Csr) == 24
-    assert C.sizeof(d.StepParams) == 48
-    assert C.sizeof(d.LayoutParams) == 72
-    assert C.sizeof(d.ObjParams) == 32
+    structs = {"drg_csr": d.Csr, "drg_step_params": d.StepParams,
+               "drg_layout_params": d.LayoutParams, "drg_obj_params": d.ObjParams,
+               "drg_allocator": d.Allocator}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "drgraph.h"',
+             "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
