@@ -382,17 +382,27 @@ static double ipow(double x, int32_t b) {
     return r;
 }
 
+/* d^{2b} from d2 = d^2 for b a whole or half number (Sec. 4.2 tabulates b;
+ * its supplement also uses 1.5 and 2.5): (d2)^floor(b), times sqrt(d2) when
+ * b has a half.  For a whole b it is ipow(d2, b) exactly. */
+static double powb(double d2, double b) {
+    int32_t h = (int32_t)floor(b);
+    double r = ipow(d2, h);
+    if (b - (double)h == 0.5) r = r * sqrt(d2);
+    return r;
+}
+
 static double clipd(double v, double c) { return v > c ? c : (v < -c ? -c : v); }
 
 /* attraction coefficient: A = coef * delta */
-static double attract_coef(double d2, int32_t b) {
-    double D = ipow(d2, b);
-    return -2.0 * (double)b * ipow(d2, b - 1) / (1.0 + D);
+static double attract_coef(double d2, double b) {
+    double D = powb(d2, b);
+    return -2.0 * b * powb(d2, b - 1.0) / (1.0 + D);
 }
 
-static double repel_coef(double d2, int32_t b) {
-    double D = ipow(d2, b);
-    return 2.0 * (double)b / (d2 * (1.0 + D));
+static double repel_coef(double d2, double b) {
+    double D = powb(d2, b);
+    return 2.0 * b / (d2 * (1.0 + D));
 }
 
 /* offset d = y_a - y_c (dim components) and its squared length, summed in
@@ -408,7 +418,7 @@ static double offset(const double* y, int32_t a, int32_t c, int32_t dim, double*
 
 void drgo_step_direction(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                          const double* qt, const uint64_t* C, const int32_t* cmap, const double* y,
-                         int32_t M, int32_t b, double gamma, double clip, uint64_t seed,
+                         int32_t M, double b, double gamma, double clip, uint64_t seed,
                          uint64_t it, double* g, int32_t dim) {
     for (int32_t i = 0; i < n0; ++i) {
         for (int32_t k = 0; k < dim; ++k) g[(size_t)dim * i + k] = 0.0;
@@ -451,7 +461,7 @@ static double* level_weights(int32_t n0, const double* qt, const int32_t* cmap, 
  *   y_a += eta * (sum_{cmap[i]=a} g_i) / (sum_{cmap[i]=a} qt_i). */
 void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                     const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
-                    int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
+                    int32_t M, double b, double gamma, double eta, double clip, uint64_t seed,
                     uint64_t it, int32_t dim) {
     double* g = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n0 > 0 ? n0 : 1));
     double* G = (double*)calloc((size_t)dim * (size_t)(nl > 0 ? nl : 1), sizeof(double));
@@ -476,7 +486,7 @@ void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const d
  * with the same weighting as the synchronous iteration. */
 void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                    const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
-                   int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
+                   int32_t M, double b, double gamma, double eta, double clip, uint64_t seed,
                    uint64_t it, int32_t dim) {
     double* w = level_weights(n0, qt, cmap, nl);
     for (int32_t i = 0; i < n0; ++i) {
@@ -512,7 +522,7 @@ void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const do
 /* log w = -log1p(d^{2b}); log(1 - w) = b log d^2 - log1p(d^{2b}).           */
 /* ------------------------------------------------------------------------ */
 double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
-                      const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                      const double* qt, const uint64_t* C, const double* y, int32_t M, double b,
                       double gamma, uint64_t seed, uint64_t it, int32_t dim) {
     double L = 0.0, d[3];
     for (int32_t i = 0; i < n; ++i) {
@@ -520,14 +530,14 @@ double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const 
         double att = 0.0;
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
             double d2 = offset(y, i, pcol[x], dim, d);
-            att += P[x] * (-log1p(ipow(d2, b)));
+            att += P[x] * (-log1p(powb(d2, b)));
         }
         double rep = 0.0;
         for (int32_t m = 0; m < M; ++m) {
             int32_t v = drgo_draw(C, n, drgo_neg_word(seed, it, i, m));
             double d2 = offset(y, i, v, dim, d);
             if (v == i || d2 == 0.0) continue;
-            rep += (double)b * log(d2) - log1p(ipow(d2, b));
+            rep += b * log(d2) - log1p(powb(d2, b));
         }
         L += att + gamma * qt[i] * rep;
     }
@@ -535,7 +545,7 @@ double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const 
 }
 
 void drgo_objective_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
-                         const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                         const double* qt, const uint64_t* C, const double* y, int32_t M, double b,
                          double gamma, uint64_t seed, uint64_t it, double* grad, int32_t dim) {
     double d[3];
     for (int64_t t = 0; t < (int64_t)dim * n; ++t) grad[t] = 0.0;
@@ -572,18 +582,18 @@ static double draw_prob(const uint64_t* C, int32_t n, int32_t v) {
 
 double drgo_objective_exact(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                             const double* qt, const uint64_t* C, const double* y, int32_t M,
-                            int32_t b, double gamma, int32_t dim) {
+                            double b, double gamma, int32_t dim) {
     double L = 0.0, d[3];
     for (int32_t i = 0; i < n; ++i) {
         if (prp[i + 1] == prp[i]) continue;
         for (int64_t x = prp[i]; x < prp[i + 1]; ++x)
-            L += P[x] * (-log1p(ipow(offset(y, i, pcol[x], dim, d), b)));
+            L += P[x] * (-log1p(powb(offset(y, i, pcol[x], dim, d), b)));
         double rep = 0.0;
         for (int32_t v = 0; v < n; ++v) {
             double pv = draw_prob(C, n, v);
             double d2 = offset(y, i, v, dim, d);
             if (v == i || d2 == 0.0 || pv == 0.0) continue;
-            rep += pv * ((double)b * log(d2) - log1p(ipow(d2, b)));
+            rep += pv * (b * log(d2) - log1p(powb(d2, b)));
         }
         L += gamma * qt[i] * (double)M * rep;
     }
@@ -592,7 +602,7 @@ double drgo_objective_exact(int32_t n, const int64_t* prp, const int32_t* pcol, 
 
 void drgo_objective_exact_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                                const double* qt, const uint64_t* C, const double* y, int32_t M,
-                               int32_t b, double gamma, double* grad, int32_t dim) {
+                               double b, double gamma, double* grad, int32_t dim) {
     double d[3];
     for (int64_t t = 0; t < (int64_t)dim * n; ++t) grad[t] = 0.0;
     for (int32_t i = 0; i < n; ++i) {
@@ -621,7 +631,7 @@ void drgo_objective_exact_grad(int32_t n, const int64_t* prp, const int32_t* pco
 }
 
 void drgo_step_expected(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
-                        const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                        const double* qt, const uint64_t* C, const double* y, int32_t M, double b,
                         double gamma, double* g, int32_t dim) {
     double d[3];
     for (int32_t i = 0; i < n; ++i) {

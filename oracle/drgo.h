@@ -72,7 +72,8 @@ int32_t drgo_coarsen_level(int32_t n, const int32_t* rp, const int32_t* col, uin
 int64_t drgo_contract(int32_t n, const int32_t* rp, const int32_t* col, const int32_t* map,
                       int32_t nc, int32_t* out_rp, int32_t* out_col);
 
-/* Coordinates are points of R^dim, dim = 2 or 3 (Sec. 3.1), stored [n][dim]. */
+/* Coordinates are points of R^dim, dim = 2 or 3 (Sec. 3.1), stored [n][dim].
+ * b (the proximity shape of Eq. gradient) is a whole or half number. */
 /* Random initial layout of the coarsest level. */
 void drgo_init(int32_t nl, uint64_t seed, int32_t level, double* y, int32_t dim);
 
@@ -82,42 +83,42 @@ void drgo_init(int32_t nl, uint64_t seed, int32_t level, double* y, int32_t dim)
  * per-component clipping at +-clip (pass INFINITY for none). */
 void drgo_step_direction(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                          const double* qt, const uint64_t* C, const int32_t* cmap, const double* y,
-                         int32_t M, int32_t b, double gamma, double clip, uint64_t seed,
+                         int32_t M, double b, double gamma, double clip, uint64_t seed,
                          uint64_t it, double* g, int32_t dim);
 /* Synchronous (Jacobi) iteration:
  * y[a] += eta * (sum_{cmap[i]=a} g_i) / (sum_{cmap[i]=a} qt_i). */
 void drgo_iter_sync(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                     const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
-                    int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
+                    int32_t M, double b, double gamma, double eta, double clip, uint64_t seed,
                     uint64_t it, int32_t dim);
 /* Sequential (Gauss-Seidel) iteration in ascending fine-node order. */
 void drgo_iter_seq(int32_t n0, const int64_t* prp, const int32_t* pcol, const double* P,
                    const double* qt, const uint64_t* C, const int32_t* cmap, int32_t nl, double* y,
-                   int32_t M, int32_t b, double gamma, double eta, double clip, uint64_t seed,
+                   int32_t M, double b, double gamma, double eta, double clip, uint64_t seed,
                    uint64_t it, int32_t dim);
 
 /* Sampled objective L^ (Eq. objectfunction with the expectation over
  * positives taken exactly and M negatives drawn per node) and its exact
  * two-sided gradient, unclipped, at level-0 coordinates y[n][dim]. */
 double drgo_objective(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
-                      const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                      const double* qt, const uint64_t* C, const double* y, int32_t M, double b,
                       double gamma, uint64_t seed, uint64_t it, int32_t dim);
 void drgo_objective_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
-                         const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                         const double* qt, const uint64_t* C, const double* y, int32_t M, double b,
                          double gamma, uint64_t seed, uint64_t it, double* grad, int32_t dim);
 
 /* Expected objective L (negatives averaged over the sampling distribution
  * W/S instead of drawn) and its gradient; O(n^2), tiny graphs only. */
 double drgo_objective_exact(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                             const double* qt, const uint64_t* C, const double* y, int32_t M,
-                            int32_t b, double gamma, int32_t dim);
+                            double b, double gamma, int32_t dim);
 void drgo_objective_exact_grad(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
                                const double* qt, const uint64_t* C, const double* y, int32_t M,
-                               int32_t b, double gamma, double* grad, int32_t dim);
+                               double b, double gamma, double* grad, int32_t dim);
 /* Expectation of the one-sided step direction over the negative draws,
  * unclipped; O(n^2). */
 void drgo_step_expected(int32_t n, const int64_t* prp, const int32_t* pcol, const double* P,
-                        const double* qt, const uint64_t* C, const double* y, int32_t M, int32_t b,
+                        const double* qt, const uint64_t* C, const double* y, int32_t M, double b,
                         double gamma, double* g, int32_t dim);
 
 #ifdef __cplusplus

@@ -67,20 +67,20 @@ def lib():
     L.drgo_init.argtypes = [C.c_int32, C.c_uint64, C.c_int32, _f64p, C.c_int32]
     cmap_t = C.c_void_p
     step_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, cmap_t, _f64p,
-                 C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_uint64, _f64p,
+                 C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64, _f64p,
                  C.c_int32]
     L.drgo_step_direction.argtypes = step_args
     it_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, cmap_t, C.c_int32, _f64p,
-               C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64,
+               C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64,
                C.c_int32]
     L.drgo_iter_sync.argtypes = it_args
     L.drgo_iter_seq.argtypes = it_args
-    obj_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, _f64p, C.c_int32, C.c_int32,
+    obj_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, _f64p, C.c_int32, C.c_double,
                 C.c_double, C.c_uint64, C.c_uint64]
     L.drgo_objective.argtypes = obj_args + [C.c_int32]
     L.drgo_objective.restype = C.c_double
     L.drgo_objective_grad.argtypes = obj_args + [_f64p, C.c_int32]
-    ex_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, _f64p, C.c_int32, C.c_int32,
+    ex_args = [C.c_int32, _i64p, _i32p, _f64p, _f64p, _u64p, _f64p, C.c_int32, C.c_double,
                C.c_double]
     L.drgo_objective_exact.argtypes = ex_args + [C.c_int32]
     L.drgo_objective_exact.restype = C.c_double
@@ -273,6 +273,14 @@ def _cm_ptr(cmap):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
+def _b(b) -> float:
+    """The proximity shape b as the oracle takes it: a whole or half number."""
+    v = float(b)
+    if v * 2 != int(v * 2) or not (1.0 <= v <= 3.0):
+        raise ValueError("b must be 1, 1.5, 2, 2.5 or 3")
+    return v
+
+
 def _dim(y) -> int:
     d = int(np.shape(y)[1])
     if d not in (2, 3):
@@ -286,7 +294,7 @@ def step_direction(sim: Sim, y, cmap=None, M=5, b=1, gamma=0.1, clip=math.inf, s
     g = np.zeros(d * sim.n, np.float64)
     yy = _c(y, np.float64).ravel()
     lib().drgo_step_direction(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C, p, yy,
-                              int(M), int(b), float(gamma), float(clip), int(seed), int(it), g, d)
+                              int(M), _b(b), float(gamma), float(clip), int(seed), int(it), g, d)
     return g.reshape(sim.n, d)
 
 
@@ -306,7 +314,7 @@ def iter_sync(sim: Sim, y, cmap=None, M=5, b=1, gamma=0.1, eta=1.0, clip=4.0, se
     d = _dim(y)
     yy = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
     fn = lib().drgo_iter_seq if seq else lib().drgo_iter_sync
-    fn(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C, p, nl, yy, int(M), int(b),
+    fn(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C, p, nl, yy, int(M), _b(b),
        float(gamma), float(eta), float(clip), int(seed), int(it), d)
     y[...] = yy.reshape(nl, d)
     return y
@@ -314,7 +322,7 @@ def iter_sync(sim: Sim, y, cmap=None, M=5, b=1, gamma=0.1, eta=1.0, clip=4.0, se
 
 def objective(sim, y, M=5, b=1, gamma=0.1, seed=0, it=0) -> float:
     return float(lib().drgo_objective(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
-                                      _c(y, np.float64).ravel(), int(M), int(b), float(gamma),
+                                      _c(y, np.float64).ravel(), int(M), _b(b), float(gamma),
                                       int(seed), int(it), _dim(y)))
 
 
@@ -322,14 +330,14 @@ def objective_grad(sim, y, M=5, b=1, gamma=0.1, seed=0, it=0) -> np.ndarray:
     d = _dim(y)
     g = np.zeros(d * sim.n, np.float64)
     lib().drgo_objective_grad(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
-                              _c(y, np.float64).ravel(), int(M), int(b), float(gamma),
+                              _c(y, np.float64).ravel(), int(M), _b(b), float(gamma),
                               int(seed), int(it), g, d)
     return g.reshape(sim.n, d)
 
 
 def objective_exact(sim, y, M=5, b=1, gamma=0.1) -> float:
     return float(lib().drgo_objective_exact(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt,
-                                            sim.C, _c(y, np.float64).ravel(), int(M), int(b),
+                                            sim.C, _c(y, np.float64).ravel(), int(M), _b(b),
                                             float(gamma), _dim(y)))
 
 
@@ -337,7 +345,7 @@ def objective_exact_grad(sim, y, M=5, b=1, gamma=0.1) -> np.ndarray:
     d = _dim(y)
     g = np.zeros(d * sim.n, np.float64)
     lib().drgo_objective_exact_grad(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
-                                    _c(y, np.float64).ravel(), int(M), int(b), float(gamma), g, d)
+                                    _c(y, np.float64).ravel(), int(M), _b(b), float(gamma), g, d)
     return g.reshape(sim.n, d)
 
 
@@ -345,7 +353,7 @@ def step_expected(sim, y, M=5, b=1, gamma=0.1) -> np.ndarray:
     d = _dim(y)
     g = np.zeros(d * sim.n, np.float64)
     lib().drgo_step_expected(sim.n, sim.row_ptr, _pcol(sim), _pP(sim), sim.qt, sim.C,
-                             _c(y, np.float64).ravel(), int(M), int(b), float(gamma), g, d)
+                             _c(y, np.float64).ravel(), int(M), _b(b), float(gamma), g, d)
     return g.reshape(sim.n, d)
 
 

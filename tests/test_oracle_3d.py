@@ -37,13 +37,13 @@ def test_init_3d_extends_the_2d_layout(oracle_lib):
     assert abs(z.mean()) < 0.05 and not np.array_equal(z, y3[:, 0])
 
 
-@pytest.mark.parametrize("b", [1, 2, 3])
+@pytest.mark.parametrize("b", [1, 1.5, 2, 2.5, 3])
 def test_sampled_gradient_3d_matches_central_differences(oracle_lib, b):
-    g, sim, y = _setup(oracle_lib, sub=b)
+    g, sim, y = _setup(oracle_lib, sub=int(2 * b))
     grad = oracle_lib.objective_grad(sim, y, M=5, b=b, gamma=0.1, seed=3, it=7)
     assert grad.shape == (g.n, 3)
     h = 1e-6
-    rng = np.random.default_rng(b)
+    rng = np.random.default_rng(int(2 * b))
     for i in rng.choice(g.n, 10, replace=False):
         for c in (0, 1, 2):
             yp, ym = y.copy(), y.copy()

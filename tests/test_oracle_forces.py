@@ -18,12 +18,14 @@ def _setup(oracle_lib, n=30, p=0.15, k=2, sub=0, scale=1.5):
     return g, sim, y
 
 
-@pytest.mark.parametrize("b", [1, 2, 3])
+@pytest.mark.parametrize("b", [1, 1.5, 2, 2.5, 3])
 def test_sampled_gradient_matches_central_differences(oracle_lib, b):
-    g, sim, y = _setup(oracle_lib, sub=b)
+    """b = 1.5 and 2.5 (half values: d^{2b} = (d^2)^floor(b) sqrt(d^2)) as
+    well as the whole ones."""
+    g, sim, y = _setup(oracle_lib, sub=int(2 * b))
     grad = oracle_lib.objective_grad(sim, y, M=5, b=b, gamma=0.1, seed=3, it=7)
     h = 1e-6
-    rng = np.random.default_rng(b)
+    rng = np.random.default_rng(int(2 * b))
     for i in rng.choice(g.n, 12, replace=False):
         for c in (0, 1):
             yp, ym = y.copy(), y.copy()
@@ -34,9 +36,9 @@ def test_sampled_gradient_matches_central_differences(oracle_lib, b):
             assert fd == pytest.approx(grad[i, c], rel=1e-5, abs=1e-7)
 
 
-@pytest.mark.parametrize("b", [1, 2])
+@pytest.mark.parametrize("b", [1, 1.5, 2])
 def test_exact_gradient_matches_central_differences(oracle_lib, b):
-    g, sim, y = _setup(oracle_lib, n=20, sub=10 + b)
+    g, sim, y = _setup(oracle_lib, n=20, sub=10 + int(2 * b))
     grad = oracle_lib.objective_exact_grad(sim, y, M=5, b=b, gamma=0.1)
     h = 1e-6
     for i in range(0, g.n, 3):
@@ -68,7 +70,7 @@ def test_two_node_student_t(oracle_lib):
 
 
 @pytest.mark.parametrize("clip", [math.inf, 0.05])
-@pytest.mark.parametrize("b", [1, 3])
+@pytest.mark.parametrize("b", [1, 2.5, 3])
 def test_zero_net_attraction(oracle_lib, clip, b):
     """P~ symmetric and the attraction antisymmetric (clipping is odd), so
     the attractive forces sum to zero."""
@@ -106,6 +108,26 @@ def test_monte_carlo_step_converges_to_expectation(oracle_lib):
     assert z.max() < 5.0
     grad_exact = oracle_lib.objective_exact_grad(sim, y, 5, 2, 0.1)
     assert np.allclose(grad_exact, 2 * expd, rtol=1e-6, atol=1e-9)
+
+
+def test_half_b_between_whole_b_and_continuous(oracle_lib):
+    """The half-b terms are the same function of b as the whole ones: the
+    two-node attraction and objective at b = 1.5 lie strictly between those
+    at b = 1 and b = 2 for d > 1, and as b -> 1.5 from a smooth family
+    (numpy's real power d^{2b} at b = 1.5 +- 1e-7) the oracle's value is
+    the limit (no jump at the half value)."""
+    g = gen.canonical_csr(2, np.array([0]), np.array([1]))
+    sim = oracle_lib.similarity(g, 1)
+    y = np.array([[0.0, 0.0], [1.7, 0.4]])
+    d2 = float(((y[0] - y[1]) ** 2).sum())
+    L = {b: oracle_lib.objective(sim, y, 0, b, 0.0, 0, 0) for b in (1, 1.5, 2)}
+    G = {b: oracle_lib.objective_grad(sim, y, 0, b, 0.0, 0, 0)[0, 0] for b in (1, 1.5, 2)}
+    assert L[2] < L[1.5] < L[1]
+    assert min(G[1], G[2]) < G[1.5] < max(G[1], G[2])
+    # P~_01 = P~_10 = 1: L = -2 log1p(d^{2b}) as a smooth function of b
+    for eps in (1e-7, -1e-7):
+        smooth = -2.0 * np.log1p(d2 ** (1.5 + eps))
+        assert abs(smooth - L[1.5]) < 1e-5
 
 
 def test_sampled_objective_is_unbiased(oracle_lib):
