@@ -167,6 +167,129 @@ void drgo_similarity(int32_t n, int32_t k, double sigma, const int64_t* prp, con
 }
 
 /* ------------------------------------------------------------------------ */
+/* Node-wise sigma_i (Eq. NS gives each node its own Gaussian): sigma_i is    */
+/* chosen so that the conditional distribution NS_{.|i} over NNG(i, k) has    */
+/* a given perplexity exp(H_i), H_i its entropy in nats -- the calibration    */
+/* of t-SNE (van der Maaten and Hinton, JMLR 2008), which the paper builds    */
+/* on.  With t = exp(-1/(2 sigma_i^2)) in (0, 1] the Gaussian of hop d is    */
+/* t^(d^2), so NS_{.|i} depends on t and the hop histogram c_d(i) only.     */
+/* Every step uses IEEE operations only (frexp, +, -, *, / and comparisons) */
+/* so that another program doing the same operations in the same order     */
+/* obtains the same bits.                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Natural logarithm, x > 0 finite: x = m 2^e with m in [sqrt(1/2), sqrt(2)),  */
+/* ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| < 0.172, and              */
+/* atanh(s) = s (1 + s^2/3 + s^4/5 + ...), summed by Horner's rule over the  */
+/* first 13 terms (the rest is below 1e-20 of the sum); ln x = e ln2 + ln m. */
+double drgo_ln(double x) {
+    int e = 0;
+    double m = frexp(x, &e); /* m in [1/2, 1) */
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double s2 = s * s;
+    double p = 1.0 / 25.0;
+    for (int j = 11; j >= 0; --j) p = p * s2 + 1.0 / (double)(2 * j + 1);
+    double lm = 2.0 * s * p;
+    return (double)e * 0.69314718055994530942 + lm;
+}
+
+/* e[d-1] = t^(d^2), d = 1..k, as a running product of d^2 factors t */
+static void hop_gauss_t(double t, int32_t k, double* e) {
+    for (int32_t d = 1; d <= k; ++d) {
+        double p = 1.0;
+        for (int32_t r = 0; r < d * d; ++r) p = p * t;
+        e[d - 1] = p;
+    }
+}
+
+/* Z = sum_d c_d t^(d^2) and H = ln Z - ln(t) S / Z, S = sum_d c_d d^2 t^(d^2):  */
+/* the entropy of p_j = t^(d_ij^2) / Z over the neighbourhood.                 */
+static double entropy_t(const int64_t* cnt, int32_t k, double t, double* zout) {
+    double e[8];
+    hop_gauss_t(t, k, e);
+    double z = 0.0, sw = 0.0;
+    for (int32_t d = 0; d < k; ++d) {
+        double c = (double)cnt[d];
+        double term = c * e[d];
+        z = z + term;
+        double dd = (double)((d + 1) * (d + 1));
+        sw = sw + term * dd;
+    }
+    if (zout) *zout = z;
+    double lt = drgo_ln(t);
+    return drgo_ln(z) - lt * (sw / z);
+}
+
+/* t of a node with a non-empty neighbourhood.  H grows with t (the entropy  */
+/* of a Gibbs distribution falls as its inverse temperature -ln t grows);    */
+/* its largest value, ln N at t = 1 (uniform), is taken when the target      */
+/* reaches it; otherwise 64 halvings of (0, 1).                              */
+static double calibrate_t(const int64_t* cnt, int32_t k, double target) {
+    if (entropy_t(cnt, k, 1.0, NULL) <= target) return 1.0;
+    double lo = 0.0, hi = 1.0;
+    for (int r = 0; r < 64; ++r) {
+        double mid = 0.5 * (lo + hi);
+        if (entropy_t(cnt, k, mid, NULL) < target)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+int32_t drgo_similarity_perplexity(int32_t n, int32_t k, double perplexity, const int64_t* prp,
+                                   const int32_t* pcol, const uint8_t* phop, double* tnode,
+                                   double* A, double* Z, double* invZ, double* P, double* qt,
+                                   uint64_t* W, uint64_t* C) {
+    if (k < 1 || k > 8 || !(perplexity >= 1.0) || !(perplexity < 1e300)) return -1;
+    const double target = drgo_ln(perplexity);
+    int64_t cnt[8];
+    double e[8];
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t d = 0; d < k; ++d) cnt[d] = 0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) cnt[phop[x] - 1] += 1;
+        if (prp[i + 1] == prp[i]) { /* isolated: no distribution */
+            tnode[i] = 1.0;
+            Z[i] = 0.0;
+            invZ[i] = 0.0;
+            for (int32_t d = 0; d < k; ++d) A[(int64_t)i * k + d] = 0.0;
+            continue;
+        }
+        double t = calibrate_t(cnt, k, target);
+        double z = 0.0;
+        entropy_t(cnt, k, t, &z);
+        hop_gauss_t(t, k, e);
+        tnode[i] = t;
+        Z[i] = z;
+        invZ[i] = 1.0 / z;
+        for (int32_t d = 0; d < k; ++d) A[(int64_t)i * k + d] = e[d] / z; /* NS_{j|i}, hop d+1 */
+    }
+    /* P~_ij = (NS_{j|i} + NS_{i|j}) / 2, scaled as in drgo_similarity */
+    C[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double q = 0.0;
+        uint64_t w = 0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            int32_t h = phop[x] - 1;
+            double s = A[(int64_t)i * k + h] + A[(int64_t)j * k + h];
+            double p = s * 0.5;
+            P[x] = p;
+            q = q + p;
+            w += (uint64_t)(p * 4294967296.0);
+        }
+        qt[i] = q;
+        W[i] = w;
+        C[i + 1] = C[i] + w;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The same similarity for a list of rows only, for graphs too large to take */
 /* whole: row s is NNG(s, k) by the bounded BFS above, ascending; Z of every */
 /* node involved is its own hop histogram weighted by e (each node's BFS run */

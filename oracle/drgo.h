@@ -52,6 +52,18 @@ void drgo_similarity(int32_t n, int32_t k, double sigma, const int64_t* prp, con
                      const uint8_t* phop, double* e, double* Z, double* invZ, double* P, double* qt,
                      uint64_t* W, uint64_t* C);
 
+/* Node-wise sigma_i calibrated to a perplexity (Eq. NS with one sigma per
+ * node; t-SNE's calibration): per node t_i = exp(-1/(2 sigma_i^2)) in
+ * tnode[n], the conditional probabilities NS_{j|i} of hop d in A[i*k + d-1],
+ * Z, invZ, and P~_ij = (NS_{j|i} + NS_{i|j}) / 2 with qt, W, C as in
+ * drgo_similarity.  Returns -1 for k outside 1..8 or perplexity < 1. */
+int32_t drgo_similarity_perplexity(int32_t n, int32_t k, double perplexity, const int64_t* prp,
+                                   const int32_t* pcol, const uint8_t* phop, double* tnode,
+                                   double* A, double* Z, double* invZ, double* P, double* qt,
+                                   uint64_t* W, uint64_t* C);
+/* Natural logarithm from IEEE operations only (atanh series), x > 0. */
+double drgo_ln(double x);
+
 /* The same similarity for the rows srcs[0..nsrc) only (k <= 8): out_rp[nsrc+1]
  * row offsets; with out_col non-NULL also the rows' columns (ascending), hops,
  * P~ values, and per row 1/Z, qt and W.  Returns the number of entries. */

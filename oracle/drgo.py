@@ -56,6 +56,12 @@ def lib():
                                        C.c_int32, _i32p, _i64p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.drgo_similarity_rows.restype = C.c_int64
+    L.drgo_similarity_perplexity.argtypes = [C.c_int32, C.c_int32, C.c_double, _i64p, _i32p,
+                                             _u8p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                             _u64p, _u64p]
+    L.drgo_similarity_perplexity.restype = C.c_int32
+    L.drgo_ln.argtypes = [C.c_double]
+    L.drgo_ln.restype = C.c_double
     L.drgo_draw.argtypes = [_u64p, C.c_int32, C.c_uint64]
     L.drgo_draw.restype = C.c_int32
     L.drgo_neg_word.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_int32]
@@ -117,6 +123,9 @@ class Sim:
     qt: np.ndarray       # float64[n]
     W: np.ndarray        # uint64[n]
     C: np.ndarray        # uint64[n+1]
+    perplexity: float = 0.0  # > 0: node-wise sigma_i calibrated to it
+    t: np.ndarray = None     # float64[n]: exp(-1/(2 sigma_i^2)) per node
+    A: np.ndarray = None     # float64[n, k]: NS_{j|i} of hop d in A[i, d-1]
 
     @property
     def nnz(self) -> int:
@@ -161,6 +170,45 @@ def similarity_from_pattern(n, k, sigma, rp, col, hop) -> Sim:
                           e, Z, invZ, P, qt, W, Cc)
     return Sim(n, k, float(sigma), _c(rp, np.int64), colc[:nnz], hopc[:nnz], e, Z, invZ,
                P[:nnz], qt, W, Cc)
+
+
+def similarity_perplexity(csr, k: int, perplexity: float) -> Sim:
+    """P~ with one sigma_i per node (Eq. NS), each chosen so that NS_{.|i}
+    has the given perplexity (t-SNE's calibration); see
+    drgo_similarity_perplexity."""
+    rp, col, hop = khop(csr, k)
+    return similarity_perplexity_from_pattern(int(csr.n), k, perplexity, rp, col, hop)
+
+
+def similarity_perplexity_from_pattern(n, k, perplexity, rp, col, hop) -> Sim:
+    nnz = int(rp[-1])
+    t = np.zeros(n, np.float64)
+    A = np.zeros(n * k, np.float64)
+    Z = np.zeros(n, np.float64)
+    invZ = np.zeros(n, np.float64)
+    P = np.zeros(max(nnz, 1), np.float64)
+    qt = np.zeros(n, np.float64)
+    W = np.zeros(n, np.uint64)
+    Cc = np.zeros(n + 1, np.uint64)
+    colc = _c(col if nnz else np.zeros(1, np.int32), np.int32)
+    hopc = _c(hop if nnz else np.ones(1, np.uint8), np.uint8)
+    rc = lib().drgo_similarity_perplexity(n, k, float(perplexity), _c(rp, np.int64), colc, hopc,
+                                          t, A, Z, invZ, P, qt, W, Cc)
+    if rc != 0:
+        raise ValueError("k must be in 1..8 and perplexity >= 1")
+    return Sim(n, k, 0.0, _c(rp, np.int64), colc[:nnz], hopc[:nnz], np.zeros(k), Z, invZ,
+               P[:nnz], qt, W, Cc, float(perplexity), t, A.reshape(n, k))
+
+
+def node_sigma(sim: Sim) -> np.ndarray:
+    """sigma_i = sqrt(-1 / (2 ln t_i)) of a node-wise similarity (inf where
+    t_i = 1, the uniform distribution; 0 for isolated nodes)."""
+    out = np.zeros(sim.n, np.float64)
+    act = np.diff(sim.row_ptr) > 0
+    with np.errstate(divide="ignore"):
+        lt = np.log(sim.t[act])
+        out[act] = np.where(lt < 0, np.sqrt(-0.5 / np.where(lt < 0, lt, -1.0)), np.inf)
+    return out
 
 
 def similarity_rows(csr, k: int, sources, sigma: float = 1.0) -> dict:
@@ -378,10 +426,13 @@ def eta_at(eta0: float, t: int, Tl: int) -> float:
 
 def layout(csr, k=1, sigma=1.0, M=5, b=1, gamma=0.1, gamma_coarsest=0.01, T=400, eta0=1.0,
            clip=4.0, rho=0.8, min_nodes=1000, max_levels=64, seed=0, mode="sync",
-           sim: Sim | None = None, hier: Hier | None = None, return_all=False, dim=2):
-    """Full multilevel layout; returns Y^0 [n, dim] (float64)."""
+           sim: Sim | None = None, hier: Hier | None = None, return_all=False, dim=2,
+           perplexity=0.0):
+    """Full multilevel layout; returns Y^0 [n, dim] (float64).  perplexity >
+    0 takes node-wise sigma_i calibrated to it instead of sigma."""
     if sim is None:
-        sim = similarity(csr, k, sigma)
+        sim = (similarity_perplexity(csr, k, perplexity) if perplexity > 0
+               else similarity(csr, k, sigma))
     if hier is None:
         hier = hierarchy(csr, seed, rho, min_nodes, max_levels)
     Lc = hier.levels
