@@ -77,7 +77,8 @@ typedef struct {
 /* Parameters of one optimisation iteration (Sec. 3.2.2, Eq. gradient). */
 typedef struct {
     int32_t M;               /* negative samples per node, >= 0 */
-    int32_t b;               /* proximity shape parameter, 1..3 (Sec. 4.2) */
+    int32_t b;               /* proximity shape parameter, 1..3 (Sec. 4.2); with b_half
+                                set, b + 1/2.  A half b runs the row-form sweep */
     float gamma;             /* weight of negative samples */
     float eta;               /* step size of this iteration */
     float clip;              /* per-pair, per-component force clip, > 0 */
@@ -86,6 +87,8 @@ typedef struct {
     int32_t dim;             /* 2 (or 0): positions in R^2, y [n][2]; 3: R^3, y [n][3] */
     uint64_t seed;
     uint64_t iter;           /* global iteration index; keys the negatives */
+    int32_t b_half;          /* 1: the shape is b + 1/2 (b = 1 or 2: 1.5, 2.5); 0: b */
+    int32_t _pad;
 } drg_step_params;
 
 /* Parameters of the whole multilevel layout (Sec. 3.2, Sec. 4 defaults). */
@@ -105,6 +108,10 @@ typedef struct {
     int32_t mode;            /* DRG_MODE_SYNC or DRG_MODE_ASYNC */
     int32_t dim;             /* 2 (or 0) or 3: coordinates [n][dim] (Sec. 3.1) */
     uint64_t seed;
+    int32_t b_half;          /* 1: the shape is b + 1/2 (b = 1 or 2) */
+    int32_t _pad;
+    double perplexity;       /* 0: one sigma for all nodes; >= 1: node-wise sigma_i
+                                calibrated to it (drg_build_similarity_perplexity) */
 } drg_layout_params;
 
 /* Parameters of the sampled objective (Eq. objectfunction). */
@@ -115,7 +122,7 @@ typedef struct {
     uint64_t seed;
     uint64_t iter;           /* keys the negatives like drg_layout_step */
     int32_t dim;             /* 2 (or 0) or 3: coordinates [n][dim] */
-    int32_t _pad;
+    int32_t b_half;          /* 1: the shape is b + 1/2 (b = 1 or 2) */
 } drg_obj_params;
 
 const char* drg_last_error(void);
@@ -169,13 +176,33 @@ drg_status drg_ctx_last_sweep(const drg_ctx* ctx, int32_t* form);
  * Synchronises.  The result lives in device memory owned by *out. */
 drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, double sigma,
                                 uint32_t flags, drg_sim** out);
+/* The same similarity with one sigma_i per node (Eq. NS writes sigma_i), each
+ * chosen so that the conditional distribution NS_{.|i} over NNG(i, k) has
+ * the given perplexity exp(H_i), H_i its entropy in nats (the calibration
+ * of t-SNE, on which the method builds).  With t_i = exp(-1/(2 sigma_i^2))
+ * the Gaussian of hop d is t_i^(d^2); t_i is found by 64 bisection steps
+ * on (0, 1) (the entropy grows with t), or is 1 (uniform over NNG(i, k))
+ * when ln(perplexity) >= ln |NNG(i, k)|.  Then
+ *   NS_{j|i} = t_i^(d_ij^2) / Z_i,  P~_ij = (NS_{j|i} + NS_{i|j}) / 2,
+ * with qt, the sampling table and 1/Z as for drg_build_similarity.  The
+ * calibration uses IEEE-754 operations only (its logarithm is the atanh
+ * series), so its results are reproducible bit for bit.  Such a similarity
+ * is swept by the row-form kernels (no column-blocked copy).
+ * perplexity >= 1 and finite; k in 1..4.  Synchronises. */
+drg_status drg_build_similarity_perplexity(drg_ctx* ctx, const drg_csr* g, int32_t k,
+                                           double perplexity, uint32_t flags, drg_sim** out);
+/* sigma_i of every node into sigma_host[n] (host; synchronises): the global
+ * sigma, or for a node-wise similarity sqrt(-1/(2 ln t_i)) (+inf where t_i = 1);
+ * 0 for isolated nodes. */
+drg_status drg_sim_node_sigma(const drg_sim* s, double* sigma_host);
 /* Host-side sizes (no synchronisation needed); *blocked (nullable) is 1 when
  * the synchronous FP32 sweep runs over the column-blocked copy of P~. */
 drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_active,
                         int32_t* k, int32_t* blocked);
 /* Copies the similarity to host arrays (each nullable; synchronises):
  * row_ptr[n+1], col[nnz], hop[nnz] (1..k), P[nnz] (FP64 P~_ij), qt[n] (FP64),
- * W[n] (uint64 sampling weights), e[k] (FP64), invZ[n] (FP64). */
+ * W[n] (uint64 sampling weights), e[k] (FP64; zeros for a node-wise
+ * similarity), invZ[n] (FP64). */
 drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop,
                           double* P, double* qt, uint64_t* W, double* e, double* invZ);
 /* Copies the rows rows[0..nrows) of the similarity to host arrays (each

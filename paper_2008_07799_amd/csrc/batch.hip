@@ -233,7 +233,7 @@ template <int B, bool CLIP>
 __device__ __forceinline__ float2 b_row(const BSweepArgs& a, const BGraph& g, int64_t i,
                                         int32_t v, int lane, float gamma) {
     return sweep_row<float, B, CLIP>(a.rec[i], a.prp[i], a.prp[i + 1], lane, g.G, a.colhop, a.rec, a.eh,
-                               g.clip, g.M, g.seed, (uint64_t)a.t, v,
+                               g.clip, false, g.M, g.seed, (uint64_t)a.t, v,
                                [&](uint64_t w) {
                                    return g.base + draw_in_graph(w, a.C, a.guide, g);
                                },
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(WIN_BLOCK) void k_b_sweep_win(BWinArgs a) {
     auto key = [&](int64_t i) { return (int32_t)(i - g.base); };
     auto item = [&](auto b_c, auto clip_c) {
         window_item<decltype(b_c)::value, decltype(clip_c)::value, RPL, WIN_BLOCK>(
-            it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh, g.clip, g.M, g.seed,
+            it, g.G, s_rec, a.CH, a.prp, a.colhop, a.rec, a.qt, a.eh, g.clip, false, g.M, g.seed,
             (uint64_t)a.t, sc.gamma, draw, key, a.g);
     };
     using yes = std::true_type;
@@ -531,6 +531,9 @@ void check_layout_params(const drg_layout_params* p) {
         throw Error(DRG_E_INVALID, "unknown mode");
     if (p->dim != 0 && p->dim != 2 && p->dim != 3)
         throw Error(DRG_E_INVALID, "dim must be 2 (or 0) or 3");
+    check_shape(p->b, p->b_half);
+    if (p->perplexity != 0.0 && !(p->perplexity >= 1.0 && p->perplexity < 1e300))
+        throw Error(DRG_E_INVALID, "perplexity must be 0 (global sigma) or >= 1 and finite");
 }
 
 template <typename T>
@@ -558,6 +561,10 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
             throw Error(DRG_E_UNSUPPORTED, "batched layout: synchronous mode only");
         if (p.dim == 3)
             throw Error(DRG_E_UNSUPPORTED, "batched layout: 2-D layouts only");
+        if (p.b_half)
+            throw Error(DRG_E_UNSUPPORTED, "batched layout: whole b only");
+        if (p.perplexity != 0.0)
+            throw Error(DRG_E_UNSUPPORTED, "batched layout: one global sigma only");
         if (p.k != params[0].k || p.sigma != params[0].sigma)
             throw Error(DRG_E_INVALID, "batched layout: k and sigma must agree over the batch");
         if (!(p.rho > 0.0 && p.rho <= 1.0) || p.max_levels < 1 || p.min_nodes < 0)

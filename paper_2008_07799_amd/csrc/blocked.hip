@@ -376,7 +376,7 @@ int blk_flat_cpl() {
 // 2b d^{2b-1} / (1 + d^{2b}) in magnitude, whose maximum over d (at
 // d^{2b} = 2b - 1) is (2b-1)^{(2b-1)/(2b)}.  A 1% margin covers the
 // rounding of the coefficient and of d^2.
-bool attract_clip_free(int b, double clip) {
+bool attract_clip_free(double b, double clip) {
     const double m = std::pow(2.0 * b - 1.0, (2.0 * b - 1.0) / (2.0 * b));
     return clip >= 1.01 * m;
 }

@@ -185,6 +185,26 @@ drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, doubl
     });
 }
 
+drg_status drg_build_similarity_perplexity(drg_ctx* ctx, const drg_csr* g, int32_t k,
+                                           double perplexity, uint32_t flags, drg_sim** out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(out, "out");
+        *out = nullptr;
+        if (!(perplexity >= 1.0) || !(perplexity < 1e300))
+            throw drg::Error(DRG_E_INVALID, "perplexity must be >= 1 and finite");
+        CtxScope scope(ctx);
+        *out = drg::build_similarity(ctx, g, k, 1.0, flags, nullptr, perplexity);
+    });
+}
+
+drg_status drg_sim_node_sigma(const drg_sim* s, double* sigma_host) {
+    return guarded([&] {
+        need(s, "sim");
+        drg::sim_node_sigma(s, sigma_host);
+    });
+}
+
 drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_active,
                         int32_t* k, int32_t* blocked) {
     return guarded([&] {
@@ -548,6 +568,7 @@ static void run_schedule(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_
             sp.level = l;
             sp.mode = p->mode;
             sp.dim = D;
+            sp.b_half = p->b_half;
             sp.seed = p->seed;
             const int32_t t0 = l == start.level ? start.t : 0;
             const int32_t t1 = l == stop.level ? stop.t : Tl;
@@ -655,7 +676,8 @@ drg_status drg_layout(drg_ctx* ctx, const drg_csr* g, const drg_layout_params* p
         check_layout_params(p);
         CtxScope scope(ctx);
         std::unique_ptr<drg_sim, void (*)(drg_sim*)> s(
-            drg::build_similarity(ctx, g, p->k, p->sigma, 0), drg_sim_destroy);
+            drg::build_similarity(ctx, g, p->k, p->sigma, 0, nullptr, p->perplexity),
+            drg_sim_destroy);
         std::unique_ptr<drg_hier, void (*)(drg_hier*)> h(
             drg::build_hierarchy(ctx, g, p->seed, p->rho, p->min_nodes, p->max_levels),
             drg_hier_destroy);

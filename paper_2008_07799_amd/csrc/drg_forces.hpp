@@ -80,6 +80,27 @@ __device__ __forceinline__ T repel_coef(T d2) {
     return T(2 * B) * recipT(d2 * (T(1) + powT<B>(d2)));
 }
 
+// The same for b = B + 1/2 (half = true): d^{2b} = (d^2)^B d and
+// d^{2b-2} = (d^2)^{B-1} d with d = sqrt(d^2).  half is uniform over a
+// launch; a whole b takes the functions above unchanged.
+template <typename T>
+__device__ __forceinline__ T sqrtT(T x) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_sqrtf(x);
+    else return __builtin_sqrt(x);
+}
+template <int B, typename T>
+__device__ __forceinline__ T attract_coef_b(T d2, bool half) {
+    if (!half) return attract_coef<B, T>(d2);
+    const T d = sqrtT(d2);
+    return T(-(2 * B + 1)) * (powT<B - 1>(d2) * d) * recipT(T(1) + powT<B>(d2) * d);
+}
+template <int B, typename T>
+__device__ __forceinline__ T repel_coef_b(T d2, bool half) {
+    if (!half) return repel_coef<B, T>(d2);
+    const T d = sqrtT(d2);
+    return T(2 * B + 1) * recipT(d2 * (T(1) + powT<B>(d2) * d));
+}
+
 template <typename T>
 __device__ __forceinline__ T clampT2(T v, T c) {
     if constexpr (std::is_same<T, float>::value) return clampf(v, c);
@@ -130,6 +151,20 @@ struct HalfE {
     }
 };
 
+// Node-wise sigma: P~_ij = (A_i[d] + A_j[d]) / 2 from the table A [n][4]
+// (A_i[d] = NS_{j|i} at hop d+1); ai holds row i's four values.  A = NULL:
+// one global sigma, P~_ij = e_d/2 (1/Z_i + 1/Z_j) from the records.
+struct PairW {
+    const double* A = nullptr;
+    HalfE<double> ai{0.0, 0.0, 0.0, 0.0};
+};
+__device__ __forceinline__ PairW pair_w(const double* __restrict__ A, int64_t i) {
+    PairW p;
+    p.A = A;
+    if (A) p.ai = HalfE<double>{A[4 * i], A[4 * i + 1], A[4 * i + 2], A[4 * i + 3]};
+    return p;
+}
+
 // Attraction of one pattern entry e (record rj) on the node with record ri,
 // added to the lane's partial (ax, ay).  Records hold (x, y, 1/Z high part,
 // 1/Z low part) in the coordinate type T; the pair's arithmetic and the
@@ -144,12 +179,18 @@ struct HalfE {
 template <typename T, int B, bool CLIP = true>
 __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
                                              const typename VT<T>::v4& rj, const HalfE<double>& eh,
-                                             double clip, double& ax, double& ay) {
+                                             double clip, bool half, double& ax, double& ay,
+                                             PairW pw = PairW{}) {
     const double dx = (double)ri.x - (double)rj.x, dy = (double)ri.y - (double)rj.y;
     const double d2 = dx * dx + dy * dy;
-    const double k = attract_coef<B, double>(d2);
-    const double zi = (double)ri.z + (double)ri.w, zj = (double)rj.z + (double)rj.w;
-    const double w = eh(e >> 30) * (zi + zj);
+    const double k = attract_coef_b<B, double>(d2, half);
+    double w;
+    if (pw.A) {
+        w = (pw.ai(e >> 30) + pw.A[4 * (int64_t)(e & COL_MASK) + (e >> 30)]) * 0.5;
+    } else {
+        const double zi = (double)ri.z + (double)ri.w, zj = (double)rj.z + (double)rj.w;
+        w = eh(e >> 30) * (zi + zj);
+    }
     if constexpr (CLIP) {
         ax += w * clampT2(k * dx, clip);
         ay += w * clampT2(k * dy, clip);
@@ -165,7 +206,8 @@ template <typename T, int B, typename Draw>
 __device__ __forceinline__ void repel_lane(const typename VT<T>::v4& ri,
                                            const typename VT<T>::v4* __restrict__ rec, int lane,
                                            int G, int M, uint64_t seed, uint64_t iter, int32_t key,
-                                           Draw draw, double clip, double& rx, double& ry) {
+                                           Draw draw, double clip, bool half, double& rx,
+                                           double& ry) {
     rx = 0.0;
     ry = 0.0;
     for (int m = lane; m < M; m += G) {
@@ -174,7 +216,7 @@ __device__ __forceinline__ void repel_lane(const typename VT<T>::v4& ri,
         const double dx = (double)ri.x - (double)rv.x, dy = (double)ri.y - (double)rv.y;
         const double d2 = dx * dx + dy * dy;
         if (d2 > 0.0) {
-            const double k = repel_coef<B, double>(d2);
+            const double k = repel_coef_b<B, double>(d2, half);
             rx += clampT2(k * dx, clip);
             ry += clampT2(k * dy, clip);
         }
@@ -203,8 +245,8 @@ template <typename T, int B, bool CLIP, typename Draw>
 __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
     const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
-    const HalfE<double>& eh, double clip, int M, uint64_t seed, uint64_t iter, int32_t key,
-    Draw draw, double gq) {
+    const HalfE<double>& eh, double clip, bool half, int M, uint64_t seed, uint64_t iter,
+    int32_t key, Draw draw, double gq, PairW pw = PairW{}) {
     using v4 = typename VT<T>::v4;
     double ax = 0.0, ay = 0.0;
     // U entries per step; the next step's entries are loaded while this
@@ -230,7 +272,8 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
 #pragma unroll
         for (int q = 0; q < U; ++q) en[q] = colhop[max(xl + (int64_t)q * G, x)];
 #pragma unroll
-        for (int q = 0; q < U; ++q) attract_pair<T, B, CLIP>(ri, e[q], rj[q], eh, clip, ax, ay);
+        for (int q = 0; q < U; ++q)
+            attract_pair<T, B, CLIP>(ri, e[q], rj[q], eh, clip, half, ax, ay, pw);
 #pragma unroll
         for (int q = 0; q < U; ++q) e[q] = en[q];
         x = xn;
@@ -238,10 +281,10 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     }
     for (; x < re; x += G) {
         const uint32_t e = colhop[x];
-        attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, ax, ay);
+        attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, half, ax, ay, pw);
     }
     double rx, ry;
-    repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, rx, ry);
+    repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, half, rx, ry);
     return row_total<T>(ax, ay, rx, ry, G, gq);
 }
 
@@ -266,7 +309,7 @@ __device__ __forceinline__ void window_item(
     const WinItem& it, int G, float4* __restrict__ lds, int CH,
     const int64_t* __restrict__ prp, const uint32_t* __restrict__ colhop,
     const float4* __restrict__ rec, const float* __restrict__ qt, const HalfE<double>& eh,
-    double clip, int M, uint64_t seed, uint64_t iter, double gamma, Draw draw, Key key,
+    double clip, bool half, int M, uint64_t seed, uint64_t iter, double gamma, Draw draw, Key key,
     float2* __restrict__ g) {
     const int tid = threadIdx.x;
     const int NG = BLOCK / G;
@@ -311,7 +354,8 @@ __device__ __forceinline__ void window_item(
                 for (; q < U; ++q) {
                     const int32_t c = (int32_t)(e[q] & COL_MASK);
                     if (c >= b1) break;
-                    attract_pair<float, B, CLIP>(ri[k], e[q], lds[c - b0], eh, clip, sx, sy);
+                    attract_pair<float, B, CLIP>(ri[k], e[q], lds[c - b0], eh, clip, half, sx,
+                                                 sy);
                 }
                 x += (int64_t)q * G;
                 if (q < U) break;
@@ -329,7 +373,8 @@ __device__ __forceinline__ void window_item(
         float2 gi = make_float2(0.0f, 0.0f);
         if (prp[i] < prp[i + 1]) {
             double rx, ry;
-            repel_lane<float, B>(ri[k], rec, lane, G, M, seed, iter, key(i), draw, clip, rx, ry);
+            repel_lane<float, B>(ri[k], rec, lane, G, M, seed, iter, key(i), draw, clip, half, rx,
+                                 ry);
             gi = row_total<float>(ax[k], ay[k], rx, ry, G, gamma * (double)qt[i]);
         }
         if (lane == 0) g[i] = gi;

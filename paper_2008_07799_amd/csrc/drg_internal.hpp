@@ -25,7 +25,8 @@ struct drg_sim {
     int device = 0;
     int32_t n = 0, k = 0, n_active = 0;
     int64_t nnz = 0;
-    double sigma = 1.0;
+    double sigma = 1.0;              // 0 with node-wise sigma
+    double perplexity = 0.0;         // > 0: node-wise sigma calibrated to it
     double e[4] = {0, 0, 0, 0};
     drg::DevBuf<int64_t> row_ptr;    // [n+1]
     drg::DevBuf<uint32_t> colhop;    // [nnz] col | (hop-1) << 30, ascending col per row
@@ -39,6 +40,10 @@ struct drg_sim {
     drg::DevBuf<float> invZf;        // [n]
     drg::DevBuf<float> invZlo;       // [n] 1/Z - invZf (so hi + lo holds 1/Z to ~48 bits)
     drg::DevBuf<float> qtf;          // [n]
+    // node-wise sigma only: A[i][d] = NS_{j|i} for j at hop d+1 (P~_ij =
+    // (A_i[d] + A_j[d]) / 2), and t_i = exp(-1/(2 sigma_i^2))
+    drg::DevBuf<double> A;           // [n][4]
+    drg::DevBuf<double> tnode;       // [n]
     // per-iteration workspace of the layout step
     drg::DevBuf<float4> rec;         // [n] staged (y_c(j), invZ_j)
     drg::DevBuf<float2> g;           // [n] one-sided steps
@@ -106,8 +111,10 @@ inline int sweep_group(double mean_len) {
 // With u, the pattern is built for every graph of the union at once, each
 // graph's row weights with the launch shape of its own single-graph build;
 // the sampling guide and the column-blocked copy are then left out.
+// perplexity != 0: node-wise sigma_i calibrated to it (sigma unused).
 drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
-                          UnionInfo* u = nullptr);
+                          UnionInfo* u = nullptr, double perplexity = 0.0);
+void sim_node_sigma(const drg_sim* s, double* sigma);
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
 void validate_csr_impl(drg_ctx* ctx, const drg_csr* g, bool full);
 void stress_sampled(drg_ctx* ctx, const drg_csr* g, const float* y, int32_t count,
@@ -138,7 +145,12 @@ void build_blocked_core(drg_ctx* ctx, int32_t n, int64_t nnz, const int64_t* prp
                         const uint32_t* colhop, int32_t col_base, BlkLayout& L);
 int blk_flat_cpl();  // chunks per lane and batch of the flat form (env DRG_BLK_FLAT: 2, 4; 0: row form)
 int blk_lanes();
-bool attract_clip_free(int b, double clip);  // the attraction clip cannot bind     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
+bool attract_clip_free(double b, double clip);
+// b = whole in 1..3, or b + 1/2 (b_half = 1) for b in 1..2; else DRG_E_INVALID
+inline void check_shape(int32_t b, int32_t b_half) {
+    if (b < 1 || b > 3 || (b_half != 0 && b_half != 1) || (b_half && b > 2))
+        throw Error(DRG_E_INVALID, "b must be 1, 1.5, 2, 2.5 or 3 (b in 1..3, b_half 0 or 1)");
+}  // the attraction clip cannot bind     // row form: lanes per segment (env DRG_BLK_LANES; 0: per item)
 // One FP32 sync sweep on the blocked layout: the one-sided steps into g.
 void sweep_blocked(drg_ctx* ctx, drg_sim* s, int b, int M, float gamma, float clip,
                    uint64_t seed, uint64_t iter, float2* g, hipEvent_t e0, hipEvent_t e1);

@@ -70,6 +70,8 @@ struct SweepArgs {
     double eh0, eh1, eh2, eh3;  // e_d / 2
     T gamma, clip;
     int32_t noclip;        // the attraction clip cannot bind (attract_clip_free)
+    int32_t half;          // b = B + 1/2
+    const double* A;       // node-wise sigma: P~ table [n0][4] (NULL: global sigma)
     uint64_t seed, iter;
     // async only
     v2* y;
@@ -97,12 +99,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
             typename VT<T>::v2 gi = mk2<T>(T(0), T(0));
             if (rs < re)
                 gi = sweep_row<T, B, CLIP>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh,
-                                           (double)a.clip,
+                                           (double)a.clip, a.half != 0,
                                            a.M, a.seed, a.iter, (int32_t)i,
                                            [&](uint64_t w) {
                                                return draw_node(w, a.C, a.guide, a.gbits, a.S);
                                            },
-                                           (double)a.gamma * (double)a.qt[i]);
+                                           (double)a.gamma * (double)a.qt[i], pair_w(a.A, i));
             if (lane == 0) a.g[i] = gi;
         }
     };
@@ -123,12 +125,12 @@ __global__ __launch_bounds__(WIN_BLOCK) void k_sweep_win(const WinItem* __restri
     auto key = [&](int64_t i) { return (int32_t)i; };
     if (a.noclip)
         window_item<B, false, RPL, WIN_BLOCK>(it, G, s_rec, CH, a.prp, a.colhop, a.rec, a.qt, eh,
-                                              a.clip, a.M, a.seed, a.iter, a.gamma, draw, key,
-                                              a.g);
+                                              a.clip, a.half != 0, a.M, a.seed, a.iter, a.gamma,
+                                              draw, key, a.g);
     else
         window_item<B, true, RPL, WIN_BLOCK>(it, G, s_rec, CH, a.prp, a.colhop, a.rec, a.qt, eh,
-                                             a.clip, a.M, a.seed, a.iter, a.gamma, draw, key,
-                                             a.g);
+                                             a.clip, a.half != 0, a.M, a.seed, a.iter, a.gamma,
+                                             draw, key, a.g);
 }
 
 template <int B, int RPL>
@@ -209,6 +211,7 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
         const int32_t ci = a.cmap ? a.cmap[i] : (int32_t)i;
         const float yix = yv[2 * ci], yiy = yv[2 * ci + 1];
         const float zi = a.invZ[i];
+        const PairW pw = pair_w(a.A, i);
         float ax = 0.0f, ay = 0.0f;
         for (int64_t x = rs + lane; x < re; x += G) {
             const uint32_t e = a.colhop[x];
@@ -217,8 +220,9 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             const float dx = yix - yv[2 * cj], dy = yiy - yv[2 * cj + 1];
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
-                const float k = attract_coef<B>(d2);
-                const float w = half_e(a, e >> 30) * (zi + a.invZ[j]);
+                const float k = attract_coef_b<B, float>(d2, a.half != 0);
+                const float w = pw.A ? (float)((pw.ai(e >> 30) + pw.A[4 * j + (e >> 30)]) * 0.5)
+                                     : half_e(a, e >> 30) * (zi + a.invZ[j]);
                 ax += w * clampT2(k * dx, a.clip);
                 ay += w * clampT2(k * dy, a.clip);
             }
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             const float dx = yix - yv[2 * cv], dy = yiy - yv[2 * cv + 1];
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
-                const float k = repel_coef<B>(d2);
+                const float k = repel_coef_b<B, float>(d2, a.half != 0);
                 rx += repelT(k, dx, a.clip);
                 ry += repelT(k, dy, a.clip);
             }
@@ -321,13 +325,14 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
                    bool staged, bool restage) {
     constexpr bool F32 = std::is_same<T, float>::value;
     if (!s || !p || !y) throw Error(DRG_E_INVALID, "layout_step: NULL argument");
-    if (p->M < 0 || p->b < 1 || p->b > 3)
-        throw Error(DRG_E_INVALID, "layout_step: M >= 0, b in 1..3");
+    check_shape(p->b, p->b_half);
+    if (p->M < 0) throw Error(DRG_E_INVALID, "layout_step: M >= 0");
     if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "layout_step: clip must be > 0");
     if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
         throw Error(DRG_E_INVALID, "layout_step: unknown mode");
     if (!F32 && p->mode == DRG_MODE_ASYNC)
         throw Error(DRG_E_UNSUPPORTED, "layout_step: the FP64 instance is synchronous only");
+    const bool half = p->b_half != 0;
     const int32_t level = p->level;
     if (level < 0 || (level > 0 && (!h || level >= (int32_t)h->lv.size())))
         throw Error(DRG_E_INVALID, "layout_step: level out of range");
@@ -374,7 +379,9 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.eh3 = 0.5 * s->e[3];
     a.gamma = (T)p->gamma;
     a.clip = (T)p->clip;
-    a.noclip = attract_clip_free(p->b, p->clip) ? 1 : 0;
+    a.noclip = attract_clip_free(p->b + (half ? 0.5 : 0.0), p->clip) ? 1 : 0;
+    a.half = half ? 1 : 0;
+    a.A = s->A.get();
     a.seed = p->seed;
     a.iter = p->iter;
     a.y = reinterpret_cast<v2*>(y);
@@ -385,7 +392,9 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     // Both modes stage the records on the column-blocked layout: its Hogwild
     // form reads neighbours from LDS copies of the records and updates them
     // in place as windows of rows finish.
-    const bool blocked = F32 && s->blk_nb > 0;
+    // the blocked sweep: whole b, one global sigma (node-wise sims have no
+    // blocked copy)
+    const bool blocked = F32 && s->blk_nb > 0 && !half && !a.A;
     const bool async = p->mode == DRG_MODE_ASYNC;
     if (async) {
         if (level == 0) {
@@ -442,7 +451,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     }
     bool win = false;
     if constexpr (F32) {
-        if (!async && window_wanted(s)) {
+        if (!async && !a.A && window_wanted(s)) {
             const int rpl = win_rpl();
             if (s->win_rpl != rpl) {
                 s->win_n = build_window_items(ctx, s, {0, n0}, {(WIN_BLOCK / G) * rpl},
@@ -500,7 +509,7 @@ void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_par
 // Everything a synchronous FP32 step builds on first use, built now (before
 // a step is recorded into a graph).
 void prepare_sync_step(drg_ctx* ctx, drg_sim* s) {
-    if (s->blk_nb > 0 || !window_wanted(s)) return;
+    if (s->blk_nb > 0 || s->A.get() || !window_wanted(s)) return;
     const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
     const int rpl = win_rpl();
     if (s->win_rpl != rpl) {

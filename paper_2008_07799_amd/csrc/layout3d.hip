@@ -64,8 +64,9 @@ __device__ __forceinline__ Sum3 sweep_row3(const typename VT<T>::v4& ri, double 
                                            const uint32_t* __restrict__ colhop,
                                            const typename VT<T>::v4* __restrict__ rec,
                                            const float* __restrict__ lo, const HalfE<double>& eh,
-                                           double clip, int M, uint64_t seed, uint64_t iter,
-                                           int32_t key, Draw draw, double gq) {
+                                           double clip, bool half, int M, uint64_t seed,
+                                           uint64_t iter, int32_t key, Draw draw, double gq,
+                                           PairW pw) {
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int64_t x = rs + lane; x < re; x += G) {
         const uint32_t e = colhop[x];
@@ -74,9 +75,14 @@ __device__ __forceinline__ Sum3 sweep_row3(const typename VT<T>::v4& ri, double 
         const double dx = (double)ri.x - (double)rj.x, dy = (double)ri.y - (double)rj.y,
                      dz = (double)ri.z - (double)rj.z;
         const double d2 = dx * dx + dy * dy + dz * dz;
-        const double k = attract_coef<B, double>(d2);
-        const double zj = (double)rj.w + (lo ? (double)lo[j] : 0.0);
-        const double w = eh(e >> 30) * (zi + zj);
+        const double k = attract_coef_b<B, double>(d2, half);
+        double w;
+        if (pw.A) {
+            w = (pw.ai(e >> 30) + pw.A[4 * (int64_t)j + (e >> 30)]) * 0.5;
+        } else {
+            const double zj = (double)rj.w + (lo ? (double)lo[j] : 0.0);
+            w = eh(e >> 30) * (zi + zj);
+        }
         if constexpr (CLIP) {
             ax += w * clampT2(k * dx, clip);
             ay += w * clampT2(k * dy, clip);
@@ -95,7 +101,7 @@ __device__ __forceinline__ Sum3 sweep_row3(const typename VT<T>::v4& ri, double 
                      dz = (double)ri.z - (double)rv.z;
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (d2 > 0.0) {
-            const double k = repel_coef<B, double>(d2);
+            const double k = repel_coef_b<B, double>(d2, half);
             rx += clampT2(k * dx, clip);
             ry += clampT2(k * dy, clip);
             rz += clampT2(k * dz, clip);
@@ -127,6 +133,8 @@ struct Sweep3Args {
     double eh0, eh1, eh2, eh3;  // e_d / 2
     double gamma, clip;
     int32_t noclip;
+    int32_t half;  // 1: the shape is b + 1/2
+    const double* A;  // node-wise sigma: P~ table [n0][4] (NULL: global sigma)
     uint64_t seed, iter;
     // async only
     T* y;
@@ -152,10 +160,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Sweep3Args<T> a) {
             const double gq = a.gamma * (double)a.qt[i];
             if (a.noclip)
                 gi = sweep_row3<T, B, false>(ri, zi, rs, re, lane, G, a.colhop, a.rec, a.lo, eh,
-                                             a.clip, a.M, a.seed, a.iter, (int32_t)i, draw, gq);
+                                             a.clip, a.half != 0, a.M, a.seed, a.iter, (int32_t)i,
+                                             draw, gq, pair_w(a.A, i));
             else
                 gi = sweep_row3<T, B, true>(ri, zi, rs, re, lane, G, a.colhop, a.rec, a.lo, eh,
-                                            a.clip, a.M, a.seed, a.iter, (int32_t)i, draw, gq);
+                                            a.clip, a.half != 0, a.M, a.seed, a.iter, (int32_t)i,
+                                            draw, gq, pair_w(a.A, i));
         }
         if (lane == 0) {
             a.g[3 * i] = (T)gi.x;
@@ -178,6 +188,7 @@ __global__ __launch_bounds__(256) void k_sweep3_async(Sweep3Args<float> a) {
         const int64_t ci = a.cmap ? a.cmap[i] : i;
         const float yi0 = yv[3 * ci], yi1 = yv[3 * ci + 1], yi2 = yv[3 * ci + 2];
         const float zi = a.invZ[i];
+        const PairW pw = pair_w(a.A, i);
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
         for (int64_t x = rs + lane; x < re; x += G) {
             const uint32_t e = a.colhop[x];
@@ -186,10 +197,11 @@ __global__ __launch_bounds__(256) void k_sweep3_async(Sweep3Args<float> a) {
             const float dx = yi0 - yv[3 * cj], dy = yi1 - yv[3 * cj + 1], dz = yi2 - yv[3 * cj + 2];
             const float d2 = dx * dx + dy * dy + dz * dz;
             if (d2 > 0.0f) {
-                const float k = attract_coef<B, float>(d2);
+                const float k = attract_coef_b<B, float>(d2, a.half != 0);
                 const uint32_t h = e >> 30;
                 const float eh = (float)(h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3)));
-                const float w = eh * (zi + a.invZ[j]);
+                const float w = pw.A ? (float)((pw.ai(h) + pw.A[4 * (int64_t)j + h]) * 0.5)
+                                     : eh * (zi + a.invZ[j]);
                 const float c = (float)a.clip;
                 ax += w * clampT2(k * dx, c);
                 ay += w * clampT2(k * dy, c);
@@ -204,7 +216,7 @@ __global__ __launch_bounds__(256) void k_sweep3_async(Sweep3Args<float> a) {
             const float dx = yi0 - yv[3 * cv], dy = yi1 - yv[3 * cv + 1], dz = yi2 - yv[3 * cv + 2];
             const float d2 = dx * dx + dy * dy + dz * dz;
             if (d2 > 0.0f) {
-                const float k = repel_coef<B, float>(d2);
+                const float k = repel_coef_b<B, float>(d2, a.half != 0);
                 const float c = (float)a.clip;
                 rx += repel_component(k, dx, c);
                 ry += repel_component(k, dy, c);
@@ -332,8 +344,8 @@ template <typename T>
 void layout_step3_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_params* p, T* y) {
     constexpr bool F32 = std::is_same<T, float>::value;
     if (!s || !p || !y) throw Error(DRG_E_INVALID, "layout_step: NULL argument");
-    if (p->M < 0 || p->b < 1 || p->b > 3)
-        throw Error(DRG_E_INVALID, "layout_step: M >= 0, b in 1..3");
+    if (p->M < 0) throw Error(DRG_E_INVALID, "layout_step: M >= 0");
+    check_shape(p->b, p->b_half);
     if (!(p->clip > 0.0f)) throw Error(DRG_E_INVALID, "layout_step: clip must be > 0");
     if (p->mode != DRG_MODE_SYNC && p->mode != DRG_MODE_ASYNC)
         throw Error(DRG_E_INVALID, "layout_step: unknown mode");
@@ -385,7 +397,9 @@ void layout_step3_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_
     a.eh3 = 0.5 * s->e[3];
     a.gamma = (double)p->gamma;
     a.clip = (double)p->clip;
-    a.noclip = attract_clip_free(p->b, p->clip) ? 1 : 0;
+    a.noclip = attract_clip_free(p->b + (p->b_half ? 0.5 : 0.0), p->clip) ? 1 : 0;
+    a.half = p->b_half ? 1 : 0;
+    a.A = s->A.get();
     a.seed = p->seed;
     a.iter = p->iter;
     a.y = y;

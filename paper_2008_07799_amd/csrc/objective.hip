@@ -5,6 +5,8 @@
 //   L^(Y) = sum_i sum_j P~_ij log w_ij + gamma sum_i qt_i sum_{m<M} log(1 - w_{i v_im})
 //   log w = -log1p(d^{2b}),  log(1 - w) = b log d^2 - log1p(d^{2b})
 //
+// b is a whole number B or B + 1/2 (half): d^{2b} = (d^2)^B sqrt(d^2).
+//
 // A negative equal to its anchor, or at distance 0, contributes nothing.
 // Gradient (unclipped): the attraction of row i appears in rows i and j with
 // the same P~ (symmetric), so it is twice row i's sum; the repulsion term of
@@ -55,6 +57,18 @@ __device__ __forceinline__ T opow(T x) {
     else return x * x * x;
 }
 
+// d^{2b} and d^{2b-2} from d2 = d^2, b = B or B + 1/2
+template <int B, typename T>
+__device__ __forceinline__ T opow_b(T d2, bool half) {
+    const T u = opow<B>(d2);
+    return half ? u * sqrtT(d2) : u;
+}
+template <int B, typename T>
+__device__ __forceinline__ T opow_bm1(T d2, bool half) {
+    const T u = opow<B - 1>(d2);
+    return half ? u * sqrtT(d2) : u;
+}
+
 template <typename T>
 struct ObjArgs {
     using v2 = typename OV<T>::v2;
@@ -70,6 +84,9 @@ struct ObjArgs {
     uint64_t S;
     T eh0, eh1, eh2, eh3;  // e_d / 2
     T gamma;
+    T bv;                  // b as a number: B, or B + 1/2 when half
+    int32_t half;          // 1: b = B + 1/2
+    const double* A;       // node-wise sigma: P~ table [n][4] (NULL: global sigma)
     uint64_t seed, iter;
     const T* dloss;        // backward: scale (NULL = 1)
     T* row_val;            // forward: per-row value
@@ -81,6 +98,14 @@ struct ObjArgs {
 template <typename T>
 __device__ __forceinline__ T oh(const ObjArgs<T>& a, uint32_t h) {
     return h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
+}
+
+// P~_ij of an entry at hop index h: (A_i[h] + A_j[h]) / 2 with node-wise
+// sigma, else e_h/2 (1/Z_i + 1/Z_j)
+template <typename T>
+__device__ __forceinline__ T obj_p(const ObjArgs<T>& a, int64_t i, int32_t j, uint32_t h, T zi) {
+    if (a.A) return (T)((a.A[4 * i + h] + a.A[4 * (int64_t)j + h]) * 0.5);
+    return oh(a, h) * (zi + a.invZ[j]);
 }
 
 template <typename T>
@@ -112,8 +137,8 @@ __global__ __launch_bounds__(256) void k_obj_rows(ObjArgs<T> a) {
                 const typename OV<T>::v2 yj = a.y[j];
                 const T dx = yi.x - yj.x, dy = yi.y - yj.y;
                 const T d2 = dx * dx + dy * dy;
-                const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
-                att += p * (-log1pT(opow<B>(d2)));
+                const T p = obj_p(a, i, j, e >> 30, zi);
+                att += p * (-log1pT(opow_b<B>(d2, a.half != 0)));
             }
             for (int m = lane; m < a.M; m += G) {
                 const int32_t v =
@@ -122,7 +147,7 @@ __global__ __launch_bounds__(256) void k_obj_rows(ObjArgs<T> a) {
                 const typename OV<T>::v2 yv = a.y[v];
                 const T dx = yi.x - yv.x, dy = yi.y - yv.y;
                 const T d2 = dx * dx + dy * dy;
-                if (d2 > T(0)) rep += T(B) * logT(d2) - log1pT(opow<B>(d2));
+                if (d2 > T(0)) rep += a.bv * logT(d2) - log1pT(opow_b<B>(d2, a.half != 0));
             }
             att = group_sum<G>(att);
             rep = group_sum<G>(rep);
@@ -162,8 +187,9 @@ __global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
                 const typename OV<T>::v2 yj = a.y[j];
                 const T dx = yi.x - yj.x, dy = yi.y - yj.y;
                 const T d2 = dx * dx + dy * dy;
-                const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
-                const T k = p * T(-2 * B) * opow<B - 1>(d2) * orcp(T(1) + opow<B>(d2));
+                const T p = obj_p(a, i, j, e >> 30, zi);
+                const T k = p * (T(-2) * a.bv) * opow_bm1<B>(d2, a.half != 0) *
+                            orcp(T(1) + opow_b<B>(d2, a.half != 0));
                 ax += k * dx;
                 ay += k * dy;
             }
@@ -175,7 +201,7 @@ __global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
                 const T dx = yi.x - yv.x, dy = yi.y - yv.y;
                 const T d2 = dx * dx + dy * dy;
                 if (d2 > T(0)) {
-                    const T k = T(2 * B) * orcp(d2 * (T(1) + opow<B>(d2)));
+                    const T k = (T(2) * a.bv) * orcp(d2 * (T(1) + opow_b<B>(d2, a.half != 0)));
                     rx += k * dx;
                     ry += k * dy;
                 }
@@ -288,7 +314,8 @@ __global__ void k_other_side(ObjArgs<T> a, const int32_t* __restrict__ seg,
         const T dx = yv.x - yu.x, dy = yv.y - yu.y;
         const T d2 = dx * dx + dy * dy;
         if (d2 > T(0)) {
-            const T k = a.gamma * a.qt[u] * T(2 * B) / (d2 * (T(1) + opow<B>(d2)));
+            const T k = a.gamma * a.qt[u] * (T(2) * a.bv) /
+                        (d2 * (T(1) + opow_b<B>(d2, a.half != 0)));
             gx += k * dx;
             gy += k * dy;
         }
@@ -326,14 +353,14 @@ __global__ __launch_bounds__(256) void k_obj_rows3(ObjArgs<T> a) {
                 const uint32_t e = a.colhop[x];
                 const int32_t j = (int32_t)(e & COL_MASK);
                 const T d2 = off3(a.y3, i, j, dx, dy, dz);
-                att += oh(a, e >> 30) * (zi + a.invZ[j]) * (-log1pT(opow<B>(d2)));
+                att += obj_p(a, i, j, e >> 30, zi) * (-log1pT(opow_b<B>(d2, a.half != 0)));
             }
             for (int m = lane; m < a.M; m += G) {
                 const int32_t v =
                     draw_node(neg_word(a.seed, a.iter, (int32_t)i, m), a.C, a.guide, a.gbits, a.S);
                 if (v == (int32_t)i) continue;
                 const T d2 = off3(a.y3, i, v, dx, dy, dz);
-                if (d2 > T(0)) rep += T(B) * logT(d2) - log1pT(opow<B>(d2));
+                if (d2 > T(0)) rep += a.bv * logT(d2) - log1pT(opow_b<B>(d2, a.half != 0));
             }
             att = group_sum<G>(att);
             rep = group_sum<G>(rep);
@@ -359,8 +386,9 @@ __global__ __launch_bounds__(256) void k_grad_rows3(ObjArgs<T> a) {
                 const uint32_t e = a.colhop[x];
                 const int32_t j = (int32_t)(e & COL_MASK);
                 const T d2 = off3(a.y3, i, j, dx, dy, dz);
-                const T p = oh(a, e >> 30) * (zi + a.invZ[j]);
-                const T k = p * T(-2 * B) * opow<B - 1>(d2) * orcp(T(1) + opow<B>(d2));
+                const T p = obj_p(a, i, j, e >> 30, zi);
+                const T k = p * (T(-2) * a.bv) * opow_bm1<B>(d2, a.half != 0) *
+                            orcp(T(1) + opow_b<B>(d2, a.half != 0));
                 ax += k * dx;
                 ay += k * dy;
                 az += k * dz;
@@ -371,7 +399,7 @@ __global__ __launch_bounds__(256) void k_grad_rows3(ObjArgs<T> a) {
                 if (v == (int32_t)i) continue;
                 const T d2 = off3(a.y3, i, v, dx, dy, dz);
                 if (d2 > T(0)) {
-                    const T k = T(2 * B) * orcp(d2 * (T(1) + opow<B>(d2)));
+                    const T k = (T(2) * a.bv) * orcp(d2 * (T(1) + opow_b<B>(d2, a.half != 0)));
                     rx += k * dx;
                     ry += k * dy;
                     rz += k * dz;
@@ -409,7 +437,8 @@ __global__ void k_other_side3(ObjArgs<T> a, const int32_t* __restrict__ seg,
         const int32_t u = pairs[x] / a.M;
         const T d2 = off3(a.y3, v, u, dx, dy, dz);
         if (d2 > T(0)) {
-            const T k = a.gamma * a.qt[u] * T(2 * B) / (d2 * (T(1) + opow<B>(d2)));
+            const T k = a.gamma * a.qt[u] * (T(2) * a.bv) /
+                        (d2 * (T(1) + opow_b<B>(d2, a.half != 0)));
             g0 += k * dx;
             g1 += k * dy;
             g2 += k * dz;
@@ -434,8 +463,8 @@ __global__ void k_negatives(int32_t n, int32_t M, const int64_t* __restrict__ pr
 
 __global__ void k_coo(int32_t n, const int64_t* __restrict__ prp, const uint32_t* __restrict__ ch,
                       const float* __restrict__ invZf, float eh0, float eh1, float eh2, float eh3,
-                      int32_t* __restrict__ rows, int32_t* __restrict__ cols,
-                      float* __restrict__ P) {
+                      const double* __restrict__ A, int32_t* __restrict__ rows,
+                      int32_t* __restrict__ cols, float* __restrict__ P) {
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int lane = __lane_id();
     if (i >= n) return;
@@ -446,7 +475,8 @@ __global__ void k_coo(int32_t n, const int64_t* __restrict__ prp, const uint32_t
         const float eh = h == 0 ? eh0 : (h == 1 ? eh1 : (h == 2 ? eh2 : eh3));
         if (rows) rows[x] = (int32_t)i;
         if (cols) cols[x] = j;
-        if (P) P[x] = eh * (invZf[i] + invZf[j]);
+        if (P) P[x] = A ? (float)((A[4 * i + h] + A[4 * (int64_t)j + h]) * 0.5)
+                        : eh * (invZf[i] + invZf[j]);
     }
 }
 
@@ -476,6 +506,9 @@ static ObjArgs<T> obj_args(drg_sim* s, const drg_obj_params* p, const T* y) {
     a.eh2 = (T)(0.5 * s->e[2]);
     a.eh3 = (T)(0.5 * s->e[3]);
     a.gamma = (T)p->gamma;
+    a.half = p->b_half ? 1 : 0;
+    a.A = s->A.get();
+    a.bv = (T)((double)p->b + (p->b_half ? 0.5 : 0.0));
     a.seed = p->seed;
     a.iter = p->iter;
     return a;
@@ -483,7 +516,8 @@ static ObjArgs<T> obj_args(drg_sim* s, const drg_obj_params* p, const T* y) {
 
 static void check_obj(const drg_sim* s, const drg_obj_params* p, const void* y) {
     if (!s || !p || !y) throw Error(DRG_E_INVALID, "objective: NULL argument");
-    if (p->M < 0 || p->b < 1 || p->b > 3) throw Error(DRG_E_INVALID, "objective: M >= 0, b in 1..3");
+    if (p->M < 0) throw Error(DRG_E_INVALID, "objective: M >= 0");
+    check_shape(p->b, p->b_half);
     if (p->dim != 0 && p->dim != 2 && p->dim != 3)
         throw Error(DRG_E_INVALID, "objective: dim must be 2 (or 0) or 3");
 }
@@ -530,7 +564,7 @@ static void obj_rows(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const Ob
     hipStream_t st = ctx->stream;
     const bool three = p->dim == 3;
     if constexpr (std::is_same<T, float>::value) {
-        if (!three && s->blk_nb > 0 && obj_blocked_wanted()) {
+        if (!three && !p->b_half && !a.A && s->blk_nb > 0 && obj_blocked_wanted()) {
             sweep_blocked_objective(ctx, s, p->b, reinterpret_cast<const float*>(a.y), grad ? 1 : 0);
             const float2* part = s->blk_partial.get();
 #define DRG_FIN(BB)                                                                          \
@@ -718,7 +752,7 @@ void sim_coo(drg_ctx* ctx, drg_sim* s, int32_t* rows, int32_t* cols, float* P) {
     hipLaunchKernelGGL(k_coo, dim3(ceil_div((int64_t)s->n * WAVE, 256)), dim3(256), 0, ctx->stream,
                        s->n, s->row_ptr.get(), s->colhop.get(), s->invZf.get(),
                        (float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]), (float)(0.5 * s->e[2]),
-                       (float)(0.5 * s->e[3]), rows, cols, P);
+                       (float)(0.5 * s->e[3]), s->A.get(), rows, cols, P);
     DRG_LAUNCH_CHECK();
 }
 

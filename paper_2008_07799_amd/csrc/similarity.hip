@@ -357,13 +357,121 @@ __global__ void k_normalise(int32_t n, int32_t k, const int32_t* __restrict__ cn
     invZlo[i] = (float)(iz - (double)hi);  // exact difference, rounded once
 }
 
-// P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2.  Per row: W_i = sum_j trunc(P~_ij 2^32)
+// ------------------------------------------------------------------ node-wise sigma
+// sigma_i chosen per node so that NS_{.|i} over NNG(i, k) has a given
+// perplexity exp(H) (t-SNE's calibration; Eq. NS gives each node its own
+// Gaussian).  With t = exp(-1/(2 sigma_i^2)) the Gaussian of hop d is
+// t^(d^2), so the distribution depends on t and the node's hop histogram
+// only.  Every step is an IEEE-754 operation (frexp, +, -, *, /, compare)
+// with contraction off, so any program that performs the same operations in
+// the same order obtains the same t bit for bit, and with it the same P~
+// and the same integer sampling table.
+
+// ln x for x > 0 finite: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m =
+// 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.172, from the odd series of
+// atanh by Horner's rule over 13 terms; ln x = e ln 2 + ln m.
+__device__ double ln_ieee(double x) {
+#pragma clang fp contract(off)
+    int ex = 0;
+    double m = frexp(x, &ex);  // exact; m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        ex = ex - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 25.0;
+    for (int j = 11; j >= 0; --j) p = p * s2 + 1.0 / (double)(2 * j + 1);
+    const double lm = 2.0 * s * p;
+    return (double)ex * 0.69314718055994530942 + lm;
+}
+
+// t^(d^2) for d = 1..k, each a running product of d^2 factors
+__device__ __forceinline__ void gauss_of_t(double t, int k, double* e) {
+#pragma clang fp contract(off)
+    for (int d = 1; d <= 4; ++d) {
+        double p = 1.0;
+        if (d <= k)
+            for (int r = 0; r < d * d; ++r) p = p * t;
+        e[d - 1] = d <= k ? p : 0.0;
+    }
+}
+
+// Z = sum_d c_d t^(d^2) in hop order; returns the entropy ln Z - ln(t) S / Z
+// with S = sum_d c_d d^2 t^(d^2)
+__device__ double entropy_of_t(const double* c, int k, double t, double& z) {
+#pragma clang fp contract(off)
+    double e[4];
+    gauss_of_t(t, k, e);
+    z = 0.0;
+    double sw = 0.0;
+    for (int d = 0; d < k; ++d) {
+        const double term = c[d] * e[d];
+        z = z + term;
+        sw = sw + term * (double)((d + 1) * (d + 1));
+    }
+    const double lt = ln_ieee(t);
+    return ln_ieee(z) - lt * (sw / z);
+}
+
+// Per node: t by bisection (the entropy grows with t; t = 1, the uniform
+// distribution, when the target reaches its largest value ln N), then
+// Z_i, 1/Z_i and A[i][d] = t^(d^2) / Z_i = NS_{j|i} for a node j at hop d+1.
+__global__ void k_calibrate(int32_t n, int32_t k, const int32_t* __restrict__ cnt, double perp,
+                            double* __restrict__ tn, double* __restrict__ A,
+                            double* __restrict__ invZ, float* __restrict__ invZf,
+                            float* __restrict__ invZlo) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t N = 0;
+    for (int d = 0; d < k; ++d) {
+        c[d] = (double)cnt[i * k + d];
+        N += cnt[i * k + d];
+    }
+    const double target = ln_ieee(perp);
+    if (N == 0) {
+        tn[i] = 1.0;
+        for (int d = 0; d < 4; ++d) A[4 * i + d] = 0.0;
+        invZ[i] = 0.0;
+        invZf[i] = 0.0f;
+        invZlo[i] = 0.0f;
+        return;
+    }
+    double z = 0.0, t = 1.0;
+    if (entropy_of_t(c, k, 1.0, z) > target) {
+        double lo = 0.0, hi = 1.0;
+        for (int r = 0; r < 64; ++r) {
+            const double mid = 0.5 * (lo + hi);
+            if (entropy_of_t(c, k, mid, z) < target)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        t = 0.5 * (lo + hi);
+    }
+    entropy_of_t(c, k, t, z);
+    double e[4];
+    gauss_of_t(t, k, e);
+    tn[i] = t;
+    for (int d = 0; d < 4; ++d) A[4 * i + d] = d < k ? e[d] / z : 0.0;
+    const double iz = 1.0 / z;
+    invZ[i] = iz;
+    const float hi = (float)iz;
+    invZf[i] = hi;
+    invZlo[i] = (float)(iz - (double)hi);
+}
+
+// P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2, or with node-wise sigma (A non-NULL)
+// (A_i[d] + A_j[d]) / 2.  Per row: W_i = sum_j trunc(P~_ij 2^32)
 // (exact integer), qt_i = sum_j P~_ij (FP64: lane l of the G lanes sums
 // entries l, l+G, ... in order, then a butterfly over the group).
 __device__ __forceinline__ void row_weights_row(int64_t i, int lane, int G,
                                                 const int64_t* __restrict__ prp,
                                                 const uint32_t* __restrict__ ch,
                                                 const double* __restrict__ invZ, const ECoef& ec,
+                                                const double* __restrict__ A,
                                                 uint64_t* __restrict__ W, double* __restrict__ qt,
                                                 float* __restrict__ qtf) {
 #pragma clang fp contract(off)
@@ -372,9 +480,15 @@ __device__ __forceinline__ void row_weights_row(int64_t i, int lane, int G,
     double qs = 0.0;
     for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += G) {
         const uint32_t e = ch[x];
-        const double s = izi + invZ[e & COL_MASK];
-        const double t = pick_e(ec.e, e >> 30) * s;
-        const double p = t * 0.5;
+        double p;
+        if (A) {
+            const double s = A[4 * i + (e >> 30)] + A[4 * (int64_t)(e & COL_MASK) + (e >> 30)];
+            p = s * 0.5;
+        } else {
+            const double s = izi + invZ[e & COL_MASK];
+            const double t = pick_e(ec.e, e >> 30) * s;
+            p = t * 0.5;
+        }
         ws += (unsigned long long)(p * 4294967296.0);
         qs = qs + p;
     }
@@ -391,13 +505,15 @@ template <int G>
 __global__ __launch_bounds__(256) void k_row_weights(int32_t n, const int64_t* __restrict__ prp,
                                                      const uint32_t* __restrict__ ch,
                                                      const double* __restrict__ invZ, ECoef ec,
+                                                     const double* __restrict__ A,
                                                      uint64_t* __restrict__ W,
                                                      double* __restrict__ qt,
                                                      float* __restrict__ qtf) {
     const int lane = threadIdx.x % G;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
-    for (int64_t i = grp; i < n; i += ngrp) row_weights_row(i, lane, G, prp, ch, invZ, ec, W, qt, qtf);
+    for (int64_t i = grp; i < n; i += ngrp)
+        row_weights_row(i, lane, G, prp, ch, invZ, ec, A, W, qt, qtf);
 }
 
 // Union of graphs: every graph keeps the group size its own single-graph
@@ -428,7 +544,9 @@ __global__ __launch_bounds__(256) void k_row_weights_union(int32_t count,
         const int4 t = gtab[lo];  // (base, n, G, -)
         const int G = t.z;
         const int32_t r = (gw - woff[lo]) * (WAVE / G) + (int32_t)(__lane_id() / G);
-        if (r < t.y) row_weights_row((int64_t)t.x + r, __lane_id() % G, G, prp, ch, invZ, ec, W, qt, qtf);
+        if (r < t.y)
+            row_weights_row((int64_t)t.x + r, __lane_id() % G, G, prp, ch, invZ, ec, nullptr, W,
+                            qt, qtf);
     }
 }
 
@@ -456,31 +574,34 @@ __global__ void k_guide(int32_t n, const uint64_t* __restrict__ C, int gbits,
     guide[b] = lo;
 }
 
+// P~ of entry e of row i, as row_weights_row computes it
+__device__ __forceinline__ double entry_p(int64_t i, uint32_t e, const double* __restrict__ invZ,
+                                          const ECoef& ec, const double* __restrict__ A) {
+#pragma clang fp contract(off)
+    if (A) {
+        const double s = A[4 * i + (e >> 30)] + A[4 * (int64_t)(e & COL_MASK) + (e >> 30)];
+        return s * 0.5;
+    }
+    const double s = invZ[i] + invZ[e & COL_MASK];
+    const double t = pick_e(ec.e, e >> 30) * s;
+    return t * 0.5;
+}
+
 __global__ void k_materialise_P(int32_t n, const int64_t* __restrict__ prp,
                                 const uint32_t* __restrict__ ch, const double* __restrict__ invZ,
-                                ECoef ec, double* __restrict__ P) {
-#pragma clang fp contract(off)
+                                ECoef ec, const double* __restrict__ A, double* __restrict__ P) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
-        const uint32_t e = ch[x];
-        const double s = invZ[i] + invZ[e & COL_MASK];
-        const double t = pick_e(ec.e, e >> 30) * s;
-        P[x] = t * 0.5;
-    }
+    for (int64_t x = prp[i]; x < prp[i + 1]; ++x) P[x] = entry_p(i, ch[x], invZ, ec, A);
 }
 
 // P~ of the entries x0 .. x1-1 of row i (same operations as k_materialise_P)
 __global__ void k_materialise_row(int32_t i, int64_t x0, int64_t x1,
                                   const uint32_t* __restrict__ ch, const double* __restrict__ invZ,
-                                  ECoef ec, double* __restrict__ P) {
-#pragma clang fp contract(off)
+                                  ECoef ec, const double* __restrict__ A, double* __restrict__ P) {
     const int64_t x = x0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= x1) return;
-    const uint32_t e = ch[x];
-    const double s = invZ[i] + invZ[e & COL_MASK];
-    const double t = pick_e(ec.e, e >> 30) * s;
-    P[x - x0] = t * 0.5;
+    P[x - x0] = entry_p(i, ch[x], invZ, ec, A);
 }
 
 static int pick_group(double mean_len) {
@@ -496,8 +617,8 @@ static void launch_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec) {
     const int64_t groups = s->n;
     const int grid = (int)std::min<int64_t>((groups * G + 255) / 256, 1 << 20);
     hipLaunchKernelGGL(k_row_weights<G>, dim3(std::max(grid, 1)), dim3(256), 0, ctx->stream, s->n,
-                       s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, s->W.get(),
-                       s->qt.get(), s->qtf.get());
+                       s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, s->A.get(),
+                       s->W.get(), s->qt.get(), s->qtf.get());
     DRG_LAUNCH_CHECK();
 }
 
@@ -550,9 +671,16 @@ static void union_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec, UnionIn
 }
 
 drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
-                          UnionInfo* u) {
+                          UnionInfo* u, double perplexity) {
     if (!g) throw Error(DRG_E_INVALID, "graph is NULL");
     if (k < 1 || k > 4) throw Error(DRG_E_INVALID, "k must be in 1..4");
+    const bool nodewise = perplexity != 0.0;
+    if (nodewise) {
+        if (!(perplexity >= 1.0) || !(perplexity < 1e300))
+            throw Error(DRG_E_INVALID, "perplexity must be >= 1 and finite");
+        if (u) throw Error(DRG_E_UNSUPPORTED, "batched layout: one global sigma only");
+        sigma = 1.0;  // not used
+    }
     if (!(sigma > 0.0) || !std::isfinite(sigma)) throw Error(DRG_E_INVALID, "sigma must be > 0");
     if (g->n <= 0 || g->n >= (1 << 30)) throw Error(DRG_E_INVALID, "n must be in 1..2^30-1");
     if (g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col))
@@ -564,10 +692,12 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     s->device = ctx->device;
     s->n = n;
     s->k = k;
-    s->sigma = sigma;
+    s->sigma = nodewise ? 0.0 : sigma;
+    s->perplexity = nodewise ? perplexity : 0.0;
     ECoef ec{};
     for (int d = 1; d <= 4; ++d) {
-        ec.e[d - 1] = d <= k ? std::exp(-(double)(d * d) / (2.0 * sigma * sigma)) : 0.0;
+        ec.e[d - 1] = (d <= k && !nodewise)
+                          ? std::exp(-(double)(d * d) / (2.0 * sigma * sigma)) : 0.0;
         s->e[d - 1] = ec.e[d - 1];
     }
     DevBuf<int32_t> cnt((int64_t)n * k);
@@ -656,8 +786,16 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     s->qtf.alloc(n);
     s->W.alloc(n);
     s->C.alloc((int64_t)n + 1);
-    hipLaunchKernelGGL(k_normalise, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k, cnt.get(), ec,
-                       s->invZ.get(), s->invZf.get(), s->invZlo.get());
+    if (nodewise) {
+        s->A.alloc(4 * (int64_t)n);
+        s->tnode.alloc(n);
+        hipLaunchKernelGGL(k_calibrate, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k,
+                           cnt.get(), perplexity, s->tnode.get(), s->A.get(),
+                           s->invZ.get(), s->invZf.get(), s->invZlo.get());
+    } else {
+        hipLaunchKernelGGL(k_normalise, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k, cnt.get(),
+                           ec, s->invZ.get(), s->invZf.get(), s->invZlo.get());
+    }
     DRG_LAUNCH_CHECK();
     const double mean_len = (double)s->nnz / (double)n;
     if (u) {
@@ -690,7 +828,8 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
                        n, s->C.get(), gbits, s->guide.get());
     DRG_LAUNCH_CHECK();
     DRG_HIP(hipStreamSynchronize(st));
-    if (blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
+    // the column-blocked sweep carries one 1/Z per record: global sigma only
+    if (!nodewise && blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
     return s.release();
 }
 
@@ -733,7 +872,8 @@ void sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows, int64
         if (len > 0 && P) {
             DevBuf<double> dP(len);
             hipLaunchKernelGGL(k_materialise_row, dim3(ceil_div(len, 256)), dim3(256), 0, nullptr,
-                               i, a[r], b[r], s->colhop.get(), s->invZ.get(), ec, dP.get());
+                               i, a[r], b[r], s->colhop.get(), s->invZ.get(), ec, s->A.get(),
+                               dP.get());
             DRG_LAUNCH_CHECK();
             DRG_HIP(hipMemcpy(P + o, dP.get(), sizeof(double) * len, hipMemcpyDeviceToHost));
         }
@@ -768,7 +908,8 @@ void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, 
         ECoef ec{};
         for (int d = 0; d < 4; ++d) ec.e[d] = s->e[d];
         hipLaunchKernelGGL(k_materialise_P, dim3(ceil_div(n, 256)), dim3(256), 0, nullptr, n,
-                           s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, dP.get());
+                           s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, s->A.get(),
+                           dP.get());
         DRG_LAUNCH_CHECK();
         DRG_HIP(hipMemcpy(P, dP.get(), sizeof(double) * nnz, hipMemcpyDeviceToHost));
     }
@@ -777,6 +918,31 @@ void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, 
     if (invZ) DRG_HIP(hipMemcpy(invZ, s->invZ.get(), sizeof(double) * n, hipMemcpyDeviceToHost));
     if (e)
         for (int d = 0; d < s->k; ++d) e[d] = s->e[d];
+}
+
+void sim_node_sigma(const drg_sim* s, double* sigma) {
+    if (!sigma) throw Error(DRG_E_INVALID, "sigma is NULL");
+    DRG_HIP(hipSetDevice(s->device));
+    DRG_HIP(hipDeviceSynchronize());
+    const int32_t n = s->n;
+    std::vector<int64_t> rp((size_t)n + 1);
+    DRG_HIP(hipMemcpy(rp.data(), s->row_ptr.get(), sizeof(int64_t) * (n + 1),
+                      hipMemcpyDeviceToHost));
+    std::vector<double> t;
+    if (s->tnode.get()) {
+        t.resize(n);
+        DRG_HIP(hipMemcpy(t.data(), s->tnode.get(), sizeof(double) * n, hipMemcpyDeviceToHost));
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (rp[i + 1] == rp[i]) {
+            sigma[i] = 0.0;
+        } else if (t.empty()) {
+            sigma[i] = s->sigma;
+        } else {
+            const double lt = std::log(t[i]);
+            sigma[i] = lt < 0.0 ? std::sqrt(-0.5 / lt) : HUGE_VAL;
+        }
+    }
 }
 
 }  // namespace drg

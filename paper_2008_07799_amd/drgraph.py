@@ -46,12 +46,13 @@ class Csr(C.Structure):
 class StepParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("b", C.c_int32), ("gamma", C.c_float), ("eta", C.c_float),
                 ("clip", C.c_float), ("level", C.c_int32), ("mode", C.c_int32),
-                ("dim", C.c_int32), ("seed", C.c_uint64), ("iter", C.c_uint64)]
+                ("dim", C.c_int32), ("seed", C.c_uint64), ("iter", C.c_uint64),
+                ("b_half", C.c_int32), ("_pad", C.c_int32)]
 
 
 class ObjParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("b", C.c_int32), ("gamma", C.c_double), ("seed", C.c_uint64),
-                ("iter", C.c_uint64), ("dim", C.c_int32), ("_pad", C.c_int32)]
+                ("iter", C.c_uint64), ("dim", C.c_int32), ("b_half", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -67,7 +68,16 @@ class LayoutParams(C.Structure):
                 ("sigma", C.c_double), ("gamma", C.c_float), ("gamma_coarsest", C.c_float),
                 ("eta0", C.c_float), ("clip", C.c_float), ("rho", C.c_double),
                 ("min_nodes", C.c_int32), ("max_levels", C.c_int32), ("mode", C.c_int32),
-                ("dim", C.c_int32), ("seed", C.c_uint64)]
+                ("dim", C.c_int32), ("seed", C.c_uint64), ("b_half", C.c_int32),
+                ("_pad", C.c_int32), ("perplexity", C.c_double)]
+
+
+def _shape(b):
+    """(whole part, half flag) of the shape parameter b: 1, 1.5, 2, 2.5 or 3."""
+    twice = float(b) * 2.0
+    if twice != int(twice) or not 2 <= twice <= 6:
+        raise ValueError(f"b must be 1, 1.5, 2, 2.5 or 3, not {b}")
+    return int(twice) // 2, int(twice) % 2
 
 
 _lib = None
@@ -98,6 +108,9 @@ def lib():
         "drg_ctx_set_profiling": ([_P, C.c_int32], st),
         "drg_ctx_kernel_stats": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)], st),
         "drg_ctx_last_sweep": ([_P, C.POINTER(C.c_int32)], st),
+        "drg_build_similarity_perplexity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double,
+                                             C.c_uint32, C.POINTER(_P)], st),
+        "drg_sim_node_sigma": ([_P, _P], st),
         "drg_build_similarity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double, C.c_uint32,
                                   C.POINTER(_P)], st),
         "drg_sim_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -261,6 +274,14 @@ class Similarity:
 
     __del__ = close
 
+    def node_sigma(self) -> np.ndarray:
+        """sigma_i per node (host float64): the global sigma, or the
+        calibrated one of a node-wise similarity (inf where uniform); 0 for
+        isolated nodes."""
+        out = np.zeros(self.n, np.float64)
+        _check(lib().drg_sim_node_sigma(self.h, _np_ptr(out)))
+        return out
+
     def export(self, values: bool = True, pattern: bool = True) -> dict:
         """The whole similarity as host numpy arrays; pattern=False leaves out
         the per-entry arrays (columns, hops, values) and copies the per-node
@@ -319,6 +340,16 @@ def drg_build_similarity(ctx: Context, row_ptr, col, k: int, sigma: float = 1.0,
     h = C.c_void_p()
     _check(lib().drg_build_similarity(ctx.h, C.byref(g), int(k), float(sigma),
                                       DRG_VALIDATE if validate else 0, C.byref(h)))
+    return Similarity(h)
+
+
+def drg_build_similarity_perplexity(ctx: Context, row_ptr, col, k: int, perplexity: float,
+                                    validate: bool = False) -> Similarity:
+    """P~ with one sigma_i per node calibrated to `perplexity` (Eq. NS)."""
+    g = _csr(row_ptr, col)
+    h = C.c_void_p()
+    _check(lib().drg_build_similarity_perplexity(ctx.h, C.byref(g), int(k), float(perplexity),
+                                                 DRG_VALIDATE if validate else 0, C.byref(h)))
     return Similarity(h)
 
 
@@ -443,20 +474,25 @@ def drg_layout_step(ctx: Context, sim: Similarity, hier, y, *, M=5, b=1, gamma=0
                     clip=4.0, level=0, mode=DRG_MODE_SYNC, seed=0, iter=0):
     nl = sim.n if level == 0 else hier.sizes[level]
     d = _dim(y)
-    p = StepParams(int(M), int(b), float(gamma), float(eta), float(clip), int(level), int(mode),
-                   d, int(seed), int(iter))
+    bw, bh = _shape(b)
+    p = StepParams(int(M), bw, float(gamma), float(eta), float(clip), int(level), int(mode),
+                   d, int(seed), int(iter), bh)
     ptr, f64 = _coords(y, "y", (nl, d))
     fn = lib().drg_layout_step_f64 if f64 else lib().drg_layout_step
     _check(fn(ctx.h, sim.h, hier.h if hier is not None else None, C.byref(p), ptr))
 
 
 def layout_params(**kw) -> LayoutParams:
+    """Defaults with keyword overrides; b may be 1, 1.5, 2, 2.5 or 3."""
     p = LayoutParams()
     _check(lib().drg_layout_params_default(C.byref(p)))
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
-        setattr(p, k, v)
+        if k == "b":
+            p.b, p.b_half = _shape(v)
+        else:
+            setattr(p, k, v)
     return p
 
 
@@ -576,6 +612,11 @@ def drg_layout_batched(ctx: Context, graphs, params, y_out):
 
 
 # ------------------------------------------------------------------ objective
+def _obj_params(M, b, gamma, seed, iter, d) -> ObjParams:
+    bw, bh = _shape(b)
+    return ObjParams(int(M), bw, float(gamma), int(seed), int(iter), d, bh)
+
+
 def drg_objective_fwd(ctx: Context, sim: Similarity, y, *, M=5, b=1, gamma=0.1, seed=0, iter=0,
                       rows=False):
     """The sampled objective L^ at y ([n,2], float32 or float64).  Returns a
@@ -583,7 +624,7 @@ def drg_objective_fwd(ctx: Context, sim: Similarity, y, *, M=5, b=1, gamma=0.1, 
     import torch
     d = _dim(y)
     ptr, f64 = _coords(y, "y", (sim.n, d))
-    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter), d, 0)
+    p = _obj_params(M, b, gamma, seed, iter, d)
     out = torch.empty((sim.n,) if rows else (), dtype=y.dtype, device=y.device)
     fn = lib().drg_objective_fwd_f64 if f64 else lib().drg_objective_fwd
     optr = C.c_void_p(out.data_ptr())
@@ -600,7 +641,7 @@ def drg_objective_fwd_noalloc(ctx: Context, sim: Similarity, y, loss, *, M=5, b=
     d = _dim(y)
     yp = _dev(y, torch.float32, "y", (sim.n, d))
     lp = _dev(loss, torch.float32, "loss", ())
-    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter), d, 0)
+    p = _obj_params(M, b, gamma, seed, iter, d)
     _check(lib().drg_objective_fwd_noalloc(ctx.h, sim.h, C.byref(p), yp, lp))
 
 
@@ -610,7 +651,7 @@ def drg_objective_bwd(ctx: Context, sim: Similarity, y, dloss=None, *, M=5, b=1,
     import torch
     d = _dim(y)
     ptr, f64 = _coords(y, "y", (sim.n, d))
-    p = ObjParams(int(M), int(b), float(gamma), int(seed), int(iter), d, 0)
+    p = _obj_params(M, b, gamma, seed, iter, d)
     dy = torch.empty_like(y)
     dl = None
     if dloss is not None:
@@ -674,4 +715,5 @@ def objective(y, ctx: Context, sim: Similarity, *, M=5, b=1, gamma=0.1, seed=0, 
     global _DRGObjective
     if _DRGObjective is None:
         _DRGObjective = _objective_function()
-    return _DRGObjective.apply(y, ctx, sim, int(M), int(b), float(gamma), int(seed), int(iter))
+    _shape(b)
+    return _DRGObjective.apply(y, ctx, sim, int(M), float(b), float(gamma), int(seed), int(iter))
