@@ -290,6 +290,129 @@ int32_t drgo_similarity_perplexity(int32_t n, int32_t k, double perplexity, cons
 }
 
 /* ------------------------------------------------------------------------ */
+/* Weighted graphs (the paper names them as future work, Sec. 6).  Eq. NS is */
+/* written with the graph distance GD; with positive symmetric edge lengths  */
+/* GD_ij is taken as the length of the shortest i-j path of at most k edges */
+/* for j in NNG(i, k) (the pattern stays the hop-defined one), made exactly  */
+/* symmetric by taking the smaller of the two directions (the sums along a  */
+/* path are rounded in path order); E_ij = exp(-GD_ij^2 / (2 sigma^2)),      */
+/* Z_i = sum_l E_il, P~_ij = E_ij (1/Z_i + 1/Z_j) / 2.  With unit lengths    */
+/* GD is the hop count and P~ the unweighted similarity.                     */
+/* ------------------------------------------------------------------------ */
+
+/* e^x for x <= 0 from IEEE operations only: Cody and Waite's reduction      */
+/* n = floor(x / ln2 + 1/2), r = (x - n L1) - n L2 with ln 2 = L1 + L2 and   */
+/* L1 holding 32 significant bits (n L1 exact), |r| <= 0.35; e^r by Taylor's */
+/* series to r^13 (Horner's rule, coefficients 1/j! by successive division); */
+/* e^x = 2^n e^r.  Below -708 (where 2^n e^r would leave the normal range)   */
+/* the result is 0.                                                          */
+double drgo_exp_neg(double x) {
+    if (x < -708.0) return 0.0;
+    double n = floor(x * 1.44269504088896340736 + 0.5);
+    double r = (x - n * 6.93147180369123816490e-01) - n * 1.90821492927058770002e-10;
+    double c[14];
+    c[0] = 1.0;
+    for (int j = 1; j < 14; ++j) c[j] = c[j - 1] / (double)j;
+    double p = c[13];
+    for (int j = 12; j >= 0; --j) p = p * r + c[j];
+    return ldexp(p, (int)n);
+}
+
+static int64_t find_in_row(const int32_t* pcol, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (pcol[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+/* gd[x] of every pattern entry: Bellman-Ford from each source over k rounds, */
+/* every round from the previous round's distances only (so round r allows   */
+/* paths of at most r edges), then the smaller of gd_ij and gd_ji.           */
+void drgo_hop_bounded_dist(int32_t n, const int32_t* rp, const int32_t* col, const double* len,
+                           int32_t k, const int64_t* prp, const int32_t* pcol, double* gd) {
+    double* prev = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* cur = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    char* inball = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    for (int32_t v = 0; v < n; ++v) prev[v] = cur[v] = INFINITY;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) inball[pcol[x]] = 1;
+        inball[i] = 1;
+        prev[i] = 0.0;
+        cur[i] = 0.0;
+        for (int32_t r = 1; r <= k; ++r) {
+            /* relax every edge out of a reached ball node, from prev into cur */
+            for (int64_t x = prp[i] - 1; x < prp[i + 1]; ++x) {
+                int32_t u = x < prp[i] ? i : pcol[x];
+                if (prev[u] == INFINITY) continue;
+                for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+                    int32_t v = col[e];
+                    if (!inball[v] || v == i) continue;
+                    double c = prev[u] + len[e];
+                    if (c < cur[v]) cur[v] = c;
+                }
+            }
+            for (int64_t x = prp[i]; x < prp[i + 1]; ++x) prev[pcol[x]] = cur[pcol[x]];
+        }
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            gd[x] = prev[pcol[x]];
+            inball[pcol[x]] = 0;
+            prev[pcol[x]] = cur[pcol[x]] = INFINITY;
+        }
+        inball[i] = 0;
+        prev[i] = cur[i] = INFINITY;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            int32_t j = pcol[x];
+            if (j < i) continue;
+            int64_t y = find_in_row(pcol, prp[j], prp[j + 1], i);
+            double m = gd[x] < gd[y] ? gd[x] : gd[y];
+            gd[x] = m;
+            gd[y] = m;
+        }
+    }
+    free(prev);
+    free(cur);
+    free(inball);
+}
+
+void drgo_similarity_weighted(int32_t n, double sigma, const int64_t* prp, const int32_t* pcol,
+                              const double* gd, double* E, double* Z, double* invZ, double* P,
+                              double* qt, uint64_t* W, uint64_t* C) {
+    const double s2 = 2.0 * sigma * sigma;
+    for (int32_t i = 0; i < n; ++i) {
+        double z = 0.0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            double a = gd[x] * gd[x];
+            E[x] = drgo_exp_neg(-(a / s2));
+            z = z + E[x];
+        }
+        Z[i] = z;
+        invZ[i] = (prp[i + 1] > prp[i]) ? 1.0 / z : 0.0;
+    }
+    C[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double q = 0.0;
+        uint64_t w = 0;
+        for (int64_t x = prp[i]; x < prp[i + 1]; ++x) {
+            double s = invZ[i] + invZ[pcol[x]];
+            double t = E[x] * s;
+            double p = t * 0.5;
+            P[x] = p;
+            q = q + p;
+            w += (uint64_t)(p * 4294967296.0);
+        }
+        qt[i] = q;
+        W[i] = w;
+        C[i + 1] = C[i] + w;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* The same similarity for a list of rows only, for graphs too large to take */
 /* whole: row s is NNG(s, k) by the bounded BFS above, ascending; Z of every */
 /* node involved is its own hop histogram weighted by e (each node's BFS run */

@@ -64,6 +64,18 @@ int32_t drgo_similarity_perplexity(int32_t n, int32_t k, double perplexity, cons
 /* Natural logarithm from IEEE operations only (atanh series), x > 0. */
 double drgo_ln(double x);
 
+/* Weighted graphs: len[e] > 0 per CSR entry (symmetric).  gd[x] = length of
+ * the shortest path of at most k edges for pattern entry x, the smaller of
+ * the two directions; then E = exp(-gd^2/(2 sigma^2)), Z, invZ, P~ = E (1/Z_i
+ * + 1/Z_j)/2, qt, W, C as in drgo_similarity. */
+void drgo_hop_bounded_dist(int32_t n, const int32_t* rp, const int32_t* col, const double* len,
+                           int32_t k, const int64_t* prp, const int32_t* pcol, double* gd);
+void drgo_similarity_weighted(int32_t n, double sigma, const int64_t* prp, const int32_t* pcol,
+                              const double* gd, double* E, double* Z, double* invZ, double* P,
+                              double* qt, uint64_t* W, uint64_t* C);
+/* e^x for x <= 0 from IEEE operations only (0 below -708). */
+double drgo_exp_neg(double x);
+
 /* The same similarity for the rows srcs[0..nsrc) only (k <= 8): out_rp[nsrc+1]
  * row offsets; with out_col non-NULL also the rows' columns (ascending), hops,
  * P~ values, and per row 1/Z, qt and W.  Returns the number of entries. */

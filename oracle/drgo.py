@@ -60,6 +60,12 @@ def lib():
                                              _u8p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                              _u64p, _u64p]
     L.drgo_similarity_perplexity.restype = C.c_int32
+    L.drgo_hop_bounded_dist.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.c_int32, _i64p,
+                                        _i32p, _f64p]
+    L.drgo_similarity_weighted.argtypes = [C.c_int32, C.c_double, _i64p, _i32p, _f64p, _f64p,
+                                           _f64p, _f64p, _f64p, _f64p, _u64p, _u64p]
+    L.drgo_exp_neg.argtypes = [C.c_double]
+    L.drgo_exp_neg.restype = C.c_double
     L.drgo_ln.argtypes = [C.c_double]
     L.drgo_ln.restype = C.c_double
     L.drgo_draw.argtypes = [_u64p, C.c_int32, C.c_uint64]
@@ -126,6 +132,8 @@ class Sim:
     perplexity: float = 0.0  # > 0: node-wise sigma_i calibrated to it
     t: np.ndarray = None     # float64[n]: exp(-1/(2 sigma_i^2)) per node
     A: np.ndarray = None     # float64[n, k]: NS_{j|i} of hop d in A[i, d-1]
+    gd: np.ndarray = None    # float64[nnz]: weighted graph distance per entry
+    E: np.ndarray = None     # float64[nnz]: exp(-gd^2 / (2 sigma^2))
 
     @property
     def nnz(self) -> int:
@@ -198,6 +206,31 @@ def similarity_perplexity_from_pattern(n, k, perplexity, rp, col, hop) -> Sim:
         raise ValueError("k must be in 1..8 and perplexity >= 1")
     return Sim(n, k, 0.0, _c(rp, np.int64), colc[:nnz], hopc[:nnz], np.zeros(k), Z, invZ,
                P[:nnz], qt, W, Cc, float(perplexity), t, A.reshape(n, k))
+
+
+def similarity_weighted(csr, lengths, k: int, sigma: float = 1.0) -> Sim:
+    """P~ of a graph with positive symmetric edge lengths (one per CSR
+    entry): GD_ij = the shortest path of at most k edges, the pattern the
+    hop-defined NNG(i, k); see drgo_hop_bounded_dist."""
+    rp, col, hop = khop(csr, k)
+    n = int(csr.n)
+    nnz = int(rp[-1])
+    colc = _c(col if nnz else np.zeros(1, np.int32), np.int32)
+    gd = np.zeros(max(nnz, 1), np.float64)
+    lib().drgo_hop_bounded_dist(n, _c(csr.row_ptr, np.int32), _c(csr.col, np.int32),
+                                _c(lengths, np.float64), int(k), _c(rp, np.int64), colc, gd)
+    E = np.zeros(max(nnz, 1), np.float64)
+    Z = np.zeros(n, np.float64)
+    invZ = np.zeros(n, np.float64)
+    P = np.zeros(max(nnz, 1), np.float64)
+    qt = np.zeros(n, np.float64)
+    W = np.zeros(n, np.uint64)
+    Cc = np.zeros(n + 1, np.uint64)
+    lib().drgo_similarity_weighted(n, float(sigma), _c(rp, np.int64), colc, gd, E, Z, invZ, P,
+                                   qt, W, Cc)
+    hopc = _c(hop if nnz else np.ones(1, np.uint8), np.uint8)
+    return Sim(n, k, float(sigma), _c(rp, np.int64), colc[:nnz], hopc[:nnz], np.zeros(k), Z,
+               invZ, P[:nnz], qt, W, Cc, gd=gd[:nnz], E=E[:nnz])
 
 
 def node_sigma(sim: Sim) -> np.ndarray:
@@ -427,12 +460,17 @@ def eta_at(eta0: float, t: int, Tl: int) -> float:
 def layout(csr, k=1, sigma=1.0, M=5, b=1, gamma=0.1, gamma_coarsest=0.01, T=400, eta0=1.0,
            clip=4.0, rho=0.8, min_nodes=1000, max_levels=64, seed=0, mode="sync",
            sim: Sim | None = None, hier: Hier | None = None, return_all=False, dim=2,
-           perplexity=0.0):
+           perplexity=0.0, lengths=None):
     """Full multilevel layout; returns Y^0 [n, dim] (float64).  perplexity >
-    0 takes node-wise sigma_i calibrated to it instead of sigma."""
+    0 takes node-wise sigma_i calibrated to it instead of sigma; lengths
+    (one per CSR entry) takes the weighted similarity."""
     if sim is None:
-        sim = (similarity_perplexity(csr, k, perplexity) if perplexity > 0
-               else similarity(csr, k, sigma))
+        if lengths is not None:
+            sim = similarity_weighted(csr, lengths, k, sigma)
+        elif perplexity > 0:
+            sim = similarity_perplexity(csr, k, perplexity)
+        else:
+            sim = similarity(csr, k, sigma)
     if hier is None:
         hier = hierarchy(csr, seed, rho, min_nodes, max_levels)
     Lc = hier.levels
