@@ -191,6 +191,27 @@ drg_status drg_build_similarity(drg_ctx* ctx, const drg_csr* g, int32_t k, doubl
  * perplexity >= 1 and finite; k in 1..4.  Synchronises. */
 drg_status drg_build_similarity_perplexity(drg_ctx* ctx, const drg_csr* g, int32_t k,
                                            double perplexity, uint32_t flags, drg_sim** out);
+/* The similarity of a weighted graph (weighted graphs are named as future
+ * work in Sec. 6; Eq. NS is written with the graph distance GD).
+ * length_dev[nnz] (device, FP64): one positive finite length per CSR entry,
+ * equal for (u, v) and (v, u).  NNG(i, k) is the hop-defined pattern; GD_ij
+ * is the length of the shortest i-j path of at most k edges (k rounds of
+ * Bellman-Ford from each source, each round from the previous round's
+ * distances), the smaller of the two directions; then
+ *   E_ij = exp(-GD_ij^2 / (2 sigma^2)),  Z_i = sum_l E_il,
+ *   P~_ij = E_ij (1/Z_i + 1/Z_j) / 2,
+ * with qt, the sampling table and 1/Z as for drg_build_similarity (unit
+ * lengths give that similarity up to the order of Z's sum).  The exponential
+ * is computed from IEEE-754 operations only (Cody-Waite reduction, Taylor
+ * series), so the results are reproducible bit for bit.  The structure is
+ * always validated (as with DRG_VALIDATE); DRG_E_INVALID for a bad length or
+ * asymmetric lengths.  Swept by the row-form kernels (no column-blocked
+ * copy); coarsening (drg_coarsen) uses the structure only.  Peak device
+ * memory of the build: 24 bytes per pattern entry besides the pattern.
+ * Synchronises. */
+drg_status drg_build_similarity_weighted(drg_ctx* ctx, const drg_csr* g,
+                                         const double* length_dev, int32_t k, double sigma,
+                                         uint32_t flags, drg_sim** out);
 /* sigma_i of every node into sigma_host[n] (host; synchronises): the global
  * sigma, or for a node-wise similarity sqrt(-1/(2 ln t_i)) (+inf where t_i = 1);
  * 0 for isolated nodes. */

@@ -198,6 +198,21 @@ drg_status drg_build_similarity_perplexity(drg_ctx* ctx, const drg_csr* g, int32
     });
 }
 
+drg_status drg_build_similarity_weighted(drg_ctx* ctx, const drg_csr* g,
+                                         const double* length_dev, int32_t k, double sigma,
+                                         uint32_t flags, drg_sim** out) {
+    return guarded([&] {
+        need(ctx, "ctx");
+        need(out, "out");
+        need(g, "graph");
+        *out = nullptr;
+        if (g->nnz > 0) need(length_dev, "length_dev");
+        CtxScope scope(ctx);
+        *out = drg::build_similarity(ctx, g, k, sigma, flags, nullptr, 0.0,
+                                     g->nnz > 0 ? length_dev : nullptr);
+    });
+}
+
 drg_status drg_sim_node_sigma(const drg_sim* s, double* sigma_host) {
     return guarded([&] {
         need(s, "sim");

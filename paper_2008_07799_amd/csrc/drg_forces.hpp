@@ -151,16 +151,20 @@ struct HalfE {
     }
 };
 
-// Node-wise sigma: P~_ij = (A_i[d] + A_j[d]) / 2 from the table A [n][4]
-// (A_i[d] = NS_{j|i} at hop d+1); ai holds row i's four values.  A = NULL:
-// one global sigma, P~_ij = e_d/2 (1/Z_i + 1/Z_j) from the records.
+// Pair weight P~_ij of pattern entry x.  Node-wise sigma: (A_i[d] +
+// A_j[d]) / 2 from the table A [n][4] (A_i[d] = NS_{j|i} at hop d+1; ai holds
+// row i's four values).  Weighted graph: E_x (1/Z_i + 1/Z_j) / 2 with E per
+// entry.  Otherwise one global sigma: e_d/2 (1/Z_i + 1/Z_j) from the records.
 struct PairW {
     const double* A = nullptr;
+    const double* Ex = nullptr;
     HalfE<double> ai{0.0, 0.0, 0.0, 0.0};
 };
-__device__ __forceinline__ PairW pair_w(const double* __restrict__ A, int64_t i) {
+__device__ __forceinline__ PairW pair_w(const double* __restrict__ A,
+                                        const double* __restrict__ Ex, int64_t i) {
     PairW p;
     p.A = A;
+    p.Ex = Ex;
     if (A) p.ai = HalfE<double>{A[4 * i], A[4 * i + 1], A[4 * i + 2], A[4 * i + 3]};
     return p;
 }
@@ -180,7 +184,7 @@ template <typename T, int B, bool CLIP = true>
 __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
                                              const typename VT<T>::v4& rj, const HalfE<double>& eh,
                                              double clip, bool half, double& ax, double& ay,
-                                             PairW pw = PairW{}) {
+                                             const PairW& pw = PairW{}, int64_t x = 0) {
     const double dx = (double)ri.x - (double)rj.x, dy = (double)ri.y - (double)rj.y;
     const double d2 = dx * dx + dy * dy;
     const double k = attract_coef_b<B, double>(d2, half);
@@ -189,7 +193,7 @@ __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint3
         w = (pw.ai(e >> 30) + pw.A[4 * (int64_t)(e & COL_MASK) + (e >> 30)]) * 0.5;
     } else {
         const double zi = (double)ri.z + (double)ri.w, zj = (double)rj.z + (double)rj.w;
-        w = eh(e >> 30) * (zi + zj);
+        w = (pw.Ex ? 0.5 * pw.Ex[x] : eh(e >> 30)) * (zi + zj);
     }
     if constexpr (CLIP) {
         ax += w * clampT2(k * dx, clip);
@@ -246,7 +250,7 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
     const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
     const HalfE<double>& eh, double clip, bool half, int M, uint64_t seed, uint64_t iter,
-    int32_t key, Draw draw, double gq, PairW pw = PairW{}) {
+    int32_t key, Draw draw, double gq, const PairW& pw = PairW{}) {
     using v4 = typename VT<T>::v4;
     double ax = 0.0, ay = 0.0;
     // U entries per step; the next step's entries are loaded while this
@@ -273,7 +277,8 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
         for (int q = 0; q < U; ++q) en[q] = colhop[max(xl + (int64_t)q * G, x)];
 #pragma unroll
         for (int q = 0; q < U; ++q)
-            attract_pair<T, B, CLIP>(ri, e[q], rj[q], eh, clip, half, ax, ay, pw);
+            attract_pair<T, B, CLIP>(ri, e[q], rj[q], eh, clip, half, ax, ay, pw,
+                                     x + (int64_t)q * G);
 #pragma unroll
         for (int q = 0; q < U; ++q) e[q] = en[q];
         x = xn;
@@ -281,7 +286,7 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     }
     for (; x < re; x += G) {
         const uint32_t e = colhop[x];
-        attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, half, ax, ay, pw);
+        attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, half, ax, ay, pw, x);
     }
     double rx, ry;
     repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, half, rx, ry);

@@ -44,6 +44,9 @@ struct drg_sim {
     // (A_i[d] + A_j[d]) / 2), and t_i = exp(-1/(2 sigma_i^2))
     drg::DevBuf<double> A;           // [n][4]
     drg::DevBuf<double> tnode;       // [n]
+    // weighted graph only: E_ij = exp(-GD_ij^2 / (2 sigma^2)) per entry, in
+    // place of e_d (P~_ij = E_ij (1/Z_i + 1/Z_j) / 2)
+    drg::DevBuf<double> Ex;          // [nnz]
     // per-iteration workspace of the layout step
     drg::DevBuf<float4> rec;         // [n] staged (y_c(j), invZ_j)
     drg::DevBuf<float2> g;           // [n] one-sided steps
@@ -112,8 +115,10 @@ inline int sweep_group(double mean_len) {
 // graph's row weights with the launch shape of its own single-graph build;
 // the sampling guide and the column-blocked copy are then left out.
 // perplexity != 0: node-wise sigma_i calibrated to it (sigma unused).
+// lengths (device, one per CSR entry): a weighted graph.
 drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
-                          UnionInfo* u = nullptr, double perplexity = 0.0);
+                          UnionInfo* u = nullptr, double perplexity = 0.0,
+                          const double* lengths = nullptr);
 void sim_node_sigma(const drg_sim* s, double* sigma);
 void validate_csr(drg_ctx* ctx, const drg_csr* g);
 void validate_csr_impl(drg_ctx* ctx, const drg_csr* g, bool full);

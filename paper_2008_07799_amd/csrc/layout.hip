@@ -72,6 +72,7 @@ struct SweepArgs {
     int32_t noclip;        // the attraction clip cannot bind (attract_clip_free)
     int32_t half;          // b = B + 1/2
     const double* A;       // node-wise sigma: P~ table [n0][4] (NULL: global sigma)
+    const double* Ex;      // weighted graph: E per entry [nnz] (NULL: e_d by hop)
     uint64_t seed, iter;
     // async only
     v2* y;
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
                                            [&](uint64_t w) {
                                                return draw_node(w, a.C, a.guide, a.gbits, a.S);
                                            },
-                                           (double)a.gamma * (double)a.qt[i], pair_w(a.A, i));
+                                           (double)a.gamma * (double)a.qt[i], pair_w(a.A, a.Ex, i));
             if (lane == 0) a.g[i] = gi;
         }
     };
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
         const int32_t ci = a.cmap ? a.cmap[i] : (int32_t)i;
         const float yix = yv[2 * ci], yiy = yv[2 * ci + 1];
         const float zi = a.invZ[i];
-        const PairW pw = pair_w(a.A, i);
+        const PairW pw = pair_w(a.A, a.Ex, i);
         float ax = 0.0f, ay = 0.0f;
         for (int64_t x = rs + lane; x < re; x += G) {
             const uint32_t e = a.colhop[x];
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             if (d2 > 0.0f) {
                 const float k = attract_coef_b<B, float>(d2, a.half != 0);
                 const float w = pw.A ? (float)((pw.ai(e >> 30) + pw.A[4 * j + (e >> 30)]) * 0.5)
-                                     : half_e(a, e >> 30) * (zi + a.invZ[j]);
+                                : (pw.Ex ? (float)(0.5 * pw.Ex[x]) : half_e(a, e >> 30)) *
+                                      (zi + a.invZ[j]);
                 ax += w * clampT2(k * dx, a.clip);
                 ay += w * clampT2(k * dy, a.clip);
             }
@@ -382,6 +384,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.noclip = attract_clip_free(p->b + (half ? 0.5 : 0.0), p->clip) ? 1 : 0;
     a.half = half ? 1 : 0;
     a.A = s->A.get();
+    a.Ex = s->Ex.get();
     a.seed = p->seed;
     a.iter = p->iter;
     a.y = reinterpret_cast<v2*>(y);
@@ -394,7 +397,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     // in place as windows of rows finish.
     // the blocked sweep: whole b, one global sigma (node-wise sims have no
     // blocked copy)
-    const bool blocked = F32 && s->blk_nb > 0 && !half && !a.A;
+    const bool blocked = F32 && s->blk_nb > 0 && !half && !a.A && !a.Ex;
     const bool async = p->mode == DRG_MODE_ASYNC;
     if (async) {
         if (level == 0) {
@@ -451,7 +454,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     }
     bool win = false;
     if constexpr (F32) {
-        if (!async && !a.A && window_wanted(s)) {
+        if (!async && !a.A && !a.Ex && window_wanted(s)) {
             const int rpl = win_rpl();
             if (s->win_rpl != rpl) {
                 s->win_n = build_window_items(ctx, s, {0, n0}, {(WIN_BLOCK / G) * rpl},
@@ -509,7 +512,7 @@ void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_par
 // Everything a synchronous FP32 step builds on first use, built now (before
 // a step is recorded into a graph).
 void prepare_sync_step(drg_ctx* ctx, drg_sim* s) {
-    if (s->blk_nb > 0 || s->A.get() || !window_wanted(s)) return;
+    if (s->blk_nb > 0 || s->A.get() || s->Ex.get() || !window_wanted(s)) return;
     const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
     const int rpl = win_rpl();
     if (s->win_rpl != rpl) {

@@ -81,7 +81,7 @@ __device__ __forceinline__ Sum3 sweep_row3(const typename VT<T>::v4& ri, double 
             w = (pw.ai(e >> 30) + pw.A[4 * (int64_t)j + (e >> 30)]) * 0.5;
         } else {
             const double zj = (double)rj.w + (lo ? (double)lo[j] : 0.0);
-            w = eh(e >> 30) * (zi + zj);
+            w = (pw.Ex ? 0.5 * pw.Ex[x] : eh(e >> 30)) * (zi + zj);
         }
         if constexpr (CLIP) {
             ax += w * clampT2(k * dx, clip);
@@ -135,6 +135,7 @@ struct Sweep3Args {
     int32_t noclip;
     int32_t half;  // 1: the shape is b + 1/2
     const double* A;  // node-wise sigma: P~ table [n0][4] (NULL: global sigma)
+    const double* Ex;  // weighted graph: E per entry [nnz] (NULL: e_d by hop)
     uint64_t seed, iter;
     // async only
     T* y;
@@ -161,11 +162,11 @@ __global__ __launch_bounds__(256) void k_sweep3(Sweep3Args<T> a) {
             if (a.noclip)
                 gi = sweep_row3<T, B, false>(ri, zi, rs, re, lane, G, a.colhop, a.rec, a.lo, eh,
                                              a.clip, a.half != 0, a.M, a.seed, a.iter, (int32_t)i,
-                                             draw, gq, pair_w(a.A, i));
+                                             draw, gq, pair_w(a.A, a.Ex, i));
             else
                 gi = sweep_row3<T, B, true>(ri, zi, rs, re, lane, G, a.colhop, a.rec, a.lo, eh,
                                             a.clip, a.half != 0, a.M, a.seed, a.iter, (int32_t)i,
-                                            draw, gq, pair_w(a.A, i));
+                                            draw, gq, pair_w(a.A, a.Ex, i));
         }
         if (lane == 0) {
             a.g[3 * i] = (T)gi.x;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void k_sweep3_async(Sweep3Args<float> a) {
         const int64_t ci = a.cmap ? a.cmap[i] : i;
         const float yi0 = yv[3 * ci], yi1 = yv[3 * ci + 1], yi2 = yv[3 * ci + 2];
         const float zi = a.invZ[i];
-        const PairW pw = pair_w(a.A, i);
+        const PairW pw = pair_w(a.A, a.Ex, i);
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
         for (int64_t x = rs + lane; x < re; x += G) {
             const uint32_t e = a.colhop[x];
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_sweep3_async(Sweep3Args<float> a) {
                 const uint32_t h = e >> 30;
                 const float eh = (float)(h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3)));
                 const float w = pw.A ? (float)((pw.ai(h) + pw.A[4 * (int64_t)j + h]) * 0.5)
-                                     : eh * (zi + a.invZ[j]);
+                                     : (pw.Ex ? (float)(0.5 * pw.Ex[x]) : eh) * (zi + a.invZ[j]);
                 const float c = (float)a.clip;
                 ax += w * clampT2(k * dx, c);
                 ay += w * clampT2(k * dy, c);
@@ -400,6 +401,7 @@ void layout_step3_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_
     a.noclip = attract_clip_free(p->b + (p->b_half ? 0.5 : 0.0), p->clip) ? 1 : 0;
     a.half = p->b_half ? 1 : 0;
     a.A = s->A.get();
+    a.Ex = s->Ex.get();
     a.seed = p->seed;
     a.iter = p->iter;
     a.y = y;

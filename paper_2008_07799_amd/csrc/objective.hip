@@ -87,6 +87,7 @@ struct ObjArgs {
     T bv;                  // b as a number: B, or B + 1/2 when half
     int32_t half;          // 1: b = B + 1/2
     const double* A;       // node-wise sigma: P~ table [n][4] (NULL: global sigma)
+    const double* Ex;      // weighted graph: E per entry [nnz] (NULL: e_d by hop)
     uint64_t seed, iter;
     const T* dloss;        // backward: scale (NULL = 1)
     T* row_val;            // forward: per-row value
@@ -100,12 +101,13 @@ __device__ __forceinline__ T oh(const ObjArgs<T>& a, uint32_t h) {
     return h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3));
 }
 
-// P~_ij of an entry at hop index h: (A_i[h] + A_j[h]) / 2 with node-wise
-// sigma, else e_h/2 (1/Z_i + 1/Z_j)
+// P~_ij of entry x at hop index h: (A_i[h] + A_j[h]) / 2 with node-wise
+// sigma, E_x/2 (1/Z_i + 1/Z_j) for a weighted graph, else e_h/2 (1/Z_i + 1/Z_j)
 template <typename T>
-__device__ __forceinline__ T obj_p(const ObjArgs<T>& a, int64_t i, int32_t j, uint32_t h, T zi) {
+__device__ __forceinline__ T obj_p(const ObjArgs<T>& a, int64_t i, int32_t j, uint32_t h, T zi,
+                                   int64_t x) {
     if (a.A) return (T)((a.A[4 * i + h] + a.A[4 * (int64_t)j + h]) * 0.5);
-    return oh(a, h) * (zi + a.invZ[j]);
+    return (a.Ex ? (T)(0.5 * a.Ex[x]) : oh(a, h)) * (zi + a.invZ[j]);
 }
 
 template <typename T>
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(256) void k_obj_rows(ObjArgs<T> a) {
                 const typename OV<T>::v2 yj = a.y[j];
                 const T dx = yi.x - yj.x, dy = yi.y - yj.y;
                 const T d2 = dx * dx + dy * dy;
-                const T p = obj_p(a, i, j, e >> 30, zi);
+                const T p = obj_p(a, i, j, e >> 30, zi, x);
                 att += p * (-log1pT(opow_b<B>(d2, a.half != 0)));
             }
             for (int m = lane; m < a.M; m += G) {
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) void k_grad_rows(ObjArgs<T> a) {
                 const typename OV<T>::v2 yj = a.y[j];
                 const T dx = yi.x - yj.x, dy = yi.y - yj.y;
                 const T d2 = dx * dx + dy * dy;
-                const T p = obj_p(a, i, j, e >> 30, zi);
+                const T p = obj_p(a, i, j, e >> 30, zi, x);
                 const T k = p * (T(-2) * a.bv) * opow_bm1<B>(d2, a.half != 0) *
                             orcp(T(1) + opow_b<B>(d2, a.half != 0));
                 ax += k * dx;
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(256) void k_obj_rows3(ObjArgs<T> a) {
                 const uint32_t e = a.colhop[x];
                 const int32_t j = (int32_t)(e & COL_MASK);
                 const T d2 = off3(a.y3, i, j, dx, dy, dz);
-                att += obj_p(a, i, j, e >> 30, zi) * (-log1pT(opow_b<B>(d2, a.half != 0)));
+                att += obj_p(a, i, j, e >> 30, zi, x) * (-log1pT(opow_b<B>(d2, a.half != 0)));
             }
             for (int m = lane; m < a.M; m += G) {
                 const int32_t v =
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(256) void k_grad_rows3(ObjArgs<T> a) {
                 const uint32_t e = a.colhop[x];
                 const int32_t j = (int32_t)(e & COL_MASK);
                 const T d2 = off3(a.y3, i, j, dx, dy, dz);
-                const T p = obj_p(a, i, j, e >> 30, zi);
+                const T p = obj_p(a, i, j, e >> 30, zi, x);
                 const T k = p * (T(-2) * a.bv) * opow_bm1<B>(d2, a.half != 0) *
                             orcp(T(1) + opow_b<B>(d2, a.half != 0));
                 ax += k * dx;
@@ -463,7 +465,8 @@ __global__ void k_negatives(int32_t n, int32_t M, const int64_t* __restrict__ pr
 
 __global__ void k_coo(int32_t n, const int64_t* __restrict__ prp, const uint32_t* __restrict__ ch,
                       const float* __restrict__ invZf, float eh0, float eh1, float eh2, float eh3,
-                      const double* __restrict__ A, int32_t* __restrict__ rows,
+                      const double* __restrict__ A, const double* __restrict__ Ex,
+                      int32_t* __restrict__ rows,
                       int32_t* __restrict__ cols, float* __restrict__ P) {
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int lane = __lane_id();
@@ -476,7 +479,7 @@ __global__ void k_coo(int32_t n, const int64_t* __restrict__ prp, const uint32_t
         if (rows) rows[x] = (int32_t)i;
         if (cols) cols[x] = j;
         if (P) P[x] = A ? (float)((A[4 * i + h] + A[4 * (int64_t)j + h]) * 0.5)
-                        : eh * (invZf[i] + invZf[j]);
+                        : (Ex ? (float)(0.5 * Ex[x]) : eh) * (invZf[i] + invZf[j]);
     }
 }
 
@@ -508,6 +511,7 @@ static ObjArgs<T> obj_args(drg_sim* s, const drg_obj_params* p, const T* y) {
     a.gamma = (T)p->gamma;
     a.half = p->b_half ? 1 : 0;
     a.A = s->A.get();
+    a.Ex = s->Ex.get();
     a.bv = (T)((double)p->b + (p->b_half ? 0.5 : 0.0));
     a.seed = p->seed;
     a.iter = p->iter;
@@ -564,7 +568,7 @@ static void obj_rows(drg_ctx* ctx, drg_sim* s, const drg_obj_params* p, const Ob
     hipStream_t st = ctx->stream;
     const bool three = p->dim == 3;
     if constexpr (std::is_same<T, float>::value) {
-        if (!three && !p->b_half && !a.A && s->blk_nb > 0 && obj_blocked_wanted()) {
+        if (!three && !p->b_half && !a.A && !a.Ex && s->blk_nb > 0 && obj_blocked_wanted()) {
             sweep_blocked_objective(ctx, s, p->b, reinterpret_cast<const float*>(a.y), grad ? 1 : 0);
             const float2* part = s->blk_partial.get();
 #define DRG_FIN(BB)                                                                          \
@@ -752,7 +756,7 @@ void sim_coo(drg_ctx* ctx, drg_sim* s, int32_t* rows, int32_t* cols, float* P) {
     hipLaunchKernelGGL(k_coo, dim3(ceil_div((int64_t)s->n * WAVE, 256)), dim3(256), 0, ctx->stream,
                        s->n, s->row_ptr.get(), s->colhop.get(), s->invZf.get(),
                        (float)(0.5 * s->e[0]), (float)(0.5 * s->e[1]), (float)(0.5 * s->e[2]),
-                       (float)(0.5 * s->e[3]), s->A.get(), rows, cols, P);
+                       (float)(0.5 * s->e[3]), s->A.get(), s->Ex.get(), rows, cols, P);
     DRG_LAUNCH_CHECK();
 }
 

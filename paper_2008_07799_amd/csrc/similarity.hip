@@ -463,7 +463,154 @@ __global__ void k_calibrate(int32_t n, int32_t k, const int32_t* __restrict__ cn
     invZlo[i] = (float)(iz - (double)hi);
 }
 
-// P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2, or with node-wise sigma (A non-NULL)
+// ------------------------------------------------------------------ weighted graphs
+// Positive symmetric edge lengths, one per CSR entry.  GD_ij of Eq. NS is
+// the length of the shortest i-j path of at most k edges for j in NNG(i, k)
+// (the hop-defined pattern), the smaller of the two directions (path sums
+// are rounded in path order); E_ij = exp(-GD_ij^2 / (2 sigma^2)) per entry
+// replaces e_d, so P~_ij = E_ij (1/Z_i + 1/Z_j) / 2 with Z_i = sum_l E_il.
+// The exponential is computed from IEEE operations only (see exp_neg_ieee),
+// so P~ and the integer sampling table are reproducible bit for bit.
+
+// every length positive and finite, and equal to that of the reverse entry
+// (the structure is validated first, so the reverse entry exists)
+__global__ void k_check_lengths(int32_t n, const int32_t* __restrict__ rp,
+                                const int32_t* __restrict__ col, const double* __restrict__ len,
+                                int* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int flag = 0;
+    for (int32_t x = rp[i]; x < rp[i + 1]; ++x) {
+        const double l = len[x];
+        if (!(l > 0.0 && l <= 1.7976931348623157e308)) flag |= 32;
+        const int32_t v = col[x];
+        int32_t lo = rp[v], hi = rp[v + 1];
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (col[mid] < (int32_t)i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo < rp[v + 1] && !(len[lo] == l)) flag |= 64;
+    }
+    if (flag) atomicOr(bad, flag);
+}
+
+// e^x for x <= 0: Cody and Waite's reduction n = floor(x / ln2 + 1/2),
+// r = (x - n L1) - n L2 (ln 2 = L1 + L2, L1 with 32 significant bits so n L1
+// is exact), |r| <= 0.35; e^r by Taylor's series to r^13 (Horner's rule,
+// coefficients 1/j! by successive division); e^x = 2^n e^r.  0 below -708,
+// where 2^n e^r would leave the normal range.
+__device__ double exp_neg_ieee(double x) {
+#pragma clang fp contract(off)
+    if (x < -708.0) return 0.0;
+    const double n = floor(x * 1.44269504088896340736 + 0.5);
+    const double r = (x - n * 6.93147180369123816490e-01) - n * 1.90821492927058770002e-10;
+    double c[14];
+    c[0] = 1.0;
+    for (int j = 1; j < 14; ++j) c[j] = c[j - 1] / (double)j;
+    double p = c[13];
+    for (int j = 12; j >= 0; --j) p = p * r + c[j];
+    return ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ int64_t row_find(const uint32_t* __restrict__ ch, int64_t lo,
+                                            int64_t hi, int32_t key) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int32_t)(ch[mid] & COL_MASK) < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_fill_inf(int64_t m, double* __restrict__ d) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < m) d[x] = __longlong_as_double(0x7FF0000000000000LL);
+}
+
+// One Bellman-Ford round from the previous round's distances only (so round
+// r admits paths of at most r edges): entry x of row i (node j) takes the
+// least of its own distance and, over the graph neighbours u of j inside
+// {i} + NNG(i, k), dist(u) + len(u, j).  One wave per row, lanes over its
+// entries; a neighbour's slot is found by binary search in the sorted row.
+__global__ __launch_bounds__(256) void k_bf_round(int32_t n, const int64_t* __restrict__ prp,
+                                                  const uint32_t* __restrict__ ch,
+                                                  const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ len,
+                                                  const double* __restrict__ dprev,
+                                                  double* __restrict__ dcur) {
+#pragma clang fp contract(off)
+    const int lane = __lane_id();
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
+    for (int64_t i = w0; i < n; i += nw) {
+        const int64_t rs = prp[i], re = prp[i + 1];
+        for (int64_t x = rs + lane; x < re; x += WAVE) {
+            const int32_t j = (int32_t)(ch[x] & COL_MASK);
+            double best = dprev[x];
+            for (int32_t e = rp[j]; e < rp[j + 1]; ++e) {
+                const int32_t u = col[e];
+                double du;
+                if (u == (int32_t)i) {
+                    du = 0.0;
+                } else {
+                    const int64_t y = row_find(ch, rs, re, u);
+                    if (y >= re || (int32_t)(ch[y] & COL_MASK) != u) continue;
+                    du = dprev[y];
+                }
+                const double c = du + len[e];
+                if (c < best) best = c;
+            }
+            dcur[x] = best;
+        }
+    }
+}
+
+// GD of every entry as the smaller of its two directions, then
+// E = exp(-GD^2 / s2) with s2 = 2 sigma^2
+__global__ __launch_bounds__(256) void k_bf_finish(int32_t n, const int64_t* __restrict__ prp,
+                                                   const uint32_t* __restrict__ ch,
+                                                   const double* __restrict__ gd, double s2,
+                                                   double* __restrict__ E) {
+#pragma clang fp contract(off)
+    const int lane = __lane_id();
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
+    for (int64_t i = w0; i < n; i += nw) {
+        for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += WAVE) {
+            const int32_t j = (int32_t)(ch[x] & COL_MASK);
+            const int64_t y = row_find(ch, prp[j], prp[j + 1], (int32_t)i);
+            const double a = gd[x], b = gd[y];
+            const double m = a < b ? a : b;
+            const double q = m * m;
+            E[x] = exp_neg_ieee(-(q / s2));
+        }
+    }
+}
+
+// Z_i = sum of the row's E in entry order (one thread per row)
+__global__ void k_weighted_z(int32_t n, const int64_t* __restrict__ prp,
+                             const double* __restrict__ E, double* __restrict__ invZ,
+                             float* __restrict__ invZf, float* __restrict__ invZlo) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double z = 0.0;
+    for (int64_t x = prp[i]; x < prp[i + 1]; ++x) z = z + E[x];
+    const double iz = prp[i + 1] > prp[i] ? 1.0 / z : 0.0;
+    invZ[i] = iz;
+    const float hi = (float)iz;
+    invZf[i] = hi;
+    invZlo[i] = (float)(iz - (double)hi);
+}
+
+// P~_ij = ((1/Z_i + 1/Z_j) e_d) / 2 (E_ij in place of e_d for a weighted
+// graph), or with node-wise sigma (A non-NULL)
 // (A_i[d] + A_j[d]) / 2.  Per row: W_i = sum_j trunc(P~_ij 2^32)
 // (exact integer), qt_i = sum_j P~_ij (FP64: lane l of the G lanes sums
 // entries l, l+G, ... in order, then a butterfly over the group).
@@ -472,6 +619,7 @@ __device__ __forceinline__ void row_weights_row(int64_t i, int lane, int G,
                                                 const uint32_t* __restrict__ ch,
                                                 const double* __restrict__ invZ, const ECoef& ec,
                                                 const double* __restrict__ A,
+                                                const double* __restrict__ Ex,
                                                 uint64_t* __restrict__ W, double* __restrict__ qt,
                                                 float* __restrict__ qtf) {
 #pragma clang fp contract(off)
@@ -486,7 +634,7 @@ __device__ __forceinline__ void row_weights_row(int64_t i, int lane, int G,
             p = s * 0.5;
         } else {
             const double s = izi + invZ[e & COL_MASK];
-            const double t = pick_e(ec.e, e >> 30) * s;
+            const double t = (Ex ? Ex[x] : pick_e(ec.e, e >> 30)) * s;
             p = t * 0.5;
         }
         ws += (unsigned long long)(p * 4294967296.0);
@@ -506,6 +654,7 @@ __global__ __launch_bounds__(256) void k_row_weights(int32_t n, const int64_t* _
                                                      const uint32_t* __restrict__ ch,
                                                      const double* __restrict__ invZ, ECoef ec,
                                                      const double* __restrict__ A,
+                                                     const double* __restrict__ Ex,
                                                      uint64_t* __restrict__ W,
                                                      double* __restrict__ qt,
                                                      float* __restrict__ qtf) {
@@ -513,7 +662,7 @@ __global__ __launch_bounds__(256) void k_row_weights(int32_t n, const int64_t* _
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
     for (int64_t i = grp; i < n; i += ngrp)
-        row_weights_row(i, lane, G, prp, ch, invZ, ec, A, W, qt, qtf);
+        row_weights_row(i, lane, G, prp, ch, invZ, ec, A, Ex, W, qt, qtf);
 }
 
 // Union of graphs: every graph keeps the group size its own single-graph
@@ -545,8 +694,8 @@ __global__ __launch_bounds__(256) void k_row_weights_union(int32_t count,
         const int G = t.z;
         const int32_t r = (gw - woff[lo]) * (WAVE / G) + (int32_t)(__lane_id() / G);
         if (r < t.y)
-            row_weights_row((int64_t)t.x + r, __lane_id() % G, G, prp, ch, invZ, ec, nullptr, W,
-                            qt, qtf);
+            row_weights_row((int64_t)t.x + r, __lane_id() % G, G, prp, ch, invZ, ec, nullptr,
+                            nullptr, W, qt, qtf);
     }
 }
 
@@ -575,33 +724,37 @@ __global__ void k_guide(int32_t n, const uint64_t* __restrict__ C, int gbits,
 }
 
 // P~ of entry e of row i, as row_weights_row computes it
-__device__ __forceinline__ double entry_p(int64_t i, uint32_t e, const double* __restrict__ invZ,
-                                          const ECoef& ec, const double* __restrict__ A) {
+__device__ __forceinline__ double entry_p(int64_t i, int64_t x, uint32_t e,
+                                          const double* __restrict__ invZ, const ECoef& ec,
+                                          const double* __restrict__ A,
+                                          const double* __restrict__ Ex) {
 #pragma clang fp contract(off)
     if (A) {
         const double s = A[4 * i + (e >> 30)] + A[4 * (int64_t)(e & COL_MASK) + (e >> 30)];
         return s * 0.5;
     }
     const double s = invZ[i] + invZ[e & COL_MASK];
-    const double t = pick_e(ec.e, e >> 30) * s;
+    const double t = (Ex ? Ex[x] : pick_e(ec.e, e >> 30)) * s;
     return t * 0.5;
 }
 
 __global__ void k_materialise_P(int32_t n, const int64_t* __restrict__ prp,
                                 const uint32_t* __restrict__ ch, const double* __restrict__ invZ,
-                                ECoef ec, const double* __restrict__ A, double* __restrict__ P) {
+                                ECoef ec, const double* __restrict__ A,
+                                const double* __restrict__ Ex, double* __restrict__ P) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int64_t x = prp[i]; x < prp[i + 1]; ++x) P[x] = entry_p(i, ch[x], invZ, ec, A);
+    for (int64_t x = prp[i]; x < prp[i + 1]; ++x) P[x] = entry_p(i, x, ch[x], invZ, ec, A, Ex);
 }
 
 // P~ of the entries x0 .. x1-1 of row i (same operations as k_materialise_P)
 __global__ void k_materialise_row(int32_t i, int64_t x0, int64_t x1,
                                   const uint32_t* __restrict__ ch, const double* __restrict__ invZ,
-                                  ECoef ec, const double* __restrict__ A, double* __restrict__ P) {
+                                  ECoef ec, const double* __restrict__ A,
+                                  const double* __restrict__ Ex, double* __restrict__ P) {
     const int64_t x = x0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= x1) return;
-    P[x - x0] = entry_p(i, ch[x], invZ, ec, A);
+    P[x - x0] = entry_p(i, x, ch[x], invZ, ec, A, Ex);
 }
 
 static int pick_group(double mean_len) {
@@ -618,7 +771,7 @@ static void launch_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec) {
     const int grid = (int)std::min<int64_t>((groups * G + 255) / 256, 1 << 20);
     hipLaunchKernelGGL(k_row_weights<G>, dim3(std::max(grid, 1)), dim3(256), 0, ctx->stream, s->n,
                        s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, s->A.get(),
-                       s->W.get(), s->qt.get(), s->qtf.get());
+                       s->Ex.get(), s->W.get(), s->qt.get(), s->qtf.get());
     DRG_LAUNCH_CHECK();
 }
 
@@ -671,7 +824,7 @@ static void union_row_weights(drg_ctx* ctx, drg_sim* s, const ECoef& ec, UnionIn
 }
 
 drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, uint32_t flags,
-                          UnionInfo* u, double perplexity) {
+                          UnionInfo* u, double perplexity, const double* lengths) {
     if (!g) throw Error(DRG_E_INVALID, "graph is NULL");
     if (k < 1 || k > 4) throw Error(DRG_E_INVALID, "k must be in 1..4");
     const bool nodewise = perplexity != 0.0;
@@ -679,15 +832,28 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
         if (!(perplexity >= 1.0) || !(perplexity < 1e300))
             throw Error(DRG_E_INVALID, "perplexity must be >= 1 and finite");
         if (u) throw Error(DRG_E_UNSUPPORTED, "batched layout: one global sigma only");
+        if (lengths) throw Error(DRG_E_UNSUPPORTED, "node-wise sigma of a weighted graph");
         sigma = 1.0;  // not used
     }
+    if (lengths && u) throw Error(DRG_E_UNSUPPORTED, "batched layout: unweighted graphs only");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) throw Error(DRG_E_INVALID, "sigma must be > 0");
     if (g->n <= 0 || g->n >= (1 << 30)) throw Error(DRG_E_INVALID, "n must be in 1..2^30-1");
     if (g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col))
         throw Error(DRG_E_INVALID, "bad CSR pointers or nnz");
-    validate_csr_impl(ctx, g, (flags & DRG_VALIDATE) != 0);
+    // a weighted build looks up reverse entries: the structure is always checked
+    validate_csr_impl(ctx, g, lengths != nullptr || (flags & DRG_VALIDATE) != 0);
     hipStream_t st = ctx->stream;
     const int32_t n = g->n;
+    if (lengths && g->nnz > 0) {
+        DevBuf<int> bad(1);
+        DRG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
+        hipLaunchKernelGGL(k_check_lengths, dim3(ceil_div(n, 256)), dim3(256), 0, st, n,
+                           g->row_ptr, g->col, lengths, bad.get());
+        DRG_LAUNCH_CHECK();
+        const int f = read_flag(bad, st);
+        if (f & 32) throw Error(DRG_E_INVALID, "edge lengths must be positive and finite");
+        if (f & 64) throw Error(DRG_E_INVALID, "edge lengths are not symmetric");
+    }
     auto s = std::make_unique<drg_sim>();
     s->device = ctx->device;
     s->n = n;
@@ -786,7 +952,36 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     s->qtf.alloc(n);
     s->W.alloc(n);
     s->C.alloc((int64_t)n + 1);
-    if (nodewise) {
+    if (lengths) {
+        // GD by k Bellman-Ford rounds (ping-pong between two distance arrays),
+        // then E per entry and Z per row
+        const int64_t nnz = s->nnz;
+        s->Ex.alloc(std::max<int64_t>(nnz, 1));
+        if (nnz > 0) {
+            DevBuf<double> da(nnz), db(nnz);
+            hipLaunchKernelGGL(k_fill_inf, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz,
+                               da.get());
+            DRG_LAUNCH_CHECK();
+            const int grid = (int)std::max<int64_t>(
+                1, std::min<int64_t>(ceil_div((int64_t)n * WAVE, 256), (int64_t)ctx->num_cu * 32));
+            double* dp = da.get();
+            double* dc = db.get();
+            for (int r = 1; r <= k; ++r) {
+                hipLaunchKernelGGL(k_bf_round, dim3(grid), dim3(256), 0, st, n,
+                                   s->row_ptr.get(), s->colhop.get(), g->row_ptr, g->col,
+                                   lengths, dp, dc);
+                DRG_LAUNCH_CHECK();
+                std::swap(dp, dc);
+            }
+            hipLaunchKernelGGL(k_bf_finish, dim3(grid), dim3(256), 0, st, n, s->row_ptr.get(),
+                               s->colhop.get(), dp, 2.0 * sigma * sigma, s->Ex.get());
+            DRG_LAUNCH_CHECK();
+            DRG_HIP(hipStreamSynchronize(st));
+        }
+        hipLaunchKernelGGL(k_weighted_z, dim3(ceil_div(n, 256)), dim3(256), 0, st, n,
+                           s->row_ptr.get(), s->Ex.get(), s->invZ.get(), s->invZf.get(),
+                           s->invZlo.get());
+    } else if (nodewise) {
         s->A.alloc(4 * (int64_t)n);
         s->tnode.alloc(n);
         hipLaunchKernelGGL(k_calibrate, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, k,
@@ -828,8 +1023,9 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
                        n, s->C.get(), gbits, s->guide.get());
     DRG_LAUNCH_CHECK();
     DRG_HIP(hipStreamSynchronize(st));
-    // the column-blocked sweep carries one 1/Z per record: global sigma only
-    if (!nodewise && blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
+    // the column-blocked sweep carries one 1/Z per record and a hop per entry:
+    // unweighted graphs with one global sigma only
+    if (!nodewise && !lengths && blocked_wanted(ctx, s.get())) build_blocked(ctx, s.get());
     return s.release();
 }
 
@@ -873,7 +1069,7 @@ void sim_export_rows(const drg_sim* s, int32_t nrows, const int32_t* rows, int64
             DevBuf<double> dP(len);
             hipLaunchKernelGGL(k_materialise_row, dim3(ceil_div(len, 256)), dim3(256), 0, nullptr,
                                i, a[r], b[r], s->colhop.get(), s->invZ.get(), ec, s->A.get(),
-                               dP.get());
+                               s->Ex.get(), dP.get());
             DRG_LAUNCH_CHECK();
             DRG_HIP(hipMemcpy(P + o, dP.get(), sizeof(double) * len, hipMemcpyDeviceToHost));
         }
@@ -909,7 +1105,7 @@ void sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop, 
         for (int d = 0; d < 4; ++d) ec.e[d] = s->e[d];
         hipLaunchKernelGGL(k_materialise_P, dim3(ceil_div(n, 256)), dim3(256), 0, nullptr, n,
                            s->row_ptr.get(), s->colhop.get(), s->invZ.get(), ec, s->A.get(),
-                           dP.get());
+                           s->Ex.get(), dP.get());
         DRG_LAUNCH_CHECK();
         DRG_HIP(hipMemcpy(P, dP.get(), sizeof(double) * nnz, hipMemcpyDeviceToHost));
     }

@@ -111,6 +111,8 @@ def lib():
         "drg_build_similarity_perplexity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double,
                                              C.c_uint32, C.POINTER(_P)], st),
         "drg_sim_node_sigma": ([_P, _P], st),
+        "drg_build_similarity_weighted": ([_P, C.POINTER(Csr), _P, C.c_int32, C.c_double,
+                                           C.c_uint32, C.POINTER(_P)], st),
         "drg_build_similarity": ([_P, C.POINTER(Csr), C.c_int32, C.c_double, C.c_uint32,
                                   C.POINTER(_P)], st),
         "drg_sim_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -350,6 +352,20 @@ def drg_build_similarity_perplexity(ctx: Context, row_ptr, col, k: int, perplexi
     h = C.c_void_p()
     _check(lib().drg_build_similarity_perplexity(ctx.h, C.byref(g), int(k), float(perplexity),
                                                  DRG_VALIDATE if validate else 0, C.byref(h)))
+    return Similarity(h)
+
+
+def drg_build_similarity_weighted(ctx: Context, row_ptr, col, lengths, k: int,
+                                  sigma: float = 1.0) -> Similarity:
+    """P~ of a weighted graph: lengths = one positive length per CSR entry
+    (float64 device tensor, symmetric); GD = shortest path of at most k
+    edges (Eq. NS with weighted graph distances)."""
+    import torch
+    g = _csr(row_ptr, col)
+    lp = _dev(lengths, torch.float64, "lengths", (int(col.numel()),))
+    h = C.c_void_p()
+    _check(lib().drg_build_similarity_weighted(ctx.h, C.byref(g), lp, int(k), float(sigma), 0,
+                                               C.byref(h)))
     return Similarity(h)
 
 

@@ -1,8 +1,9 @@
 """Seeded synthetic input graphs.
 
-This module only makes inputs: undirected, unweighted graphs in canonical CSR
+This module only makes inputs: undirected graphs in canonical CSR
 form (symmetric, rows sorted ascending, no self-loops, no duplicate edges),
-which is the input the layout method takes (Sec. 3.1, problem statement).
+which is the input the layout method takes (Sec. 3.1, problem statement),
+and edge lengths for weighted variants of them.
 It holds none of the layout method's arithmetic, so both the GPU library's
 tests and the CPU oracle's tests can draw their inputs from it.
 
@@ -215,6 +216,20 @@ def random_graph(n: int, p: float, seed: int = 0, sub: int = 0) -> CSR:
     iu, ju = np.triu_indices(n, 1)
     keep = rng.random(iu.size) < p
     return canonical_csr(n, iu[keep], ju[keep], f"er{n}")
+
+
+_TAG_LENGTHS = 17
+
+
+def edge_lengths(g: CSR, seed: int = 0, lo: float = 0.2, hi: float = 3.0) -> np.ndarray:
+    """Edge lengths for a weighted variant of g: one float64 per CSR entry,
+    uniform in [lo, hi), equal for (u, v) and (v, u)."""
+    rng = _rng(seed, _TAG_LENGTHS)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    a = np.minimum(rows, g.col.astype(np.int64))
+    b = np.maximum(rows, g.col.astype(np.int64))
+    uniq, inv = np.unique(a * g.n + b, return_inverse=True)
+    return rng.uniform(lo, hi, size=len(uniq))[inv]
 
 
 def named(config: str, seed: int = 0) -> CSR:

@@ -11,14 +11,7 @@ from paper_2008_07799_amd import gen
 
 
 def _lengths(g, seed, lo=0.2, hi=3.0):
-    """Symmetric random lengths, one per CSR entry."""
-    rng = np.random.default_rng(seed)
-    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
-    a = np.minimum(rows, g.col).astype(np.int64)
-    b = np.maximum(rows, g.col).astype(np.int64)
-    key = a * g.n + b
-    uniq, inv = np.unique(key, return_inverse=True)
-    return rng.uniform(lo, hi, size=len(uniq))[inv]
+    return gen.edge_lengths(g, seed, lo, hi)
 
 
 def _brute(g, ln, k, i):
