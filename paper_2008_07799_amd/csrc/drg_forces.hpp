@@ -151,24 +151,26 @@ struct HalfE {
     }
 };
 
-// Pair weight P~_ij of pattern entry x.  Node-wise sigma: (A_i[d] +
-// A_j[d]) / 2 from the table A [n][4] (A_i[d] = NS_{j|i} at hop d+1; ai holds
-// row i's four values).  Weighted graph: E_x (1/Z_i + 1/Z_j) / 2 with E per
-// entry.  Otherwise one global sigma: e_d/2 (1/Z_i + 1/Z_j) from the records.
+// Pair weight P~_ij of pattern entry x, by form WM (a compile-time choice,
+// so the default form carries no per-pair branch):
+//   PW_HOP   one global sigma: e_d/2 (1/Z_i + 1/Z_j) from the records;
+//   PW_NODE  node-wise sigma: (A_i[d] + A_j[d]) / 2 from the table A [n][4]
+//            (A_i[d] = NS_{j|i} at hop d+1; Ai = A + 4 i);
+//   PW_ENTRY weighted graph: E_x/2 (1/Z_i + 1/Z_j) with E per entry.
+constexpr int PW_HOP = 0, PW_NODE = 1, PW_ENTRY = 2;
 struct PairW {
-    const double* A = nullptr;
-    const double* Ex = nullptr;
-    HalfE<double> ai{0.0, 0.0, 0.0, 0.0};
+    const double* A = nullptr;   // the node table (PW_NODE)
+    const double* Ai = nullptr;  // row i's four values (PW_NODE)
+    const double* Ex = nullptr;  // per-entry E (PW_ENTRY)
 };
 __device__ __forceinline__ PairW pair_w(const double* __restrict__ A,
                                         const double* __restrict__ Ex, int64_t i) {
     PairW p;
     p.A = A;
+    p.Ai = A ? A + 4 * i : nullptr;
     p.Ex = Ex;
-    if (A) p.ai = HalfE<double>{A[4 * i], A[4 * i + 1], A[4 * i + 2], A[4 * i + 3]};
     return p;
 }
-
 // Attraction of one pattern entry e (record rj) on the node with record ri,
 // added to the lane's partial (ax, ay).  Records hold (x, y, 1/Z high part,
 // 1/Z low part) in the coordinate type T; the pair's arithmetic and the
@@ -180,7 +182,7 @@ __device__ __forceinline__ PairW pair_w(const double* __restrict__ A,
 // the partial's value unchanged.  CLIP = false when the clip cannot bind
 // (|k dx| stays below it for every offset): the clamp would return its
 // argument, so it is left out and the weight is folded into k first.
-template <typename T, int B, bool CLIP = true>
+template <typename T, int B, bool CLIP = true, int WM = PW_HOP>
 __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint32_t e,
                                              const typename VT<T>::v4& rj, const HalfE<double>& eh,
                                              double clip, bool half, double& ax, double& ay,
@@ -189,11 +191,14 @@ __device__ __forceinline__ void attract_pair(const typename VT<T>::v4& ri, uint3
     const double d2 = dx * dx + dy * dy;
     const double k = attract_coef_b<B, double>(d2, half);
     double w;
-    if (pw.A) {
-        w = (pw.ai(e >> 30) + pw.A[4 * (int64_t)(e & COL_MASK) + (e >> 30)]) * 0.5;
+    if constexpr (WM == PW_NODE) {
+        w = (pw.Ai[e >> 30] + pw.A[4 * (int64_t)(e & COL_MASK) + (e >> 30)]) * 0.5;
     } else {
         const double zi = (double)ri.z + (double)ri.w, zj = (double)rj.z + (double)rj.w;
-        w = (pw.Ex ? 0.5 * pw.Ex[x] : eh(e >> 30)) * (zi + zj);
+        if constexpr (WM == PW_ENTRY)
+            w = (0.5 * pw.Ex[x]) * (zi + zj);
+        else
+            w = eh(e >> 30) * (zi + zj);
     }
     if constexpr (CLIP) {
         ax += w * clampT2(k * dx, clip);
@@ -245,7 +250,7 @@ __device__ __forceinline__ typename VT<T>::v2 row_total(double ax, double ay, do
 // the group.  Returns g_i (valid in every lane) = attraction + gq *
 // repulsion, where `key` is the node's own id for the negative words and
 // draw(w) turns a word into the record index of the drawn node.
-template <typename T, int B, bool CLIP, typename Draw>
+template <typename T, int B, bool CLIP, int WM = PW_HOP, typename Draw>
 __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
     const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
@@ -254,8 +259,11 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     using v4 = typename VT<T>::v4;
     double ax = 0.0, ay = 0.0;
     // U entries per step; the next step's entries are loaded while this
-    // step's records are gathered and used (the terms still go in order)
-    constexpr int U = 4;
+    // step's records are gathered and used (the terms still go in order).
+    // Two, not four: with FP64 pair terms four in flight need 92 VGPRs (5
+    // waves per SIMD) against 72 (7 waves), and the row form is bound by the
+    // latency of its gathers (R-MAT 2^20 at k = 1: 1.04 vs 1.15 ms per sweep)
+    constexpr int U = 2;
     const int64_t step = (int64_t)U * G;
     int64_t x = rs + lane;
     uint32_t e[U];
@@ -277,8 +285,8 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
         for (int q = 0; q < U; ++q) en[q] = colhop[max(xl + (int64_t)q * G, x)];
 #pragma unroll
         for (int q = 0; q < U; ++q)
-            attract_pair<T, B, CLIP>(ri, e[q], rj[q], eh, clip, half, ax, ay, pw,
-                                     x + (int64_t)q * G);
+            attract_pair<T, B, CLIP, WM>(ri, e[q], rj[q], eh, clip, half, ax, ay, pw,
+                                         x + (int64_t)q * G);
 #pragma unroll
         for (int q = 0; q < U; ++q) e[q] = en[q];
         x = xn;
@@ -286,7 +294,7 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     }
     for (; x < re; x += G) {
         const uint32_t e = colhop[x];
-        attract_pair<T, B, CLIP>(ri, e, rec[e & COL_MASK], eh, clip, half, ax, ay, pw, x);
+        attract_pair<T, B, CLIP, WM>(ri, e, rec[e & COL_MASK], eh, clip, half, ax, ay, pw, x);
     }
     double rx, ry;
     repel_lane<T, B>(ri, rec, lane, G, M, seed, iter, key, draw, clip, half, rx, ry);

@@ -87,7 +87,9 @@ __device__ __forceinline__ T half_e(const SweepArgs<T>& a, uint32_t h) {
     return (T)(h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3)));
 }
 
-template <typename T, int B, int G>
+// WM: the pair-weight form (PW_HOP, PW_NODE, PW_ENTRY), one kernel each so
+// that the common form keeps its register budget
+template <typename T, int B, int G, int WM>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
     const int lane = threadIdx.x % G;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
@@ -99,17 +101,20 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
             const int64_t rs = a.prp[i], re = a.prp[i + 1];
             typename VT<T>::v2 gi = mk2<T>(T(0), T(0));
             if (rs < re)
-                gi = sweep_row<T, B, CLIP>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh,
-                                           (double)a.clip, a.half != 0,
-                                           a.M, a.seed, a.iter, (int32_t)i,
-                                           [&](uint64_t w) {
-                                               return draw_node(w, a.C, a.guide, a.gbits, a.S);
-                                           },
-                                           (double)a.gamma * (double)a.qt[i], pair_w(a.A, a.Ex, i));
+                gi = sweep_row<T, B, CLIP, WM>(a.rec[i], rs, re, lane, G, a.colhop, a.rec, eh,
+                                               (double)a.clip, a.half != 0,
+                                               a.M, a.seed, a.iter, (int32_t)i,
+                                               [&](uint64_t w) {
+                                                   return draw_node(w, a.C, a.guide, a.gbits,
+                                                                    a.S);
+                                               },
+                                               (double)a.gamma * (double)a.qt[i],
+                                               pair_w(a.A, a.Ex, i));
             if (lane == 0) a.g[i] = gi;
         }
     };
-    if (a.noclip)
+    // the node-wise and per-entry weights run with the clamp in place
+    if (WM == PW_HOP && a.noclip)
         rows(std::false_type{});
     else
         rows(std::true_type{});
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
                 const float k = attract_coef_b<B, float>(d2, a.half != 0);
-                const float w = pw.A ? (float)((pw.ai(e >> 30) + pw.A[4 * j + (e >> 30)]) * 0.5)
+                const float w = pw.A ? (float)((pw.Ai[e >> 30] + pw.A[4 * j + (e >> 30)]) * 0.5)
                                 : (pw.Ex ? (float)(0.5 * pw.Ex[x]) : half_e(a, e >> 30)) *
                                       (zi + a.invZ[j]);
                 ax += w * clampT2(k * dx, a.clip);
@@ -276,7 +281,15 @@ static void launch_one(hipStream_t st, const SweepArgs<T>& a, bool async) {
             return;
         }
     }
-    hipLaunchKernelGGL((k_sweep<T, B, G>), dim3(grid), dim3(256), 0, st, a);
+    switch (a.A ? PW_NODE : (a.Ex ? PW_ENTRY : PW_HOP)) {
+        case PW_NODE:
+            hipLaunchKernelGGL((k_sweep<T, B, G, PW_NODE>), dim3(grid), dim3(256), 0, st, a);
+            break;
+        case PW_ENTRY:
+            hipLaunchKernelGGL((k_sweep<T, B, G, PW_ENTRY>), dim3(grid), dim3(256), 0, st, a);
+            break;
+        default: hipLaunchKernelGGL((k_sweep<T, B, G, PW_HOP>), dim3(grid), dim3(256), 0, st, a);
+    }
     DRG_LAUNCH_CHECK();
 }
 

@@ -78,7 +78,7 @@ __device__ __forceinline__ Sum3 sweep_row3(const typename VT<T>::v4& ri, double 
         const double k = attract_coef_b<B, double>(d2, half);
         double w;
         if (pw.A) {
-            w = (pw.ai(e >> 30) + pw.A[4 * (int64_t)j + (e >> 30)]) * 0.5;
+            w = (pw.Ai[e >> 30] + pw.A[4 * (int64_t)j + (e >> 30)]) * 0.5;
         } else {
             const double zj = (double)rj.w + (lo ? (double)lo[j] : 0.0);
             w = (pw.Ex ? 0.5 * pw.Ex[x] : eh(e >> 30)) * (zi + zj);
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_sweep3_async(Sweep3Args<float> a) {
                 const float k = attract_coef_b<B, float>(d2, a.half != 0);
                 const uint32_t h = e >> 30;
                 const float eh = (float)(h == 0 ? a.eh0 : (h == 1 ? a.eh1 : (h == 2 ? a.eh2 : a.eh3)));
-                const float w = pw.A ? (float)((pw.ai(h) + pw.A[4 * (int64_t)j + h]) * 0.5)
+                const float w = pw.A ? (float)((pw.Ai[h] + pw.A[4 * (int64_t)j + h]) * 0.5)
                                      : (pw.Ex ? (float)(0.5 * pw.Ex[x]) : eh) * (zi + a.invZ[j]);
                 const float c = (float)a.clip;
                 ax += w * clampT2(k * dx, c);
