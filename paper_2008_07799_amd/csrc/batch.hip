@@ -232,7 +232,8 @@ struct BSweepArgs {
 template <int B, bool CLIP>
 __device__ __forceinline__ float2 b_row(const BSweepArgs& a, const BGraph& g, int64_t i,
                                         int32_t v, int lane, float gamma) {
-    return sweep_row<float, B, CLIP>(a.rec[i], a.prp[i], a.prp[i + 1], lane, g.G, a.colhop, a.rec, a.eh,
+    return sweep_row<float, B, CLIP>(a.rec[i], a.prp[i], a.prp[i + 1], lane, g.G, a.colhop,
+                               a.rec, a.eh,
                                g.clip, false, g.M, g.seed, (uint64_t)a.t, v,
                                [&](uint64_t w) {
                                    return g.base + draw_in_graph(w, a.C, a.guide, g);

@@ -250,7 +250,7 @@ __device__ __forceinline__ typename VT<T>::v2 row_total(double ax, double ay, do
 // the group.  Returns g_i (valid in every lane) = attraction + gq *
 // repulsion, where `key` is the node's own id for the negative words and
 // draw(w) turns a word into the record index of the drawn node.
-template <typename T, int B, bool CLIP, int WM = PW_HOP, typename Draw>
+template <typename T, int B, bool CLIP, int WM = PW_HOP, int U = 2, typename Draw>
 __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     const typename VT<T>::v4& ri, int64_t rs, int64_t re, int lane, int G,
     const uint32_t* __restrict__ colhop, const typename VT<T>::v4* __restrict__ rec,
@@ -259,11 +259,12 @@ __device__ __forceinline__ typename VT<T>::v2 sweep_row(
     using v4 = typename VT<T>::v4;
     double ax = 0.0, ay = 0.0;
     // U entries per step; the next step's entries are loaded while this
-    // step's records are gathered and used (the terms still go in order).
-    // Two, not four: with FP64 pair terms four in flight need 92 VGPRs (5
-    // waves per SIMD) against 72 (7 waves), and the row form is bound by the
-    // latency of its gathers (R-MAT 2^20 at k = 1: 1.04 vs 1.15 ms per sweep)
-    constexpr int U = 2;
+    // step's records are gathered and used (the terms still go in order, so
+    // U does not change the result).  Two by default: with FP64 pair terms
+    // four in flight need 92-96 VGPRs (5 waves per SIMD) against 70-72 (7
+    // waves), and the more waves hide the gathers better (R-MAT 2^20 at
+    // k = 1: 1.04 vs 1.15 ms per sweep; the 512-graph batch's row sweep 1.46
+    // vs 1.65 ms per iteration).
     const int64_t step = (int64_t)U * G;
     int64_t x = rs + lane;
     uint32_t e[U];
