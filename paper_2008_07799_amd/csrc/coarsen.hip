@@ -9,12 +9,12 @@
 // local decisions over all nodes in parallel: a node becomes a centre once all
 // its higher-priority neighbours are decided non-centres, and a member once
 // any of them is a centre.  Coarse ids are the centres ranked by node id.
-// The coarse graph keeps one edge between two groups joined by a fine edge;
-// it is built like a BFS row: the fine neighbours of all members, mapped to
-// their group, are collected in a bitmap and emitted in ascending order.
+// The coarse graph keeps one edge between two groups joined by a fine edge:
+// every fine edge becomes the pair (group of u, group of v), the pairs are
+// sorted and the first of each run of equal pairs is kept, so every coarse
+// row comes out ascending and free of duplicates.
 #include <memory>
 
-#include "drg_bitmap.hpp"
 #include "drg_internal.hpp"
 
 namespace drg {
@@ -57,29 +57,68 @@ __global__ void k_mis_round(int32_t n, const int32_t* __restrict__ rp,
         *undecided = 1;
 }
 
-__global__ void k_owner(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                        const uint64_t* __restrict__ pri, const int32_t* __restrict__ state,
-                        int32_t* __restrict__ owner, int32_t* __restrict__ is_centre) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    if (state[v] == 1) {
-        owner[v] = (int32_t)v;
-        is_centre[v] = 1;
-        return;
+// the better of two owner candidates (b = -1: none)
+__device__ __forceinline__ void owner_better(uint64_t& pb, int32_t& b, uint64_t pu, int32_t u) {
+    if (u >= 0 && (b < 0 || outranks(pu, u, pb, b))) {
+        b = u;
+        pb = pu;
     }
+}
+
+// Every non-centre joins the highest-priority centre among its neighbours
+// (-1 if none).  One lane per node; a node with more than OWNER_SEQ
+// neighbours (an R-MAT hub) is scanned by the whole wave, lane l taking
+// neighbours l, l+64, ..., then a butterfly of the candidates: the order of
+// a maximum does not change it.
+constexpr int OWNER_SEQ = 64;
+
+__global__ __launch_bounds__(256) void k_owner(int32_t n, const int32_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col,
+                                               const uint64_t* __restrict__ pri,
+                                               const int32_t* __restrict__ state,
+                                               int32_t* __restrict__ owner,
+                                               int32_t* __restrict__ is_centre) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = v < n;
+    if (__ballot(valid) == 0) return;  // the whole wave leaves
+    const int lane = __lane_id();
+    const int32_t rs = valid ? rp[v] : 0, re = valid ? rp[v + 1] : 0;
+    const bool centre = valid && state[v] == 1;
+    const bool big = valid && !centre && re - rs > OWNER_SEQ;
     int32_t best = -1;
     uint64_t pb = 0;
-    for (int32_t x = rp[v]; x < rp[v + 1]; ++x) {
-        const int32_t u = col[x];
-        if (state[u] != 1) continue;
-        const uint64_t pu = pri[u];
-        if (best < 0 || outranks(pu, u, pb, best)) {
-            best = u;
-            pb = pu;
+    if (valid && !centre && !big) {
+        for (int32_t x = rs; x < re; ++x) {
+            const int32_t u = col[x];
+            if (state[u] == 1) owner_better(pb, best, pri[u], u);
         }
     }
-    owner[v] = best;
-    is_centre[v] = 0;
+    uint64_t m = __ballot(big);
+    while (m) {
+        const int src = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int32_t b0 = __builtin_amdgcn_readlane(rs, src);
+        const int32_t b1 = __builtin_amdgcn_readlane(re, src);
+        int32_t wb = -1;
+        uint64_t wp = 0;
+        for (int32_t x = b0 + lane; x < b1; x += WAVE) {
+            const int32_t u = col[x];
+            if (state[u] == 1) owner_better(wp, wb, pri[u], u);
+        }
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+            const uint32_t lo = __shfl_xor((uint32_t)wp, off);
+            const uint32_t hi = __shfl_xor((uint32_t)(wp >> 32), off);
+            const int32_t ob = __shfl_xor(wb, off);
+            owner_better(wp, wb, ((uint64_t)hi << 32) | lo, ob);
+        }
+        if (lane == src) {
+            best = wb;
+            pb = wp;
+        }
+    }
+    if (!valid) return;
+    owner[v] = centre ? (int32_t)v : best;
+    is_centre[v] = centre ? 1 : 0;
 }
 
 __global__ void k_map(int32_t n, const int32_t* __restrict__ owner, const int32_t* __restrict__ rank,
@@ -118,81 +157,44 @@ __global__ void k_compose(int32_t n0, const int32_t* __restrict__ prev,
     if (i < n0) out[i] = map[prev[i]];
 }
 
-constexpr int CT_BLOCK = 256;
-constexpr int CT_WPT = 8;
-
-struct ContractArgs {
-    int32_t nc, nwords;
-    const int32_t* rp;
-    const int32_t* col;
-    const int32_t* map;
-    const int32_t* perm;   // fine nodes grouped by coarse node
-    const int32_t* seg;    // [nc+1]
-    int32_t* cnt;          // count pass: [nc]
-    const int32_t* crp;    // fill pass: [nc+1]
-    int32_t* ccol;         // fill pass
-    uint32_t* gbm;
-    int32_t* work;
-    const int32_t* node_base;  // per coarse node: first coarse id of its graph (NULL: 0)
-};
-
-template <bool FILL, bool LDS_BM, int G>
-__global__ __launch_bounds__(CT_BLOCK) void k_contract(ContractArgs a) {
-    extern __shared__ uint32_t s_bm[];
-    __shared__ int32_t s_c;
-    __shared__ int32_t s_red[CT_BLOCK / WAVE];
-    uint32_t* bm = LDS_BM ? s_bm : a.gbm + (size_t)blockIdx.x * (size_t)a.nwords;
-    const int tid = threadIdx.x;
-    for (int w = tid; w < a.nwords; w += CT_BLOCK) bm[w] = 0;
-    __syncthreads();
-    for (;;) {
-        if (tid == 0) s_c = atomicAdd(a.work, 1);
-        __syncthreads();
-        const int32_t c = s_c;
-        if (c >= a.nc) break;
-        // bitmap bit of coarse node t is t - cb: a group only reaches its own graph
-        const int32_t cb = a.node_base ? a.node_base[c] : 0;
-        const int32_t mb = a.seg[c], me = a.seg[c + 1];
-        for (int32_t fi = tid / G; fi < me - mb; fi += CT_BLOCK / G) {
-            const int32_t u = a.perm[mb + fi];
-            for (int32_t x = a.rp[u] + (tid % G); x < a.rp[u + 1]; x += G) {
-                const int32_t t = a.map[a.col[x]];
-                if (t != c) atomicOr(&bm[(t - cb) >> 5], 1u << ((t - cb) & 31));
-            }
+// (group of u, group of v) of every fine edge, one wave per fine row; a pair
+// inside one group gets c = nc, which sorts after every kept pair
+__global__ __launch_bounds__(256) void k_edge_pairs(int32_t n, int32_t nc,
+                                                    const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ map,
+                                                    uint32_t* __restrict__ t_out,
+                                                    int32_t* __restrict__ c_out) {
+    const int lane = __lane_id();
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
+    for (int64_t u = w0; u < n; u += nw) {
+        const int32_t c = map[u];
+        for (int32_t x = rp[u] + lane; x < rp[u + 1]; x += WAVE) {
+            const int32_t t = map[col[x]];
+            const bool self = t == c;
+            t_out[x] = self ? 0u : (uint32_t)t;
+            c_out[x] = self ? nc : c;
         }
-        __syncthreads();
-        if constexpr (!FILL) {
-            const int total = bitmap_count_clear<CT_BLOCK>(bm, a.nwords, s_red);
-            if (tid == 0) a.cnt[c] = total;
-        } else {
-            int32_t* out = a.ccol;
-            bitmap_emit_clear<CT_BLOCK, CT_WPT>(
-                bm, a.nwords, -1, (int64_t)a.crp[c], s_red,
-                [&](int64_t o, uint32_t v) { out[o] = cb + (int32_t)v; });
-        }
-        __syncthreads();
     }
 }
 
-template <bool FILL, bool LDS_BM>
-static void launch_contract(drg_ctx* ctx, const ContractArgs& a, int G, int grid, size_t lds) {
-#define DRG_CT_CASE(GG)                                                                         \
-    case GG: {                                                                                  \
-        auto fn = k_contract<FILL, LDS_BM, GG>;                                                 \
-        if (LDS_BM)                                                                             \
-            DRG_HIP(hipFuncSetAttribute((const void*)fn,                                        \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(CT_BLOCK), LDS_BM ? lds : 0, ctx->stream, a);   \
-        break;                                                                                  \
-    }
-    switch (G) {
-        DRG_CT_CASE(4)
-        DRG_CT_CASE(16)
-        default:
-        DRG_CT_CASE(64)
-    }
-#undef DRG_CT_CASE
-    DRG_LAUNCH_CHECK();
+// head[x] = 1 for the first of each run of equal (c, t) pairs with c < nc
+__global__ void k_pair_heads(int64_t m, int32_t nc, const uint32_t* __restrict__ c,
+                             const int32_t* __restrict__ t, int32_t* __restrict__ head) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= m) return;
+    head[x] = (c[x] < (uint32_t)nc && (x == 0 || c[x] != c[x - 1] || t[x] != t[x - 1])) ? 1 : 0;
+}
+
+__global__ void k_pair_emit(int64_t m, const uint32_t* __restrict__ c,
+                            const int32_t* __restrict__ t, const int32_t* __restrict__ head,
+                            const int32_t* __restrict__ pos, uint32_t* __restrict__ ck,
+                            int32_t* __restrict__ ccol) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= m || !head[x]) return;
+    ck[pos[x]] = c[x];
+    ccol[pos[x]] = t[x];
 }
 
 static int key_bits_for(int64_t nc) {
@@ -241,16 +243,12 @@ __global__ void k_prio_union(int32_t n, const int32_t* __restrict__ gid,
                  .w[0];
 }
 
-// Graph and coarse base of every coarse node, from its first member.
-__global__ void k_coarse_owner(int32_t nc, const int32_t* __restrict__ seg,
-                               const int32_t* __restrict__ perm, const int32_t* __restrict__ gid,
-                               const int32_t* __restrict__ cbase, int32_t* __restrict__ cgid,
-                               int32_t* __restrict__ cnb) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= nc) return;
-    const int32_t c = gid[perm[seg[u]]];
-    cgid[u] = c;
-    cnb[u] = cbase[c];
+// graph of every coarse node: all members of a group belong to one graph,
+// so every member writes the same value
+__global__ void k_coarse_gid(int32_t n, const int32_t* __restrict__ map,
+                             const int32_t* __restrict__ gid, int32_t* __restrict__ cgid) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) cgid[map[v]] = gid[v];
 }
 
 __global__ void k_gather_i32(int32_t m, const int32_t* __restrict__ at,
@@ -307,11 +305,6 @@ static void coarsen_one(drg_ctx* ctx, int32_t n, const int32_t* rp, const int32_
     hipLaunchKernelGGL(k_map, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, owner.get(),
                        rank.get(), out.map.get());
     DRG_LAUNCH_CHECK();
-    // members of each coarse node, then the contracted adjacency
-    DevBuf<int32_t> perm(n), seg((int64_t)nc + 1), cnt(nc);
-    group_by(ctx, n, nc, out.map.get(), perm.get(), seg.get());
-    int32_t span = nc;
-    DevBuf<int32_t> cnb;
     if (u) {
         // coarse base of every member graph = rank of its first node
         const int32_t m = (int32_t)u->members.size();
@@ -333,67 +326,55 @@ static void coarsen_one(drg_ctx* ctx, int32_t n, const int32_t* rp, const int32_
         const int32_t count = (int32_t)u->hbase.size();
         u->cbase.assign(count, -1);
         u->cn.assign(count, 0);
-        span = 1;
         for (int32_t i = 0; i < m; ++i) {
             const int32_t c = u->members[i];
             u->cbase[c] = hv[2 * i];
             u->cn[c] = hv[2 * i + 1] - hv[2 * i];
-            span = std::max(span, u->cn[c]);
         }
-        DevBuf<int32_t> dcb;
-        to_dev(dcb, u->cbase, st);
         u->cgid.alloc(nc);
-        cnb.alloc(nc);
-        if (nc > 0) {
-            hipLaunchKernelGGL(k_coarse_owner, dim3(ceil_div(nc, 256)), dim3(256), 0, st, nc,
-                               seg.get(), perm.get(), u->gid, dcb.get(), u->cgid.get(),
-                               cnb.get());
-            DRG_LAUNCH_CHECK();
-        }
-        DRG_HIP(hipStreamSynchronize(st));
+        hipLaunchKernelGGL(k_coarse_gid, dim3(ceil_div(n, 256)), dim3(256), 0, st, n,
+                           out.map.get(), u->gid, u->cgid.get());
+        DRG_LAUNCH_CHECK();
     }
-    const int nwords = (span + 31) / 32;
-    const size_t lds = (size_t)nwords * 4;
-    const bool in_lds = lds + 256 <= (size_t)ctx->max_lds;
-    int per_cu = in_lds ? std::max(1, (int)(ctx->max_lds / (lds + 256))) : 4;
-    per_cu = std::min(per_cu, 8);
-    const int grid = std::max(1, std::min<int>(ctx->num_cu * per_cu, nc));
-    DevBuf<uint32_t> gbm;
-    if (!in_lds) gbm.alloc((int64_t)grid * nwords);
-    DevBuf<int32_t> work(1);
-    const double mean_deg = n > 0 ? (double)nnz / n : 1.0;
-    const int G = mean_deg <= 6 ? 4 : (mean_deg <= 24 ? 16 : 64);
-    ContractArgs a{};
-    a.nc = nc;
-    a.nwords = nwords;
-    a.rp = rp;
-    a.col = col;
-    a.map = out.map.get();
-    a.perm = perm.get();
-    a.seg = seg.get();
-    a.cnt = cnt.get();
-    a.gbm = gbm.get();
-    a.work = work.get();
-    a.node_base = u ? cnb.get() : nullptr;
-    DRG_HIP(hipMemsetAsync(work.get(), 0, sizeof(int32_t), st));
-    if (in_lds)
-        launch_contract<false, true>(ctx, a, G, grid, lds);
-    else
-        launch_contract<false, false>(ctx, a, G, grid, 0);
+    // the contracted adjacency: (c, t) pairs of all fine edges, sorted by t
+    // then (stably) by c, the first of each run kept
     out.rp.alloc((int64_t)nc + 1);
-    exclusive_scan<int32_t>(cnt.get(), out.rp.get(), nc, st);
-    int32_t cnnz = 0;
-    DRG_HIP(hipMemcpyAsync(&cnnz, out.rp.get() + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    DRG_HIP(hipStreamSynchronize(st));
-    out.nnz = cnnz;
-    out.col.alloc(cnnz);
-    a.crp = out.rp.get();
-    a.ccol = out.col.get();
-    DRG_HIP(hipMemsetAsync(work.get(), 0, sizeof(int32_t), st));
-    if (in_lds)
-        launch_contract<true, true>(ctx, a, G, grid, lds);
-    else
-        launch_contract<true, false>(ctx, a, G, grid, 0);
+    DevBuf<uint32_t> tk(std::max<int64_t>(nnz, 1));
+    DevBuf<int32_t> cv(std::max<int64_t>(nnz, 1));
+    if (nnz > 0) {
+        const int grid = (int)std::max<int64_t>(
+            1, std::min<int64_t>(ceil_div((int64_t)n * WAVE, 256), (int64_t)ctx->num_cu * 32));
+        hipLaunchKernelGGL(k_edge_pairs, dim3(grid), dim3(256), 0, st, n, nc, rp, col,
+                           out.map.get(), tk.get(), cv.get());
+        DRG_LAUNCH_CHECK();
+        radix_sort_pairs(tk.get(), cv.get(), nnz, key_bits_for(nc), st);
+        // now sort by c: keys and values swap roles
+        uint32_t* ck = reinterpret_cast<uint32_t*>(cv.get());
+        int32_t* tv = reinterpret_cast<int32_t*>(tk.get());
+        radix_sort_pairs(ck, tv, nnz, key_bits_for((int64_t)nc + 1), st);
+        DevBuf<int32_t> head(nnz), pos(nnz + 1);
+        hipLaunchKernelGGL(k_pair_heads, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, nc, ck,
+                           tv, head.get());
+        DRG_LAUNCH_CHECK();
+        exclusive_scan<int32_t>(head.get(), pos.get(), nnz, st);
+        int32_t cnnz = 0;
+        DRG_HIP(hipMemcpyAsync(&cnnz, pos.get() + nnz, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               st));
+        DRG_HIP(hipStreamSynchronize(st));
+        out.nnz = cnnz;
+        out.col.alloc(std::max(cnnz, 1));
+        DevBuf<uint32_t> crow(std::max(cnnz, 1));
+        hipLaunchKernelGGL(k_pair_emit, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, ck, tv,
+                           head.get(), pos.get(), crow.get(), out.col.get());
+        DRG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_seg_bounds, dim3(ceil_div((int64_t)nc + 1, 256)), dim3(256), 0, st,
+                           cnnz, nc, crow.get(), out.rp.get());
+        DRG_LAUNCH_CHECK();
+    } else {
+        out.nnz = 0;
+        out.col.alloc(1);
+        DRG_HIP(hipMemsetAsync(out.rp.get(), 0, sizeof(int32_t) * ((int64_t)nc + 1), st));
+    }
     DRG_HIP(hipStreamSynchronize(st));
     out.n_active = (int32_t)count_nonempty_rows<int32_t>(out.rp.get(), nc, st);
 }
