@@ -626,7 +626,30 @@ __device__ __forceinline__ void row_weights_row(int64_t i, int lane, int G,
     const double izi = invZ[i];
     unsigned long long ws = 0;
     double qs = 0.0;
-    for (int64_t x = prp[i] + lane; x < prp[i + 1]; x += G) {
+    int64_t x = prp[i] + lane;
+    const int64_t re = prp[i + 1];
+    if (!A && !Ex) {
+        // one global sigma: four entries' loads and gathers in flight, the
+        // terms still added in entry order
+        constexpr int U = 4;
+        for (; x + (int64_t)(U - 1) * G < re; x += (int64_t)U * G) {
+            uint32_t e[U];
+            double zj[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) e[q] = ch[x + (int64_t)q * G];
+#pragma unroll
+            for (int q = 0; q < U; ++q) zj[q] = invZ[e[q] & COL_MASK];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const double s = izi + zj[q];
+                const double t = pick_e(ec.e, e[q] >> 30) * s;
+                const double p = t * 0.5;
+                ws += (unsigned long long)(p * 4294967296.0);
+                qs = qs + p;
+            }
+        }
+    }
+    for (; x < re; x += G) {
         const uint32_t e = ch[x];
         double p;
         if (A) {
