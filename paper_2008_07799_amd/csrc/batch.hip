@@ -632,13 +632,18 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
     b->sim.reset(build_similarity(ctx, &uc, params[0].k, params[0].sigma, 0, &ui));
     drg_sim* s = b->sim.get();
     b->nnz_total = s->nnz;
-    // per-graph active rows and sampling totals
+    // per-graph active rows, row-length statistics and sampling totals
     std::vector<int32_t> nact(count, 0);
     std::vector<uint64_t> Cb(count + 1, 0);
+    std::vector<unsigned long long> len2(count, 0);  // sum of squared row lengths
     {
         DevBuf<int32_t> cnt(count);
+        DevBuf<unsigned long long> l2(count);
         count_nonempty_by_group<int64_t>(s->row_ptr.get(), b->gid.get(), N, cnt.get(), count, st);
+        sum_len2_by_group(s->row_ptr.get(), b->gid.get(), N, l2.get(), count, st);
         DRG_HIP(hipMemcpyAsync(nact.data(), cnt.get(), sizeof(int32_t) * count,
+                               hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipMemcpyAsync(len2.data(), l2.get(), sizeof(unsigned long long) * count,
                                hipMemcpyDeviceToHost, st));
         for (int32_t c = 0; c <= count; ++c)
             DRG_HIP(hipMemcpyAsync(&Cb[c], s->C.get() + nbase[c], sizeof(uint64_t),
@@ -660,7 +665,8 @@ drg_batch* batch_create(drg_ctx* ctx, const drg_csr* graphs, int32_t count,
         BGraph& g = gt[c];
         g.base = nbase[c];
         g.n = n;
-        g.G = sweep_group((double)ui.nnz[c] / (double)std::max(1, nact[c]));
+        // the lanes per row of the graph's own single-graph sweep
+        g.G = sweep_group(ui.nnz[c] > 0 ? (double)len2[c] / (double)ui.nnz[c] : 0.0, nact[c]);
         g.blk = blocked_wanted_for(ctx, n, ui.nnz[c]) ? 1 : 0;
         g.b = p.b;
         g.S = Cb[c + 1] - Cb[c];

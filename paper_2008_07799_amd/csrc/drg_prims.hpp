@@ -81,6 +81,10 @@ void radix_sort_pairs(uint32_t* keys, int32_t* vals, int64_t n, int key_bits, hi
 template <typename T>
 int64_t count_nonempty_rows(const T* rp, int64_t n, hipStream_t s);
 
+// out[g] = sum of squared row lengths of group g (gid NULL: one group, out[0]).
+// Enqueued on s, no wait.
+void sum_len2_by_group(const int64_t* rp, const int32_t* gid, int64_t n, unsigned long long* out,
+                       int32_t groups, hipStream_t s);
 // cnt[c] = number of i in [0, n) with gid[i] == c and rp[i+1] > rp[i], for
 // c in [0, groups); gid[i] must lie in [0, groups).  Enqueued on s, no wait.
 template <typename T>

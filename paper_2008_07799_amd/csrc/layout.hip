@@ -204,18 +204,32 @@ __global__ void k_level_weights(int32_t nl, const int32_t* __restrict__ seg,
     w[a] = s;
 }
 
+// A node's two coordinates as one 64-bit access, so a concurrent reader sees
+// both from before or both from after an update (never x from one and y
+// from the other, a position the layout never held).
+__device__ __forceinline__ float2 pos_load(const float2* p) {
+    const uint64_t v = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float2*>(p)),
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+__device__ __forceinline__ void pos_store(float2* p, float x, float y) {
+    const uint64_t v = (uint64_t)__float_as_uint(x) | ((uint64_t)__float_as_uint(y) << 32);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Hogwild: reads the live coordinates, adds eta g_i / w_{c(i)} to y[c(i)] at once.
 template <int B, int G>
 __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
     const int lane = threadIdx.x % G;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
-    volatile float* yv = reinterpret_cast<volatile float*>(a.y);
     for (int64_t i = grp; i < a.n0; i += ngrp) {
         const int64_t rs = a.prp[i], re = a.prp[i + 1];
         if (rs >= re) continue;
         const int32_t ci = a.cmap ? a.cmap[i] : (int32_t)i;
-        const float yix = yv[2 * ci], yiy = yv[2 * ci + 1];
+        const float2 pi = pos_load(a.y + ci);
+        const float yix = pi.x, yiy = pi.y;
         const float zi = a.invZ[i];
         const PairW pw = pair_w(a.A, a.Ex, i);
         float ax = 0.0f, ay = 0.0f;
@@ -223,7 +237,8 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             const uint32_t e = a.colhop[x];
             const int32_t j = (int32_t)(e & COL_MASK);
             const int32_t cj = a.cmap ? a.cmap[j] : j;
-            const float dx = yix - yv[2 * cj], dy = yiy - yv[2 * cj + 1];
+            const float2 pj = pos_load(a.y + cj);
+            const float dx = yix - pj.x, dy = yiy - pj.y;
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
                 const float k = attract_coef_b<B, float>(d2, a.half != 0);
@@ -239,7 +254,8 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
             const uint64_t w = neg_word(a.seed, a.iter, (int32_t)i, m);
             const int32_t v = draw_node(w, a.C, a.guide, a.gbits, a.S);
             const int32_t cv = a.cmap ? a.cmap[v] : v;
-            const float dx = yix - yv[2 * cv], dy = yiy - yv[2 * cv + 1];
+            const float2 pv = pos_load(a.y + cv);
+            const float dx = yix - pv.x, dy = yiy - pv.y;
             const float d2 = dx * dx + dy * dy;
             if (d2 > 0.0f) {
                 const float k = repel_coef_b<B, float>(d2, a.half != 0);
@@ -261,8 +277,7 @@ __global__ __launch_bounds__(256) void k_sweep_async(SweepArgs<float> a) {
                     atomicAdd(&a.y[ci].x, sx);
                     atomicAdd(&a.y[ci].y, sy);
                 } else {
-                    yv[2 * ci] = yix + sx;
-                    yv[2 * ci + 1] = yiy + sy;
+                    pos_store(a.y + ci, yix + sx, yiy + sy);
                 }
             }
         }
@@ -404,7 +419,7 @@ void layout_step_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_p
     a.cmap = cmap;
     a.invZ = invZ;
     a.eta = (T)p->eta;
-    const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
+    const int G = sweep_group(s->len_wmean, s->n_active);
     // Both modes stage the records on the column-blocked layout: its Hogwild
     // form reads neighbours from LDS copies of the records and updates them
     // in place as windows of rows finish.
@@ -526,7 +541,7 @@ void layout_step(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_par
 // a step is recorded into a graph).
 void prepare_sync_step(drg_ctx* ctx, drg_sim* s) {
     if (s->blk_nb > 0 || s->A.get() || s->Ex.get() || !window_wanted(s)) return;
-    const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
+    const int G = sweep_group(s->len_wmean, s->n_active);
     const int rpl = win_rpl();
     if (s->win_rpl != rpl) {
         s->win_n = build_window_items(ctx, s, {0, s->n}, {(WIN_BLOCK / G) * rpl}, s->win_items);

@@ -431,7 +431,7 @@ void layout_step3_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_
         DRG_HIP(hipEventCreate(&e1));
         DRG_HIP(hipEventRecord(e0, st));
     }
-    const int G = sweep_group((double)s->nnz / (double)std::max(1, s->n_active));
+    const int G = sweep_group(s->len_wmean, s->n_active);
     switch (p->b) {
         case 1: launch3<T, 1>(st, a, G, async); break;
         case 2: launch3<T, 2>(st, a, G, async); break;

@@ -256,6 +256,34 @@ void count_nonempty_by_group(const T* rp, const int32_t* gid, int64_t n, int32_t
     }
 }
 
+// out[g] = sum over the rows of group g of len^2 (gid NULL: one group).  A
+// wave whose rows all belong to one group adds with one atomic.
+__global__ void k_sum_len2(const int64_t* __restrict__ rp, const int32_t* __restrict__ gid,
+                           int64_t n, unsigned long long* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < n;
+    const unsigned long long l = in ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull;
+    const unsigned long long v = l * l;
+    const int32_t g = in ? (gid ? gid[i] : 0) : -1;
+    const int32_t g0 = __builtin_amdgcn_readfirstlane(g);
+    if (__all(g == g0 || !in)) {
+        const unsigned long long t = group_sum<WAVE>(v);
+        if (__lane_id() == 0 && t) atomicAdd(&out[g0], t);
+    } else if (in && v) {
+        atomicAdd(&out[g], v);
+    }
+}
+
+void sum_len2_by_group(const int64_t* rp, const int32_t* gid, int64_t n, unsigned long long* out,
+                       int32_t groups, hipStream_t s) {
+    DRG_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long) * (size_t)std::max<int32_t>(groups, 1),
+                           s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_sum_len2, dim3(ceil_div(n, 256)), dim3(256), 0, s, rp, gid, n, out);
+        DRG_LAUNCH_CHECK();
+    }
+}
+
 template void count_nonempty_by_group<int32_t>(const int32_t*, const int32_t*, int64_t, int32_t*,
                                                int32_t, hipStream_t);
 template void count_nonempty_by_group<int64_t>(const int64_t*, const int32_t*, int64_t, int32_t*,

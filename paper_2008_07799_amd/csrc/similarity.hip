@@ -1031,6 +1031,14 @@ drg_sim* build_similarity(drg_ctx* ctx, const drg_csr* g, int k, double sigma, u
     DRG_HIP(hipMemcpyAsync(&s->S, s->C.get() + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     DRG_HIP(hipStreamSynchronize(st));
     s->n_active = (int32_t)count_nonempty_rows<int64_t>(s->row_ptr.get(), n, st);
+    if (!u && s->nnz > 0) {
+        DevBuf<unsigned long long> l2(1);
+        sum_len2_by_group(s->row_ptr.get(), nullptr, n, l2.get(), 1, st);
+        unsigned long long h = 0;
+        DRG_HIP(hipMemcpyAsync(&h, l2.get(), sizeof(h), hipMemcpyDeviceToHost, st));
+        DRG_HIP(hipStreamSynchronize(st));
+        s->len_wmean = (double)h / (double)s->nnz;
+    }
     s->rec.alloc(n);
     s->g.alloc(n);
     if (u) {  // per-graph guides belong to the batch

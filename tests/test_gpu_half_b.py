@@ -85,17 +85,21 @@ def test_objective_and_gradient(oracle_lib, b, dim, f64):
     assert eg < (1e-10 if f64 else 1e-5)
 
 
-@pytest.mark.parametrize("b,mode", [(1.5, 0), (2.5, 0), (2.5, 1)])
+@pytest.mark.parametrize("b,mode", [(1.5, 0), (1.5, 1), (2.5, 0), (2.5, 1)])
 def test_full_layout_statistics(oracle_lib, b, mode):
     """R-MAT 2^13, edge factor 16, k=2, M=5, T=300, coarsened until < 1000
     nodes: the product's end-to-end layout (sync, and the Hogwild row form)
     against the oracle's sync layout, final objective within 1% and NP
-    within 0.01."""
+    within 0.01.  At b = 2.5 the step size is 1/2: as with b = 3 (the grid
+    workload's 1/4), the stiffer forces leave the iteration ill-conditioned
+    at 1, where six Hogwild runs ended 0.0-4.2% below the synchronous
+    objective (NP .195-.217 against .216); at 1/2 they stay within 0.8% of
+    the oracle and 0.002 of its NP."""
     from oracle import evaluate
     from paper_2008_07799_amd import drgraph as d
     say("half-b layout", b, "mode", mode)
     g = gen.rmat(13, 16, seed=1)
-    kw = dict(k=2, M=5, b=b, T=300, min_nodes=1000)
+    kw = dict(k=2, M=5, b=b, T=300, min_nodes=1000, eta0=0.5 if b == 2.5 else 1.0)
     c = ctx()
     rp, col = dev_graph(g)
     y = zeros_y(g.n)
