@@ -112,16 +112,6 @@ __device__ __forceinline__ T repelT(T k, T d, T c) {
     else return clampT2(k * d, c);
 }
 
-// Runtime-b forms with exactly the operations of the compile-time ones.
-template <typename T>
-__device__ __forceinline__ T attract_coef_rt(T d2, int b) {
-    return b == 1 ? attract_coef<1>(d2) : (b == 2 ? attract_coef<2>(d2) : attract_coef<3>(d2));
-}
-template <typename T>
-__device__ __forceinline__ T repel_coef_rt(T d2, int b) {
-    return b == 1 ? repel_coef<1>(d2) : (b == 2 ? repel_coef<2>(d2) : repel_coef<3>(d2));
-}
-
 // ------------------------------------------------------------------ per-node steps
 // These bodies are the whole arithmetic of one node in the iteration; the
 // single-graph and the batched kernels call them with the same arguments, so
@@ -232,16 +222,17 @@ __device__ __forceinline__ void repel_lane(const typename VT<T>::v4& ri,
     }
 }
 
-// Butterfly sums over the group, then g_i = attraction + gq * repulsion,
-// rounded once to the coordinate type.
+// g_i = attraction + gq * repulsion: each lane combines its own partials,
+// then butterfly sums over the group (two values, not four: the butterflies
+// are a large part of a short row's work), rounded once to the coordinate
+// type.
 template <typename T>
 __device__ __forceinline__ typename VT<T>::v2 row_total(double ax, double ay, double rx,
                                                         double ry, int G, double gq) {
-    ax = group_sum_rt(ax, G);
-    ay = group_sum_rt(ay, G);
-    rx = group_sum_rt(rx, G);
-    ry = group_sum_rt(ry, G);
-    return mk2<T>((T)(ax + gq * rx), (T)(ay + gq * ry));
+    double tx = ax + gq * rx, ty = ay + gq * ry;
+    tx = group_sum_rt(tx, G);
+    ty = group_sum_rt(ty, G);
+    return mk2<T>((T)tx, (T)ty);
 }
 
 // One row of the sweep, computed by the G lanes of a group (lane = 0..G-1):

@@ -107,13 +107,12 @@ __device__ __forceinline__ Sum3 sweep_row3(const typename VT<T>::v4& ri, double 
             rz += clampT2(k * dz, clip);
         }
     }
-    ax = group_sum_rt(ax, G);
-    ay = group_sum_rt(ay, G);
-    az = group_sum_rt(az, G);
-    rx = group_sum_rt(rx, G);
-    ry = group_sum_rt(ry, G);
-    rz = group_sum_rt(rz, G);
-    return Sum3{ax + gq * rx, ay + gq * ry, az + gq * rz};
+    // each lane's attraction + gq * repulsion, then one butterfly per axis
+    double tx = ax + gq * rx, ty = ay + gq * ry, tz = az + gq * rz;
+    tx = group_sum_rt(tx, G);
+    ty = group_sum_rt(ty, G);
+    tz = group_sum_rt(tz, G);
+    return Sum3{tx, ty, tz};
 }
 
 template <typename T>
