@@ -89,3 +89,25 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(d, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         d.lib()
+
+
+def test_shape_parameter_split():
+    """b crosses the ABI as its whole part plus a half flag (1, 1.5, 2, 2.5,
+    3); other values are refused before any call."""
+    from paper_2008_07799_amd import drgraph as d
+    assert [d._shape(b) for b in (1, 1.5, 2, 2.5, 3)] == [(1, 0), (1, 1), (2, 0), (2, 1), (3, 0)]
+    for bad in (0.5, 1.25, 3.5, 4, 0):
+        with pytest.raises(ValueError):
+            d._shape(bad)
+    p = d.StepParams(5, *d._shape(2.5)[:1], 0.1, 1.0, 4.0, 0, 0, 2, 0, 0, d._shape(2.5)[1])
+    assert (p.b, p.b_half) == (2, 1)
+
+
+def test_layout_params_variants(lib):
+    """Defaults leave the variants off (whole b, one global sigma); keyword
+    overrides set them."""
+    from paper_2008_07799_amd import drgraph as d
+    p = d.layout_params()
+    assert (p.b_half, p.perplexity, p.dim) == (0, 0.0, 0)
+    q = d.layout_params(b=1.5, perplexity=30.0, dim=3)
+    assert (q.b, q.b_half, q.perplexity, q.dim) == (1, 1, 30.0, 3)
