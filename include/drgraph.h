@@ -222,8 +222,9 @@ drg_status drg_sim_info(const drg_sim* s, int32_t* n, int64_t* nnz, int32_t* n_a
                         int32_t* k, int32_t* blocked);
 /* Copies the similarity to host arrays (each nullable; synchronises):
  * row_ptr[n+1], col[nnz], hop[nnz] (1..k), P[nnz] (FP64 P~_ij), qt[n] (FP64),
- * W[n] (uint64 sampling weights), e[k] (FP64; zeros for a node-wise
- * similarity), invZ[n] (FP64). */
+ * W[n] (uint64 sampling weights), e[k] (FP64 exp(-d^2 / (2 sigma^2)) per
+ * hop d; zeros for a node-wise similarity; for a weighted similarity the same
+ * hop values, which its P~ does not use), invZ[n] (FP64). */
 drg_status drg_sim_export(const drg_sim* s, int64_t* row_ptr, int32_t* col, uint8_t* hop,
                           double* P, double* qt, uint64_t* W, double* e, double* invZ);
 /* Copies the rows rows[0..nrows) of the similarity to host arrays (each
