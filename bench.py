@@ -19,7 +19,8 @@ Prints one JSON line.  Extra objects:
                   launch time, against 256 CUs x 64 lanes x 2.4 GHz.  Row-form
                   sweeps are reported against HBM with the algorithmic bytes
                   16 nnz + 16 M N_a + 28 N per launch.  `traffic` (HBM bytes per
-                  launch), `hbm_measured` and `valu_issue` come from committed
+                  launch), `hbm_measured`, `valu_issue` and `l2_hit_rate` come
+                  from committed
                   rocprofv3 counter summaries and are null unless those were
                   taken on the current sources; `convention` keeps the
                   algorithmic-bytes figure of the blocked sweep, which counts
@@ -91,6 +92,19 @@ def _traffic(workload: str, kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def _l2_hit_rate(workload: str, kernel: str):
+    """L2 hit rate of the kernel (TCC_HIT / (TCC_HIT + TCC_MISS)) from a
+    committed rocprofv3 counter summary, if taken on the current source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_l2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != _kernel_source_hash(kernel):
+        return None
+    return rec.get("l2_hit_rate")
+
+
 # Lane-operation issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes
 # x 2.4 GHz (one wave64 VALU instruction per CU per cycle).
 VALU_LANE_PEAK = 256 * 64 * 2.4e9
@@ -133,6 +147,7 @@ def roofline(workload, kernel, avg_ms, launches, nnz, n_active, n, M, b, copy_gb
     common = {"kernel": kernel, "launches": launches, "avg_launch_ms": avg_ms,
               "traffic": traffic, "hbm_measured": hbm_measured,
               "valu_issue": _valu_issue(workload, kernel, avg_ms),
+              "l2_hit_rate": _l2_hit_rate(workload, kernel),
               "measured_copy_GBs": copy_gbs}
     if kernel.startswith("k_sweep_blocked") and b == 1 and t > 0:
         ops = ALU_OPS_PER_PAIR * float(nnz)

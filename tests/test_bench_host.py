@@ -53,6 +53,21 @@ def test_valu_issue_rate(monkeypatch):
     assert bench._valu_issue("rmat20_k2", "k_sweep_blocked", 20.0) is None
 
 
+@pytest.mark.parametrize("name,workload,kernel", [
+    ("k_sweep_blocked_rmat20_k2_l2.json", "rmat20_k2", "k_sweep_blocked"),
+    ("k_sweep_rmat20_k1_l2.json", "rmat20_k1", "k_sweep"),
+])
+def test_l2_hit_rate(monkeypatch, name, workload, kernel):
+    rec = _summary(name)
+    c = rec["counters_per_dispatch"]
+    assert rec["l2_hit_rate"] == pytest.approx(c["TCC_HIT_sum"] / (c["TCC_HIT_sum"] + c["TCC_MISS_sum"]))
+    assert 0.0 <= rec["l2_hit_rate"] <= 1.0
+    monkeypatch.setattr(bench, "_kernel_source_hash", lambda k: rec["source_hash"])
+    assert bench._l2_hit_rate(workload, kernel) == rec["l2_hit_rate"]
+    monkeypatch.setattr(bench, "_kernel_source_hash", lambda k: "changed")
+    assert bench._l2_hit_rate(workload, kernel) is None
+
+
 
 def test_roofline_is_a_fraction_of_the_binding_roof(monkeypatch):
     """The blocked sweep is priced at its 15 VALU lane-instructions per stored
