@@ -20,9 +20,9 @@ Prints one JSON line.  Extra objects:
                   sweeps are reported against HBM with the algorithmic bytes
                   16 nnz + 16 M N_a + 28 N per launch.  `traffic` (HBM bytes per
                   launch), `hbm_measured`, `valu_issue` and `l2_hit_rate` come
-                  from committed
-                  rocprofv3 counter summaries and are null unless those were
-                  taken on the current sources; `convention` keeps the
+                  from committed rocprofv3 counter summaries and are null
+                  unless those were taken on the current sources; `convention`
+                  keeps the
                   algorithmic-bytes figure of the blocked sweep, which counts
                   16 bytes per pair that LDS and recomputation serve and is
                   therefore not a fraction of any roof;
