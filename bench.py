@@ -22,10 +22,9 @@ Prints one JSON line.  Extra objects:
                   launch), `hbm_measured`, `valu_issue` and `l2_hit_rate` come
                   from committed rocprofv3 counter summaries and are null
                   unless those were taken on the current sources; `convention`
-                  keeps the
-                  algorithmic-bytes figure of the blocked sweep, which counts
-                  16 bytes per pair that LDS and recomputation serve and is
-                  therefore not a fraction of any roof;
+                  keeps the algorithmic-bytes figure of the blocked sweep,
+                  which counts 16 bytes per pair that LDS and recomputation
+                  serve and is therefore not a fraction of any roof;
   cpu_baseline -- the FP64 oracle, single-threaded, timed on a bounded sample
                   of the same workload family, with the time-to-layout of the
                   workload extrapolated from it (labelled as such).
