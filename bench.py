@@ -665,7 +665,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_per_launch": n * 4, "launches": 8}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library and this benchmark run on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
