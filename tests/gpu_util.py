@@ -43,3 +43,42 @@ def zeros_y(n, dtype=None):
 def to_y(a, dtype=np.float32):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype)).cuda()
+
+
+def hogwild_vs_oracle_spread(oracle_lib, g, kw, gpu_layout, dim=2, seeds=8, width=4.0):
+    """Holds Hogwild layouts to the distribution of the oracle's layouts.
+
+    A Hogwild run (Sec. 3.2.2's updates applied in place while other nodes
+    read them) follows an update order the hardware picks, so its result is
+    one draw of a random process and no single oracle run is its reference.
+    On the grid workload (32x32, k=3, b=3) the final objective varies by
+    about 7% (one standard deviation) from seed to seed, in 2-D and 3-D, and
+    the range of a few runs misses a fresh draw often.  The oracle runs
+    seeds 0..seeds-1 in Jacobi (sync) and Gauss-Seidel order, the two ends
+    between which Hogwild updates fall; gpu_layout(seed) returns the GPU
+    layout of the same parameters.  Checked, for the sampled objective and
+    NP: every GPU run lies within the oracle's mean +- width standard
+    deviations, and the mean of the GPU runs within width standard errors
+    (two-sample) of the oracle's mean."""
+    from oracle import evaluate
+
+    def stats(y, sim):
+        return (evaluate.objective_eval(sim, y, M=kw["M"], b=kw["b"], gamma=0.1),
+                evaluate.neighbourhood_preservation(g, y))
+
+    ref, sim = [], None
+    for mode in ("sync", "seq"):
+        for seed in range(seeds):
+            y, sim, _ = oracle_lib.layout(g, seed=seed, return_all=True, dim=dim, mode=mode, **kw)
+            ref.append(stats(y, sim))
+    got = np.array([stats(np.asarray(gpu_layout(seed), np.float64), sim)
+                    for seed in range(seeds)])
+    ref = np.array(ref)
+    for q, name in ((0, "objective"), (1, "NP")):
+        mo, so = ref[:, q].mean(), ref[:, q].std(ddof=1)
+        mg, sg = got[:, q].mean(), got[:, q].std(ddof=1)
+        se = np.sqrt(so * so / len(ref) + sg * sg / len(got))
+        say(f"  {name}: oracle mean {mo:.4f} sd {so:.4f}; hogwild mean {mg:.4f} sd {sg:.4f} "
+            f"min {got[:, q].min():.4f} max {got[:, q].max():.4f}")
+        assert np.all(np.abs(got[:, q] - mo) <= width * so), (name, got[:, q], mo, so)
+        assert abs(mg - mo) <= width * se, (name, mg, mo, se)

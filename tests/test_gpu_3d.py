@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2008_07799_amd import gen
-from tests.gpu_util import ctx, dev_graph, normwise_rel, say, to_y
+from tests.gpu_util import ctx, dev_graph, hogwild_vs_oracle_spread, normwise_rel, say, to_y
 
 pytestmark = pytest.mark.gpu
 
@@ -205,28 +205,16 @@ def test_3d_full_layout_statistics(oracle_lib, case, mode):
     np_r = evaluate.neighbourhood_preservation(g, yr)
     say("  3-D layout", case, "mode", mode, "objective", o_g, o_r, "NP", np_g, np_r)
     if case == "grid32" and mode == 1:
-        # On the grid workload the method's own outcome varies more than the
-        # 1% bar: the oracle's layouts over seeds 0..3 (Jacobi and
-        # Gauss-Seidel) span objectives -96.9 .. -114.5 and NP .525 .. .606,
-        # and Gauss-Seidel lands 1.0% and 0.018 NP from Jacobi at seed 0.  The
-        # Hogwild layout is held to that range, widened by 1% and 0.01.
-        lo_o, hi_o, lo_n, hi_n = _oracle_spread(oracle_lib, g, kw, 3)
-        assert lo_o - 0.01 * abs(lo_o) <= o_g <= hi_o + 0.01 * abs(hi_o)
-        assert lo_n - 0.01 <= np_g <= hi_n + 0.01
+        # a Hogwild run is one draw of a random process; on this workload the
+        # oracle's own 3-D layouts vary by about 7% in objective across seeds
+        def run(seed):
+            yy = _z(g.n)
+            d.drg_layout(c, rp, col, d.layout_params(seed=seed, mode=1, dim=3, **kw), yy)
+            assert c.last_sweep() == d.DRG_SWEEP_ROW_ASYNC
+            return yy.cpu().numpy()
+        hogwild_vs_oracle_spread(oracle_lib, g, kw, run, dim=3)
         return
     assert abs(o_g - o_r) <= 0.01 * abs(o_r)
     assert abs(np_g - np_r) <= 0.01
 
 
-def _oracle_spread(oracle_lib, g, kw, dim):
-    """Range of the oracle's final objective and NP over seeds 0..3, Jacobi
-    (sync) and Gauss-Seidel iterations."""
-    from oracle import evaluate
-    objs, nps = [], []
-    for mode in ("sync", "seq"):
-        for seed in range(4):
-            y, sim, _ = oracle_lib.layout(g, seed=seed, return_all=True, dim=dim, mode=mode, **kw)
-            objs.append(evaluate.objective_eval(sim, y, M=kw["M"], b=kw["b"], gamma=0.1))
-            nps.append(evaluate.neighbourhood_preservation(g, y))
-    say("  oracle spread: objective", min(objs), max(objs), "NP", min(nps), max(nps))
-    return min(objs), max(objs), min(nps), max(nps)

@@ -16,7 +16,8 @@ import numpy as np
 import pytest
 
 from paper_2008_07799_amd import gen
-from tests.gpu_util import ctx, dev_graph, normwise_rel, say, to_y, zeros_y
+from tests.gpu_util import (ctx, dev_graph, hogwild_vs_oracle_spread, normwise_rel, say,
+                            to_y, zeros_y)
 
 pytestmark = pytest.mark.gpu
 
@@ -283,7 +284,8 @@ def test_full_layout_statistics(oracle_lib, case, mode):
     """End to end (FP32 sync, FP32 async) vs the oracle's sync layout with the
     same parameters: final sampled objective within 1% and NP within 0.01.
     grid32 is the grid workload (k=3, M=5, b=3, T=300, one level, its step
-    size); its async run is the Hogwild row sweep.  R-MAT 2^13, edge factor
+    size); its async run is the Hogwild row sweep, held to the distribution
+    of the oracle's layouts over seeds.  R-MAT 2^13, edge factor
     16, k=2, M=5, b=1, T=300, coarsened until < 1000 nodes, is above the
     column-blocked threshold: its async run is the Hogwild form of the
     blocked sweep.  Across seeds the oracle's own final objective varies by
@@ -315,19 +317,14 @@ def test_full_layout_statistics(oracle_lib, case, mode):
     np_r = evaluate.neighbourhood_preservation(g, yr)
     say("  objective", obj_g, obj_r, "NP", np_g, np_r)
     if case == "grid32" and mode == 1:
-        # the grid workload's outcome varies across seeds far beyond 1%: the
-        # oracle's layouts over seeds 0..3 (Jacobi and Gauss-Seidel) span
-        # objectives -184.9 .. -218.5 and NP .211 .. .258; the Hogwild layout
-        # is held to that range, widened by 1% and 0.01
-        objs, nps = [], []
-        for m in ("sync", "seq"):
-            for seed in range(4):
-                yo, so, _ = oracle_lib.layout(g, seed=seed, return_all=True, mode=m, **kw)
-                objs.append(evaluate.objective_eval(so, yo, M=M, b=b, gamma=0.1))
-                nps.append(evaluate.neighbourhood_preservation(g, yo))
-        say("  oracle spread", min(objs), max(objs), min(nps), max(nps))
-        assert min(objs) - 0.01 * abs(min(objs)) <= obj_g <= max(objs) + 0.01 * abs(max(objs))
-        assert min(nps) - 0.01 <= np_g <= max(nps) + 0.01
+        # a Hogwild run is one draw of a random process; on this workload the
+        # oracle's own layouts vary by about 7% in objective across seeds
+        def run(seed):
+            yy = zeros_y(g.n)
+            d.drg_layout(c, rp, col, d.layout_params(seed=seed, mode=1, **kw), yy)
+            assert c.last_sweep() == want
+            return yy.cpu().numpy()
+        hogwild_vs_oracle_spread(oracle_lib, g, kw, run)
         return
     assert abs(obj_g - obj_r) <= 0.01 * abs(obj_r)
     assert abs(np_g - np_r) <= 0.01
