@@ -330,6 +330,40 @@ def test_full_layout_statistics(oracle_lib, case, mode):
     assert abs(np_g - np_r) <= 0.01
 
 
+def test_blocked_async_many_blocks_statistics(oracle_lib, monkeypatch):
+    """The asynchronous form of the blocked sweep (rows moved stage by stage,
+    Sec. 3.2.2's updates seen by the later stages) on a pattern cut into 16
+    column blocks of 512 nodes, as on large graphs where a stage's work items
+    span many blocks and a row's partials come from items of several
+    workgroups: R-MAT 2^13, edge factor 16, k=2, M=5, b=1, T=300, coarsened
+    until < 1000 nodes, 4 stages; end to end against the oracle's sync
+    layout, objective within 1% and NP within 0.01 (the oracle's own final
+    objective varies by about 0.1% across seeds on this graph)."""
+    from oracle import evaluate
+    from paper_2008_07799_amd import drgraph as d
+    monkeypatch.setenv("DRG_SWEEP_BLOCKED", "1")
+    monkeypatch.setenv("DRG_BLOCK_BITS", "9")
+    monkeypatch.setenv("DRG_ASYNC_STAGES", "4")
+    say("blocked async, 16 blocks")
+    g = gen.rmat(13, 16, seed=1)
+    kw = dict(k=2, M=5, b=1, T=300, min_nodes=1000)
+    c = ctx()
+    rp, col = dev_graph(g)
+    y = zeros_y(g.n)
+    d.drg_layout(c, rp, col, d.layout_params(seed=0, mode=1, **kw), y)
+    assert c.last_sweep() == d.DRG_SWEEP_BLOCKED_ASYNC
+    yg = y.cpu().numpy().astype(np.float64)
+    assert np.isfinite(yg).all()
+    yr, rsim, _ = oracle_lib.layout(g, seed=0, return_all=True, **kw)
+    obj_g = evaluate.objective_eval(rsim, yg, M=5, b=1, gamma=0.1)
+    obj_r = evaluate.objective_eval(rsim, yr, M=5, b=1, gamma=0.1)
+    np_g = evaluate.neighbourhood_preservation(g, yg)
+    np_r = evaluate.neighbourhood_preservation(g, yr)
+    say("  objective", obj_g, obj_r, "NP", np_g, np_r)
+    assert abs(obj_g - obj_r) <= 0.01 * abs(obj_r)
+    assert abs(np_g - np_r) <= 0.01
+
+
 @pytest.mark.parametrize("bits,form", [(8, "flat2"), (10, "flat2"), (10, "flat4"), (12, "flat4"),
                                        (8, "rows0"), (8, "rows16"), (10, "rows32"),
                                        (10, "rows64")])
