@@ -1,5 +1,6 @@
 // drg_internal.hpp -- library-private state behind the opaque C handles.
 #pragma once
+#include <atomic>
 #include <vector>
 
 #include "../../include/drgraph.h"
@@ -21,6 +22,15 @@ struct drg_ctx {
 };
 
 // Sparse similarity P~ over the finest graph plus the sampling table.
+namespace drg {
+// a number no other object of the process gets (cache keys that must not
+// match a later object allocated at a freed one's address)
+inline uint64_t next_uid() {
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
+}  // namespace drg
+
 struct drg_sim {
     int device = 0;
     int32_t n = 0, k = 0, n_active = 0;
@@ -52,6 +62,8 @@ struct drg_sim {
     drg::DevBuf<float4> rec;         // [n] staged (y_c(j), invZ_j)
     drg::DevBuf<float2> g;           // [n] one-sided steps
     drg::DevBuf<float> wlev;         // [n] anchor weights of level nodes (async)
+    uint64_t wlev_hier = 0;          // uid of the hierarchy whose level wlev holds (0: none)
+    int32_t wlev_level = -1;
     drg::DevBuf<double4> rec64;      // FP64 instance workspace (allocated on use)
     drg::DevBuf<double2> g64;
     drg::DevBuf<float> g3;           // [n][3] steps of a 3-D layout (allocated on use)
@@ -86,6 +98,7 @@ struct drg_level {
 struct drg_hier {
     int device = 0;
     int32_t n0 = 0;
+    uint64_t uid = drg::next_uid();  // distinct for every hierarchy of the process
     std::vector<drg_level> lv;       // lv[0] describes G^0 (sizes only)
 };
 

@@ -413,10 +413,16 @@ void layout_step3_t(drg_ctx* ctx, drg_sim* s, const drg_hier* h, const drg_step_
             a.w = qt;
         } else {
             if (!s->wlev.get()) s->wlev.alloc(n0);
-            const drg_level& L = h->lv[level];
-            hipLaunchKernelGGL(k_level_weights3<float>, dim3(ceil_div(nl, 256)), dim3(256), 0, st,
-                               nl, L.seg.get(), L.perm.get(), s->qtf.get(), s->wlev.get());
-            DRG_LAUNCH_CHECK();
+            // a level node's anchor weight (its members' q~ summed) is fixed
+            // for the level: computed once per (hierarchy, level)
+            if (s->wlev_hier != h->uid || s->wlev_level != level) {
+                const drg_level& L = h->lv[level];
+                hipLaunchKernelGGL(k_level_weights3<float>, dim3(ceil_div(nl, 256)), dim3(256), 0, st,
+                                   nl, L.seg.get(), L.perm.get(), s->qtf.get(), s->wlev.get());
+                DRG_LAUNCH_CHECK();
+                s->wlev_hier = h->uid;
+                s->wlev_level = level;
+            }
             a.w = reinterpret_cast<const T*>(s->wlev.get());
         }
     } else {

@@ -364,6 +364,46 @@ def test_blocked_async_many_blocks_statistics(oracle_lib, monkeypatch):
     assert abs(np_g - np_r) <= 0.01
 
 
+def test_async_level_weights_follow_the_hierarchy(monkeypatch):
+    """A coarse level's anchor weights (each level node's members' q~
+    summed) are computed once per (hierarchy, level) and reused by later
+    asynchronous steps.  Checked through a case where the asynchronous step
+    has a deterministic counterpart: the blocked sweep in one stage and
+    without negatives takes every attraction from the records staged at the
+    step's start, as the synchronous step does, so each level node moves as
+    in the synchronous step up to the order of its FP32 additions.  Two
+    hierarchies of one similarity in turn, every coarse level, two
+    asynchronous steps (the second on the stored weights) per level."""
+    from paper_2008_07799_amd import drgraph as d
+    monkeypatch.setenv("DRG_SWEEP_BLOCKED", "1")
+    monkeypatch.setenv("DRG_BLOCK_BITS", "9")
+    monkeypatch.setenv("DRG_ASYNC_STAGES", "1")
+    say("async level weights across hierarchies")
+    g = gen.rmat(12, 8, seed=3)
+    c = ctx()
+    rp, col = dev_graph(g)
+    sim = d.drg_build_similarity(c, rp, col, 2)
+    assert sim.blocked
+    hs = [d.drg_coarsen(c, rp, col, seed=s, rho=0.8, min_nodes=50, max_levels=3) for s in (1, 2)]
+    assert all(h.levels >= 2 for h in hs)
+    rng = np.random.default_rng(8)
+    kw = dict(M=0, b=1, gamma=0.1, eta=0.9, clip=4.0, seed=4, iter=1)
+    for h in (hs[0], hs[1], hs[0]):
+        for l in range(1, h.levels):
+            y0 = rng.uniform(-3, 3, size=(h.sizes[l], 2)).astype(np.float32)
+            ys = to_y(y0)
+            d.drg_layout_step(c, sim, h, ys, level=l, mode=d.DRG_MODE_SYNC, **kw)
+            step_s = ys.cpu().numpy().astype(np.float64) - y0
+            for rep in range(2):
+                ya = to_y(y0)
+                d.drg_layout_step(c, sim, h, ya, level=l, mode=d.DRG_MODE_ASYNC, **kw)
+                assert c.last_sweep() == d.DRG_SWEEP_BLOCKED_ASYNC
+                step_a = ya.cpu().numpy().astype(np.float64) - y0
+                err = normwise_rel(step_a, step_s)
+                say("  level", l, "rep", rep, "step error", err)
+                assert err < 1e-4
+
+
 @pytest.mark.parametrize("bits,form", [(8, "flat2"), (10, "flat2"), (10, "flat4"), (12, "flat4"),
                                        (8, "rows0"), (8, "rows16"), (10, "rows32"),
                                        (10, "rows64")])
